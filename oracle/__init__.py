@@ -1,0 +1,127 @@
+"""FP64 CPU oracle for the 3PCF multipoles -- test infrastructure.
+
+Only the tests, the smoke check and the benchmark's ``cpu_baseline`` leg may import this
+package. The GPU library never calls it and shares no code with it. The C source
+(``tpcf_oracle.c``) states the definition it computes and every reading taken where the paper
+is silent; this module only loads it with ctypes and converts arrays.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "tpcf_oracle.c")
+_LIB = os.path.join(_HERE, "libtpcf_oracle.so")
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (-O2, no fast-math, OpenMP). Returns the library path."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+                               "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB)
+        p = ctypes.c_void_p
+        i64 = ctypes.c_int64
+        d = ctypes.c_double
+        i = ctypes.c_int
+        lib.oracle_lattice_bits.argtypes = [d, d, i]
+        lib.oracle_lattice_bits.restype = i
+        lib.oracle_thresholds.argtypes = [i, d, d, d, i, p]
+        lib.oracle_thresholds.restype = None
+        lib.oracle_snap.argtypes = [i64, p, d, i, i, p]
+        lib.oracle_snap.restype = None
+        lib.oracle_ylm.argtypes = [i, i64, p, p, p, p, p]
+        lib.oracle_ylm.restype = i
+        lib.oracle_zeta.argtypes = [i64, p, p, p, p, d, i, i, d, d, i, i64, i64, p, p, p, p, i]
+        lib.oracle_zeta.restype = i
+        _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def lattice_bits(box: float, rmax: float, periodic: bool) -> int:
+    return int(_load().oracle_lattice_bits(float(box), float(rmax), int(bool(periodic))))
+
+
+def thresholds(nbins: int, rmin: float, rmax: float, box: float, K: int) -> np.ndarray:
+    T = np.zeros(nbins + 1, dtype=np.uint64)
+    _load().oracle_thresholds(int(nbins), float(rmin), float(rmax), float(box), int(K), _ptr(T))
+    return T
+
+
+def snap(x, box: float, K: int, periodic: bool) -> np.ndarray:
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    q = np.zeros(x.shape[0], dtype=np.int64)
+    _load().oracle_snap(x.shape[0], _ptr(x), float(box), int(K), int(bool(periodic)), _ptr(q))
+    return q
+
+
+def ylm(ux, uy, uz, lmax: int) -> np.ndarray:
+    """Y_lm of unit vectors; returns complex [n, (lmax+1)^2], column l*l + l + m."""
+    ux = np.ascontiguousarray(ux, dtype=np.float64)
+    uy = np.ascontiguousarray(uy, dtype=np.float64)
+    uz = np.ascontiguousarray(uz, dtype=np.float64)
+    n = ux.shape[0]
+    nc = (lmax + 1) ** 2
+    re = np.zeros((n, nc))
+    im = np.zeros((n, nc))
+    rc = _load().oracle_ylm(int(lmax), n, _ptr(ux), _ptr(uy), _ptr(uz), _ptr(re), _ptr(im))
+    if rc:
+        raise ValueError("oracle_ylm: invalid lmax")
+    return re + 1j * im
+
+
+class Result:
+    def __init__(self, zeta, counts, alm, npairs):
+        self.zeta = zeta
+        self.counts = counts
+        self.alm = alm
+        self.npairs = npairs
+
+
+def zeta(x, y, z, w, box: float, periodic: bool, nbins: int, rmin: float, rmax: float,
+         lmax: int, p_begin: int = 0, p_end: int | None = None, want_counts: bool = False,
+         want_alm: bool = False, threads: int = 0) -> Result:
+    """zeta_l(b1, b2) in FP64 for primaries [p_begin, p_end) against all secondaries."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    n = x.shape[0]
+    w = np.ones(n) if w is None else np.ascontiguousarray(w, dtype=np.float64)
+    if p_end is None:
+        p_end = n
+    npr = p_end - p_begin
+    zt = np.zeros((lmax + 1, nbins, nbins))
+    counts = np.zeros((npr, nbins), dtype=np.int64) if want_counts else None
+    alm = np.zeros((npr, nbins, (lmax + 1) ** 2, 2)) if want_alm else None
+    npairs = ctypes.c_int64(0)
+    rc = _load().oracle_zeta(
+        n, _ptr(x), _ptr(y), _ptr(z), _ptr(w), float(box), int(bool(periodic)), int(nbins),
+        float(rmin), float(rmax), int(lmax), int(p_begin), int(p_end), _ptr(zt),
+        _ptr(counts) if counts is not None else None,
+        _ptr(alm) if alm is not None else None, ctypes.byref(npairs), int(threads))
+    if rc:
+        raise ValueError("oracle_zeta: invalid arguments")
+    a = None if alm is None else alm[..., 0] + 1j * alm[..., 1]
+    return Result(zt, counts, a, int(npairs.value))
+
+
+def zeta_catalog(cat, nbins, rmin, rmax, lmax, **kw) -> Result:
+    return zeta(cat.x, cat.y, cat.z, cat.w, cat.box, cat.periodic, nbins, rmin, rmax, lmax, **kw)

@@ -1,0 +1,304 @@
+/*
+ * tpcf_oracle.c -- plain, slow FP64 CPU oracle for the 3PCF multipoles.
+ *
+ * TEST INFRASTRUCTURE ONLY. Only the test suite, the smoke check and the benchmark's CPU
+ * baseline may load this library. The product path never calls it, and this file shares no
+ * code, header, table or constant with the GPU library: everything below is written out
+ * from the definition of the estimator.
+ *
+ * What is computed (Implementation section of the paper: a harmonic decomposition of the
+ * triangle angle; per pivot, all neighbours in range fill multipole bins; the spherical
+ * harmonic form is the 3D version of the expansion the paper builds on, Szapudi 2004 and
+ * Slepian & Eisenstein 2015, both cited in the Statement of need and Features sections):
+ *
+ *   for every primary p and secondary j != p with r_min <= |x_j - x_p| < r_max,
+ *     b(p,j)     = radial bin of the separation,
+ *     a_lm(p,b)  = sum_{j in b} w_j conj(Y_lm(unit(x_j - x_p))),    -l <= m <= l,
+ *   zeta_l(b1,b2) = sum_p w_p sum_{m=-l}^{l} Re[ a_lm(p,b1) conj(a_lm(p,b2)) ].
+ *
+ * Y_lm is the orthonormal spherical harmonic with the Condon-Shortley phase, evaluated here
+ * the textbook way: theta = acos(u_z), phi = atan2(u_y, u_x),
+ *   Y_lm = N_lm P_l^m(cos theta) e^{i m phi},  N_lm = sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!),
+ *   Y_{l,-m} = (-1)^m conj(Y_lm).
+ * P_l^m comes from the standard upward recurrence in l at fixed m, seeded by
+ *   P_m^m = (-1)^m (2m-1)!! (1-x^2)^{m/2},  P_{m+1}^m = (2m+1) x P_m^m.
+ *
+ * Readings where the paper is silent (the paper prints no estimator formula):
+ *   - Positions are snapped to a cubic lattice of spacing s = L / 2^K with
+ *     K = 25 + floor(log2(L / r_max)), capped at 32 (periodic) or 31 (non-periodic), so that
+ *     r_max / s <= 2^25 and every in-range squared separation is an exact integer below 2^53.
+ *     q = floor(x * (2^K / L)) taken mod 2^K (periodic) or clamped to [0, 2^K) (non-periodic).
+ *   - Periodic boxes use the minimum image of the lattice displacement.
+ *   - Bins are half-open and linear: e_k = r_min + k (r_max - r_min)/n_b, e_{n_b} = r_max;
+ *     integer thresholds T_k = ceil(fl64(fl64(e_k * 2^K/L)^2)); the pair is in bin k iff
+ *     T_k <= R^2 < T_{k+1} with R^2 the exact integer squared lattice separation.
+ *   - Pairs with R^2 = 0 have no direction and are skipped.
+ *   - The primary weight w_p multiplies each primary's contribution.
+ *   - The j = k term (one secondary on both triangle legs) is included, as it is in
+ *     a a^* itself.
+ *
+ * Summation: each primary's a_lm is a plain sequential FP64 sum over j in input order. The
+ * primaries are cut into at most ORACLE_CHUNKS fixed chunks; each chunk is summed
+ * sequentially and the chunk partials are added in chunk order, so the result does not depend
+ * on the number of threads.
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORACLE_LMAX_CAP 16
+#define ORACLE_CHUNKS 1024
+
+/* ---------------------------------------------------------------- lattice and bins */
+
+int oracle_lattice_bits(double box, double rmax, int periodic)
+{
+    int e = 0;
+    frexp(box / rmax, &e); /* box/rmax = f * 2^e with f in [0.5, 1): floor(log2) = e - 1 */
+    int K = 25 + (e - 1);
+    int kcap = periodic ? 32 : 31;
+    if (K > kcap) K = kcap;
+    if (K < 1) K = 1;
+    return K;
+}
+
+static double lattice_scale(double box, int K) { return ldexp(1.0, K) / box; }
+
+void oracle_thresholds(int nbins, double rmin, double rmax, double box, int K, uint64_t *T)
+{
+    double sc = lattice_scale(box, K);
+    double delta = (rmax - rmin) / nbins;
+    for (int k = 0; k <= nbins; k++) {
+        double e = (k == nbins) ? rmax : rmin + k * delta;
+        double v = e * sc;
+        T[k] = (uint64_t)ceil(v * v);
+    }
+}
+
+/* Lattice coordinate of one position. */
+static int64_t snap(double x, double sc, int K, int periodic)
+{
+    int64_t M = (int64_t)1 << K;
+    int64_t t = (int64_t)floor(x * sc);
+    if (periodic) {
+        t %= M;
+        if (t < 0) t += M;
+    } else {
+        if (t < 0) t = 0;
+        if (t > M - 1) t = M - 1;
+    }
+    return t;
+}
+
+/* Snap a whole catalogue (exported so tests can check the lattice itself). */
+void oracle_snap(int64_t n, const double *x, double box, int K, int periodic, int64_t *q)
+{
+    double sc = lattice_scale(box, K);
+    for (int64_t i = 0; i < n; i++) q[i] = snap(x[i], sc, K, periodic);
+}
+
+/* ---------------------------------------------------------------- spherical harmonics */
+
+static int lm_index(int l, int m) { return l * l + l + m; } /* m in [-l, l] */
+
+/* Y_lm(u) for 0 <= l <= lmax, -l <= m <= l, into Y[lm_index(l,m)]. u must be a unit vector. */
+static void ylm_unit(int lmax, double ux, double uy, double uz, double complex *Y)
+{
+    double P[ORACLE_LMAX_CAP + 1][ORACLE_LMAX_CAP + 1];
+    double ct = uz;
+    if (ct > 1.0) ct = 1.0;
+    if (ct < -1.0) ct = -1.0;
+    double theta = acos(ct);
+    double phi = atan2(uy, ux);
+    double x = cos(theta);
+    double sx = sin(theta); /* (1 - x^2)^{1/2} >= 0 */
+
+    for (int m = 0; m <= lmax; m++) {
+        /* P_m^m = (-1)^m (2m-1)!! (1-x^2)^{m/2} */
+        double pmm = 1.0;
+        for (int i = 1; i <= m; i++) pmm *= -(2.0 * i - 1.0) * sx;
+        P[m][m] = pmm;
+        if (m + 1 <= lmax) P[m + 1][m] = (2.0 * m + 1.0) * x * pmm;
+        for (int l = m + 2; l <= lmax; l++)
+            P[l][m] = ((2.0 * l - 1.0) * x * P[l - 1][m] - (l + m - 1.0) * P[l - 2][m]) / (double)(l - m);
+    }
+    for (int l = 0; l <= lmax; l++) {
+        for (int m = 0; m <= l; m++) {
+            long double ratio = 1.0L; /* (l-m)!/(l+m)! */
+            for (int i = l - m + 1; i <= l + m; i++) ratio /= (long double)i;
+            double N = sqrt((double)((2.0L * l + 1.0L) / (4.0L * 3.14159265358979323846264338327950288L) * ratio));
+            double complex e = cos(m * phi) + I * sin(m * phi);
+            double complex y = N * P[l][m] * e;
+            Y[lm_index(l, m)] = y;
+            if (m > 0) Y[lm_index(l, -m)] = ((m & 1) ? -1.0 : 1.0) * conj(y);
+        }
+    }
+}
+
+/* Exported for the tests: Y_lm of n unit vectors, out arrays [n][(lmax+1)^2]. */
+int oracle_ylm(int lmax, int64_t n, const double *ux, const double *uy, const double *uz,
+               double *out_re, double *out_im)
+{
+    if (lmax < 0 || lmax > ORACLE_LMAX_CAP) return 1;
+    int nc = (lmax + 1) * (lmax + 1);
+    double complex Y[(ORACLE_LMAX_CAP + 1) * (ORACLE_LMAX_CAP + 1)];
+    for (int64_t i = 0; i < n; i++) {
+        ylm_unit(lmax, ux[i], uy[i], uz[i], Y);
+        for (int c = 0; c < nc; c++) {
+            out_re[i * nc + c] = creal(Y[c]);
+            out_im[i * nc + c] = cimag(Y[c]);
+        }
+    }
+    return 0;
+}
+
+/* ---------------------------------------------------------------- the estimator */
+
+typedef struct {
+    int64_t n;
+    const int64_t *qx, *qy, *qz;
+    const double *w;
+    int K, periodic, nbins, lmax;
+    const uint64_t *T;
+} problem;
+
+/* Minimum-image (periodic) or plain lattice displacement along one axis. */
+static int64_t displacement(int64_t qj, int64_t qp, int K, int periodic)
+{
+    int64_t d = qj - qp;
+    if (periodic) {
+        int64_t M = (int64_t)1 << K;
+        if (d >= M / 2) d -= M;
+        if (d < -M / 2) d += M;
+    }
+    return d;
+}
+
+/* Bin of the pair (p, j): -1 when out of range. Also returns the displacement. */
+static int pair_bin(const problem *P, int64_t p, int64_t j, int64_t d[3])
+{
+    d[0] = displacement(P->qx[j], P->qx[p], P->K, P->periodic);
+    d[1] = displacement(P->qy[j], P->qy[p], P->K, P->periodic);
+    d[2] = displacement(P->qz[j], P->qz[p], P->K, P->periodic);
+    const int64_t lim = (int64_t)1 << 26; /* beyond this on one axis, R^2 > 2^52 > T_nb */
+    for (int a = 0; a < 3; a++)
+        if (d[a] > lim || d[a] < -lim) return -1;
+    uint64_t R2 = (uint64_t)(d[0] * d[0]) + (uint64_t)(d[1] * d[1]) + (uint64_t)(d[2] * d[2]);
+    if (R2 == 0) return -1;
+    if (R2 < P->T[0] || R2 >= P->T[P->nbins]) return -1;
+    int b = 0;
+    while (b + 1 < P->nbins && R2 >= P->T[b + 1]) b++;
+    return b;
+}
+
+/* One primary: a_lm over all secondaries, then its contribution to zeta (added into zacc). */
+static void one_primary(const problem *P, int64_t p, double complex *alm, double complex *Y,
+                        double *zacc, int64_t *counts, int64_t *npairs)
+{
+    const int nb = P->nbins, lmax = P->lmax, nc = (lmax + 1) * (lmax + 1);
+    memset(alm, 0, sizeof(double complex) * (size_t)nb * nc);
+    for (int b = 0; b < nb; b++) counts[b] = 0;
+    for (int64_t j = 0; j < P->n; j++) {
+        if (j == p) continue;
+        int64_t d[3];
+        int b = pair_bin(P, p, j, d);
+        if (b < 0) continue;
+        double r = sqrt((double)d[0] * d[0] + (double)d[1] * d[1] + (double)d[2] * d[2]);
+        ylm_unit(lmax, d[0] / r, d[1] / r, d[2] / r, Y);
+        double complex *a = alm + (size_t)b * nc;
+        for (int c = 0; c < nc; c++) a[c] += P->w[j] * conj(Y[c]);
+        counts[b]++;
+        (*npairs)++;
+    }
+    const double wp = P->w[p];
+    for (int l = 0; l <= lmax; l++)
+        for (int b1 = 0; b1 < nb; b1++)
+            for (int b2 = 0; b2 < nb; b2++) {
+                double s = 0.0;
+                for (int m = -l; m <= l; m++) {
+                    int c = lm_index(l, m);
+                    s += creal(alm[(size_t)b1 * nc + c] * conj(alm[(size_t)b2 * nc + c]));
+                }
+                zacc[((size_t)l * nb + b1) * nb + b2] += wp * s;
+            }
+}
+
+/*
+ * zeta[(lmax+1)][nbins][nbins]: primaries are input indices [p_begin, p_end), secondaries are
+ * all n points. counts (optional) receives [p_end-p_begin][nbins] unit-weight pair counts;
+ * alm_out (optional) receives a_lm as [p_end-p_begin][nbins][(lmax+1)^2][2] (re, im).
+ * Returns 0, or 1 on invalid arguments.
+ */
+int oracle_zeta(int64_t n, const double *x, const double *y, const double *z, const double *w,
+                double box, int periodic, int nbins, double rmin, double rmax, int lmax,
+                int64_t p_begin, int64_t p_end, double *zeta, int64_t *counts, double *alm_out,
+                int64_t *npairs_out, int nthreads)
+{
+    if (n < 0 || nbins < 1 || lmax < 0 || lmax > ORACLE_LMAX_CAP || !(rmin >= 0.0) ||
+        !(rmax > rmin) || !(box > 0.0) || p_begin < 0 || p_end > n || p_begin > p_end)
+        return 1;
+    const int nb = nbins, nc = (lmax + 1) * (lmax + 1);
+    const size_t zsize = (size_t)(lmax + 1) * nb * nb;
+    memset(zeta, 0, sizeof(double) * zsize);
+    if (npairs_out) *npairs_out = 0;
+    if (n == 0 || p_begin == p_end) return 0;
+
+    int K = oracle_lattice_bits(box, rmax, periodic);
+    int64_t *q = (int64_t *)malloc(sizeof(int64_t) * 3 * (size_t)n);
+    uint64_t *T = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(nb + 1));
+    oracle_snap(n, x, box, K, periodic, q);
+    oracle_snap(n, y, box, K, periodic, q + n);
+    oracle_snap(n, z, box, K, periodic, q + 2 * n);
+    oracle_thresholds(nb, rmin, rmax, box, K, T);
+    problem P = {n, q, q + n, q + 2 * n, w, K, periodic, nb, lmax, T};
+
+    const int64_t np = p_end - p_begin;
+    const int64_t nchunk = np < ORACLE_CHUNKS ? np : ORACLE_CHUNKS;
+    double *part = (double *)calloc((size_t)nchunk * zsize, sizeof(double));
+    int64_t *pairs = (int64_t *)calloc((size_t)nchunk, sizeof(int64_t));
+
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel
+    {
+        double complex *alm = (double complex *)malloc(sizeof(double complex) * (size_t)nb * nc);
+        double complex *Y = (double complex *)malloc(sizeof(double complex) * (size_t)nc);
+        int64_t *cnt = (int64_t *)malloc(sizeof(int64_t) * (size_t)nb);
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t c = 0; c < nchunk; c++) {
+            int64_t lo = p_begin + np * c / nchunk, hi = p_begin + np * (c + 1) / nchunk;
+            for (int64_t p = lo; p < hi; p++) {
+                one_primary(&P, p, alm, Y, part + (size_t)c * zsize, cnt, &pairs[c]);
+                if (counts)
+                    for (int b = 0; b < nb; b++) counts[(p - p_begin) * nb + b] = cnt[b];
+                if (alm_out)
+                    for (size_t k = 0; k < (size_t)nb * nc; k++) {
+                        alm_out[((size_t)(p - p_begin) * nb * nc + k) * 2] = creal(alm[k]);
+                        alm_out[((size_t)(p - p_begin) * nb * nc + k) * 2 + 1] = cimag(alm[k]);
+                    }
+            }
+        }
+        free(alm);
+        free(Y);
+        free(cnt);
+    }
+    int64_t total = 0;
+    for (int64_t c = 0; c < nchunk; c++) {
+        for (size_t k = 0; k < zsize; k++) zeta[k] += part[(size_t)c * zsize + k];
+        total += pairs[c];
+    }
+    if (npairs_out) *npairs_out = total;
+    free(part);
+    free(pairs);
+    free(q);
+    free(T);
+    return 0;
+}

@@ -1,0 +1,101 @@
+"""Independent numpy routes used to pin the oracle (test helpers, no shared code with it).
+
+* ``lattice``/``pair_table``: the lattice snapping and integer binning, re-implemented in
+  numpy from their stated definition.
+* ``zeta_triangles``: the Legendre (triangle) form of the estimator,
+      zeta_l(b1,b2) = (2l+1)/(4 pi) sum_p w_p sum_{j in b1} sum_{k in b2} w_j w_k P_l(u_pj . u_pk),
+  which follows from the spherical-harmonic addition theorem and needs no Y_lm at all.
+* ``pair_counts``: unit-weight per-primary per-bin pair counts.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+from scipy.special import eval_legendre
+
+
+def lattice_bits(box, rmax, periodic):
+    m, e = math.frexp(box / rmax)
+    K = 25 + (e - 1)
+    return max(1, min(K, 32 if periodic else 31))
+
+
+def snap(x, box, K, periodic):
+    sc = math.ldexp(1.0, K) / box
+    t = np.floor(np.asarray(x, dtype=np.float64) * sc).astype(np.int64)
+    M = 1 << K
+    if periodic:
+        return np.mod(t, M)
+    return np.clip(t, 0, M - 1)
+
+
+def thresholds(nbins, rmin, rmax, box, K):
+    sc = math.ldexp(1.0, K) / box
+    delta = (rmax - rmin) / nbins
+    T = []
+    for k in range(nbins + 1):
+        e = rmax if k == nbins else rmin + k * delta
+        v = e * sc
+        T.append(int(math.ceil(v * v)))
+    return np.array(T, dtype=object)
+
+
+def pair_table(x, y, z, box, periodic, nbins, rmin, rmax, primaries=None):
+    """Lists of (p, j, bin, unit vector) for every in-range pair, by the stated definition."""
+    n = len(x)
+    K = lattice_bits(box, rmax, periodic)
+    M = 1 << K
+    q = np.stack([snap(x, box, K, periodic), snap(y, box, K, periodic), snap(z, box, K, periodic)], 1)
+    T = thresholds(nbins, rmin, rmax, box, K)
+    Tlo, Thi = int(T[0]), int(T[-1])
+    out = []
+    for p in (range(n) if primaries is None else primaries):
+        d = q - q[p]
+        if periodic:
+            d = np.where(d >= M // 2, d - M, d)
+            d = np.where(d < -(M // 2), d + M, d)
+        for j in range(n):
+            if j == p:
+                continue
+            dx, dy, dz = (int(v) for v in d[j])
+            R2 = dx * dx + dy * dy + dz * dz  # Python ints: exact
+            if R2 == 0 or R2 < Tlo or R2 >= Thi:
+                continue
+            b = max(k for k in range(nbins) if int(T[k]) <= R2)
+            r = math.sqrt(R2)
+            out.append((p, j, b, (dx / r, dy / r, dz / r)))
+    return out
+
+
+def zeta_triangles(x, y, z, w, box, periodic, nbins, rmin, rmax, lmax, primaries=None):
+    n = len(x)
+    w = np.ones(n) if w is None else np.asarray(w, dtype=np.float64)
+    pairs = pair_table(x, y, z, box, periodic, nbins, rmin, rmax, primaries)
+    zeta = np.zeros((lmax + 1, nbins, nbins))
+    by_p = {}
+    for p, j, b, u in pairs:
+        by_p.setdefault(p, []).append((j, b, u))
+    for p, lst in by_p.items():
+        js = np.array([t[0] for t in lst])
+        bs = np.array([t[1] for t in lst])
+        U = np.array([t[2] for t in lst])
+        cosg = np.clip(U @ U.T, -1.0, 1.0)
+        ww = np.outer(w[js], w[js])
+        for l in range(lmax + 1):
+            Pl = eval_legendre(l, cosg) * ww
+            # accumulate sum over (j,k) into (b_j, b_k)
+            acc = np.zeros((nbins, nbins))
+            np.add.at(acc, (bs[:, None].repeat(len(js), 1), bs[None, :].repeat(len(js), 0)), Pl)
+            zeta[l] += w[p] * (2 * l + 1) / (4 * math.pi) * acc
+    return zeta
+
+
+def pair_counts(x, y, z, box, periodic, nbins, rmin, rmax, primaries=None):
+    n = len(x)
+    prim = list(range(n)) if primaries is None else list(primaries)
+    idx = {p: i for i, p in enumerate(prim)}
+    counts = np.zeros((len(prim), nbins), dtype=np.int64)
+    for p, j, b, u in pair_table(x, y, z, box, periodic, nbins, rmin, rmax, prim):
+        counts[idx[p], b] += 1
+    return counts

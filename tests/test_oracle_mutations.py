@@ -1,0 +1,125 @@
+"""The pins are strong enough: each planted mistake in a copy of the oracle fails one of them.
+
+Every mutant is a textual edit of ``oracle/tpcf_oracle.c`` compiled into a temporary library
+on the CPU; the committed oracle is never modified.
+"""
+import ctypes
+import math
+import os
+import shutil
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+from scipy.special import eval_legendre, sph_harm_y
+
+import oracle
+from tests import brute
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "tpcf_oracle.c")
+
+MUTANTS = {
+    "normalisation 2l-1": ("(2.0L * l + 1.0L)", "(2.0L * l - 1.0L)"),
+    "no Condon-Shortley phase": ("pmm *= -(2.0 * i - 1.0) * sx", "pmm *= (2.0 * i - 1.0) * sx"),
+    "recurrence coefficient": ("(l + m - 1.0) * P[l - 2][m]", "(l + m + 1.0) * P[l - 2][m]"),
+    "primary weight dropped": ("zacc[((size_t)l * nb + b1) * nb + b2] += wp * s;",
+                               "zacc[((size_t)l * nb + b1) * nb + b2] += s;"),
+    "lower edge exclusive": ("R2 < P->T[0] || R2 >= P->T[P->nbins]",
+                             "R2 <= P->T[0] || R2 >= P->T[P->nbins]"),
+    "inner edge inclusive": ("while (b + 1 < P->nbins && R2 >= P->T[b + 1]) b++;",
+                             "while (b + 1 < P->nbins && R2 > P->T[b + 1]) b++;"),
+    "no minimum image": ("if (d >= M / 2) d -= M;", "if (d >= M) d -= M;"),
+    "missing conjugate in contraction": ("* conj(alm[(size_t)b2 * nc + c]));",
+                                         "* alm[(size_t)b2 * nc + c]);"),
+    "m = l term dropped": ("for (int m = -l; m <= l; m++) {", "for (int m = -l; m < l; m++) {"),
+    "negative m phase": ("((m & 1) ? -1.0 : 1.0) * conj(y)", "conj(y)"),
+    "secondary weight dropped": ("a[c] += P->w[j] * conj(Y[c]);", "a[c] += conj(Y[c]);"),
+}
+
+
+def _pins():
+    """Cheap versions of the pins; returns the names of the ones that fail."""
+    failed = []
+    # worked triangle
+    O = np.array([125.0, 125.0, 125.0])
+    Pt = np.array([O, O + [10.0, 0, 0], O + [0, 10.0, 0]])
+    r = oracle.zeta(Pt[:, 0], Pt[:, 1], Pt[:, 2], None, 250.0, True, 10, 5.0, 50.0, 4)
+    for l in range(5):
+        c = (2 * l + 1) / (4 * math.pi)
+        if (abs(r.zeta[l, 1, 1] - c * (4 + 2 * eval_legendre(l, 0.0))) > 1e-9
+                or abs(r.zeta[l, 1, 2] - 2 * c * eval_legendre(l, 2**-0.5)) > 1e-9):
+            failed.append("worked triangle")
+            break
+    # brute-force triangles, weighted, both geometries
+    rng = np.random.default_rng(3)
+    P = rng.random((70, 3)) * 50.0
+    w = rng.normal(0.5, 1.0, 70)
+    for periodic in (True, False):
+        z = oracle.zeta(P[:, 0], P[:, 1], P[:, 2], w, 50.0, periodic, 4, 2.0, 20.0, 5).zeta
+        ref = brute.zeta_triangles(P[:, 0], P[:, 1], P[:, 2], w, 50.0, periodic, 4, 2.0, 20.0, 5)
+        if np.max(np.abs(z - ref)) > 1e-12 * np.max(np.abs(ref)):
+            failed.append("brute-force triangles")
+            break
+    # Y_lm against scipy
+    v = rng.normal(size=(50, 3))
+    v /= np.linalg.norm(v, axis=1)[:, None]
+    Y = oracle.ylm(v[:, 0], v[:, 1], v[:, 2], 6)
+    th, ph = np.arccos(v[:, 2]), np.arctan2(v[:, 1], v[:, 0])
+    ok = all(np.allclose(Y[:, l * l + l + m], sph_harm_y(l, m, th, ph), atol=1e-13, rtol=0)
+             for l in range(7) for m in range(-l, l + 1))
+    if not ok:
+        failed.append("Y_lm vs scipy")
+    # exact bin edges
+    box, K = 256.0, 27
+    s = box / 2**K
+    x0 = 100.0 + 0.5 * s
+    xs = np.array([x0, x0 + 16.0, x0 + 16.0 - s, x0 + 64.0, x0 + 8.0])
+    zz = np.full(5, 50.0 + 0.5 * s)
+    r = oracle.zeta(xs, zz, zz, None, box, True, 7, 8.0, 64.0, 0, 0, 1, want_counts=True)
+    if list(r.counts[0]) != [2, 1, 0, 0, 0, 0, 0]:
+        failed.append("bin edges")
+    # translation across the periodic boundary
+    K = brute.lattice_bits(60.0, 20.0, True)
+    M = 2**K
+    q = rng.integers(0, M, size=(60, 3))
+    X = (q + 0.5) * (60.0 / M)
+    z0 = oracle.zeta(X[:, 0], X[:, 1], X[:, 2], w[:60], 60.0, True, 4, 2.0, 20.0, 3).zeta
+    Xt = ((q + M // 2 + 12345) % M + 0.5) * (60.0 / M)
+    z1 = oracle.zeta(Xt[:, 0], Xt[:, 1], Xt[:, 2], w[:60], 60.0, True, 4, 2.0, 20.0, 3).zeta
+    if np.max(np.abs(z1 - z0)) > 1e-12 * np.max(np.abs(z0)):
+        failed.append("translation")
+    return failed
+
+
+@pytest.fixture
+def mutant_loader(monkeypatch):
+    tmp = tempfile.mkdtemp(prefix="oracle_mut_")
+
+    def load(old, new):
+        src = open(SRC).read()
+        assert src.count(old) == 1, old
+        path_c = os.path.join(tmp, "mut.c")
+        open(path_c, "w").write(src.replace(old, new))
+        so = os.path.join(tmp, "mut%d.so" % len(os.listdir(tmp)))
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-o", so,
+                               path_c, "-lm"])
+        monkeypatch.setattr(oracle, "_LIB", so)
+        monkeypatch.setattr(oracle, "build", lambda force=False: so)
+        monkeypatch.setattr(oracle, "_lib", None)
+
+    yield load
+    oracle._lib = None
+    shutil.rmtree(tmp, ignore_errors=True)
+
+
+def test_unmutated_oracle_passes_cheap_pins():
+    assert _pins() == []
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, mutant_loader):
+    old, new = MUTANTS[name]
+    mutant_loader(old, new)
+    failed = _pins()
+    assert failed, f"mutant '{name}' passed every pin"

@@ -1,0 +1,326 @@
+"""Pins for the FP64 oracle: each test checks it against something other than itself.
+
+* worked triangle: hand-derived closed form (golden fixture);
+* brute-force triangle sum in the Legendre form (no Y_lm, independent numpy route);
+* l = 0 reduces to products of pair counts;
+* Y_lm against scipy's spherical harmonics and its special values;
+* the 48 cube symmetries and lattice translations (exact on the lattice);
+* Poisson expectation on uniform boxes;
+* positive semi-definiteness, bin merging, weight homogeneity, primary-range additivity;
+* integer pair counts against a numpy pair loop, including pairs exactly on bin edges.
+"""
+import itertools
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.special import eval_legendre, sph_harm_y
+
+import catalogs
+import oracle
+from tests import brute
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _rel(a, b):
+    return np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)
+
+
+# ---------------------------------------------------------------- worked example
+
+def _worked_points():
+    O = np.array([125.0, 125.0, 125.0])
+    P = np.array([O, O + [10.0, 0, 0], O + [0, 10.0, 0]])
+    return P[:, 0], P[:, 1], P[:, 2]
+
+
+def test_worked_triangle_fixture_matches_closed_form():
+    rows = np.loadtxt(os.path.join(HERE, "golden", "worked_triangle.txt"))
+    for l, z11, z22, z12 in rows:
+        l = int(l)
+        c = (2 * l + 1) / (4 * math.pi)
+        assert z11 == pytest.approx(c * (4 + 2 * eval_legendre(l, 0.0)), abs=1e-9)
+        assert z22 == pytest.approx(2 * c, abs=1e-9)
+        assert z12 == pytest.approx(2 * c * eval_legendre(l, 1 / math.sqrt(2)), abs=1e-9)
+
+
+def test_worked_triangle():
+    x, y, z = _worked_points()
+    r = oracle.zeta(x, y, z, None, 250.0, True, 10, 5.0, 50.0, 4, want_counts=True)
+    rows = np.loadtxt(os.path.join(HERE, "golden", "worked_triangle.txt"))
+    expect = np.zeros((5, 10, 10))
+    for l, z11, z22, z12 in rows:
+        l = int(l)
+        expect[l, 1, 1], expect[l, 2, 2] = z11, z22
+        expect[l, 1, 2] = expect[l, 2, 1] = z12
+    np.testing.assert_allclose(r.zeta, expect, atol=5e-10)
+    cnt = np.zeros((3, 10), dtype=np.int64)
+    cnt[0, 1] = 2
+    cnt[1, 1] = cnt[1, 2] = cnt[2, 1] = cnt[2, 2] = 1
+    np.testing.assert_array_equal(r.counts, cnt)
+    assert r.npairs == 6
+
+
+# ---------------------------------------------------------------- brute-force triangles
+
+@pytest.mark.parametrize("periodic", [True, False])
+def test_bruteforce_triangles(periodic):
+    rng = np.random.default_rng(7)
+    n, box = 160, 100.0
+    P = rng.random((n, 3)) * box
+    w = rng.normal(0.3, 1.0, n)  # includes negative weights
+    nb, rmin, rmax, lmax = 6, 4.0, 40.0, 6
+    r = oracle.zeta(P[:, 0], P[:, 1], P[:, 2], w, box, periodic, nb, rmin, rmax, lmax)
+    ref = brute.zeta_triangles(P[:, 0], P[:, 1], P[:, 2], w, box, periodic, nb, rmin, rmax, lmax)
+    for l in range(lmax + 1):
+        assert _rel(r.zeta[l], ref[l]) < 1e-12, l
+
+
+def test_bruteforce_triangles_subset_at_larger_n():
+    c = catalogs.uniform(1500, 120.0, 3)
+    w = catalogs.gaussian_weights(c.n, 4)
+    prim = [5, 77, 1020]
+    nb, rmin, rmax, lmax = 5, 3.0, 25.0, 8
+    ref = brute.zeta_triangles(c.x, c.y, c.z, w, c.box, True, nb, rmin, rmax, lmax, primaries=prim)
+    tot = np.zeros_like(ref)
+    for p in prim:
+        tot += oracle.zeta(c.x, c.y, c.z, w, c.box, True, nb, rmin, rmax, lmax, p, p + 1).zeta
+    for l in range(lmax + 1):
+        assert _rel(tot[l], ref[l]) < 1e-12
+
+
+# ---------------------------------------------------------------- l = 0 and pair counts
+
+def test_l0_is_product_of_pair_counts():
+    c = catalogs.uniform(400, 80.0, 11)
+    w = catalogs.gaussian_weights(c.n, 12, 1.0, 0.5)
+    nb, rmin, rmax = 8, 2.0, 30.0
+    r = oracle.zeta(c.x, c.y, c.z, w, c.box, True, nb, rmin, rmax, 2)
+    Np = np.zeros((c.n, nb))
+    for p, j, b, u in brute.pair_table(c.x, c.y, c.z, c.box, True, nb, rmin, rmax):
+        Np[p, b] += w[j]
+    ref = np.einsum("p,pa,pb->ab", w, Np, Np) / (4 * math.pi)
+    assert _rel(r.zeta[0], ref) < 1e-12
+
+
+@pytest.mark.parametrize("periodic", [True, False])
+def test_pair_counts_exact(periodic):
+    c = catalogs.uniform(300, 60.0, 21)
+    nb, rmin, rmax = 7, 1.5, 22.0
+    r = oracle.zeta(c.x, c.y, c.z, None, c.box, periodic, nb, rmin, rmax, 1, want_counts=True)
+    ref = brute.pair_counts(c.x, c.y, c.z, c.box, periodic, nb, rmin, rmax)
+    np.testing.assert_array_equal(r.counts, ref)
+    assert r.npairs == int(ref.sum())
+
+
+def test_bin_edges_are_half_open():
+    # box 256 and bins [8, 64) of width 8: with K = 27 every edge is a whole number of lattice
+    # steps, so separations can sit exactly on an edge. A separation of exactly 16 belongs to
+    # bin 1 ([16, 24)); one lattice step less belongs to bin 0; exactly 8 is bin 0; exactly 64
+    # is out of range.
+    box, nb, rmin, rmax = 256.0, 7, 8.0, 64.0
+    K = oracle.lattice_bits(box, rmax, True)
+    assert K == 27
+    s = box / 2**K
+    x0 = 100.0 + 0.5 * s  # mid-cell so snapping is unambiguous
+    xs = np.array([x0, x0 + 16.0, x0 + 16.0 - s, x0 + 64.0, x0 + 8.0])
+    zeros = np.full(5, 50.0 + 0.5 * s)
+    r = oracle.zeta(xs, zeros, zeros, None, box, True, nb, rmin, rmax, 0, 0, 1, want_counts=True)
+    np.testing.assert_array_equal(r.counts[0], [2, 1, 0, 0, 0, 0, 0])
+    T = oracle.thresholds(nb, rmin, rmax, box, K)
+    assert int(T[1]) == (16 * 2**K // 256) ** 2
+    assert int(T[0]) == (8 * 2**K // 256) ** 2 and int(T[7]) == (64 * 2**K // 256) ** 2
+    assert [int(t) for t in T] == [int(v) for v in brute.thresholds(nb, rmin, rmax, box, K)]
+
+
+# ---------------------------------------------------------------- spherical harmonics
+
+def test_ylm_against_scipy():
+    rng = np.random.default_rng(5)
+    v = rng.normal(size=(4000, 3))
+    v /= np.linalg.norm(v, axis=1)[:, None]
+    lmax = 10
+    Y = oracle.ylm(v[:, 0], v[:, 1], v[:, 2], lmax)
+    theta = np.arccos(np.clip(v[:, 2], -1, 1))
+    phi = np.arctan2(v[:, 1], v[:, 0])
+    for l in range(lmax + 1):
+        for m in range(-l, l + 1):
+            ref = sph_harm_y(l, m, theta, phi)
+            np.testing.assert_allclose(Y[:, l * l + l + m], ref, atol=1e-13, rtol=0)
+
+
+def test_ylm_special_values():
+    lmax = 12
+    Y = oracle.ylm(np.array([0.0, 0.0]), np.array([0.0, 0.0]), np.array([1.0, -1.0]), lmax)
+    assert Y[0, 0] == pytest.approx(1 / math.sqrt(4 * math.pi), abs=1e-15)
+    for l in range(lmax + 1):
+        for m in range(-l, l + 1):
+            c = l * l + l + m
+            if m == 0:
+                val = math.sqrt((2 * l + 1) / (4 * math.pi))
+                assert Y[0, c] == pytest.approx(val, abs=1e-13)
+                assert Y[1, c] == pytest.approx(val * (-1) ** l, abs=1e-13)
+            else:
+                assert abs(Y[0, c]) < 1e-13 and abs(Y[1, c]) < 1e-13
+    # Y_11 on the x axis: -sqrt(3/(8 pi)) (Condon-Shortley phase)
+    Y = oracle.ylm(np.array([1.0]), np.array([0.0]), np.array([0.0]), 1)
+    assert Y[0, 3].real == pytest.approx(-math.sqrt(3 / (8 * math.pi)), abs=1e-15)
+
+
+# ---------------------------------------------------------------- invariances
+
+def _lattice_catalog(n, box, rmax, seed, periodic=True):
+    """Points exactly at lattice-cell centres, so symmetries act exactly on the lattice."""
+    K = oracle.lattice_bits(box, rmax, periodic)
+    rng = np.random.default_rng(seed)
+    q = rng.integers(0, 2**K, size=(n, 3))
+    return q, K
+
+
+def _from_lattice(q, box, K):
+    return (q.astype(np.float64) + 0.5) * (box / 2**K)
+
+
+def test_cube_symmetries_periodic():
+    box, nb, rmin, rmax, lmax = 60.0, 5, 2.0, 20.0, 6
+    q, K = _lattice_catalog(250, box, rmax, 31)
+    M = 2**K
+    w = catalogs.gaussian_weights(250, 32)
+    X = _from_lattice(q, box, K)
+    base = oracle.zeta(X[:, 0], X[:, 1], X[:, 2], w, box, True, nb, rmin, rmax, lmax).zeta
+    for perm in itertools.permutations(range(3)):
+        for signs in itertools.product([1, -1], repeat=3):
+            qq = q[:, perm].copy()
+            for a in range(3):
+                if signs[a] < 0:
+                    qq[:, a] = (M - 1 - qq[:, a]) % M  # reflection of cell centres
+            Xs = _from_lattice(qq, box, K)
+            z = oracle.zeta(Xs[:, 0], Xs[:, 1], Xs[:, 2], w, box, True, nb, rmin, rmax, lmax).zeta
+            assert _rel(z, base) < 1e-12, (perm, signs)
+
+
+def test_translation_and_permutation_invariance():
+    box, nb, rmin, rmax, lmax = 60.0, 5, 2.0, 20.0, 5
+    q, K = _lattice_catalog(250, box, rmax, 41)
+    M = 2**K
+    w = catalogs.gaussian_weights(250, 42)
+    X = _from_lattice(q, box, K)
+    base = oracle.zeta(X[:, 0], X[:, 1], X[:, 2], w, box, True, nb, rmin, rmax, lmax).zeta
+    rng = np.random.default_rng(43)
+    for _ in range(3):
+        t = rng.integers(0, M, size=3)
+        Xt = _from_lattice((q + t) % M, box, K)
+        z = oracle.zeta(Xt[:, 0], Xt[:, 1], Xt[:, 2], w, box, True, nb, rmin, rmax, lmax).zeta
+        assert _rel(z, base) < 1e-12
+    # positions outside [0, L) wrap onto the same lattice
+    Xw = X + box * np.array([1.0, -2.0, 3.0])
+    z = oracle.zeta(Xw[:, 0], Xw[:, 1], Xw[:, 2], w, box, True, nb, rmin, rmax, lmax).zeta
+    assert _rel(z, base) < 1e-12
+    perm = rng.permutation(250)
+    z = oracle.zeta(X[perm, 0], X[perm, 1], X[perm, 2], w[perm], box, True, nb, rmin, rmax,
+                    lmax).zeta
+    assert _rel(z, base) < 1e-12
+
+
+def test_rotation_nonperiodic_with_tolerance():
+    # Away from the walls a non-periodic catalogue's zeta is rotation invariant up to pairs
+    # that move across a bin edge under the rotation (none for this configuration).
+    rng = np.random.default_rng(51)
+    n, box, nb, rmin, rmax, lmax = 200, 100.0, 4, 3.0, 15.0, 6
+    P = 50.0 + (rng.random((n, 3)) - 0.5) * 40.0
+    w = rng.normal(1.0, 0.3, n)
+    A = rng.normal(size=(3, 3))
+    Qm, _ = np.linalg.qr(A)
+    Pr = (P - 50.0) @ Qm.T + 50.0
+    z0 = oracle.zeta(P[:, 0], P[:, 1], P[:, 2], w, box, False, nb, rmin, rmax, lmax, want_counts=True)
+    z1 = oracle.zeta(Pr[:, 0], Pr[:, 1], Pr[:, 2], w, box, False, nb, rmin, rmax, lmax, want_counts=True)
+    np.testing.assert_array_equal(z0.counts, z1.counts)
+    for l in range(lmax + 1):
+        assert _rel(z1.zeta[l], z0.zeta[l]) < 1e-6
+
+
+# ---------------------------------------------------------------- Poisson expectation
+
+def _shell_fraction(box, rmin, rmax, nb):
+    e = rmin + (rmax - rmin) / nb * np.arange(nb + 1)
+    e[-1] = rmax
+    return 4 * math.pi / 3 * (e[1:] ** 3 - e[:-1] ** 3) / box**3
+
+
+@pytest.mark.slow
+def test_poisson_expectation_uniform_box():
+    N, box, nb, rmin, rmax, lmax = 10000, 250.0, 10, 5.0, 50.0, 4
+    samples = []
+    for seed in range(16):
+        c = catalogs.uniform(N, box, seed)
+        samples.append(oracle.zeta_catalog(c, nb, rmin, rmax, lmax).zeta)
+    S = np.array(samples)
+    mean = S.mean(0)
+    se = S.std(0, ddof=1) / math.sqrt(len(samples))
+    q = _shell_fraction(box, rmin, rmax, nb)
+    E = np.zeros((lmax + 1, nb, nb))
+    for l in range(lmax + 1):
+        cl = (2 * l + 1) / (4 * math.pi)
+        E[l] = cl * N * np.diag((N - 1) * q)
+        if l == 0:
+            E[l] += cl * N * (N - 1) * (N - 2) * np.outer(q, q)
+    # the values quoted for this configuration
+    assert E[0, 0, 0] == pytest.approx(4628.89, abs=0.01)
+    assert E[0, 9, 9] == pytest.approx(5490719.27, abs=0.01)
+    assert E[0, 0, 9] == pytest.approx(128982.96, abs=0.01)
+    z = (mean - E) / se
+    tested = np.zeros_like(z, dtype=bool)
+    tested[0] = True
+    for l in range(1, lmax + 1):
+        tested[l] = np.eye(nb, dtype=bool)
+    assert np.max(np.abs(z[tested])) < 6.0
+    assert np.mean(z[tested] ** 2) < 2.0
+    # relative agreement of the large entries
+    assert np.max(np.abs(mean[0] - E[0]) / E[0]) < 0.01
+
+
+# ---------------------------------------------------------------- structure
+
+def test_psd_for_nonnegative_weights():
+    c = catalogs.uniform(600, 70.0, 61)
+    w = np.abs(catalogs.gaussian_weights(c.n, 62, 1.0, 0.4))
+    z = oracle.zeta(c.x, c.y, c.z, w, c.box, True, 8, 2.0, 25.0, 8).zeta
+    for l in range(z.shape[0]):
+        np.testing.assert_allclose(z[l], z[l].T, rtol=0, atol=1e-12 * np.abs(z[l]).max())
+        ev = np.linalg.eigvalsh(z[l])
+        assert ev.min() >= -1e-12 * np.abs(ev).max()
+
+
+def test_bin_merging():
+    c = catalogs.uniform(500, 70.0, 71)
+    w = catalogs.gaussian_weights(c.n, 72)
+    z20 = oracle.zeta(c.x, c.y, c.z, w, c.box, True, 20, 2.0, 25.0, 6).zeta
+    z1 = oracle.zeta(c.x, c.y, c.z, w, c.box, True, 1, 2.0, 25.0, 6).zeta
+    np.testing.assert_allclose(z20.sum(axis=(1, 2)), z1[:, 0, 0], rtol=1e-12)
+
+
+def test_weight_homogeneity_and_range_additivity():
+    c = catalogs.uniform(400, 70.0, 81)
+    w = catalogs.gaussian_weights(c.n, 82)
+    args = (c.box, True, 6, 2.0, 25.0, 5)
+    z = oracle.zeta(c.x, c.y, c.z, w, *args).zeta
+    for alpha in (-1.0, 2.5):
+        za = oracle.zeta(c.x, c.y, c.z, alpha * w, *args).zeta
+        np.testing.assert_allclose(za, alpha**3 * z, rtol=1e-12, atol=1e-12 * np.abs(z).max())
+    k = 137
+    zlo = oracle.zeta(c.x, c.y, c.z, w, *args, p_begin=0, p_end=k).zeta
+    zhi = oracle.zeta(c.x, c.y, c.z, w, *args, p_begin=k, p_end=c.n).zeta
+    np.testing.assert_allclose(zlo + zhi, z, rtol=1e-12, atol=1e-13 * np.abs(z).max())
+
+
+def test_degenerate_sizes():
+    z = oracle.zeta(np.zeros(0), np.zeros(0), np.zeros(0), None, 10.0, True, 3, 1.0, 4.0, 2)
+    assert z.zeta.shape == (3, 3, 3) and not z.zeta.any() and z.npairs == 0
+    z = oracle.zeta(np.array([1.0]), np.array([1.0]), np.array([1.0]), None, 10.0, True, 3, 1.0, 4.0, 2)
+    assert not z.zeta.any() and z.npairs == 0
+    # two coincident points: no direction, no pair even with r_min = 0
+    z = oracle.zeta(np.array([1.0, 1.0]), np.array([1.0, 1.0]), np.array([1.0, 1.0]), None, 10.0,
+                    True, 3, 0.0, 4.0, 2)
+    assert z.npairs == 0
