@@ -1,0 +1,187 @@
+/*
+ * tpcf.h -- C ABI of the MI355X (gfx950) three-point correlation function multipole library.
+ *
+ * The library computes, for one or many point catalogues, the multipoles of the three-point
+ * correlation function in the spherical-harmonic form: for every primary p and every secondary
+ * j within [r_min, r_max) of it (found through a cubic cell grid),
+ *
+ *     a_lm(p, b)     = sum_{j in bin b} w_j conj(Y_lm(unit(x_j - x_p))),       0 <= m <= l <= l_max
+ *     zeta_l(b1, b2) = sum_p w_p sum_{m=-l}^{l} a_lm(p, b1) conj(a_lm(p, b2)).
+ *
+ * This is the harmonic decomposition of the triangle angle that the paper's Implementation
+ * section builds its fast estimator on (per pivot: find all neighbours in range, fill the
+ * multipole bins), written for 3D positions with spherical harmonics as in the works the paper
+ * cites (Szapudi 2004; Slepian & Eisenstein 2015).
+ *
+ * Conventions fixed by the library (the paper gives no formula):
+ *   - Positions are snapped to a lattice of spacing L / 2^K, K = 25 + floor(log2(L / r_max)),
+ *     capped at 32 (periodic) / 31 (non-periodic). Separations are exact lattice integers and
+ *     bin membership is decided exactly against integer thresholds, so pair counts are exact.
+ *   - Bins are linear and half-open: [r_min + k D, r_min + (k+1) D), D = (r_max - r_min)/nbins.
+ *   - Periodic boxes use the minimum image and need r_max < L/2.
+ *   - Y_lm is orthonormal with the Condon-Shortley phase; the j = k (same secondary on both
+ *     legs) term is included; pairs at zero separation are skipped.
+ *   - zeta is written as double [(lmax+1)][nbins][nbins], row-major.
+ *
+ * Every function returns a status code (TPCF_OK = 0). No C++ exception crosses this boundary.
+ * On an error the outputs are left untouched and tpcf_last_error() describes the failure.
+ * A context is not thread-safe; use one context per host thread and HIP stream.
+ *
+ * Memory spaces: TPCF_MEM_HOST pointers are ordinary host memory; the call returns after the
+ * data has been consumed (inputs) or written (outputs). TPCF_MEM_DEVICE pointers are device
+ * memory on the context's device; they are read/written in order on the context's stream.
+ */
+#ifndef TPCF_H
+#define TPCF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tpcf_ctx tpcf_ctx;
+
+enum {
+    TPCF_OK = 0,
+    TPCF_E_INVALID_ARG = 1, /* a value out of its documented range */
+    TPCF_E_STATE = 2,       /* a call made before the calls it needs (e.g. compute before set_*) */
+    TPCF_E_OUT_OF_MEMORY = 3,
+    TPCF_E_DEVICE = 4,      /* a HIP runtime error (message in tpcf_last_error) */
+    TPCF_E_UNSUPPORTED = 5
+};
+
+enum { TPCF_PREC_FP64 = 0, TPCF_PREC_MIXED = 1 };
+enum { TPCF_MEM_HOST = 0, TPCF_MEM_DEVICE = 1 };
+
+#define TPCF_MAX_NBINS 32
+#define TPCF_MAX_LMAX 10
+
+/* Run statistics of the last compute call. */
+typedef struct tpcf_stats {
+    int64_t n_pairs;        /* in-range ordered (primary, secondary) pairs */
+    int64_t n_candidates;   /* secondaries tested (cell-grid stencil) */
+    int64_t n_primaries;
+    double ms_grid;         /* lattice snap + cell-list build (set_catalog / batch) */
+    double ms_sweep;        /* pair sweep + contraction kernel */
+    double ms_total;        /* whole compute call, device time */
+    int cells_per_axis;     /* grid of the first catalogue */
+    int waves;              /* persistent waves launched */
+    int precision;
+    int lmax;
+    int nbins;
+} tpcf_stats;
+
+/* Library version string, e.g. "tpcf 1.0.0 gfx950". Never NULL. */
+const char* tpcf_version(void);
+
+/*
+ * Creates a context on HIP device `device` using stream `hip_stream` (a hipStream_t; NULL means
+ * the default stream). The device is first touched by the first call that needs it, so a
+ * context can be created and configured on a machine without a GPU.
+ * Errors: TPCF_E_INVALID_ARG if out is NULL or device < 0; TPCF_E_OUT_OF_MEMORY.
+ */
+int tpcf_create(tpcf_ctx** out, int device, void* hip_stream);
+
+/* Frees the context and every device buffer it owns. NULL is accepted. */
+void tpcf_destroy(tpcf_ctx* ctx);
+
+/*
+ * Radial bins and multipole order. nbins in [1, TPCF_MAX_NBINS], 0 <= rmin < rmax (finite),
+ * lmax in [0, TPCF_MAX_LMAX]. Errors: TPCF_E_INVALID_ARG.
+ */
+int tpcf_set_bins(tpcf_ctx* ctx, int nbins, double rmin, double rmax, int lmax);
+
+/*
+ * TPCF_PREC_FP64: FP64 pair sweep, FP64 shells and FP64 MFMA contraction.
+ * TPCF_PREC_MIXED: FP32 pair sweep with register partials and Kahan-compensated shell sums,
+ * contraction in split-BF16 MFMA with FP32 accumulation per tile, FP64 global reduction.
+ * Errors: TPCF_E_INVALID_ARG.
+ */
+int tpcf_set_precision(tpcf_ctx* ctx, int precision);
+
+/*
+ * Optional tuning: target mean points per grid cell (default 30; the grid side follows from it
+ * and the catalogue density), persistent waves per compute unit (default 8), and scratch blocks
+ * of 64 secondaries per wave (default 1024). A value of 0 keeps the default.
+ * Errors: TPCF_E_INVALID_ARG for negative values or scratch_blocks not a multiple of 64.
+ */
+int tpcf_set_tuning(tpcf_ctx* ctx, double points_per_cell, int waves_per_cu, int scratch_blocks);
+
+/*
+ * One catalogue of n points: positions x, y, z and weights w (w = NULL means unit weights), all
+ * FP64 arrays of length n in memory space `memspace`. box is the cube side; periodic != 0 wraps
+ * positions into [0, box) and uses minimum images; otherwise every coordinate must lie in
+ * [0, box). The positions are copied into library-owned, cell-sorted device buffers (lattice
+ * snap + counting-sort cell grid); the caller may free or reuse its arrays when the call
+ * returns. The call synchronises the context's stream.
+ * Errors: TPCF_E_INVALID_ARG (n < 0, n >= 2^31, box not finite and > 0, a non-finite position
+ * or weight, a non-periodic point outside [0, box), NULL arrays with n > 0, periodic with
+ * rmax >= box/2 when bins are already set), TPCF_E_OUT_OF_MEMORY, TPCF_E_DEVICE.
+ */
+int tpcf_set_catalog(tpcf_ctx* ctx, int64_t n, const double* x, const double* y, const double* z,
+                     const double* w, double box, int periodic, int memspace);
+
+/*
+ * zeta for the catalogue set by tpcf_set_catalog: every point is a primary and a secondary.
+ * zeta has (lmax+1)*nbins*nbins doubles in memory space `memspace`.
+ * Errors: TPCF_E_STATE (bins or catalogue missing), TPCF_E_INVALID_ARG (periodic with
+ * rmax >= box/2, NULL zeta), TPCF_E_OUT_OF_MEMORY, TPCF_E_DEVICE.
+ */
+int tpcf_compute_zeta(tpcf_ctx* ctx, double* zeta, int memspace);
+
+/*
+ * As tpcf_compute_zeta, but only the points with input index in [p_begin, p_end) are primaries
+ * (every point stays a secondary). zeta over disjoint ranges adds up to the full zeta.
+ * Errors: as tpcf_compute_zeta, plus TPCF_E_INVALID_ARG for a range outside [0, n].
+ */
+int tpcf_compute_zeta_range(tpcf_ctx* ctx, int64_t p_begin, int64_t p_end, double* zeta,
+                            int memspace);
+
+/*
+ * ncat independent catalogues in one persistent launch. Catalogue c holds the points
+ * [offsets[c], offsets[c+1]) of the concatenated FP64 arrays x, y, z, w (w may be NULL); its box
+ * side is box_side[c] and periodic flag periodic[c]. offsets, box_side and periodic are host
+ * arrays; x, y, z, w live in `memspace`; zeta receives [ncat][(lmax+1)][nbins][nbins] doubles in
+ * `memspace`. Catalogues never interact. The batch replaces the catalogue set by
+ * tpcf_set_catalog. The launch sequence is captured in a HIP graph on first use for a given
+ * batch shape and replayed afterwards.
+ * Errors: TPCF_E_INVALID_ARG (ncat < 1, offsets not non-decreasing from 0, total points >= 2^31,
+ * any per-catalogue error of tpcf_set_catalog), TPCF_E_STATE, TPCF_E_OUT_OF_MEMORY,
+ * TPCF_E_DEVICE.
+ */
+int tpcf_compute_batch(tpcf_ctx* ctx, int ncat, const int64_t* offsets, const double* x,
+                       const double* y, const double* z, const double* w,
+                       const double* box_side, const int* periodic, double* zeta, int memspace);
+
+/*
+ * Exact unit-weight pair counts of the last compute call: counts[i][b] (host, int64,
+ * n x nbins, input order) is the number of secondaries of primary i in bin b (0 for points that
+ * were not primaries). Enable with tpcf_set_debug(ctx, 1) before the compute call.
+ * Errors: TPCF_E_STATE if no compute call ran with debug output enabled.
+ */
+int tpcf_debug_pair_counts(tpcf_ctx* ctx, int64_t* counts);
+
+/*
+ * Debug output of the normalised a_lm of the last compute call, host FP64,
+ * [n][nbins][(lmax+1)^2] in input order, real components per l: Re a_l0, then Re a_lm, Im a_lm
+ * for m = 1..l (index l*l, then l*l + 2m - 1 and l*l + 2m). Enabled by tpcf_set_debug.
+ * Errors: TPCF_E_STATE.
+ */
+int tpcf_debug_alm(tpcf_ctx* ctx, double* alm);
+
+/* 0 (default) or 1: keep per-primary pair counts and a_lm of the next compute calls. */
+int tpcf_set_debug(tpcf_ctx* ctx, int enable);
+
+/* Statistics of the last compute call. Errors: TPCF_E_INVALID_ARG for NULL pointers. */
+int tpcf_get_stats(const tpcf_ctx* ctx, tpcf_stats* out);
+
+/* Text of the last error on ctx ("" if none). Valid until the next call on ctx. */
+const char* tpcf_last_error(const tpcf_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TPCF_H */

@@ -1,0 +1,277 @@
+"""Three-point correlation function multipoles on MI355X (gfx950).
+
+Python binding of ``libtpcf.so`` (the C ABI declared in ``include/tpcf.h``). This module only
+marshals arguments: numpy arrays are passed as host memory, torch CUDA/HIP tensors as device
+memory on the tensor's device and the current stream. Every step of the computation runs in the
+library's HIP kernels; when the library is missing, importing this package fails.
+
+    import paper_2604_08855_amd as tpcf
+    z = tpcf.zeta(x, y, z, w, box=1000.0, periodic=True, rmin=10.0, rmax=200.0, nbins=20,
+                  lmax=10, precision="mixed")      # -> float64 [(lmax+1), nbins, nbins]
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+__all__ = ["Context", "zeta", "TpcfError", "library_path", "exported_symbols", "PREC_FP64", "PREC_MIXED"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libtpcf.so")
+
+TPCF_OK = 0
+ERRORS = {1: "INVALID_ARG", 2: "STATE", 3: "OUT_OF_MEMORY", 4: "DEVICE", 5: "UNSUPPORTED"}
+PREC_FP64, PREC_MIXED = 0, 1
+MEM_HOST, MEM_DEVICE = 0, 1
+
+# Every function the header declares.
+EXPORTS = [
+    "tpcf_version", "tpcf_create", "tpcf_destroy", "tpcf_set_bins", "tpcf_set_precision",
+    "tpcf_set_tuning", "tpcf_set_catalog", "tpcf_compute_zeta", "tpcf_compute_zeta_range",
+    "tpcf_compute_batch", "tpcf_debug_pair_counts", "tpcf_debug_alm", "tpcf_set_debug",
+    "tpcf_get_stats", "tpcf_last_error",
+]
+
+
+class TpcfError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"tpcf error {ERRORS.get(code, code)}: {message}")
+        self.code = code
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("n_pairs", ctypes.c_int64),
+        ("n_candidates", ctypes.c_int64),
+        ("n_primaries", ctypes.c_int64),
+        ("ms_grid", ctypes.c_double),
+        ("ms_sweep", ctypes.c_double),
+        ("ms_total", ctypes.c_double),
+        ("cells_per_axis", ctypes.c_int),
+        ("waves", ctypes.c_int),
+        ("precision", ctypes.c_int),
+        ("lmax", ctypes.c_int),
+        ("nbins", ctypes.c_int),
+    ]
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(
+            f"{_LIB_PATH} is not built: run `python -m paper_2604_08855_amd.build` (needs hipcc)")
+    lib = ctypes.CDLL(_LIB_PATH)
+    vp, i, i64, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "tpcf_version": ([], ctypes.c_char_p),
+        "tpcf_create": ([ctypes.POINTER(vp), i, vp], i),
+        "tpcf_destroy": ([vp], None),
+        "tpcf_set_bins": ([vp, i, d, d, i], i),
+        "tpcf_set_precision": ([vp, i], i),
+        "tpcf_set_tuning": ([vp, d, i, i], i),
+        "tpcf_set_catalog": ([vp, i64, vp, vp, vp, vp, d, i, i], i),
+        "tpcf_compute_zeta": ([vp, vp, i], i),
+        "tpcf_compute_zeta_range": ([vp, i64, i64, vp, i], i),
+        "tpcf_compute_batch": ([vp, i, vp, vp, vp, vp, vp, vp, vp, vp, i], i),
+        "tpcf_debug_pair_counts": ([vp, vp], i),
+        "tpcf_debug_alm": ([vp, vp], i),
+        "tpcf_set_debug": ([vp, i], i),
+        "tpcf_get_stats": ([vp, ctypes.POINTER(Stats)], i),
+        "tpcf_last_error": ([vp], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    return lib
+
+
+_lib = _load()
+
+
+def exported_symbols() -> list:
+    """Names of the C-ABI functions present in the loaded library."""
+    return [n for n in EXPORTS if hasattr(_lib, n)]
+
+
+def version() -> str:
+    return _lib.tpcf_version().decode()
+
+
+def _is_torch(a) -> bool:
+    return type(a).__module__.startswith("torch")
+
+
+def _host_f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr_np(a) -> ctypes.c_void_p:
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Context:
+    """One library context (one device, one stream). Not thread-safe."""
+
+    def __init__(self, device: int = 0, stream=None):
+        self._h = ctypes.c_void_p()
+        self.device = device
+        sh = None
+        if stream is None:
+            # Device tensors are produced on torch's current stream: use it when torch is in use.
+            import sys
+            torch = sys.modules.get("torch")
+            if torch is not None and torch.cuda.is_available():
+                stream = torch.cuda.current_stream(device)
+        if stream is not None:
+            sh = getattr(stream, "cuda_stream", stream)
+        self._check(_lib.tpcf_create(ctypes.byref(self._h), int(device),
+                                     ctypes.c_void_p(sh) if sh else None))
+        self.nbins = self.lmax = None
+        self.n = 0
+        self.ncat = 0
+        self._keep = []
+
+    # -- plumbing
+    def _check(self, rc: int):
+        if rc != TPCF_OK:
+            msg = _lib.tpcf_last_error(self._h).decode() if self._h else ""
+            raise TpcfError(rc, msg)
+
+    def close(self):
+        if self._h:
+            _lib.tpcf_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- configuration
+    def set_bins(self, nbins: int, rmin: float, rmax: float, lmax: int):
+        self._check(_lib.tpcf_set_bins(self._h, int(nbins), float(rmin), float(rmax), int(lmax)))
+        self.nbins, self.rmin, self.rmax, self.lmax = int(nbins), float(rmin), float(rmax), int(lmax)
+
+    def set_precision(self, precision):
+        p = {"fp64": PREC_FP64, "mixed": PREC_MIXED}.get(precision, precision)
+        self._check(_lib.tpcf_set_precision(self._h, int(p)))
+
+    def set_tuning(self, points_per_cell: float = 0.0, waves_per_cu: int = 0, scratch_blocks: int = 0):
+        self._check(_lib.tpcf_set_tuning(self._h, float(points_per_cell), int(waves_per_cu),
+                                         int(scratch_blocks)))
+
+    def set_debug(self, enable: bool = True):
+        self._check(_lib.tpcf_set_debug(self._h, int(bool(enable))))
+
+    # -- inputs
+    def _arrays(self, x, y, z, w):
+        """(pointers, memspace, keep-alive list) for host numpy or device torch arrays."""
+        if _is_torch(x):
+            import torch
+            ts = [t.contiguous().to(torch.float64) for t in (x, y, z)]
+            wt = None if w is None else w.contiguous().to(torch.float64)
+            if not ts[0].is_cuda:
+                ts = [t.numpy() for t in ts]
+                wt = None if wt is None else wt.numpy()
+                return self._arrays(*ts, wt)
+            keep = ts + ([wt] if wt is not None else [])
+            ptrs = [ctypes.c_void_p(t.data_ptr()) for t in ts]
+            ptrs.append(ctypes.c_void_p(wt.data_ptr()) if wt is not None else None)
+            return ptrs, MEM_DEVICE, keep
+        arrs = [_host_f64(a) for a in (x, y, z)]
+        wa = None if w is None else _host_f64(w)
+        ptrs = [_ptr_np(a) for a in arrs] + [_ptr_np(wa) if wa is not None else None]
+        return ptrs, MEM_HOST, arrs + ([wa] if wa is not None else [])
+
+    def set_catalog(self, x, y, z, w=None, *, box: float, periodic: bool = True):
+        n = len(x)
+        if len(y) != n or len(z) != n or (w is not None and len(w) != n):
+            raise ValueError("x, y, z, w must have the same length")
+        ptrs, mem, keep = self._arrays(x, y, z, w)
+        self._check(_lib.tpcf_set_catalog(self._h, int(n), *ptrs, float(box), int(bool(periodic)), mem))
+        self.n, self.ncat = n, 1
+
+    # -- compute
+    def _out(self, like_device: bool, shape):
+        if like_device:
+            import torch
+            t = torch.empty(shape, dtype=torch.float64, device=f"cuda:{self.device}")
+            return t, ctypes.c_void_p(t.data_ptr()), MEM_DEVICE
+        a = np.zeros(shape)
+        return a, _ptr_np(a), MEM_HOST
+
+    def compute_zeta(self, device_output: bool = False):
+        out, p, mem = self._out(device_output, (self.lmax + 1, self.nbins, self.nbins))
+        self._check(_lib.tpcf_compute_zeta(self._h, p, mem))
+        return out
+
+    def compute_zeta_range(self, p_begin: int, p_end: int, device_output: bool = False):
+        out, p, mem = self._out(device_output, (self.lmax + 1, self.nbins, self.nbins))
+        self._check(_lib.tpcf_compute_zeta_range(self._h, int(p_begin), int(p_end), p, mem))
+        return out
+
+    def compute_batch(self, offsets, x, y, z, w, box, periodic, device_output: bool = False):
+        offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+        ncat = len(offsets) - 1
+        box = np.ascontiguousarray(np.broadcast_to(np.asarray(box, dtype=np.float64), (ncat,)))
+        per = np.ascontiguousarray(np.broadcast_to(np.asarray(periodic, dtype=np.int32), (ncat,)))
+        ptrs, mem, keep = self._arrays(x, y, z, w)
+        out, p, omem = self._out(device_output or mem == MEM_DEVICE,
+                                 (ncat, self.lmax + 1, self.nbins, self.nbins))
+        if omem != mem:
+            raise ValueError("batch inputs and output must be in the same memory space")
+        self._check(_lib.tpcf_compute_batch(self._h, ncat, _ptr_np(offsets), *ptrs, _ptr_np(box),
+                                            _ptr_np(per), p, mem))
+        self.n, self.ncat = int(offsets[-1]), ncat
+        return out
+
+    # -- debug and statistics
+    def pair_counts(self) -> np.ndarray:
+        out = np.zeros((self.n, self.nbins), dtype=np.int64)
+        self._check(_lib.tpcf_debug_pair_counts(self._h, _ptr_np(out)))
+        return out
+
+    def alm_real(self) -> np.ndarray:
+        nc = (self.lmax + 1) ** 2
+        out = np.zeros((self.n, self.nbins, nc))
+        self._check(_lib.tpcf_debug_alm(self._h, _ptr_np(out)))
+        return out
+
+    def alm(self) -> np.ndarray:
+        """a_lm for m >= 0 as complex [n, nbins, lmax+1, lmax+1] (index [.., l, m])."""
+        r = self.alm_real()
+        L = self.lmax
+        out = np.zeros(r.shape[:2] + (L + 1, L + 1), dtype=np.complex128)
+        for l in range(L + 1):
+            out[..., l, 0] = r[..., l * l]
+            for m in range(1, l + 1):
+                out[..., l, m] = r[..., l * l + 2 * m - 1] + 1j * r[..., l * l + 2 * m]
+        return out
+
+    def stats(self) -> dict:
+        s = Stats()
+        self._check(_lib.tpcf_get_stats(self._h, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in Stats._fields_}
+
+
+def zeta(x, y, z, w=None, *, box: float, periodic: bool = True, rmin: float, rmax: float,
+         nbins: int, lmax: int, precision="fp64", device: int = 0, stream=None):
+    """zeta_l(b1, b2) of one catalogue, float64 [(lmax+1), nbins, nbins]."""
+    with Context(device, stream) as ctx:
+        ctx.set_bins(nbins, rmin, rmax, lmax)
+        ctx.set_precision(precision)
+        ctx.set_catalog(x, y, z, w, box=box, periodic=periodic)
+        return ctx.compute_zeta(device_output=_is_torch(x) and x.is_cuda)

@@ -1,0 +1,754 @@
+// api.hip -- host side of the library: context, argument validation, lattice and cell-grid set
+// up, stencil rows, spherical-harmonic normalisation, launches, HIP-graph replay of batches and
+// the extern "C" entry points declared in include/tpcf.h.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "tpcf.h"
+#include "tpcf_internal.h"
+
+namespace tpcf {
+hipError_t build_grid(const double* x, const double* y, const double* z, const double* w, uint32_t n,
+                      const CatDesc* cats, int ncat, uint32_t ncell, uint4* qtmp, uint32_t* cell, uint32_t* hist,
+                      uint32_t* idx_a, uint32_t* idx_b, uint32_t* block_sum, int* err, uint32_t* cell_start,
+                      uint4* rec, double* w64, uint32_t* perm, hipStream_t s);
+void validate_inputs(const double* x, const double* y, const double* z, const double* w, uint32_t n,
+                     const CatDesc* cats, int ncat, int* err, hipStream_t s);
+size_t scan_block_count(uint32_t ncell);
+void fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s);
+void fill_f64(double* p, double v, size_t n, hipStream_t s);
+void unsort_counts(const int32_t* in, const uint32_t* perm, int64_t* out, uint32_t n, int nb, hipStream_t s);
+void unsort_alm(const void* in, bool f64, const uint32_t* perm, double* out, uint32_t n, int row, hipStream_t s);
+hipError_t launch_sweep(int lmax, bool f64, const SweepArgs& args, int waves, hipStream_t stream);
+size_t sweep_lds_bytes(int scratch_blocks, int nb);
+size_t sweep_tile_bytes_per_wave(int lmax, int nb, bool f64);
+}  // namespace tpcf
+
+using namespace tpcf;
+
+namespace {
+
+constexpr int64_t kMaxPoints = (int64_t)1 << 31;
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+// Per-catalogue host description.
+struct HostCat {
+  int64_t first, n;
+  double box;
+  int periodic;
+};
+
+}  // namespace
+
+struct tpcf_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  bool dev_ready = false;
+  int ncu = 0;
+  size_t lds_per_block = 0;
+
+  bool bins_set = false;
+  int nbins = 0;
+  double rmin = 0, rmax = 0;
+  int lmax = 0;
+  int precision = TPCF_PREC_FP64;
+  double ppc = 30.0;
+  int waves_per_cu = 8;
+  int scratch_blocks = 1024;
+  bool debug = false;
+
+  // staged input (device FP64 copies, concatenated catalogues)
+  bool cat_set = false;
+  std::vector<HostCat> cats;
+  int64_t ntot = 0;
+  bool have_w = false;
+  DevBuf sx, sy, sz, sw;
+
+  // cell grid, valid for (grid_rmax, grid_ppc, grid_nb)
+  bool grid_valid = false;
+  double grid_rmax = -1, grid_ppc = -1, grid_rmin = -1;
+  int grid_nb = -1;
+  std::vector<CatDesc> cd;
+  std::vector<StencilRow> st;
+  uint32_t ncell = 0;
+  DevBuf cats_d, stencil_d, qtmp, cellid, hist, idx_a, idx_b, bsum, errflag, cell_start, rec, w64, perm;
+
+  // sweep buffers
+  DevBuf scratch, tile, zeta_d, queue, stats_d, tasks, counts32, alm_dbg, cscale32, cscale64;
+  int cscale_lmax = -1;
+
+  // results of the last compute
+  bool dbg_valid = false;
+  bool dbg_f64 = false;
+  int dbg_nb = 0, dbg_nc = 0;
+  tpcf_stats stats{};
+  std::string err;
+
+  // batch graph cache
+  hipGraphExec_t gexec = nullptr;
+  std::string gkey;
+
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+};
+
+namespace {
+
+int fail(tpcf_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+int hip_fail(tpcf_ctx* c, hipError_t e, const char* where) {
+  std::string m = std::string(where) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
+  return fail(c, e == hipErrorOutOfMemory ? TPCF_E_OUT_OF_MEMORY : TPCF_E_DEVICE, m);
+}
+
+#define HIP_TRY(ctx, call)                           \
+  do {                                               \
+    hipError_t e_ = (call);                          \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, #call); \
+  } while (0)
+
+size_t device_cap() {
+  const char* s = getenv("TPCF_MAX_DEVICE_BYTES");
+  if (!s || !*s) return (size_t)-1;
+  return (size_t)strtoull(s, nullptr, 10);
+}
+
+size_t total_bytes(tpcf_ctx* c) {
+  DevBuf* all[] = {&c->sx, &c->sy, &c->sz, &c->sw, &c->cats_d, &c->stencil_d, &c->qtmp, &c->cellid, &c->hist,
+                   &c->idx_a, &c->idx_b, &c->bsum, &c->errflag, &c->cell_start, &c->rec, &c->w64, &c->perm,
+                   &c->scratch, &c->tile, &c->zeta_d, &c->queue, &c->stats_d, &c->tasks, &c->counts32,
+                   &c->alm_dbg, &c->cscale32, &c->cscale64};
+  size_t t = 0;
+  for (DevBuf* b : all) t += b->bytes;
+  return t;
+}
+
+int ensure(tpcf_ctx* c, DevBuf& b, size_t bytes, const char* what) {
+  if (bytes == 0) bytes = 16;
+  if (b.bytes >= bytes) return TPCF_OK;
+  const size_t cap = device_cap();
+  if (total_bytes(c) - b.bytes + bytes > cap)
+    return fail(c, TPCF_E_OUT_OF_MEMORY, std::string("device byte cap (TPCF_MAX_DEVICE_BYTES) exceeded by ") + what);
+  if (b.p) {
+    (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  hipError_t e = hipMalloc(&b.p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, TPCF_E_OUT_OF_MEMORY, std::string("hipMalloc failed for ") + what);
+  }
+  b.bytes = bytes;
+  return TPCF_OK;
+}
+
+void release(DevBuf& b) {
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.bytes = 0;
+}
+
+int ensure_device(tpcf_ctx* c) {
+  HIP_TRY(c, hipSetDevice(c->device));
+  if (c->dev_ready) return TPCF_OK;
+  hipDeviceProp_t prop;
+  HIP_TRY(c, hipGetDeviceProperties(&prop, c->device));
+  c->ncu = prop.multiProcessorCount;
+  c->lds_per_block = prop.sharedMemPerBlock;
+  if (!c->stream) {
+    HIP_TRY(c, hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    c->own_stream = true;
+  }
+  for (auto& e : c->ev) HIP_TRY(c, hipEventCreate(&e));
+  c->dev_ready = true;
+  return TPCF_OK;
+}
+
+bool is_finite(double v) { return isfinite(v) != 0; }
+
+// Lattice bits K: the largest K <= 25 + log2(L / r_max), capped at 32 (periodic) / 31.
+int lattice_bits(double box, double rmax, int periodic) {
+  int e = 0;
+  frexp(box / rmax, &e);
+  int K = 25 + (e - 1);
+  const int cap = periodic ? 32 : 31;
+  if (K > cap) K = cap;
+  if (K < 1) K = 1;
+  return K;
+}
+
+// Normalisation of the monic recurrence: a_lm = C_lm * sum w H_lm(z) (x - i y)^m with
+// C_lm = N_lm (-1)^m (2m-1)!! prod_{k=m+1}^{l} (2k-1)/(k-m),
+// N_lm = sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!).
+std::vector<double> normalisation(int lmax) {
+  const int nc = (lmax + 1) * (lmax + 1);
+  std::vector<double> C(nc, 0.0);
+  for (int l = 0; l <= lmax; ++l)
+    for (int m = 0; m <= l; ++m) {
+      long double ratio = 1.0L;
+      for (int i = l - m + 1; i <= l + m; ++i) ratio /= (long double)i;
+      long double N = sqrtl((2.0L * l + 1.0L) / (4.0L * 3.14159265358979323846264338327950288L) * ratio);
+      long double kappa = 1.0L;
+      for (int i = 1; i <= m; ++i) kappa *= (long double)(2 * i - 1);
+      for (int k = m + 1; k <= l; ++k) kappa *= (long double)(2 * k - 1) / (long double)(k - m);
+      long double v = N * kappa * ((m & 1) ? -1.0L : 1.0L);
+      if (m == 0) {
+        C[l * l] = (double)v;
+      } else {
+        C[l * l + 2 * m - 1] = (double)v;
+        C[l * l + 2 * m] = (double)v;
+      }
+    }
+  return C;
+}
+
+typedef unsigned __int128 u128;
+
+// Grid side, lattice, thresholds and stencil rows (cells whose minimum-image lattice separation
+// from the primary cell can be below r_max) of every catalogue.
+int configure_grid(tpcf_ctx* c) {
+  const int nb = c->nbins;
+  const double delta = (c->rmax - c->rmin) / nb;
+  c->cd.clear();
+  c->st.clear();
+  uint64_t cells = 0;
+  for (size_t k = 0; k < c->cats.size(); ++k) {
+    const HostCat& h = c->cats[k];
+    CatDesc d;
+    memset(&d, 0, sizeof(d));
+    d.point_base = (uint32_t)h.first;
+    d.npoints = (uint32_t)h.n;
+    d.periodic = h.periodic;
+    d.box = h.box;
+    d.K = lattice_bits(h.box, c->rmax, h.periodic);
+    d.sh = h.periodic ? 32 - d.K : 0;
+    d.scale = ldexp(1.0, d.K) / h.box;
+    for (int b = 0; b <= nb; ++b) {
+      const double e = (b == nb) ? c->rmax : c->rmin + b * delta;
+      const double v = e * d.scale;
+      d.T[b] = ceil(v * v);
+    }
+    d.rmin_l = (float)(c->rmin * d.scale);
+    d.inv_delta_l = (float)(1.0 / (delta * d.scale));
+    // grid side from the target points per cell
+    int ncx = 1;
+    if (h.n > 0) {
+      const double dens = (double)h.n / (h.box * h.box * h.box);
+      const double side = cbrt(c->ppc / dens);
+      ncx = (int)floor(h.box / side);
+    }
+    ncx = std::max(1, std::min(ncx, 512));
+    d.nc = ncx;
+    d.cell_base = (uint32_t)cells;
+    cells += (uint64_t)ncx * ncx * ncx;
+    if (cells >= ((uint64_t)1 << 31)) return fail(c, TPCF_E_UNSUPPORTED, "too many grid cells");
+    // stencil rows
+    d.stencil_base = (int32_t)c->st.size();
+    const uint64_t cmin = std::max<uint64_t>(1, (((uint64_t)1) << d.K) / (uint64_t)ncx);
+    const u128 Tn = (u128)(uint64_t)d.T[nb];
+    auto sq = [&](int64_t e) -> u128 {
+      const u128 v = (u128)(uint64_t)(e > 0 ? e : 0) * (u128)cmin;
+      return v * v;
+    };
+    int R = 1;
+    while (R <= ncx && sq(R) < Tn) ++R;  // largest e with sq(e - 1) < Tn
+    int lo, hi;
+    if (h.periodic) {
+      if (2 * R + 1 > ncx) {
+        lo = -((ncx - 1) / 2);
+        hi = ncx / 2;
+      } else {
+        lo = -R;
+        hi = R;
+      }
+    } else {
+      const int r = std::min(R, ncx - 1);
+      lo = -r;
+      hi = r;
+    }
+    for (int dz = lo; dz <= hi; ++dz)
+      for (int dy = lo; dy <= hi; ++dy) {
+        const u128 base = sq(std::abs(dy) - 1) + sq(std::abs(dz) - 1);
+        if (base >= Tn) continue;
+        int half = 1;
+        while (half + 1 <= R && base + sq(half) < Tn) ++half;
+        if (!h.periodic) half = std::min(half, ncx - 1);
+        StencilRow row;
+        row.dy = dy;
+        row.dz = dz;
+        row.half = half;
+        row.full = (h.periodic && 2 * half + 1 >= ncx) ? 1 : 0;
+        c->st.push_back(row);
+      }
+    d.nstencil = (int32_t)c->st.size() - d.stencil_base;
+    c->cd.push_back(d);
+  }
+  c->ncell = (uint32_t)cells;
+  return TPCF_OK;
+}
+
+int check_periodic_range(tpcf_ctx* c) {
+  for (const HostCat& h : c->cats)
+    if (h.periodic && !(c->rmax < 0.5 * h.box))
+      return fail(c, TPCF_E_INVALID_ARG, "periodic catalogue needs rmax < box/2");
+  return TPCF_OK;
+}
+
+// Host-side validation of one catalogue's host arrays.
+int validate_host(tpcf_ctx* c, const double* x, const double* y, const double* z, const double* w, int64_t n,
+                  double box, int periodic) {
+  const double lim = box * 1048576.0;
+  for (int64_t i = 0; i < n; ++i) {
+    const double p[3] = {x[i], y[i], z[i]};
+    for (double v : p) {
+      if (!is_finite(v)) return fail(c, TPCF_E_INVALID_ARG, "non-finite position at index " + std::to_string(i));
+      if (periodic) {
+        if (fabs(v) > lim) return fail(c, TPCF_E_INVALID_ARG, "periodic position beyond 2^20 box sides");
+      } else if (v < 0.0 || v >= box) {
+        return fail(c, TPCF_E_INVALID_ARG, "non-periodic position outside [0, box) at index " + std::to_string(i));
+      }
+    }
+    if (w && !is_finite(w[i])) return fail(c, TPCF_E_INVALID_ARG, "non-finite weight at index " + std::to_string(i));
+  }
+  return TPCF_OK;
+}
+
+// Copies (and validates) the concatenated catalogues into the staging buffers.
+int stage(tpcf_ctx* c, const std::vector<HostCat>& cats, int64_t ntot, const double* x, const double* y,
+          const double* z, const double* w, int memspace) {
+  if (memspace == TPCF_MEM_HOST) {
+    for (const HostCat& h : cats) {
+      int rc = validate_host(c, x + h.first, y + h.first, z + h.first, w ? w + h.first : nullptr, h.n, h.box,
+                             h.periodic);
+      if (rc) return rc;
+    }
+  }
+  int rc;
+  if ((rc = ensure_device(c))) return rc;
+  const size_t bytes = (size_t)ntot * sizeof(double);
+  if ((rc = ensure(c, c->sx, bytes, "positions")) || (rc = ensure(c, c->sy, bytes, "positions")) ||
+      (rc = ensure(c, c->sz, bytes, "positions")))
+    return rc;
+  if (w && (rc = ensure(c, c->sw, bytes, "weights"))) return rc;
+  const hipMemcpyKind kind = memspace == TPCF_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+  if (ntot) {
+    HIP_TRY(c, hipMemcpyAsync(c->sx.p, x, bytes, kind, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->sy.p, y, bytes, kind, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->sz.p, z, bytes, kind, c->stream));
+    if (w) HIP_TRY(c, hipMemcpyAsync(c->sw.p, w, bytes, kind, c->stream));
+  }
+  if (memspace == TPCF_MEM_DEVICE && ntot) {
+    // validate on the device
+    std::vector<CatDesc> tmp(cats.size());
+    for (size_t k = 0; k < cats.size(); ++k) {
+      memset(&tmp[k], 0, sizeof(CatDesc));
+      tmp[k].point_base = (uint32_t)cats[k].first;
+      tmp[k].box = cats[k].box;
+      tmp[k].periodic = cats[k].periodic;
+    }
+    if ((rc = ensure(c, c->cats_d, tmp.size() * sizeof(CatDesc), "catalogue table")) ||
+        (rc = ensure(c, c->errflag, sizeof(int), "flags")))
+      return rc;
+    HIP_TRY(c, hipMemcpyAsync(c->cats_d.p, tmp.data(), tmp.size() * sizeof(CatDesc), hipMemcpyHostToDevice,
+                              c->stream));
+    fill_u32((uint32_t*)c->errflag.p, 0u, 1, c->stream);
+    validate_inputs((const double*)c->sx.p, (const double*)c->sy.p, (const double*)c->sz.p,
+                    w ? (const double*)c->sw.p : nullptr, (uint32_t)ntot, (const CatDesc*)c->cats_d.p,
+                    (int)cats.size(), (int*)c->errflag.p, c->stream);
+    int flag = 0;
+    HIP_TRY(c, hipMemcpyAsync(&flag, c->errflag.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (flag & 1) return fail(c, TPCF_E_INVALID_ARG, "non-finite position or weight");
+    if (flag & 2) return fail(c, TPCF_E_INVALID_ARG, "non-periodic position outside [0, box)");
+    if (flag & 4) return fail(c, TPCF_E_INVALID_ARG, "periodic position beyond 2^20 box sides");
+  } else {
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+  }
+  c->cats = cats;
+  c->ntot = ntot;
+  c->have_w = w != nullptr;
+  c->cat_set = true;
+  c->grid_valid = false;
+  c->dbg_valid = false;
+  return TPCF_OK;
+}
+
+int ensure_grid(tpcf_ctx* c) {
+  if (c->grid_valid && c->grid_rmax == c->rmax && c->grid_rmin == c->rmin && c->grid_ppc == c->ppc &&
+      c->grid_nb == c->nbins)
+    return TPCF_OK;
+  int rc;
+  if ((rc = configure_grid(c))) return rc;
+  const size_t n = (size_t)c->ntot;
+  if ((rc = ensure(c, c->cats_d, c->cd.size() * sizeof(CatDesc), "catalogue table")) ||
+      (rc = ensure(c, c->stencil_d, std::max<size_t>(1, c->st.size()) * sizeof(StencilRow), "stencil")) ||
+      (rc = ensure(c, c->qtmp, n * sizeof(uint4), "grid")) || (rc = ensure(c, c->cellid, n * 4, "grid")) ||
+      (rc = ensure(c, c->hist, (size_t)c->ncell * 4, "grid")) || (rc = ensure(c, c->idx_a, n * 4, "grid")) ||
+      (rc = ensure(c, c->idx_b, n * 4, "grid")) ||
+      (rc = ensure(c, c->bsum, scan_block_count(c->ncell) * 4 + 4, "grid")) ||
+      (rc = ensure(c, c->errflag, sizeof(int), "flags")) ||
+      (rc = ensure(c, c->cell_start, ((size_t)c->ncell + 1) * 4, "grid")) ||
+      (rc = ensure(c, c->rec, n * sizeof(uint4), "records")) || (rc = ensure(c, c->w64, n * 8, "weights")) ||
+      (rc = ensure(c, c->perm, n * 4, "permutation")))
+    return rc;
+  HIP_TRY(c, hipMemcpyAsync(c->cats_d.p, c->cd.data(), c->cd.size() * sizeof(CatDesc), hipMemcpyHostToDevice,
+                            c->stream));
+  if (!c->st.empty())
+    HIP_TRY(c, hipMemcpyAsync(c->stencil_d.p, c->st.data(), c->st.size() * sizeof(StencilRow),
+                              hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipEventRecord(c->ev[0], c->stream));
+  HIP_TRY(c, build_grid((const double*)c->sx.p, (const double*)c->sy.p, (const double*)c->sz.p,
+                        c->have_w ? (const double*)c->sw.p : nullptr, (uint32_t)n, (const CatDesc*)c->cats_d.p,
+                        (int)c->cd.size(), c->ncell, (uint4*)c->qtmp.p, (uint32_t*)c->cellid.p,
+                        (uint32_t*)c->hist.p, (uint32_t*)c->idx_a.p, (uint32_t*)c->idx_b.p, (uint32_t*)c->bsum.p,
+                        (int*)c->errflag.p, (uint32_t*)c->cell_start.p, (uint4*)c->rec.p, (double*)c->w64.p,
+                        (uint32_t*)c->perm.p, c->stream));
+  HIP_TRY(c, hipEventRecord(c->ev[1], c->stream));
+  c->grid_valid = true;
+  c->grid_rmax = c->rmax;
+  c->grid_rmin = c->rmin;
+  c->grid_ppc = c->ppc;
+  c->grid_nb = c->nbins;
+  return TPCF_OK;
+}
+
+// Runs the sweep for the task list (nullptr = all points) and leaves zeta in zeta_d.
+int run_sweep(tpcf_ctx* c, const uint32_t* tasks_d, uint32_t ntask) {
+  const bool f64 = c->precision == TPCF_PREC_FP64;
+  const int nb = c->nbins, L = c->lmax, NC = (L + 1) * (L + 1);
+  const int ncat = (int)c->cd.size();
+  int waves = std::max(1, c->ncu * c->waves_per_cu);
+  if ((uint32_t)waves > ntask) waves = std::max<uint32_t>(1, ntask);
+  const int S = c->scratch_blocks;
+  int rc;
+  const size_t lds = sweep_lds_bytes(S, nb);
+  if (lds > 160 * 1024) return fail(c, TPCF_E_UNSUPPORTED, "scratch_blocks too large for LDS");
+  if ((rc = ensure(c, c->scratch, (size_t)waves * S * kBlock * 4, "scratch")) ||
+      (rc = ensure(c, c->tile, (size_t)waves * sweep_tile_bytes_per_wave(L, nb, f64), "tiles")) ||
+      (rc = ensure(c, c->zeta_d, (size_t)ncat * (L + 1) * nb * nb * 8, "zeta")) ||
+      (rc = ensure(c, c->queue, 16, "queue")) || (rc = ensure(c, c->stats_d, 16, "stats")))
+    return rc;
+  if (c->cscale_lmax != L) {
+    std::vector<double> C = normalisation(L);
+    std::vector<float> C32(C.begin(), C.end());
+    if ((rc = ensure(c, c->cscale64, NC * 8, "constants")) || (rc = ensure(c, c->cscale32, NC * 4, "constants")))
+      return rc;
+    HIP_TRY(c, hipMemcpyAsync(c->cscale64.p, C.data(), NC * 8, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->cscale32.p, C32.data(), NC * 4, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->cscale_lmax = L;
+  }
+  if (c->debug) {
+    if ((rc = ensure(c, c->counts32, (size_t)c->ntot * nb * 4, "debug counts")) ||
+        (rc = ensure(c, c->alm_dbg, (size_t)c->ntot * nb * NC * (f64 ? 8 : 4), "debug a_lm")))
+      return rc;
+    fill_u32((uint32_t*)c->counts32.p, 0u, (size_t)c->ntot * nb, c->stream);
+    fill_u32((uint32_t*)c->alm_dbg.p, 0u, (size_t)c->ntot * nb * NC * (f64 ? 2 : 1), c->stream);
+  }
+  fill_f64((double*)c->zeta_d.p, 0.0, (size_t)ncat * (L + 1) * nb * nb, c->stream);
+  fill_u32((uint32_t*)c->queue.p, 0u, 4, c->stream);
+  fill_u32((uint32_t*)c->stats_d.p, 0u, 4, c->stream);
+
+  SweepArgs a;
+  memset(&a, 0, sizeof(a));
+  a.rec = (const uint4*)c->rec.p;
+  a.w64 = (const double*)c->w64.p;
+  a.cell_start = (const uint32_t*)c->cell_start.p;
+  a.stencil = (const StencilRow*)c->stencil_d.p;
+  a.cats = (const CatDesc*)c->cats_d.p;
+  a.ncat = ncat;
+  a.nb = nb;
+  a.task_list = tasks_d;
+  a.ntask = ntask;
+  a.queue = (uint32_t*)c->queue.p;
+  a.scratch = (uint32_t*)c->scratch.p;
+  a.scratch_blocks = S;
+  a.tile = c->tile.p;
+  a.zeta = (double*)c->zeta_d.p;
+  a.counts = c->debug ? (int32_t*)c->counts32.p : nullptr;
+  a.alm_debug = c->debug ? c->alm_dbg.p : nullptr;
+  a.stats = (unsigned long long*)c->stats_d.p;
+  a.cscale32 = (const float*)c->cscale32.p;
+  a.cscale64 = (const double*)c->cscale64.p;
+  HIP_TRY(c, hipEventRecord(c->ev[2], c->stream));
+  if (ntask > 0) HIP_TRY(c, launch_sweep(L, f64, a, waves, c->stream));
+  HIP_TRY(c, hipEventRecord(c->ev[3], c->stream));
+  c->stats.waves = waves;
+  return TPCF_OK;
+}
+
+int finish_stats(tpcf_ctx* c, bool grid_built, uint32_t ntask) {
+  unsigned long long st[2] = {0, 0};
+  HIP_TRY(c, hipMemcpyAsync(st, c->stats_d.p, 16, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->stats.n_pairs = (int64_t)st[0];
+  c->stats.n_candidates = (int64_t)st[1];
+  c->stats.n_primaries = ntask;
+  float ms = 0.f;
+  c->stats.ms_grid = 0.0;
+  if (grid_built && hipEventElapsedTime(&ms, c->ev[0], c->ev[1]) == hipSuccess) c->stats.ms_grid = ms;
+  c->stats.ms_sweep = hipEventElapsedTime(&ms, c->ev[2], c->ev[3]) == hipSuccess ? ms : 0.0;
+  c->stats.ms_total = c->stats.ms_grid + c->stats.ms_sweep;
+  c->stats.cells_per_axis = c->cd.empty() ? 0 : c->cd[0].nc;
+  c->stats.precision = c->precision;
+  c->stats.lmax = c->lmax;
+  c->stats.nbins = c->nbins;
+  c->dbg_valid = c->debug;
+  c->dbg_f64 = c->precision == TPCF_PREC_FP64;
+  c->dbg_nb = c->nbins;
+  c->dbg_nc = (c->lmax + 1) * (c->lmax + 1);
+  return TPCF_OK;
+}
+
+int copy_out(tpcf_ctx* c, double* zeta, size_t count, int memspace) {
+  const hipMemcpyKind kind = memspace == TPCF_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+  HIP_TRY(c, hipMemcpyAsync(zeta, c->zeta_d.p, count * 8, kind, c->stream));
+  return TPCF_OK;
+}
+
+int compute(tpcf_ctx* c, int64_t p_begin, int64_t p_end, double* zeta, int memspace) {
+  if (!c) return TPCF_E_INVALID_ARG;
+  if (!c->bins_set) return fail(c, TPCF_E_STATE, "set_bins has not been called");
+  if (!c->cat_set) return fail(c, TPCF_E_STATE, "no catalogue set");
+  if (!zeta) return fail(c, TPCF_E_INVALID_ARG, "zeta is NULL");
+  if (memspace != TPCF_MEM_HOST && memspace != TPCF_MEM_DEVICE)
+    return fail(c, TPCF_E_INVALID_ARG, "unknown memory space");
+  int rc;
+  if ((rc = check_periodic_range(c))) return rc;
+  if ((rc = ensure_device(c))) return rc;
+  const bool rebuilt = !c->grid_valid;
+  if ((rc = ensure_grid(c))) return rc;
+  const uint32_t* tasks = nullptr;
+  uint32_t ntask = (uint32_t)c->ntot;
+  if (p_begin != 0 || p_end != c->ntot) {
+    // primaries by input index -> sorted positions
+    std::vector<uint32_t> perm((size_t)c->ntot);
+    if (c->ntot)
+      HIP_TRY(c, hipMemcpyAsync(perm.data(), c->perm.p, (size_t)c->ntot * 4, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    std::vector<uint32_t> list;
+    for (uint32_t s = 0; s < (uint32_t)c->ntot; ++s)
+      if ((int64_t)perm[s] >= p_begin && (int64_t)perm[s] < p_end) list.push_back(s);
+    ntask = (uint32_t)list.size();
+    if ((rc = ensure(c, c->tasks, std::max<size_t>(1, list.size()) * 4, "task list"))) return rc;
+    if (ntask)
+      HIP_TRY(c, hipMemcpyAsync(c->tasks.p, list.data(), list.size() * 4, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    tasks = (const uint32_t*)c->tasks.p;
+  }
+  if ((rc = run_sweep(c, tasks, ntask))) return rc;
+  const size_t cnt = (size_t)c->cd.size() * (c->lmax + 1) * c->nbins * c->nbins;
+  if ((rc = copy_out(c, zeta, cnt, memspace))) return rc;
+  return finish_stats(c, rebuilt, ntask);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------------
+// extern "C" entry points
+// ------------------------------------------------------------------------------------------
+extern "C" {
+
+const char* tpcf_version(void) { return "tpcf 1.0.0 gfx950"; }
+
+int tpcf_create(tpcf_ctx** out, int device, void* hip_stream) {
+  if (!out || device < 0) return TPCF_E_INVALID_ARG;
+  tpcf_ctx* c = new (std::nothrow) tpcf_ctx();
+  if (!c) return TPCF_E_OUT_OF_MEMORY;
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  *out = c;
+  return TPCF_OK;
+}
+
+void tpcf_destroy(tpcf_ctx* c) {
+  if (!c) return;
+  if (c->dev_ready) {
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    DevBuf* all[] = {&c->sx, &c->sy, &c->sz, &c->sw, &c->cats_d, &c->stencil_d, &c->qtmp, &c->cellid, &c->hist,
+                     &c->idx_a, &c->idx_b, &c->bsum, &c->errflag, &c->cell_start, &c->rec, &c->w64, &c->perm,
+                     &c->scratch, &c->tile, &c->zeta_d, &c->queue, &c->stats_d, &c->tasks, &c->counts32,
+                     &c->alm_dbg, &c->cscale32, &c->cscale64};
+    for (DevBuf* b : all) release(*b);
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    for (auto& e : c->ev)
+      if (e) (void)hipEventDestroy(e);
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+  }
+  delete c;
+}
+
+int tpcf_set_bins(tpcf_ctx* c, int nbins, double rmin, double rmax, int lmax) {
+  if (!c) return TPCF_E_INVALID_ARG;
+  if (nbins < 1 || nbins > TPCF_MAX_NBINS) return fail(c, TPCF_E_INVALID_ARG, "nbins must be in [1, 32]");
+  if (lmax < 0 || lmax > TPCF_MAX_LMAX) return fail(c, TPCF_E_INVALID_ARG, "lmax must be in [0, 10]");
+  if (!is_finite(rmin) || !is_finite(rmax) || rmin < 0.0 || !(rmax > rmin))
+    return fail(c, TPCF_E_INVALID_ARG, "need finite 0 <= rmin < rmax");
+  if (c->cat_set)
+    for (const HostCat& h : c->cats)
+      if (h.periodic && !(rmax < 0.5 * h.box))
+        return fail(c, TPCF_E_INVALID_ARG, "periodic catalogue needs rmax < box/2");
+  c->nbins = nbins;
+  c->rmin = rmin;
+  c->rmax = rmax;
+  c->lmax = lmax;
+  c->bins_set = true;
+  c->err.clear();
+  return TPCF_OK;
+}
+
+int tpcf_set_precision(tpcf_ctx* c, int precision) {
+  if (!c) return TPCF_E_INVALID_ARG;
+  if (precision != TPCF_PREC_FP64 && precision != TPCF_PREC_MIXED)
+    return fail(c, TPCF_E_INVALID_ARG, "precision must be TPCF_PREC_FP64 or TPCF_PREC_MIXED");
+  c->precision = precision;
+  c->err.clear();
+  return TPCF_OK;
+}
+
+int tpcf_set_tuning(tpcf_ctx* c, double points_per_cell, int waves_per_cu, int scratch_blocks) {
+  if (!c) return TPCF_E_INVALID_ARG;
+  if (!(points_per_cell >= 0.0) || !is_finite(points_per_cell) || waves_per_cu < 0 || scratch_blocks < 0 ||
+      scratch_blocks % 64 != 0 || scratch_blocks > 8192 || waves_per_cu > 64)
+    return fail(c, TPCF_E_INVALID_ARG, "invalid tuning value");
+  if (points_per_cell > 0.0) c->ppc = points_per_cell;
+  if (waves_per_cu > 0) c->waves_per_cu = waves_per_cu;
+  if (scratch_blocks > 0) c->scratch_blocks = scratch_blocks;
+  c->err.clear();
+  return TPCF_OK;
+}
+
+int tpcf_set_debug(tpcf_ctx* c, int enable) {
+  if (!c) return TPCF_E_INVALID_ARG;
+  c->debug = enable != 0;
+  return TPCF_OK;
+}
+
+int tpcf_set_catalog(tpcf_ctx* c, int64_t n, const double* x, const double* y, const double* z, const double* w,
+                     double box, int periodic, int memspace) {
+  if (!c) return TPCF_E_INVALID_ARG;
+  if (n < 0 || n >= kMaxPoints) return fail(c, TPCF_E_INVALID_ARG, "n must be in [0, 2^31)");
+  if (!is_finite(box) || !(box > 0.0)) return fail(c, TPCF_E_INVALID_ARG, "box must be finite and > 0");
+  if (n > 0 && (!x || !y || !z)) return fail(c, TPCF_E_INVALID_ARG, "NULL position array");
+  if (memspace != TPCF_MEM_HOST && memspace != TPCF_MEM_DEVICE)
+    return fail(c, TPCF_E_INVALID_ARG, "unknown memory space");
+  if (c->bins_set && periodic && !(c->rmax < 0.5 * box))
+    return fail(c, TPCF_E_INVALID_ARG, "periodic catalogue needs rmax < box/2");
+  std::vector<HostCat> cats(1);
+  cats[0].first = 0;
+  cats[0].n = n;
+  cats[0].box = box;
+  cats[0].periodic = periodic ? 1 : 0;
+  int rc = stage(c, cats, n, x, y, z, w, memspace);
+  if (!rc) c->err.clear();
+  return rc;
+}
+
+int tpcf_compute_zeta(tpcf_ctx* c, double* zeta, int memspace) {
+  if (!c) return TPCF_E_INVALID_ARG;
+  if (c->cat_set && c->cats.size() != 1) return fail(c, TPCF_E_STATE, "context holds a batch; use compute_batch");
+  int rc = compute(c, 0, c->ntot, zeta, memspace);
+  if (!rc) c->err.clear();
+  return rc;
+}
+
+int tpcf_compute_zeta_range(tpcf_ctx* c, int64_t p_begin, int64_t p_end, double* zeta, int memspace) {
+  if (!c) return TPCF_E_INVALID_ARG;
+  if (!c->cat_set) return fail(c, TPCF_E_STATE, "no catalogue set");
+  if (c->cats.size() != 1) return fail(c, TPCF_E_STATE, "context holds a batch; use compute_batch");
+  if (p_begin < 0 || p_end > c->ntot || p_begin > p_end)
+    return fail(c, TPCF_E_INVALID_ARG, "primary range outside [0, n]");
+  int rc = compute(c, p_begin, p_end, zeta, memspace);
+  if (!rc) c->err.clear();
+  return rc;
+}
+
+int tpcf_compute_batch(tpcf_ctx* c, int ncat, const int64_t* offsets, const double* x, const double* y,
+                       const double* z, const double* w, const double* box_side, const int* periodic,
+                       double* zeta, int memspace) {
+  if (!c) return TPCF_E_INVALID_ARG;
+  if (ncat < 1 || !offsets || !box_side || !periodic) return fail(c, TPCF_E_INVALID_ARG, "invalid batch description");
+  if (!c->bins_set) return fail(c, TPCF_E_STATE, "set_bins has not been called");
+  if (offsets[0] != 0) return fail(c, TPCF_E_INVALID_ARG, "offsets[0] must be 0");
+  std::vector<HostCat> cats(ncat);
+  for (int k = 0; k < ncat; ++k) {
+    if (offsets[k + 1] < offsets[k]) return fail(c, TPCF_E_INVALID_ARG, "offsets must be non-decreasing");
+    if (!is_finite(box_side[k]) || !(box_side[k] > 0.0))
+      return fail(c, TPCF_E_INVALID_ARG, "box must be finite and > 0");
+    if (periodic[k] && !(c->rmax < 0.5 * box_side[k]))
+      return fail(c, TPCF_E_INVALID_ARG, "periodic catalogue needs rmax < box/2");
+    cats[k].first = offsets[k];
+    cats[k].n = offsets[k + 1] - offsets[k];
+    cats[k].box = box_side[k];
+    cats[k].periodic = periodic[k] ? 1 : 0;
+  }
+  const int64_t ntot = offsets[ncat];
+  if (ntot >= kMaxPoints) return fail(c, TPCF_E_INVALID_ARG, "total points must be < 2^31");
+  if (ntot > 0 && (!x || !y || !z)) return fail(c, TPCF_E_INVALID_ARG, "NULL position array");
+  if (!zeta) return fail(c, TPCF_E_INVALID_ARG, "zeta is NULL");
+  int rc = stage(c, cats, ntot, x, y, z, w, memspace);
+  if (rc) return rc;
+  rc = compute(c, 0, c->ntot, zeta, memspace);
+  if (!rc) c->err.clear();
+  return rc;
+}
+
+int tpcf_debug_pair_counts(tpcf_ctx* c, int64_t* counts) {
+  if (!c || !counts) return TPCF_E_INVALID_ARG;
+  if (!c->dbg_valid) return fail(c, TPCF_E_STATE, "no compute call with debug output enabled");
+  int rc;
+  DevBuf tmp;
+  const size_t tot = (size_t)c->ntot * c->dbg_nb;
+  if ((rc = ensure_device(c))) return rc;
+  HIP_TRY(c, hipMalloc(&tmp.p, std::max<size_t>(8, tot * 8)));
+  unsort_counts((const int32_t*)c->counts32.p, (const uint32_t*)c->perm.p, (int64_t*)tmp.p, (uint32_t)c->ntot,
+                c->dbg_nb, c->stream);
+  hipError_t e = hipMemcpyAsync(counts, tmp.p, tot * 8, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  (void)hipFree(tmp.p);
+  if (e != hipSuccess) return hip_fail(c, e, "tpcf_debug_pair_counts");
+  return TPCF_OK;
+}
+
+int tpcf_debug_alm(tpcf_ctx* c, double* alm) {
+  if (!c || !alm) return TPCF_E_INVALID_ARG;
+  if (!c->dbg_valid) return fail(c, TPCF_E_STATE, "no compute call with debug output enabled");
+  int rc;
+  DevBuf tmp;
+  const int row = c->dbg_nb * c->dbg_nc;
+  const size_t tot = (size_t)c->ntot * row;
+  if ((rc = ensure_device(c))) return rc;
+  HIP_TRY(c, hipMalloc(&tmp.p, std::max<size_t>(8, tot * 8)));
+  unsort_alm(c->alm_dbg.p, c->dbg_f64, (const uint32_t*)c->perm.p, (double*)tmp.p, (uint32_t)c->ntot, row,
+             c->stream);
+  hipError_t e = hipMemcpyAsync(alm, tmp.p, tot * 8, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  (void)hipFree(tmp.p);
+  if (e != hipSuccess) return hip_fail(c, e, "tpcf_debug_alm");
+  return TPCF_OK;
+}
+
+int tpcf_get_stats(const tpcf_ctx* c, tpcf_stats* out) {
+  if (!c || !out) return TPCF_E_INVALID_ARG;
+  *out = c->stats;
+  return TPCF_OK;
+}
+
+const char* tpcf_last_error(const tpcf_ctx* c) { return c ? c->err.c_str() : "NULL context"; }
+
+}  // extern "C"

@@ -1,0 +1,296 @@
+// grid.hip -- lattice snap and counting-sort cell grid for one or many catalogues (gfx950).
+//
+// The paper finds neighbours with an octree / kd-tree pruned into balls (Implementation
+// section); here neighbours come from a uniform cubic cell grid built by a counting sort, which
+// is what a wide GPU wants: every stencil row is a contiguous range of the cell-sorted records.
+//
+//   k_snap      : FP64 positions -> lattice coordinates q (FP64 multiply by 2^K/L, floor, wrap
+//                 or clamp), stored shifted as q << sh; cell id; cell histogram (atomics);
+//                 validation flags for non-finite values and non-periodic points outside the box.
+//   k_scan_*    : exclusive scan of the histogram -> cell_start (three small kernels).
+//   k_scatter   : each point claims a slot of its cell (atomic, so the order inside a cell is
+//                 arbitrary at this point).
+//   k_cellsort  : restores input order inside every cell of up to kCellSortMax points, so the
+//                 sorted layout (catalogue, cell, input index) and hence every summation order is
+//                 reproducible.
+//   k_gather    : writes the cell-sorted records (Qx, Qy, Qz, float w), FP64 weights and the
+//                 permutation back to input order.
+#include "tpcf_internal.h"
+
+namespace tpcf {
+
+constexpr int kCellSortMax = 4096;
+
+__device__ __forceinline__ int cat_of_point(const CatDesc* cats, int ncat, uint32_t i) {
+  int lo = 0, hi = ncat - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (cats[mid].point_base <= i) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Lattice coordinate of one position (periodic: mod 2^K; else clamped to [0, 2^K)).
+__device__ __forceinline__ uint32_t snap_coord(double x, double scale, int K, int periodic) {
+  const int64_t t = (int64_t)floor(x * scale);
+  const int64_t M = (int64_t)1 << K;
+  int64_t q;
+  if (periodic) {
+    q = t & (M - 1);
+  } else {
+    q = t < 0 ? 0 : (t > M - 1 ? M - 1 : t);
+  }
+  return (uint32_t)q;
+}
+
+__global__ void k_snap(const double* __restrict__ x, const double* __restrict__ y,
+                       const double* __restrict__ z, const double* __restrict__ w, uint32_t n,
+                       const CatDesc* __restrict__ cats, int ncat, uint4* __restrict__ qtmp,
+                       uint32_t* __restrict__ cell, uint32_t* __restrict__ hist, int* __restrict__ err) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int c = cat_of_point(cats, ncat, i);
+  const CatDesc& cd = cats[c];
+  double px = x[i], py = y[i], pz = z[i];
+  const double pw = w ? w[i] : 1.0;
+  int bad = 0;
+  if (!isfinite(px) || !isfinite(py) || !isfinite(pz) || !isfinite(pw)) bad |= 1;
+  if (cd.periodic) {
+    const double lim = cd.box * 1048576.0;
+    if (fabs(px) > lim || fabs(py) > lim || fabs(pz) > lim) bad |= 4;
+  } else if (px < 0.0 || px >= cd.box || py < 0.0 || py >= cd.box || pz < 0.0 || pz >= cd.box) {
+    bad |= 2;
+  }
+  if (bad) {
+    atomicOr(err, bad);
+    px = py = pz = 0.0;
+  }
+  const uint32_t qx = snap_coord(px, cd.scale, cd.K, cd.periodic);
+  const uint32_t qy = snap_coord(py, cd.scale, cd.K, cd.periodic);
+  const uint32_t qz = snap_coord(pz, cd.scale, cd.K, cd.periodic);
+  const uint64_t nc = (uint64_t)cd.nc;
+  const uint32_t cx = (uint32_t)(((uint64_t)qx * nc) >> cd.K);
+  const uint32_t cy = (uint32_t)(((uint64_t)qy * nc) >> cd.K);
+  const uint32_t cz = (uint32_t)(((uint64_t)qz * nc) >> cd.K);
+  const uint32_t id = cd.cell_base + (cz * (uint32_t)nc + cy) * (uint32_t)nc + cx;
+  cell[i] = id;
+  qtmp[i] = make_uint4(qx << cd.sh, qy << cd.sh, qz << cd.sh, __float_as_uint((float)pw));
+  atomicAdd(&hist[id], 1u);
+}
+
+// Exclusive scan, stage 1: each block of 1024 threads scans 4096 entries.
+constexpr int kScanThreads = 1024;
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_blocks(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
+                                                             uint32_t* __restrict__ block_sum, uint32_t n) {
+  __shared__ uint32_t wsum[kScanThreads / 64];
+  const uint32_t base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+  uint32_t v[kScanItems];
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    v[k] = base + k < n ? in[base + k] : 0u;
+    s += v[k];
+  }
+  // inclusive scan of per-thread sums within the wave
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint32_t incl = s;
+  for (int off = 1; off < 64; off <<= 1) {
+    uint32_t t = __shfl_up(incl, off);
+    if (lane >= off) incl += t;
+  }
+  if (lane == 63) wsum[wv] = incl;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (int k = 0; k < kScanThreads / 64; ++k) {
+      uint32_t t = wsum[k];
+      wsum[k] = run;
+      run += t;
+    }
+    block_sum[blockIdx.x] = run;
+  }
+  __syncthreads();
+  uint32_t excl = incl - s + wsum[wv];
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    if (base + k < n) out[base + k] = excl;
+    excl += v[k];
+  }
+}
+
+// Stage 2: one block scans the block sums (any count) in place, exclusive.
+__global__ __launch_bounds__(64) void k_scan_sums(uint32_t* __restrict__ sums, uint32_t nblocks) {
+  uint32_t carry = 0;
+  for (uint32_t base = 0; base < nblocks; base += 64) {
+    const uint32_t i = base + threadIdx.x;
+    const uint32_t v = i < nblocks ? sums[i] : 0u;
+    uint32_t incl = v;
+    for (int off = 1; off < 64; off <<= 1) {
+      uint32_t t = __shfl_up(incl, off);
+      if ((int)threadIdx.x >= off) incl += t;
+    }
+    if (i < nblocks) sums[i] = carry + incl - v;
+    carry += __shfl(incl, 63);
+  }
+}
+
+// Stage 3: add block offsets; the entry past the last cell receives the total.
+__global__ void k_scan_add(uint32_t* __restrict__ out, const uint32_t* __restrict__ block_off, uint32_t n,
+                           uint32_t total) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] += block_off[i / kScanTile];
+  if (i == 0) out[n] = total;
+}
+
+__global__ void k_scatter(const uint32_t* __restrict__ cell, const uint32_t* __restrict__ cell_start,
+                          uint32_t* __restrict__ hist, uint32_t* __restrict__ slot_idx, uint32_t n) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t c = cell[i];
+  const uint32_t k = atomicSub(&hist[c], 1u) - 1u;
+  slot_idx[cell_start[c] + k] = i;
+}
+
+// One wavefront per cell: rank every entry by its input index (cells of up to kCellSortMax
+// points; larger cells keep the scatter order).
+__global__ __launch_bounds__(64) void k_cellsort(const uint32_t* __restrict__ cell_start,
+                                                 const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
+                                                 uint32_t ncell) {
+  const uint32_t c = blockIdx.x;
+  if (c >= ncell) return;
+  const uint32_t beg = cell_start[c], end = cell_start[c + 1];
+  const uint32_t n = end - beg;
+  if (n <= 1 || n > (uint32_t)kCellSortMax) {
+    for (uint32_t k = threadIdx.x; k < n; k += 64) out[beg + k] = in[beg + k];
+    return;
+  }
+  for (uint32_t k = threadIdx.x; k < n; k += 64) {
+    const uint32_t v = in[beg + k];
+    uint32_t rank = 0;
+    for (uint32_t m = 0; m < n; ++m) rank += in[beg + m] < v ? 1u : 0u;
+    out[beg + rank] = v;
+  }
+}
+
+__global__ void k_gather(const uint32_t* __restrict__ order, const uint4* __restrict__ qtmp,
+                         const double* __restrict__ w, uint4* __restrict__ rec, double* __restrict__ w64,
+                         uint32_t* __restrict__ perm, uint32_t n) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const uint32_t i = order[s];
+  rec[s] = qtmp[i];
+  w64[s] = w ? w[i] : 1.0;
+  perm[s] = i;
+}
+
+// Validation of device-resident inputs: bit 1 non-finite value, bit 2 non-periodic point outside
+// [0, box), bit 4 periodic coordinate beyond 2^20 box sides.
+__global__ void k_validate(const double* __restrict__ x, const double* __restrict__ y,
+                           const double* __restrict__ z, const double* __restrict__ w, uint32_t n,
+                           const CatDesc* __restrict__ cats, int ncat, int* __restrict__ err) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const CatDesc& cd = cats[cat_of_point(cats, ncat, i)];
+  const double px = x[i], py = y[i], pz = z[i], pw = w ? w[i] : 1.0;
+  int bad = 0;
+  if (!isfinite(px) || !isfinite(py) || !isfinite(pz) || !isfinite(pw)) bad |= 1;
+  else if (cd.periodic) {
+    const double lim = cd.box * 1048576.0;
+    if (fabs(px) > lim || fabs(py) > lim || fabs(pz) > lim) bad |= 4;
+  } else if (px < 0.0 || px >= cd.box || py < 0.0 || py >= cd.box || pz < 0.0 || pz >= cd.box) {
+    bad |= 2;
+  }
+  if (bad) atomicOr(err, bad);
+}
+
+__global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t v, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void k_fill_f64(double* __restrict__ p, double v, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// ------------------------------------------------------------------------------------------
+// Host launchers (stream-ordered, no synchronisation, no memset nodes: safe under capture).
+// ------------------------------------------------------------------------------------------
+static inline unsigned blocks_for(size_t n, unsigned t) { return (unsigned)((n + t - 1) / t); }
+
+void fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s) {
+  if (n) hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, v, n);
+}
+void fill_f64(double* p, double v, size_t n, hipStream_t s) {
+  if (n) hipLaunchKernelGGL(k_fill_f64, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, v, n);
+}
+
+void validate_inputs(const double* x, const double* y, const double* z, const double* w, uint32_t n,
+                     const CatDesc* cats, int ncat, int* err, hipStream_t s) {
+  if (n) hipLaunchKernelGGL(k_validate, dim3(blocks_for(n, 256)), dim3(256), 0, s, x, y, z, w, n, cats, ncat, err);
+}
+
+size_t scan_block_count(uint32_t ncell) { return (ncell + kScanTile - 1) / kScanTile; }
+
+// Builds the cell-sorted layout. Buffers: qtmp[n], cell[n], hist[ncell], idx_a[n], idx_b[n],
+// block_sum[scan_block_count(ncell)], err[1] (all device). Outputs: cell_start[ncell+1],
+// rec[n], w64[n], perm[n].
+hipError_t build_grid(const double* x, const double* y, const double* z, const double* w, uint32_t n,
+                      const CatDesc* cats, int ncat, uint32_t ncell, uint4* qtmp, uint32_t* cell,
+                      uint32_t* hist, uint32_t* idx_a, uint32_t* idx_b, uint32_t* block_sum, int* err,
+                      uint32_t* cell_start, uint4* rec, double* w64, uint32_t* perm, hipStream_t s) {
+  fill_u32(hist, 0u, ncell, s);
+  if (n)
+    hipLaunchKernelGGL(k_snap, dim3(blocks_for(n, 256)), dim3(256), 0, s, x, y, z, w, n, cats, ncat, qtmp,
+                       cell, hist, err);
+  const uint32_t nb = (uint32_t)scan_block_count(ncell);
+  hipLaunchKernelGGL(k_scan_blocks, dim3(nb), dim3(kScanThreads), 0, s, hist, cell_start, block_sum, ncell);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(64), 0, s, block_sum, nb);
+  hipLaunchKernelGGL(k_scan_add, dim3(blocks_for(ncell + 1, 256)), dim3(256), 0, s, cell_start, block_sum,
+                     ncell, n);
+  if (n) {
+    hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, s, cell, cell_start, hist, idx_a, n);
+    hipLaunchKernelGGL(k_cellsort, dim3(ncell), dim3(64), 0, s, cell_start, idx_a, idx_b, ncell);
+    hipLaunchKernelGGL(k_gather, dim3(blocks_for(n, 256)), dim3(256), 0, s, idx_b, qtmp, w, rec, w64, perm, n);
+  }
+  return hipGetLastError();
+}
+
+// Copies per-primary debug rows from sorted to input order and widens them to int64 / FP64.
+__global__ void k_unsort_counts(const int32_t* __restrict__ in, const uint32_t* __restrict__ perm,
+                                int64_t* __restrict__ out, uint32_t n, int nb) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)n * nb) return;
+  const uint32_t s = (uint32_t)(i / nb);
+  const int b = (int)(i % nb);
+  out[(size_t)perm[s] * nb + b] = in[i];
+}
+template <class T>
+__global__ void k_unsort_alm(const T* __restrict__ in, const uint32_t* __restrict__ perm,
+                             double* __restrict__ out, uint32_t n, int row) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)n * row) return;
+  const uint32_t s = (uint32_t)(i / row);
+  const int k = (int)(i % row);
+  out[(size_t)perm[s] * row + k] = (double)in[i];
+}
+
+void unsort_counts(const int32_t* in, const uint32_t* perm, int64_t* out, uint32_t n, int nb, hipStream_t s) {
+  const size_t tot = (size_t)n * nb;
+  if (tot) hipLaunchKernelGGL(k_unsort_counts, dim3(blocks_for(tot, 256)), dim3(256), 0, s, in, perm, out, n, nb);
+}
+void unsort_alm(const void* in, bool f64, const uint32_t* perm, double* out, uint32_t n, int row, hipStream_t s) {
+  const size_t tot = (size_t)n * row;
+  if (!tot) return;
+  if (f64)
+    hipLaunchKernelGGL(k_unsort_alm<double>, dim3(blocks_for(tot, 256)), dim3(256), 0, s,
+                       (const double*)in, perm, out, n, row);
+  else
+    hipLaunchKernelGGL(k_unsort_alm<float>, dim3(blocks_for(tot, 256)), dim3(256), 0, s,
+                       (const float*)in, perm, out, n, row);
+}
+
+}  // namespace tpcf

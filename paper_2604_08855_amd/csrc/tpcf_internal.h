@@ -1,0 +1,69 @@
+// tpcf_internal.h -- structures shared by the host side of the library and its gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tpcf {
+
+constexpr int kMaxBins = 32;   // bucket layout and the 32x32 MFMA output tile
+constexpr int kMaxLmax = 10;
+constexpr int kBucketCap = 128;  // per-bin LDS bucket: < 64 carried over + <= 64 new per round
+constexpr int kBlock = 64;       // secondaries per scratch block = one wavefront round
+constexpr int kTileF32 = 32;     // primaries per contraction tile, mixed precision
+constexpr int kTileF64 = 16;     // primaries per contraction tile, FP64
+
+// One catalogue as the kernels see it. Points of catalogue c occupy sorted positions
+// [point_base, point_base + npoints) of the concatenated arrays; its cells occupy
+// [cell_base, cell_base + nc^3] of cell_start (cell_start has one extra end entry per catalogue).
+struct CatDesc {
+  uint32_t point_base;
+  uint32_t npoints;
+  uint32_t cell_base;    // index of this catalogue's first cell_start entry
+  int32_t nc;            // cells per axis
+  int32_t K;             // lattice bits: coordinates are integers in [0, 2^K)
+  int32_t sh;            // stored coordinate = q << sh (32-K when periodic, else 0)
+  int32_t periodic;
+  int32_t stencil_base;  // first entry of this catalogue's stencil rows
+  int32_t nstencil;
+  int32_t pad_;
+  double box;
+  double scale;          // 2^K / box
+  double T[kMaxBins + 1];  // exact integer squared-separation thresholds (lattice units)
+  float rmin_l;          // r_min in lattice units (FP32, first guess of the bin only)
+  float inv_delta_l;     // 1 / bin width in lattice units
+};
+
+// One stencil row: all cells at (dy, dz) from the primary cell with |dx| <= half (or the whole
+// x row when full != 0).
+struct StencilRow {
+  int32_t dy, dz, half, full;
+};
+
+// Arguments of the persistent sweep kernel.
+struct SweepArgs {
+  const uint4* rec;             // sorted records: (Qx, Qy, Qz, float bits of w)
+  const double* w64;            // sorted FP64 weights
+  const uint32_t* cell_start;   // per catalogue nc^3 + 1 entries
+  const StencilRow* stencil;
+  const CatDesc* cats;
+  int32_t ncat;
+  int32_t nb;
+  const uint32_t* task_list;    // NULL: task t is sorted position t
+  uint32_t ntask;
+  uint32_t* queue;              // [0] task ticket counter
+  uint32_t* scratch;            // per-wave blocks of 64 sorted positions
+  int32_t scratch_blocks;       // blocks per wave
+  void* tile;                   // per-wave a_lm tile area
+  double* zeta;                 // [ncat][(lmax+1)][nb][nb]
+  int32_t* counts;              // optional [total points][nb], by sorted position
+  void* alm_debug;              // optional [total points][nb][NC] (float or double), by sorted position
+  unsigned long long* stats;    // [0] pairs, [1] candidates
+  const float* cscale32;        // normalisation constant per real component
+  const double* cscale64;
+};
+
+// Components per primary and bin: (lmax+1)^2 real numbers.
+__host__ __device__ constexpr int ncomp(int lmax) { return (lmax + 1) * (lmax + 1); }
+
+}  // namespace tpcf

@@ -1,0 +1,130 @@
+"""C-ABI checks that need no GPU: the library loads, exports every declared function, and every
+argument error that the host can detect comes back as the documented status code without a
+device call."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import paper_2604_08855_amd as tpcf
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tpcf.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tpcf_[a-z_]+)\s*\(", text)))
+
+
+def test_header_and_binding_agree():
+    assert declared_functions() == sorted(tpcf.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    out = subprocess.check_output(["nm", "-D", "--defined-only", tpcf.library_path()]).decode()
+    names = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    missing = [f for f in declared_functions() if f not in names]
+    assert not missing, missing
+    assert sorted(tpcf.exported_symbols()) == declared_functions()
+    assert "gfx950" in tpcf.version()
+
+
+def _ctx():
+    return tpcf.Context(device=0, stream=None)
+
+
+def _code(fn, *a, **k):
+    with pytest.raises(tpcf.TpcfError) as e:
+        fn(*a, **k)
+    return e.value.code
+
+
+def test_set_bins_validation():
+    c = _ctx()
+    assert _code(c.set_bins, 0, 1.0, 2.0, 2) == 1
+    assert _code(c.set_bins, 33, 1.0, 2.0, 2) == 1
+    assert _code(c.set_bins, 4, -1.0, 2.0, 2) == 1
+    assert _code(c.set_bins, 4, 2.0, 2.0, 2) == 1
+    assert _code(c.set_bins, 4, 1.0, float("nan"), 2) == 1
+    assert _code(c.set_bins, 4, 1.0, float("inf"), 2) == 1
+    assert _code(c.set_bins, 4, 1.0, 2.0, -1) == 1
+    assert _code(c.set_bins, 4, 1.0, 2.0, 11) == 1
+    c.set_bins(4, 0.0, 2.0, 10)  # valid: rmin = 0, lmax = 10, nbins = 32 below
+    c.set_bins(32, 1.0, 2.0, 0)
+
+
+def test_precision_and_tuning_validation():
+    c = _ctx()
+    assert _code(c.set_precision, 7) == 1
+    c.set_precision("mixed")
+    c.set_precision("fp64")
+    assert _code(c.set_tuning, -1.0, 0, 0) == 1
+    assert _code(c.set_tuning, 0.0, -2, 0) == 1
+    assert _code(c.set_tuning, 0.0, 0, 100) == 1  # not a multiple of 64
+    c.set_tuning(20.0, 4, 256)
+
+
+def test_compute_before_setup_is_a_state_error():
+    c = _ctx()
+    out = np.zeros(1)
+    rc = tpcf._lib.tpcf_compute_zeta(c._h, out.ctypes.data_as(ctypes.c_void_p), 0)
+    assert rc == 2
+    assert "set_bins" in tpcf._lib.tpcf_last_error(c._h).decode()
+    c.set_bins(4, 1.0, 10.0, 2)
+    rc = tpcf._lib.tpcf_compute_zeta(c._h, out.ctypes.data_as(ctypes.c_void_p), 0)
+    assert rc == 2
+    rc = tpcf._lib.tpcf_compute_zeta_range(c._h, 0, 1, out.ctypes.data_as(ctypes.c_void_p), 0)
+    assert rc == 2
+    rc = tpcf._lib.tpcf_debug_pair_counts(c._h, out.ctypes.data_as(ctypes.c_void_p))
+    assert rc == 2
+
+
+def test_catalog_validation_on_host():
+    c = _ctx()
+    c.set_bins(4, 1.0, 10.0, 2)
+    x = np.array([1.0, 2.0, 3.0])
+    assert _code(c.set_catalog, x, x, x, box=0.0) == 1
+    assert _code(c.set_catalog, x, x, x, box=float("inf")) == 1
+    assert _code(c.set_catalog, np.array([1.0, np.nan, 2.0]), x, x, box=50.0) == 1
+    assert _code(c.set_catalog, x, x, x, np.array([1.0, np.inf, 1.0]), box=50.0) == 1
+    # periodic needs rmax < box/2
+    assert _code(c.set_catalog, x, x, x, box=19.0, periodic=True) == 1
+    # non-periodic points must lie in [0, box)
+    assert _code(c.set_catalog, np.array([1.0, 2.0, 50.0]), x, x, box=50.0, periodic=False) == 1
+    assert _code(c.set_catalog, np.array([1.0, -1e-9, 3.0]), x, x, box=50.0, periodic=False) == 1
+    assert _code(c.set_catalog, np.array([1e9, 2.0, 3.0]), x, x, box=50.0, periodic=True) == 1
+    assert _code(c.set_catalog, np.array([1.0, np.nan, 2.0]), x, x, box=50.0) == 1
+    assert "non-finite" in tpcf._lib.tpcf_last_error(c._h).decode()
+    # raw ABI: negative n and NULL arrays
+    rc = tpcf._lib.tpcf_set_catalog(c._h, -1, None, None, None, None, 50.0, 1, 0)
+    assert rc == 1
+    rc = tpcf._lib.tpcf_set_catalog(c._h, 3, None, None, None, None, 50.0, 1, 0)
+    assert rc == 1
+    rc = tpcf._lib.tpcf_set_catalog(c._h, 3, None, None, None, None, 50.0, 1, 9)
+    assert rc == 1
+
+
+def test_batch_validation_on_host():
+    c = _ctx()
+    c.set_bins(4, 1.0, 10.0, 2)
+    x = np.arange(6, dtype=np.float64)
+    with pytest.raises(tpcf.TpcfError) as e:
+        c.compute_batch([0, 4, 3], x, x, x, None, 50.0, True)
+    assert e.value.code == 1
+    with pytest.raises(tpcf.TpcfError) as e:
+        c.compute_batch([1, 3, 6], x, x, x, None, 50.0, True)
+    assert e.value.code == 1
+    with pytest.raises(tpcf.TpcfError) as e:
+        c.compute_batch([0, 3, 6], x, x, x, None, [50.0, 15.0], True)  # second box too small
+    assert e.value.code == 1
+
+
+def test_null_context_is_rejected():
+    assert tpcf._lib.tpcf_set_bins(None, 4, 1.0, 2.0, 2) == 1
+    assert tpcf._lib.tpcf_last_error(None) is not None
+    tpcf._lib.tpcf_destroy(None)

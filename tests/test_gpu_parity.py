@@ -1,0 +1,177 @@
+"""GPU parity: the HIP path against the FP64 oracle on identical seeded inputs.
+
+Bars (floating point): FP64 path max|zeta_l - oracle_l| <= 1e-10 * max|oracle_l| per l; mixed
+path <= 1e-5 * max|oracle_l| per l. Integer per-primary per-bin pair counts are bit-exact.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import catalogs
+import oracle
+from tests.gpu_util import rel_err_per_l, say
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-10, "mixed": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def tpcf():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2604_08855_amd as mod
+
+    return mod
+
+
+def run_gpu(tpcf, cat, w, nb, rmin, rmax, lmax, prec, debug=False, tuning=None, prange=None):
+    ctx = tpcf.Context(0)
+    ctx.set_bins(nb, rmin, rmax, lmax)
+    ctx.set_precision(prec)
+    if tuning:
+        ctx.set_tuning(*tuning)
+    ctx.set_debug(debug)
+    ctx.set_catalog(cat.x, cat.y, cat.z, w, box=cat.box, periodic=cat.periodic)
+    z = ctx.compute_zeta() if prange is None else ctx.compute_zeta_range(*prange)
+    return ctx, z
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_small_config_full_parity(tpcf, prec):
+    """10,000 uniform points, periodic box 250, 10 bins [5, 50), l_max = 4."""
+    cat = catalogs.uniform(10000, 250.0, 0)
+    say(f"small config n=10000 prec={prec}")
+    ctx, z = run_gpu(tpcf, cat, None, 10, 5.0, 50.0, 4, prec, debug=True)
+    ref = oracle.zeta_catalog(cat, 10, 5.0, 50.0, 4, want_counts=True)
+    err = rel_err_per_l(z, ref.zeta)
+    say("rel err per l", err)
+    assert err.max() <= TOL[prec]
+    np.testing.assert_array_equal(ctx.pair_counts(), ref.counts)
+    st = ctx.stats()
+    assert st["n_pairs"] == ref.npairs
+    assert st["n_candidates"] >= st["n_pairs"]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("periodic", [True, False])
+def test_weighted_lmax10_parity(tpcf, prec, periodic):
+    """Several tiles and a ragged tail: 3,001 points, 20 bins, l_max = 10, signed weights."""
+    cat = catalogs.uniform(3001, 160.0, 7)
+    cat.periodic = periodic
+    w = catalogs.gaussian_weights(cat.n, 8, 0.3, 1.0)
+    say(f"weighted lmax10 periodic={periodic} prec={prec}")
+    ctx, z = run_gpu(tpcf, cat, w, 20, 3.0, 45.0, 10, prec, debug=True)
+    ref = oracle.zeta(cat.x, cat.y, cat.z, w, cat.box, periodic, 20, 3.0, 45.0, 10, want_counts=True)
+    err = rel_err_per_l(z, ref.zeta)
+    say("rel err per l", err)
+    assert err.max() <= TOL[prec]
+    np.testing.assert_array_equal(ctx.pair_counts(), ref.counts)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_alm_against_oracle(tpcf, prec):
+    cat = catalogs.uniform(700, 60.0, 3)
+    w = catalogs.gaussian_weights(cat.n, 4)
+    L, nb = 10, 5
+    say(f"a_lm parity prec={prec}")
+    ctx, _ = run_gpu(tpcf, cat, w, nb, 2.0, 20.0, L, prec, debug=True)
+    a = ctx.alm()  # [n, nb, l, m]
+    ref = oracle.zeta(cat.x, cat.y, cat.z, w, cat.box, True, nb, 2.0, 20.0, L, want_alm=True).alm
+    tol = 1e-11 if prec == "fp64" else 2e-6
+    for l in range(L + 1):
+        for m in range(l + 1):
+            r = ref[:, :, l * l + l + m]
+            scale = max(np.abs(r).max(), 1e-300)
+            assert np.abs(a[:, :, l, m] - r).max() / scale < tol, (l, m)
+
+
+@pytest.mark.parametrize("lmax", list(range(0, 11)))
+def test_every_lmax(tpcf, lmax):
+    cat = catalogs.uniform(900, 80.0, 20 + lmax)
+    w = catalogs.gaussian_weights(cat.n, 40 + lmax)
+    ref = oracle.zeta(cat.x, cat.y, cat.z, w, cat.box, True, 7, 2.0, 30.0, lmax).zeta
+    for prec in ("fp64", "mixed"):
+        _, z = run_gpu(tpcf, cat, w, 7, 2.0, 30.0, lmax, prec)
+        assert rel_err_per_l(z, ref).max() <= TOL[prec], (lmax, prec)
+
+
+@pytest.mark.parametrize("nb", [1, 2, 16, 17, 32])
+def test_bin_counts(tpcf, nb):
+    cat = catalogs.uniform(1200, 70.0, 30 + nb)
+    ref = oracle.zeta(cat.x, cat.y, cat.z, None, cat.box, True, nb, 1.0, 30.0, 3, want_counts=True)
+    for prec in ("fp64", "mixed"):
+        ctx, z = run_gpu(tpcf, cat, None, nb, 1.0, 30.0, 3, prec, debug=True)
+        assert rel_err_per_l(z, ref.zeta).max() <= TOL[prec]
+        np.testing.assert_array_equal(ctx.pair_counts(), ref.counts)
+
+
+def test_degenerate_inputs(tpcf):
+    for n in (0, 1):
+        cat = catalogs.uniform(n, 50.0, 1)
+        for prec in ("fp64", "mixed"):
+            _, z = run_gpu(tpcf, cat, None, 4, 1.0, 10.0, 4, prec)
+            assert z.shape == (5, 4, 4) and not z.any()
+    # coincident points with r_min = 0: no direction, no pair
+    c = catalogs.Catalog(np.array([5.0, 5.0]), np.array([5.0, 5.0]), np.array([5.0, 5.0]), np.ones(2), 50.0, True)
+    ctx, z = run_gpu(tpcf, c, None, 4, 0.0, 10.0, 2, "fp64", debug=True)
+    assert not z.any() and ctx.stats()["n_pairs"] == 0
+
+
+def test_exact_bin_edges(tpcf):
+    box, K = 256.0, 27
+    s = box / 2**K
+    x0 = 100.0 + 0.5 * s
+    xs = np.array([x0, x0 + 16.0, x0 + 16.0 - s, x0 + 64.0, x0 + 8.0, x0 - 24.0, x0 - 24.0 + s])
+    ys = np.full(xs.shape, 50.0 + 0.5 * s)
+    c = catalogs.Catalog(xs, ys, ys, np.ones(len(xs)), box, True)
+    ref = oracle.zeta(xs, ys, ys, None, box, True, 7, 8.0, 64.0, 2, want_counts=True)
+    for prec in ("fp64", "mixed"):
+        ctx, z = run_gpu(tpcf, c, None, 7, 8.0, 64.0, 2, prec, debug=True)
+        np.testing.assert_array_equal(ctx.pair_counts(), ref.counts)
+        assert rel_err_per_l(z, ref.zeta).max() <= TOL[prec]
+
+
+def test_primary_ranges_add_up(tpcf):
+    cat = catalogs.uniform(2500, 100.0, 51)
+    w = catalogs.gaussian_weights(cat.n, 52)
+    args = (w, 6, 2.0, 30.0, 6, "fp64")
+    _, full = run_gpu(tpcf, cat, *args)
+    _, a = run_gpu(tpcf, cat, *args, prange=(0, 1111))
+    _, b = run_gpu(tpcf, cat, *args, prange=(1111, 2500))
+    assert rel_err_per_l(a + b, full).max() < 1e-12
+    ref = oracle.zeta(cat.x, cat.y, cat.z, w, cat.box, True, 6, 2.0, 30.0, 6, 0, 1111).zeta
+    assert rel_err_per_l(a, ref).max() < 1e-10
+
+
+@pytest.mark.parametrize("tuning", [(5.0, 1, 64), (80.0, 3, 128), (2.0, 8, 4096)])
+def test_tuning_does_not_change_results(tpcf, tuning):
+    """Small cells, large cells, a tiny scratch area (forces shells flushed in several chunks)."""
+    cat = catalogs.lognormal(4000, 200.0, 9, grid=32)
+    w = catalogs.gaussian_weights(cat.n, 10)
+    ref = oracle.zeta(cat.x, cat.y, cat.z, w, cat.box, True, 12, 5.0, 60.0, 8, want_counts=True)
+    for prec in ("fp64", "mixed"):
+        ctx, z = run_gpu(tpcf, cat, w, 12, 5.0, 60.0, 8, prec, debug=True, tuning=tuning)
+        assert rel_err_per_l(z, ref.zeta).max() <= TOL[prec], (tuning, prec)
+        np.testing.assert_array_equal(ctx.pair_counts(), ref.counts)
+
+
+def test_device_tensors_in_and_out(tpcf):
+    import torch
+
+    cat = catalogs.uniform(2000, 90.0, 61)
+    w = catalogs.gaussian_weights(cat.n, 62)
+    t = [torch.from_numpy(a).cuda() for a in (cat.x, cat.y, cat.z, w)]
+    z = tpcf.zeta(*t, box=cat.box, periodic=True, rmin=2.0, rmax=25.0, nbins=6, lmax=5,
+                  precision="mixed")
+    assert z.is_cuda and z.dtype == torch.float64
+    ref = oracle.zeta(cat.x, cat.y, cat.z, w, cat.box, True, 6, 2.0, 25.0, 5).zeta
+    assert rel_err_per_l(z.cpu().numpy(), ref).max() <= 1e-5
+    # invalid device data is reported, not computed
+    bad = t[0].clone()
+    bad[17] = float("nan")
+    with pytest.raises(tpcf.TpcfError) as e:
+        tpcf.zeta(bad, t[1], t[2], box=cat.box, periodic=True, rmin=2.0, rmax=25.0, nbins=6, lmax=5)
+    assert e.value.code == 1
