@@ -78,8 +78,9 @@ const char* tpcf_version(void);
 
 /*
  * Creates a context on HIP device `device` using stream `hip_stream` (a hipStream_t; NULL means
- * the default stream). The device is first touched by the first call that needs it, so a
- * context can be created and configured on a machine without a GPU.
+ * the null stream). Every device operation of the context is ordered on that stream. The device
+ * is first touched by the first call that needs it, so a context can be created and configured
+ * on a machine without a GPU.
  * Errors: TPCF_E_INVALID_ARG if out is NULL or device < 0; TPCF_E_OUT_OF_MEMORY.
  */
 int tpcf_create(tpcf_ctx** out, int device, void* hip_stream);
@@ -145,8 +146,10 @@ int tpcf_compute_zeta_range(tpcf_ctx* ctx, int64_t p_begin, int64_t p_end, doubl
  * side is box_side[c] and periodic flag periodic[c]. offsets, box_side and periodic are host
  * arrays; x, y, z, w live in `memspace`; zeta receives [ncat][(lmax+1)][nbins][nbins] doubles in
  * `memspace`. Catalogues never interact. The batch replaces the catalogue set by
- * tpcf_set_catalog. The launch sequence is captured in a HIP graph on first use for a given
- * batch shape and replayed afterwards.
+ * tpcf_set_catalog. On a non-null stream the device sequence (grid build, clears, persistent
+ * sweep) is captured in a HIP graph on first use for a given batch shape and replayed by later
+ * calls of the same shape (environment TPCF_GRAPH=0 disables this); stats then report the
+ * whole graph as ms_sweep.
  * Errors: TPCF_E_INVALID_ARG (ncat < 1, offsets not non-decreasing from 0, total points >= 2^31,
  * any per-catalogue error of tpcf_set_catalog), TPCF_E_STATE, TPCF_E_OUT_OF_MEMORY,
  * TPCF_E_DEVICE.

@@ -169,10 +169,6 @@ int ensure_device(tpcf_ctx* c) {
   HIP_TRY(c, hipGetDeviceProperties(&prop, c->device));
   c->ncu = prop.multiProcessorCount;
   c->lds_per_block = prop.sharedMemPerBlock;
-  if (!c->stream) {
-    HIP_TRY(c, hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
-    c->own_stream = true;
-  }
   for (auto& e : c->ev) HIP_TRY(c, hipEventCreate(&e));
   c->dev_ready = true;
   return TPCF_OK;
@@ -387,10 +383,13 @@ int stage(tpcf_ctx* c, const std::vector<HostCat>& cats, int64_t ntot, const dou
   return TPCF_OK;
 }
 
-int ensure_grid(tpcf_ctx* c) {
-  if (c->grid_valid && c->grid_rmax == c->rmax && c->grid_rmin == c->rmin && c->grid_ppc == c->ppc &&
-      c->grid_nb == c->nbins)
-    return TPCF_OK;
+bool grid_current(const tpcf_ctx* c) {
+  return c->grid_valid && c->grid_rmax == c->rmax && c->grid_rmin == c->rmin && c->grid_ppc == c->ppc &&
+         c->grid_nb == c->nbins;
+}
+
+// Host part of the grid build: grid geometry, stencil rows, buffers, tables on the device.
+int prepare_grid(tpcf_ctx* c) {
   int rc;
   if ((rc = configure_grid(c))) return rc;
   const size_t n = (size_t)c->ntot;
@@ -410,29 +409,37 @@ int ensure_grid(tpcf_ctx* c) {
   if (!c->st.empty())
     HIP_TRY(c, hipMemcpyAsync(c->stencil_d.p, c->st.data(), c->st.size() * sizeof(StencilRow),
                               hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(c, hipEventRecord(c->ev[0], c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return TPCF_OK;
+}
+
+// Device part of the grid build (stream-ordered kernels only).
+int record_grid(tpcf_ctx* c) {
   HIP_TRY(c, build_grid((const double*)c->sx.p, (const double*)c->sy.p, (const double*)c->sz.p,
-                        c->have_w ? (const double*)c->sw.p : nullptr, (uint32_t)n, (const CatDesc*)c->cats_d.p,
-                        (int)c->cd.size(), c->ncell, (uint4*)c->qtmp.p, (uint32_t*)c->cellid.p,
-                        (uint32_t*)c->hist.p, (uint32_t*)c->idx_a.p, (uint32_t*)c->idx_b.p, (uint32_t*)c->bsum.p,
-                        (int*)c->errflag.p, (uint32_t*)c->cell_start.p, (uint4*)c->rec.p, (double*)c->w64.p,
-                        (uint32_t*)c->perm.p, c->stream));
-  HIP_TRY(c, hipEventRecord(c->ev[1], c->stream));
+                        c->have_w ? (const double*)c->sw.p : nullptr, (uint32_t)c->ntot,
+                        (const CatDesc*)c->cats_d.p, (int)c->cd.size(), c->ncell, (uint4*)c->qtmp.p,
+                        (uint32_t*)c->cellid.p, (uint32_t*)c->hist.p, (uint32_t*)c->idx_a.p,
+                        (uint32_t*)c->idx_b.p, (uint32_t*)c->bsum.p, (int*)c->errflag.p,
+                        (uint32_t*)c->cell_start.p, (uint4*)c->rec.p, (double*)c->w64.p, (uint32_t*)c->perm.p,
+                        c->stream));
+  return TPCF_OK;
+}
+
+void mark_grid(tpcf_ctx* c) {
   c->grid_valid = true;
   c->grid_rmax = c->rmax;
   c->grid_rmin = c->rmin;
   c->grid_ppc = c->ppc;
   c->grid_nb = c->nbins;
-  return TPCF_OK;
 }
 
-// Runs the sweep for the task list (nullptr = all points) and leaves zeta in zeta_d.
-int run_sweep(tpcf_ctx* c, const uint32_t* tasks_d, uint32_t ntask) {
+// Host part of the sweep: buffers, normalisation constants and the kernel arguments.
+int prepare_sweep(tpcf_ctx* c, const uint32_t* tasks_d, uint32_t ntask, SweepArgs& a, int& waves) {
   const bool f64 = c->precision == TPCF_PREC_FP64;
   const int nb = c->nbins, L = c->lmax, NC = (L + 1) * (L + 1);
   const int ncat = (int)c->cd.size();
-  int waves = std::max(1, c->ncu * c->waves_per_cu);
-  if ((uint32_t)waves > ntask) waves = std::max<uint32_t>(1, ntask);
+  waves = std::max(1, c->ncu * c->waves_per_cu);
+  if ((uint32_t)waves > ntask) waves = (int)std::max<uint32_t>(1, ntask);
   const int S = c->scratch_blocks;
   int rc;
   const size_t lds = sweep_lds_bytes(S, nb);
@@ -456,14 +463,7 @@ int run_sweep(tpcf_ctx* c, const uint32_t* tasks_d, uint32_t ntask) {
     if ((rc = ensure(c, c->counts32, (size_t)c->ntot * nb * 4, "debug counts")) ||
         (rc = ensure(c, c->alm_dbg, (size_t)c->ntot * nb * NC * (f64 ? 8 : 4), "debug a_lm")))
       return rc;
-    fill_u32((uint32_t*)c->counts32.p, 0u, (size_t)c->ntot * nb, c->stream);
-    fill_u32((uint32_t*)c->alm_dbg.p, 0u, (size_t)c->ntot * nb * NC * (f64 ? 2 : 1), c->stream);
   }
-  fill_f64((double*)c->zeta_d.p, 0.0, (size_t)ncat * (L + 1) * nb * nb, c->stream);
-  fill_u32((uint32_t*)c->queue.p, 0u, 4, c->stream);
-  fill_u32((uint32_t*)c->stats_d.p, 0u, 4, c->stream);
-
-  SweepArgs a;
   memset(&a, 0, sizeof(a));
   a.rec = (const uint4*)c->rec.p;
   a.w64 = (const double*)c->w64.p;
@@ -484,10 +484,21 @@ int run_sweep(tpcf_ctx* c, const uint32_t* tasks_d, uint32_t ntask) {
   a.stats = (unsigned long long*)c->stats_d.p;
   a.cscale32 = (const float*)c->cscale32.p;
   a.cscale64 = (const double*)c->cscale64.p;
-  HIP_TRY(c, hipEventRecord(c->ev[2], c->stream));
-  if (ntask > 0) HIP_TRY(c, launch_sweep(L, f64, a, waves, c->stream));
-  HIP_TRY(c, hipEventRecord(c->ev[3], c->stream));
-  c->stats.waves = waves;
+  return TPCF_OK;
+}
+
+// Device part of the sweep: clears (fill kernels, never memset nodes) and the persistent launch.
+int record_sweep(tpcf_ctx* c, const SweepArgs& a, int waves) {
+  const bool f64 = c->precision == TPCF_PREC_FP64;
+  const int nb = c->nbins, L = c->lmax, NC = (L + 1) * (L + 1);
+  if (c->debug) {
+    fill_u32((uint32_t*)c->counts32.p, 0u, (size_t)c->ntot * nb, c->stream);
+    fill_u32((uint32_t*)c->alm_dbg.p, 0u, (size_t)c->ntot * nb * NC * (f64 ? 2 : 1), c->stream);
+  }
+  fill_f64((double*)c->zeta_d.p, 0.0, (size_t)a.ncat * (L + 1) * nb * nb, c->stream);
+  fill_u32((uint32_t*)c->queue.p, 0u, 4, c->stream);
+  fill_u32((uint32_t*)c->stats_d.p, 0u, 4, c->stream);
+  if (a.ntask > 0) HIP_TRY(c, launch_sweep(L, f64, a, waves, c->stream));
   return TPCF_OK;
 }
 
@@ -520,7 +531,31 @@ int copy_out(tpcf_ctx* c, double* zeta, size_t count, int memspace) {
   return TPCF_OK;
 }
 
-int compute(tpcf_ctx* c, int64_t p_begin, int64_t p_end, double* zeta, int memspace) {
+// Key of everything a captured batch graph depends on.
+std::string graph_key(const tpcf_ctx* c, const SweepArgs& a, int waves) {
+  std::string k;
+  auto add = [&](const void* p, size_t n) { k.append((const char*)p, n); };
+  add(&c->ntot, sizeof(c->ntot));
+  for (const HostCat& h : c->cats) add(&h, sizeof(h));
+  add(&c->nbins, sizeof(int));
+  add(&c->rmin, sizeof(double));
+  add(&c->rmax, sizeof(double));
+  add(&c->lmax, sizeof(int));
+  add(&c->precision, sizeof(int));
+  add(&c->ppc, sizeof(double));
+  add(&c->have_w, sizeof(bool));
+  add(&c->debug, sizeof(bool));
+  add(&a, sizeof(a));
+  add(&waves, sizeof(int));
+  return k;
+}
+
+bool graphs_enabled() {
+  const char* s = getenv("TPCF_GRAPH");
+  return !(s && s[0] == '0');
+}
+
+int compute(tpcf_ctx* c, int64_t p_begin, int64_t p_end, double* zeta, int memspace, bool use_graph) {
   if (!c) return TPCF_E_INVALID_ARG;
   if (!c->bins_set) return fail(c, TPCF_E_STATE, "set_bins has not been called");
   if (!c->cat_set) return fail(c, TPCF_E_STATE, "no catalogue set");
@@ -530,12 +565,16 @@ int compute(tpcf_ctx* c, int64_t p_begin, int64_t p_end, double* zeta, int memsp
   int rc;
   if ((rc = check_periodic_range(c))) return rc;
   if ((rc = ensure_device(c))) return rc;
-  const bool rebuilt = !c->grid_valid;
-  if ((rc = ensure_grid(c))) return rc;
+  const bool rebuild = !grid_current(c);
+  if (rebuild && (rc = prepare_grid(c))) return rc;
   const uint32_t* tasks = nullptr;
   uint32_t ntask = (uint32_t)c->ntot;
   if (p_begin != 0 || p_end != c->ntot) {
-    // primaries by input index -> sorted positions
+    // primaries by input index -> sorted positions (needs the grid: build it eagerly first)
+    if (rebuild) {
+      if ((rc = record_grid(c))) return rc;
+      mark_grid(c);
+    }
     std::vector<uint32_t> perm((size_t)c->ntot);
     if (c->ntot)
       HIP_TRY(c, hipMemcpyAsync(perm.data(), c->perm.p, (size_t)c->ntot * 4, hipMemcpyDeviceToHost, c->stream));
@@ -550,10 +589,60 @@ int compute(tpcf_ctx* c, int64_t p_begin, int64_t p_end, double* zeta, int memsp
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     tasks = (const uint32_t*)c->tasks.p;
   }
-  if ((rc = run_sweep(c, tasks, ntask))) return rc;
+  const bool grid_in_run = rebuild && !c->grid_valid;
+  SweepArgs a;
+  int waves = 0;
+  if ((rc = prepare_sweep(c, tasks, ntask, a, waves))) return rc;
+  c->stats.waves = waves;
+  // The null stream cannot be captured: batches on it launch eagerly.
+  const bool graph = use_graph && graphs_enabled() && c->stream != nullptr;
+  if (graph) {
+    // The whole device sequence (grid build + clears + persistent sweep) as one HIP graph,
+    // captured once per batch shape and replayed afterwards.
+    const std::string key = graph_key(c, a, waves) + (grid_in_run ? "g" : "-");
+    if (!c->gexec || key != c->gkey) {
+      if (c->gexec) {
+        (void)hipGraphExecDestroy(c->gexec);
+        c->gexec = nullptr;
+        c->gkey.clear();
+      }
+      hipGraph_t g = nullptr;
+      HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+      int rc1 = grid_in_run ? record_grid(c) : TPCF_OK;
+      int rc2 = rc1 ? rc1 : record_sweep(c, a, waves);
+      hipError_t e = hipStreamEndCapture(c->stream, &g);
+      if (rc2) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc2;
+      }
+      if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
+      e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) {
+        c->gexec = nullptr;
+        return hip_fail(c, e, "hipGraphInstantiate");
+      }
+      c->gkey = key;
+    }
+    HIP_TRY(c, hipEventRecord(c->ev[2], c->stream));
+    HIP_TRY(c, hipGraphLaunch(c->gexec, c->stream));
+    HIP_TRY(c, hipEventRecord(c->ev[3], c->stream));
+    if (grid_in_run) mark_grid(c);
+    c->stats.ms_grid = -1.0;
+  } else {
+    if (grid_in_run) {
+      HIP_TRY(c, hipEventRecord(c->ev[0], c->stream));
+      if ((rc = record_grid(c))) return rc;
+      HIP_TRY(c, hipEventRecord(c->ev[1], c->stream));
+      mark_grid(c);
+    }
+    HIP_TRY(c, hipEventRecord(c->ev[2], c->stream));
+    if ((rc = record_sweep(c, a, waves))) return rc;
+    HIP_TRY(c, hipEventRecord(c->ev[3], c->stream));
+  }
   const size_t cnt = (size_t)c->cd.size() * (c->lmax + 1) * c->nbins * c->nbins;
   if ((rc = copy_out(c, zeta, cnt, memspace))) return rc;
-  return finish_stats(c, rebuilt, ntask);
+  return finish_stats(c, grid_in_run && !graph, ntask);
 }
 
 }  // namespace
@@ -662,7 +751,7 @@ int tpcf_set_catalog(tpcf_ctx* c, int64_t n, const double* x, const double* y, c
 int tpcf_compute_zeta(tpcf_ctx* c, double* zeta, int memspace) {
   if (!c) return TPCF_E_INVALID_ARG;
   if (c->cat_set && c->cats.size() != 1) return fail(c, TPCF_E_STATE, "context holds a batch; use compute_batch");
-  int rc = compute(c, 0, c->ntot, zeta, memspace);
+  int rc = compute(c, 0, c->ntot, zeta, memspace, false);
   if (!rc) c->err.clear();
   return rc;
 }
@@ -673,7 +762,7 @@ int tpcf_compute_zeta_range(tpcf_ctx* c, int64_t p_begin, int64_t p_end, double*
   if (c->cats.size() != 1) return fail(c, TPCF_E_STATE, "context holds a batch; use compute_batch");
   if (p_begin < 0 || p_end > c->ntot || p_begin > p_end)
     return fail(c, TPCF_E_INVALID_ARG, "primary range outside [0, n]");
-  int rc = compute(c, p_begin, p_end, zeta, memspace);
+  int rc = compute(c, p_begin, p_end, zeta, memspace, false);
   if (!rc) c->err.clear();
   return rc;
 }
@@ -703,7 +792,7 @@ int tpcf_compute_batch(tpcf_ctx* c, int ncat, const int64_t* offsets, const doub
   if (!zeta) return fail(c, TPCF_E_INVALID_ARG, "zeta is NULL");
   int rc = stage(c, cats, ntot, x, y, z, w, memspace);
   if (rc) return rc;
-  rc = compute(c, 0, c->ntot, zeta, memspace);
+  rc = compute(c, 0, c->ntot, zeta, memspace, true);
   if (!rc) c->err.clear();
   return rc;
 }

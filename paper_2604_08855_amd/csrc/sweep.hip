@@ -21,7 +21,7 @@
 //             compensated (Kahan) sum (mixed precision) or plain FP64.
 //   contract: every 32 (mixed) or 16 (FP64) primaries, the wave multiplies its tile of shells on
 //             MFMA: per l, zeta_l += X_l diag(f w) X_l^T with X_l the [bins x (primaries*(2l+1))]
-//             matrix of real components. Mixed: two-piece BF16 split, three products, FP32
+//             matrix of real components. Mixed: three-piece BF16 split, six products, FP32
 //             accumulation within the tile. FP64: v_mfma_f64_16x16x4. Tile results are added into
 //             a per-wave FP64 partial; partials are added into zeta (FP64 atomics) when the wave
 //             changes catalogue and when it finishes.
@@ -276,7 +276,7 @@ __device__ __noinline__ void contract_tile(const float* __restrict__ tile, const
     int t0 = kh / n2, c0 = kh - (kh / n2) * n2;
 #pragma unroll 1
     for (int k0 = 0; k0 < K; k0 += 16) {
-      bf16x8 ah, al, bh, bl;
+      bf16x8 a0, a1, a2, b0, b1, b2;
       int t = t0, cc = c0;
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
@@ -287,20 +287,39 @@ __device__ __noinline__ void contract_tile(const float* __restrict__ tile, const
           wv = wt[t] * (cc == 0 ? 1.f : 2.f);
         }
         const float yv = xv * wv;
-        const __bf16 xh = (__bf16)xv;
-        const __bf16 yh = (__bf16)yv;
-        ah[j] = xh;
-        al[j] = (__bf16)(xv - (float)xh);
-        bh[j] = yh;
-        bl[j] = (__bf16)(yv - (float)yh);
-        if (++cc == n2) { cc = 0; ++t; }
+        // three-piece BF16 split: v = v0 + v1 + v2 to within 2^-27 |v|
+        const __bf16 x0 = (__bf16)xv;
+        const float xr = xv - (float)x0;
+        const __bf16 x1 = (__bf16)xr;
+        const __bf16 x2 = (__bf16)(xr - (float)x1);
+        const __bf16 y0 = (__bf16)yv;
+        const float yr = yv - (float)y0;
+        const __bf16 y1 = (__bf16)yr;
+        const __bf16 y2 = (__bf16)(yr - (float)y1);
+        a0[j] = x0;
+        a1[j] = x1;
+        a2[j] = x2;
+        b0[j] = y0;
+        b1[j] = y1;
+        b2[j] = y2;
+        if (++cc == n2) {
+          cc = 0;
+          ++t;
+        }
       }
       // advance the first (t, cc) by 16
       c0 += 16;
-      while (c0 >= n2) { c0 -= n2; ++t0; }
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc, 0, 0, 0);
+      while (c0 >= n2) {
+        c0 -= n2;
+        ++t0;
+      }
+      // every product of total order <= 2, smallest first
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2, b0, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b2, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b0, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b1, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc, 0, 0, 0);
     }
     const int col = lane & 31;
 #pragma unroll
@@ -352,10 +371,10 @@ __device__ __noinline__ void contract_tile(const double* __restrict__ tile, cons
         ++t;
       }
     }
-    // D[i][j] of a 16x16 block: lane j + 16*(i/4), register i%4.
+    // D[i][j] of a 16x16 block: lane j + 16*(i%4), register i/4.
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int row = 4 * kq + r;
+      const int row = kq + 4 * r;
       if (row < nb && rl < nb) part[(l * nb + row) * nb + rl] += acc00[r];
       if (two) {
         if (row < nb && 16 + rl < nb) part[(l * nb + row) * nb + 16 + rl] += acc01[r];

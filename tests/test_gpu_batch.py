@@ -1,0 +1,122 @@
+"""Batch form: several independent catalogues in one persistent launch (and its HIP graph)."""
+import os
+
+import numpy as np
+import pytest
+
+import catalogs
+import oracle
+from tests.gpu_util import rel_err_per_l, say
+
+pytestmark = pytest.mark.gpu
+TOL = {"fp64": 1e-10, "mixed": 1e-5}
+NB, RMIN, RMAX, L = 8, 3.0, 40.0, 6
+
+
+@pytest.fixture(scope="module")
+def tpcf():
+    import torch
+
+    assert torch.cuda.is_available()
+    import paper_2604_08855_amd as mod
+
+    return mod
+
+
+def make_batch(seed):
+    """Uneven mocks: sizes 0, 1, 700, 2500, 4100; different boxes and periodicity."""
+    specs = [(0, 100.0, True), (1, 100.0, True), (700, 90.0, False), (2500, 120.0, True), (4100, 150.0, True)]
+    cats = []
+    for k, (n, box, per) in enumerate(specs):
+        if n >= 2500:
+            c = catalogs.lognormal(n, box, seed + k, grid=32, periodic=per)
+        else:
+            c = catalogs.uniform(n, box, seed + k)
+            c.periodic = per
+        c.w = catalogs.gaussian_weights(n, 100 + seed + k)
+        cats.append(c)
+    return cats
+
+
+def concat(cats):
+    off = np.concatenate([[0], np.cumsum([c.n for c in cats])]).astype(np.int64)
+    cat = lambda f: np.concatenate([getattr(c, f) for c in cats])
+    return off, cat("x"), cat("y"), cat("z"), cat("w")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batch_matches_oracle_per_catalogue(tpcf, prec):
+    cats = make_batch(3)
+    off, x, y, z, w = concat(cats)
+    ctx = tpcf.Context(0)
+    ctx.set_bins(NB, RMIN, RMAX, L)
+    ctx.set_precision(prec)
+    say(f"batch of {len(cats)} catalogues, {off[-1]} points, prec={prec}")
+    zb = ctx.compute_batch(off, x, y, z, w, [c.box for c in cats], [c.periodic for c in cats])
+    assert zb.shape == (len(cats), L + 1, NB, NB)
+    for k, c in enumerate(cats):
+        ref = oracle.zeta(c.x, c.y, c.z, c.w, c.box, c.periodic, NB, RMIN, RMAX, L).zeta
+        if c.n < 2:
+            assert not zb[k].any()
+            continue
+        err = rel_err_per_l(zb[k], ref)
+        say(k, c.n, err.max())
+        assert err.max() <= TOL[prec], k
+
+
+def test_graph_replays_match_eager(tpcf):
+    """The captured graph is replayed several times on new data, with eager work and
+    synchronisations in between; every replay must equal the eager result."""
+    import torch
+
+    stream = torch.cuda.Stream()
+    ctx = tpcf.Context(0, stream)
+    ctx.set_bins(NB, RMIN, RMAX, L)
+    ctx.set_precision("mixed")
+    other = tpcf.Context(0)
+    other.set_bins(NB, RMIN, RMAX, L)
+    other.set_precision("fp64")
+    for rep in range(4):
+        cats = make_batch(10 + rep)  # same shape, new data every time
+        off, x, y, z, w = concat(cats)
+        boxes, per = [c.box for c in cats], [c.periodic for c in cats]
+        os.environ["TPCF_GRAPH"] = "1"
+        zg = ctx.compute_batch(off, x, y, z, w, boxes, per)
+        # unrelated eager work on another context and torch work in between
+        one = cats[3]
+        other.set_catalog(one.x, one.y, one.z, one.w, box=one.box, periodic=one.periodic)
+        other.compute_zeta()
+        torch.ones(1000, device="cuda").sum().item()
+        torch.cuda.synchronize()
+        os.environ["TPCF_GRAPH"] = "0"
+        eager = tpcf.Context(0, stream)
+        eager.set_bins(NB, RMIN, RMAX, L)
+        eager.set_precision("mixed")
+        ze = eager.compute_batch(off, x, y, z, w, boxes, per)
+        eager.close()
+        os.environ["TPCF_GRAPH"] = "1"
+        for k in range(len(cats)):
+            if cats[k].n < 2:
+                assert not zg[k].any()
+                continue
+            assert rel_err_per_l(zg[k], ze[k]).max() < 1e-6, (rep, k)
+        say(f"replay {rep} ok")
+
+
+def test_batch_equals_single_runs(tpcf):
+    cats = make_batch(21)
+    off, x, y, z, w = concat(cats)
+    ctx = tpcf.Context(0)
+    ctx.set_bins(NB, RMIN, RMAX, L)
+    ctx.set_precision("fp64")
+    zb = ctx.compute_batch(off, x, y, z, w, [c.box for c in cats], [c.periodic for c in cats])
+    for k, c in enumerate(cats):
+        s = tpcf.Context(0)
+        s.set_bins(NB, RMIN, RMAX, L)
+        s.set_precision("fp64")
+        s.set_catalog(c.x, c.y, c.z, c.w, box=c.box, periodic=c.periodic)
+        zs = s.compute_zeta()
+        if c.n < 2:
+            assert not zs.any() and not zb[k].any()
+        else:
+            assert rel_err_per_l(zb[k], zs).max() < 1e-12
