@@ -107,6 +107,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--fp64-steps", type=int, default=None)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -120,6 +122,15 @@ def main():
     cat, w = make_catalog()
     dev = [torch.from_numpy(a).cuda() for a in (cat.x, cat.y, cat.z, w)]
     torch.cuda.synchronize()
+    if args.copy_calibration_mib > 0:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE calibrate the HBM counters
+        src = torch.ones(args.copy_calibration_mib * 2**20 // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy of {args.copy_calibration_mib} MiB done")
+        del src, dst
 
     ms, sweep_ms, st, zmix = time_path(tpcf, torch, dev, "mixed", args.steps, args.warmup)
     pairs = st["n_pairs"]

@@ -63,7 +63,7 @@ struct tpcf_ctx {
   double rmin = 0, rmax = 0;
   int lmax = 0;
   int precision = TPCF_PREC_FP64;
-  double ppc = 30.0;
+  double ppc = 4.0;
   int waves_per_cu = 8;
   int scratch_blocks = 1024;
   bool debug = false;
@@ -80,13 +80,13 @@ struct tpcf_ctx {
   double grid_rmax = -1, grid_ppc = -1, grid_rmin = -1;
   int grid_nb = -1;
   std::vector<CatDesc> cd;
-  std::vector<StencilRow> st;
   uint32_t ncell = 0;
-  DevBuf cats_d, stencil_d, qtmp, cellid, hist, idx_a, idx_b, bsum, errflag, cell_start, rec, w64, perm;
+  DevBuf cats_d, qtmp, cellid, hist, idx_a, idx_b, bsum, errflag, cell_start, rec, w64, perm;
 
   // sweep buffers
-  DevBuf scratch, tile, zeta_d, queue, stats_d, tasks, counts32, alm_dbg, cscale32, cscale64;
-  int cscale_lmax = -1;
+  DevBuf scratch, tile, zeta_d, queue, stats_d, tasks, counts32, alm_dbg, conv_idx, conv32, conv64, regions;
+  int conv_lmax = -1;
+  int regions_key = -1;
 
   // results of the last compute
   bool dbg_valid = false;
@@ -127,10 +127,10 @@ size_t device_cap() {
 }
 
 size_t total_bytes(tpcf_ctx* c) {
-  DevBuf* all[] = {&c->sx, &c->sy, &c->sz, &c->sw, &c->cats_d, &c->stencil_d, &c->qtmp, &c->cellid, &c->hist,
+  DevBuf* all[] = {&c->sx, &c->sy, &c->sz, &c->sw, &c->cats_d, &c->qtmp, &c->cellid, &c->hist,
                    &c->idx_a, &c->idx_b, &c->bsum, &c->errflag, &c->cell_start, &c->rec, &c->w64, &c->perm,
                    &c->scratch, &c->tile, &c->zeta_d, &c->queue, &c->stats_d, &c->tasks, &c->counts32,
-                   &c->alm_dbg, &c->cscale32, &c->cscale64};
+                   &c->alm_dbg, &c->conv_idx, &c->conv32, &c->conv64, &c->regions};
   size_t t = 0;
   for (DevBuf* b : all) t += b->bytes;
   return t;
@@ -187,40 +187,79 @@ int lattice_bits(double box, double rmax, int periodic) {
   return K;
 }
 
-// Normalisation of the monic recurrence: a_lm = C_lm * sum w H_lm(z) (x - i y)^m with
-// C_lm = N_lm (-1)^m (2m-1)!! prod_{k=m+1}^{l} (2k-1)/(k-m),
-// N_lm = sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!).
-std::vector<double> normalisation(int lmax) {
+// Conversion of the Chebyshev moments M_{m,k} = sum_j w_j T_k(z_j) (x_j - i y_j)^m into a_lm:
+//   a_lm = N_lm (-1)^m sum_k g_lmk M_{m,k},   d^m P_l / dz^m = sum_k g_lmk T_k(z),
+//   N_lm = sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!),
+// so that a_lm = sum_j w_j conj(Y_lm) with the Condon-Shortley phase. Real component c of a_lm
+// (index l*l, or l*l + 2m - 1 / l*l + 2m for Re / Im) is a sum of at most kConvTerms moments;
+// moment (m, k) has the index of component (m + k, m). Entries with idx = -1 are unused.
+void conversion(int lmax, std::vector<int16_t>& idx, std::vector<double>& coef) {
   const int nc = (lmax + 1) * (lmax + 1);
-  std::vector<double> C(nc, 0.0);
-  for (int l = 0; l <= lmax; ++l)
-    for (int m = 0; m <= l; ++m) {
-      long double ratio = 1.0L;
-      for (int i = l - m + 1; i <= l + m; ++i) ratio /= (long double)i;
-      long double N = sqrtl((2.0L * l + 1.0L) / (4.0L * 3.14159265358979323846264338327950288L) * ratio);
-      long double kappa = 1.0L;
-      for (int i = 1; i <= m; ++i) kappa *= (long double)(2 * i - 1);
-      for (int k = m + 1; k <= l; ++k) kappa *= (long double)(2 * k - 1) / (long double)(k - m);
-      long double v = N * kappa * ((m & 1) ? -1.0L : 1.0L);
-      if (m == 0) {
-        C[l * l] = (double)v;
+  idx.assign((size_t)nc * kConvTerms, (int16_t)-1);
+  coef.assign((size_t)nc * kConvTerms, 0.0);
+  const int D = lmax + 1;
+  // A[n][t]: z^n = sum_t A[n][t] T_t(z)
+  std::vector<long double> A((size_t)D * D, 0.0L);
+  A[0] = 1.0L;
+  for (int n = 0; n + 1 < D; ++n)
+    for (int t = 0; t < D; ++t) {
+      const long double v = A[(size_t)n * D + t];
+      if (v == 0.0L) continue;
+      if (t == 0) {
+        A[(size_t)(n + 1) * D + 1] += v;
       } else {
-        C[l * l + 2 * m - 1] = (double)v;
-        C[l * l + 2 * m] = (double)v;
+        if (t + 1 < D) A[(size_t)(n + 1) * D + t + 1] += 0.5L * v;
+        A[(size_t)(n + 1) * D + t - 1] += 0.5L * v;
       }
     }
-  return C;
+  auto choose = [](int n, int k) {
+    long double r = 1.0L;
+    for (int i = 1; i <= k; ++i) r = r * (long double)(n - k + i) / (long double)i;
+    return r;
+  };
+  for (int l = 0; l <= lmax; ++l) {
+    // monomial coefficients of P_l
+    std::vector<long double> pl(D, 0.0L);
+    for (int k = 0; 2 * k <= l; ++k)
+      pl[l - 2 * k] = ((k & 1) ? -1.0L : 1.0L) * choose(l, k) * choose(2 * l - 2 * k, l) / powl(2.0L, (long double)l);
+    for (int m = 0; m <= l; ++m) {
+      // d^m P_l / dz^m in monomials, then in Chebyshev polynomials
+      std::vector<long double> g(D, 0.0L), gc(D, 0.0L);
+      for (int n = 0; n + m <= l; ++n) {
+        long double f = 1.0L;
+        for (int i = n + 1; i <= n + m; ++i) f *= (long double)i;
+        g[n] = pl[n + m] * f;
+      }
+      for (int n = 0; n < D; ++n)
+        if (g[n] != 0.0L)
+          for (int t = 0; t < D; ++t) gc[t] += g[n] * A[(size_t)n * D + t];
+      long double ratio = 1.0L;
+      for (int i = l - m + 1; i <= l + m; ++i) ratio /= (long double)i;
+      const long double N =
+          sqrtl((2.0L * l + 1.0L) / (4.0L * 3.14159265358979323846264338327950288L) * ratio) * ((m & 1) ? -1.0L : 1.0L);
+      for (int part = 0; part < (m == 0 ? 1 : 2); ++part) {
+        const int c = m == 0 ? l * l : l * l + 2 * m - 1 + part;
+        int q = 0;
+        for (int k = 0; k <= l - m; ++k) {
+          if ((l - m - k) & 1) continue;  // parity of d^m P_l
+          const int mi = m == 0 ? (m + k) * (m + k) : (m + k) * (m + k) + 2 * m - 1 + part;
+          idx[(size_t)c * kConvTerms + q] = (int16_t)mi;
+          coef[(size_t)c * kConvTerms + q] = (double)(N * gc[k]);
+          ++q;
+        }
+      }
+    }
+  }
 }
 
 typedef unsigned __int128 u128;
 
-// Grid side, lattice, thresholds and stencil rows (cells whose minimum-image lattice separation
-// from the primary cell can be below r_max) of every catalogue.
+// Grid side, lattice, thresholds, stencil geometry and FP32 bin-decision bound of every
+// catalogue.
 int configure_grid(tpcf_ctx* c) {
   const int nb = c->nbins;
   const double delta = (c->rmax - c->rmin) / nb;
   c->cd.clear();
-  c->st.clear();
   uint64_t cells = 0;
   for (size_t k = 0; k < c->cats.size(); ++k) {
     const HostCat& h = c->cats[k];
@@ -238,8 +277,6 @@ int configure_grid(tpcf_ctx* c) {
       const double v = e * d.scale;
       d.T[b] = ceil(v * v);
     }
-    d.rmin_l = (float)(c->rmin * d.scale);
-    d.inv_delta_l = (float)(1.0 / (delta * d.scale));
     // grid side from the target points per cell
     int ncx = 1;
     if (h.n > 0) {
@@ -252,49 +289,61 @@ int configure_grid(tpcf_ctx* c) {
     d.cell_base = (uint32_t)cells;
     cells += (uint64_t)ncx * ncx * ncx;
     if (cells >= ((uint64_t)1 << 31)) return fail(c, TPCF_E_UNSUPPORTED, "too many grid cells");
-    // stencil rows
-    d.stencil_base = (int32_t)c->st.size();
-    const uint64_t cmin = std::max<uint64_t>(1, (((uint64_t)1) << d.K) / (uint64_t)ncx);
-    const u128 Tn = (u128)(uint64_t)d.T[nb];
-    auto sq = [&](int64_t e) -> u128 {
-      const u128 v = (u128)(uint64_t)(e > 0 ? e : 0) * (u128)cmin;
-      return v * v;
-    };
-    int R = 1;
-    while (R <= ncx && sq(R) < Tn) ++R;  // largest e with sq(e - 1) < Tn
-    int lo, hi;
+    // per-primary stencil: rows within reach = r_max + margin (lattice units) of the primary
+    const double span = ldexp(1.0, d.K);
+    const double margin = ldexp(1.0, d.K - 14);
+    const double reach = c->rmax * d.scale + margin;
+    const double cs_min = floor(span / ncx);
+    int R = (int)ceil(reach / cs_min) + 1;
     if (h.periodic) {
       if (2 * R + 1 > ncx) {
-        lo = -((ncx - 1) / 2);
-        hi = ncx / 2;
+        d.row_lo = -((ncx - 1) / 2);
+        d.row_w = ncx;
       } else {
-        lo = -R;
-        hi = R;
+        d.row_lo = -R;
+        d.row_w = 2 * R + 1;
       }
     } else {
-      const int r = std::min(R, ncx - 1);
-      lo = -r;
-      hi = r;
+      R = std::min(R, ncx - 1);
+      d.row_lo = -R;
+      d.row_w = 2 * R + 1;
     }
-    for (int dz = lo; dz <= hi; ++dz)
-      for (int dy = lo; dy <= hi; ++dy) {
-        const u128 base = sq(std::abs(dy) - 1) + sq(std::abs(dz) - 1);
-        if (base >= Tn) continue;
-        int half = 1;
-        while (half + 1 <= R && base + sq(half) < Tn) ++half;
-        if (!h.periodic) half = std::min(half, ncx - 1);
-        StencilRow row;
-        row.dy = dy;
-        row.dz = dz;
-        row.half = half;
-        row.full = (h.periodic && 2 * half + 1 >= ncx) ? 1 : 0;
-        c->st.push_back(row);
-      }
-    d.nstencil = (int32_t)c->st.size() - d.stencil_base;
+    d.cs = (float)(span / ncx);
+    d.inv_cs = (float)(ncx / span);
+    d.span = (float)span;
+    d.reach = (float)reach;
+    d.margin = (float)margin;
+    d.inv_delta_l = (float)(1.0 / (delta * d.scale));
+    d.u0 = (float)(-c->rmin / delta);
+    // |u_fp32 - u_exact| <= 13 * 2^-24 * r_max / delta bins (see the kernel); a decision is
+    // taken in FP32 only when the fractional bin position is 4x that far from an edge.
+    double eps = 52.0 * ldexp(1.0, -24) * (c->rmax / delta + 1.0);
+    if (eps > 0.2) eps = 2.0;  // no FP32 decisions at all: every candidate takes the exact path
+    d.eps = (float)eps;
     c->cd.push_back(d);
   }
   c->ncell = (uint32_t)cells;
   return TPCF_OK;
+}
+
+// Scratch regions per bin: two blocks each plus a share of the rest proportional to the bin's
+// shell volume.
+std::vector<uint32_t> scratch_regions(int nb, double rmin, double rmax, int S) {
+  std::vector<double> vol(nb);
+  double tot = 0.0;
+  const double delta = (rmax - rmin) / nb;
+  for (int b = 0; b < nb; ++b) {
+    const double e0 = rmin + b * delta, e1 = (b + 1 == nb) ? rmax : rmin + (b + 1) * delta;
+    vol[b] = e1 * e1 * e1 - e0 * e0 * e0;
+    tot += vol[b];
+  }
+  std::vector<uint32_t> r(nb + 1, 0);
+  const int spare = S - 2 * nb;
+  for (int b = 0; b < nb; ++b) {
+    const uint32_t share = (uint32_t)floor(spare * vol[b] / tot);
+    r[b + 1] = r[b] + 2 + share;
+  }
+  return r;
 }
 
 int check_periodic_range(tpcf_ctx* c) {
@@ -394,7 +443,6 @@ int prepare_grid(tpcf_ctx* c) {
   if ((rc = configure_grid(c))) return rc;
   const size_t n = (size_t)c->ntot;
   if ((rc = ensure(c, c->cats_d, c->cd.size() * sizeof(CatDesc), "catalogue table")) ||
-      (rc = ensure(c, c->stencil_d, std::max<size_t>(1, c->st.size()) * sizeof(StencilRow), "stencil")) ||
       (rc = ensure(c, c->qtmp, n * sizeof(uint4), "grid")) || (rc = ensure(c, c->cellid, n * 4, "grid")) ||
       (rc = ensure(c, c->hist, (size_t)c->ncell * 4, "grid")) || (rc = ensure(c, c->idx_a, n * 4, "grid")) ||
       (rc = ensure(c, c->idx_b, n * 4, "grid")) ||
@@ -406,9 +454,6 @@ int prepare_grid(tpcf_ctx* c) {
     return rc;
   HIP_TRY(c, hipMemcpyAsync(c->cats_d.p, c->cd.data(), c->cd.size() * sizeof(CatDesc), hipMemcpyHostToDevice,
                             c->stream));
-  if (!c->st.empty())
-    HIP_TRY(c, hipMemcpyAsync(c->stencil_d.p, c->st.data(), c->st.size() * sizeof(StencilRow),
-                              hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return TPCF_OK;
 }
@@ -449,15 +494,26 @@ int prepare_sweep(tpcf_ctx* c, const uint32_t* tasks_d, uint32_t ntask, SweepArg
       (rc = ensure(c, c->zeta_d, (size_t)ncat * (L + 1) * nb * nb * 8, "zeta")) ||
       (rc = ensure(c, c->queue, 16, "queue")) || (rc = ensure(c, c->stats_d, 16, "stats")))
     return rc;
-  if (c->cscale_lmax != L) {
-    std::vector<double> C = normalisation(L);
-    std::vector<float> C32(C.begin(), C.end());
-    if ((rc = ensure(c, c->cscale64, NC * 8, "constants")) || (rc = ensure(c, c->cscale32, NC * 4, "constants")))
+  if (c->conv_lmax != L) {
+    std::vector<int16_t> idx;
+    std::vector<double> coef;
+    conversion(L, idx, coef);
+    std::vector<float> coef32(coef.begin(), coef.end());
+    if ((rc = ensure(c, c->conv_idx, idx.size() * 2, "constants")) ||
+        (rc = ensure(c, c->conv64, coef.size() * 8, "constants")) ||
+        (rc = ensure(c, c->conv32, coef.size() * 4, "constants")))
       return rc;
-    HIP_TRY(c, hipMemcpyAsync(c->cscale64.p, C.data(), NC * 8, hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(c->cscale32.p, C32.data(), NC * 4, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->conv_idx.p, idx.data(), idx.size() * 2, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->conv64.p, coef.data(), coef.size() * 8, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->conv32.p, coef32.data(), coef32.size() * 4, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
-    c->cscale_lmax = L;
+    c->conv_lmax = L;
+  }
+  {
+    std::vector<uint32_t> regs = scratch_regions(nb, c->rmin, c->rmax, S);
+    if ((rc = ensure(c, c->regions, regs.size() * 4, "regions"))) return rc;
+    HIP_TRY(c, hipMemcpyAsync(c->regions.p, regs.data(), regs.size() * 4, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
   }
   if (c->debug) {
     if ((rc = ensure(c, c->counts32, (size_t)c->ntot * nb * 4, "debug counts")) ||
@@ -468,7 +524,6 @@ int prepare_sweep(tpcf_ctx* c, const uint32_t* tasks_d, uint32_t ntask, SweepArg
   a.rec = (const uint4*)c->rec.p;
   a.w64 = (const double*)c->w64.p;
   a.cell_start = (const uint32_t*)c->cell_start.p;
-  a.stencil = (const StencilRow*)c->stencil_d.p;
   a.cats = (const CatDesc*)c->cats_d.p;
   a.ncat = ncat;
   a.nb = nb;
@@ -477,13 +532,15 @@ int prepare_sweep(tpcf_ctx* c, const uint32_t* tasks_d, uint32_t ntask, SweepArg
   a.queue = (uint32_t*)c->queue.p;
   a.scratch = (uint32_t*)c->scratch.p;
   a.scratch_blocks = S;
+  a.regions = (const uint32_t*)c->regions.p;
   a.tile = c->tile.p;
   a.zeta = (double*)c->zeta_d.p;
   a.counts = c->debug ? (int32_t*)c->counts32.p : nullptr;
   a.alm_debug = c->debug ? c->alm_dbg.p : nullptr;
   a.stats = (unsigned long long*)c->stats_d.p;
-  a.cscale32 = (const float*)c->cscale32.p;
-  a.cscale64 = (const double*)c->cscale64.p;
+  a.conv_idx = (const int16_t*)c->conv_idx.p;
+  a.conv_coef32 = (const float*)c->conv32.p;
+  a.conv_coef64 = (const double*)c->conv64.p;
   return TPCF_OK;
 }
 
@@ -669,10 +726,10 @@ void tpcf_destroy(tpcf_ctx* c) {
   if (c->dev_ready) {
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
-    DevBuf* all[] = {&c->sx, &c->sy, &c->sz, &c->sw, &c->cats_d, &c->stencil_d, &c->qtmp, &c->cellid, &c->hist,
+    DevBuf* all[] = {&c->sx, &c->sy, &c->sz, &c->sw, &c->cats_d, &c->qtmp, &c->cellid, &c->hist,
                      &c->idx_a, &c->idx_b, &c->bsum, &c->errflag, &c->cell_start, &c->rec, &c->w64, &c->perm,
                      &c->scratch, &c->tile, &c->zeta_d, &c->queue, &c->stats_d, &c->tasks, &c->counts32,
-                     &c->alm_dbg, &c->cscale32, &c->cscale64};
+                     &c->alm_dbg, &c->conv_idx, &c->conv32, &c->conv64, &c->regions};
     for (DevBuf* b : all) release(*b);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     for (auto& e : c->ev)

@@ -3,22 +3,29 @@
 // zeta_l(b1, b2) += w_p sum_m a_lm(b1) a*_lm(b2) on MFMA, for gfx950 (wave64).
 //
 // Method (paper, Implementation section): for each pivot (primary), find every neighbour in
-// the search range and fill the multipole bins; the per-multipole work uses a recurrence
-// instead of trigonometric functions. Nearby pivots share neighbour lists: here every primary
-// of a grid cell scans the same stencil of cells.
+// the search range and fill the multipole bins, with Chebyshev polynomials in place of
+// trigonometric functions. Here the Chebyshev polynomials are those of the polar cosine z:
+// every a_lm of a bin is a fixed linear combination of the moments
+//     M_{m,k} = sum_j w_j T_k(z_j) (x_j - i y_j)^m,   0 <= k <= l_max - m,
+// because d^m P_l / dz^m is a polynomial of degree l - m in z. T_k costs one FMA each
+// (T_k = 2 z T_{k-1} - T_{k-2}) and is shared by all m, so a pair costs about one FMA per real
+// moment plus the powers of (x - i y).
 //
 // One wavefront owns one primary at a time (tasks come from a global atomic queue):
-//   pass    : the wave walks the primary's stencil in rounds of 64 candidates, decides each
-//             candidate's bin exactly (integer lattice separation, FP64 squared distance against
-//             integer thresholds) and appends it to a per-bin LDS bucket. A bucket that reaches
-//             64 entries is written as one block of 64 sorted positions to the wave's scratch
-//             area, so every block holds 64 secondaries of a single bin.
-//   shells  : bin by bin, the wave replays that bin's blocks. Each lane evaluates the
-//             (l_max+1)^2 real harmonic components of its pair with a register recurrence
-//             (powers of (x - i y) times monic associated-Legendre polynomials in z) and adds them
-//             into register accumulators. Every <= 64 rounds the 64 lanes are reduced with a
-//             transpose-reduction (permlane32/16 swaps, then DPP) and added into the shell with a
-//             compensated (Kahan) sum (mixed precision) or plain FP64.
+//   stencil : the primary's own stencil: every (y, z) row of cells whose slab comes within
+//             r_max of the primary, clipped in x to the chord of the r_max sphere (cell
+//             granularity). Rows are built 64 at a time, one per lane; the rows' cell ranges are
+//             contiguous runs of the cell-sorted records.
+//   pass    : rounds of 64 consecutive candidates, packed across runs. Each candidate's bin is
+//             decided in FP32 when its fractional bin position is farther than a proven error
+//             bound from a bin edge, and otherwise exactly (FP64 squared lattice separation
+//             against integer thresholds). Accepted candidates go to a per-bin LDS bucket; a
+//             full bucket becomes one scratch block of 64 sorted positions, tagged with its bin.
+//   shells  : bin by bin, the wave replays that bin's blocks: each lane adds its pair's moments
+//             into register accumulators; every <= 64 rounds the 64 lanes are combined with a
+//             transpose-reduction (permlane32/16 swaps, then DPP) into a compensated (Kahan)
+//             shell sum (mixed precision) or a plain FP64 sum. At the end of the bin the moments
+//             are turned into normalised a_lm through LDS.
 //   contract: every 32 (mixed) or 16 (FP64) primaries, the wave multiplies its tile of shells on
 //             MFMA: per l, zeta_l += X_l diag(f w) X_l^T with X_l the [bins x (primaries*(2l+1))]
 //             matrix of real components. Mixed: three-piece BF16 split, six products, FP32
@@ -112,19 +119,17 @@ struct Plan {
   }
 };
 
-// Recurrence coefficient of the monic associated-Legendre polynomials in z:
-// H_mm = 1, H_{m+1,m} = z, H_lm = z H_{l-1,m} - beta_lm H_{l-2,m}.
-__host__ __device__ constexpr double beta(int l, int m) {
-  return double((l + m - 1) * (l - 1 - m)) / double((2 * l - 1) * (2 * l - 3));
-}
-
-// Adds the group-G components of w * conj(Y_lm(x,y,z)) / C_lm into acc (unnormalised: the
-// constant C_lm is applied when a shell is stored). (x, y, z) is a unit vector.
+// Adds the group-G moments w T_k(z) (x - i y)^m of one pair into acc. Moment (m, k) occupies
+// the register slot of component (l = m + k, m) of the plan.
 template <int LMAX, bool F64, int G, class real, int S>
-__device__ __forceinline__ void add_harmonics(real (&acc)[S], real x, real y, real z, real w) {
+__device__ __forceinline__ void add_moments(real (&acc)[S], real x, real y, real z, real w) {
   using P = Plan<LMAX, F64>;
+  real T[LMAX + 1];
+  T[0] = real(1);
+  if constexpr (LMAX >= 1) T[1] = z;
+  const real z2 = z + z;
+  static_for<2, LMAX + 1>([&](auto K) { T[K] = z2 * T[K - 1] - T[K - 2]; });
   real pr = w, pi = real(0);  // w (x - i y)^m
-  const real zz = z * z;
   static_for<0, LMAX + 1>([&](auto M) {
     constexpr int m = M;
     if constexpr (m > 0) {
@@ -134,21 +139,15 @@ __device__ __forceinline__ void add_harmonics(real (&acc)[S], real x, real y, re
       pi = ni;
     }
     if constexpr (P::group_of(m) == G) {
-      acc[P::loc(m, m, 0)] += pr;
-      if constexpr (m > 0) acc[P::loc(m, m, 1)] += pi;
-      if constexpr (m + 1 <= LMAX) {
-        acc[P::loc(m + 1, m, 0)] += z * pr;
-        if constexpr (m > 0) acc[P::loc(m + 1, m, 1)] += z * pi;
-      }
-      real h2 = real(1), h1 = z;
-      static_for<m + 2, LMAX + 1>([&](auto L) {
-        constexpr int l = L;
-        constexpr real bt = real(beta(l, m));
-        real h = (l == m + 2) ? (zz - bt) : (z * h1 - bt * h2);
-        acc[P::loc(l, m, 0)] += h * pr;
-        if constexpr (m > 0) acc[P::loc(l, m, 1)] += h * pi;
-        h2 = h1;
-        h1 = h;
+      static_for<0, LMAX - m + 1>([&](auto Kk) {
+        constexpr int k = Kk;
+        if constexpr (k == 0) {
+          acc[P::loc(m, m, 0)] += pr;
+          if constexpr (m > 0) acc[P::loc(m, m, 1)] += pi;
+        } else {
+          acc[P::loc(m + k, m, 0)] += T[k] * pr;
+          if constexpr (m > 0) acc[P::loc(m + k, m, 1)] += T[k] * pi;
+        }
       });
     }
   });
@@ -405,16 +404,96 @@ __device__ __forceinline__ T uniform(T v) {
 
 // LDS layout (bytes), one wavefront per workgroup.
 struct Lds {
-  static constexpr int T = 0;                    // double[kMaxBins + 1]
-  static constexpr int WT = 272;                 // real[32]
-  static constexpr int BCNT = WT + 256;          // uint32[32]
-  static constexpr int BTOT = BCNT + 128;        // uint32[32]
-  static constexpr int HEAD = BTOT + 128;        // uint16[32]
-  static constexpr int TAIL = HEAD + 64;         // uint16[32]
-  static constexpr int NEXT = TAIL + 64;         // uint16[S]
-  static __host__ __device__ int bucket(int S) { return (NEXT + 2 * S + 15) & ~15; }
-  static __host__ __device__ int bytes(int S, int nb) { return bucket(S) + nb * kBucketCap * 4; }
+  static constexpr int T = 0;                    // double[kMaxBins + 1] thresholds
+  static constexpr int WT = 272;                 // real[32] tile weights
+  static constexpr int BCNT = WT + 256;          // uint32[32] bucket fill
+  static constexpr int BTOT = BCNT + 128;        // uint32[32] pairs per bin (this primary)
+  static constexpr int BBLK = BTOT + 128;        // uint32[32] blocks per bin (this chunk)
+  static constexpr int REG = BBLK + 128;         // uint32[33] scratch region start per bin
+  static constexpr int MOM = REG + 144;          // real[128] moments of one bin
+  static constexpr int RUNS = MOM + 1024;        // uint2[128] non-empty runs of one row chunk
+  static constexpr int BUCKET = RUNS + 1024;     // uint32[nb][kBucketCap]
+  static __host__ __device__ int bytes(int nb) { return BUCKET + nb * kBucketCap * 4; }
 };
+
+// One row of the per-primary stencil: up to two runs [b, e) of sorted positions.
+struct Row {
+  uint32_t b0, e0, b1, e1;
+};
+
+// Wave-uniform catalogue parameters.
+struct CatU {
+  int sh, K, nc, periodic, row_lo, row_w;
+  uint32_t cell_base;
+  float cs, inv_cs, span, inv_span, reach, margin, inv_dl, u0, eps, inv_w;
+};
+
+// Builds row t of the primary's stencil (rows are offsets (dy, dz) from the primary's cell):
+// the x cells whose slab intersects the chord of the r_max sphere through that row.
+__device__ __forceinline__ Row make_row(const uint32_t* __restrict__ cell_start, const CatU& c, int t, int cx,
+                                        int cy, int cz, float qx, float qy, float qz) {
+  Row r = {0u, 0u, 0u, 0u};
+  const int W = c.row_w;
+  if (t >= W * W) return r;
+  const int tz = (int)(((float)t + 0.5f) * c.inv_w);
+  const int ty = t - tz * W;
+  const int y = cy + c.row_lo + ty, z = cz + c.row_lo + tz;
+  const int nc = c.nc;
+  float dyf, dzf;
+  int yw = y, zw = z;
+  if (c.periodic) {
+    float oy = ((float)y + 0.5f) * c.cs - qy;
+    float oz = ((float)z + 0.5f) * c.cs - qz;
+    oy -= c.span * rintf(oy * c.inv_span);
+    oz -= c.span * rintf(oz * c.inv_span);
+    dyf = fmaxf(fabsf(oy) - 0.5f * c.cs, 0.f);
+    dzf = fmaxf(fabsf(oz) - 0.5f * c.cs, 0.f);
+    yw = y % nc;
+    yw += yw < 0 ? nc : 0;
+    zw = z % nc;
+    zw += zw < 0 ? nc : 0;
+  } else {
+    if (y < 0 || y >= nc || z < 0 || z >= nc) return r;
+    dyf = fmaxf(fmaxf((float)y * c.cs - qy, qy - (float)(y + 1) * c.cs), 0.f);
+    dzf = fmaxf(fmaxf((float)z * c.cs - qz, qz - (float)(z + 1) * c.cs), 0.f);
+  }
+  const float rr = c.reach * c.reach;
+  const float d2 = dyf * dyf + dzf * dzf;
+  if (d2 >= rr) return r;
+  const float h = __builtin_amdgcn_sqrtf(rr - d2) + c.margin;
+  const int xa = (int)floorf((qx - h) * c.inv_cs);
+  const int xb = (int)floorf((qx + h) * c.inv_cs);
+  const uint32_t rowbase = c.cell_base + (uint32_t)((zw * nc + yw) * nc);
+  int a0, b0, a1 = 0, b1 = -1;
+  if (c.periodic) {
+    if (xb - xa + 1 >= nc) {
+      a0 = 0;
+      b0 = nc - 1;
+    } else {
+      int aw = xa % nc;
+      aw += aw < 0 ? nc : 0;
+      const int bw = aw + (xb - xa);
+      a0 = aw;
+      if (bw < nc) {
+        b0 = bw;
+      } else {
+        b0 = nc - 1;
+        b1 = bw - nc;
+      }
+    }
+  } else {
+    a0 = xa < 0 ? 0 : xa;
+    b0 = xb > nc - 1 ? nc - 1 : xb;
+    if (a0 > b0) return r;
+  }
+  r.b0 = cell_start[rowbase + a0];
+  r.e0 = cell_start[rowbase + b0 + 1];
+  if (b1 >= a1) {
+    r.b1 = cell_start[rowbase + a1];
+    r.e1 = cell_start[rowbase + b1 + 1];
+  }
+  return r;
+}
 
 template <int LMAX, bool F64>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sweep_kernel(SweepArgs a) {
@@ -428,49 +507,43 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sw
   real* swt = reinterpret_cast<real*>(smem + Lds::WT);
   uint32_t* bcnt = reinterpret_cast<uint32_t*>(smem + Lds::BCNT);
   uint32_t* btot = reinterpret_cast<uint32_t*>(smem + Lds::BTOT);
-  uint16_t* head = reinterpret_cast<uint16_t*>(smem + Lds::HEAD);
-  uint16_t* tail = reinterpret_cast<uint16_t*>(smem + Lds::TAIL);
-  uint16_t* nxt = reinterpret_cast<uint16_t*>(smem + Lds::NEXT);
-  const int S = a.scratch_blocks;
-  uint32_t* bucket = reinterpret_cast<uint32_t*>(smem + Lds::bucket(S));
+  uint32_t* bblk = reinterpret_cast<uint32_t*>(smem + Lds::BBLK);
+  uint32_t* reg = reinterpret_cast<uint32_t*>(smem + Lds::REG);
+  real* mom = reinterpret_cast<real*>(smem + Lds::MOM);
+  uint2* runs = reinterpret_cast<uint2*>(smem + Lds::RUNS);
+  uint32_t* bucket = reinterpret_cast<uint32_t*>(smem + Lds::BUCKET);
 
   const int lane = threadIdx.x;
   const int nb = a.nb;
+  const int S = a.scratch_blocks;
   const uint32_t wave = blockIdx.x;
   uint32_t* scratch = a.scratch + (size_t)wave * S * kBlock;
   real* tile = reinterpret_cast<real*>(a.tile) + (size_t)wave * (TP * nb * NC + (LMAX + 1) * nb * nb * (F64 ? 1 : 2));
-  // per-wave FP64 zeta partial follows the tile area
   double* part = reinterpret_cast<double*>(tile + TP * nb * NC);
 
-  // Component index and normalisation of the slots this lane holds after a reduction.
-  int comp[P::NG][2];
-  real cs[P::NG][2];
+  // Scratch regions: bin b owns blocks [reg[b], reg[b+1]); a full region triggers the shells.
+  if (lane <= nb) reg[lane] = a.regions[lane];
+
+  // Moment index held by each of this lane's reduction slots, per group.
+  int mslot[P::NG][2];
   static_for<0, P::NG>([&](auto G) {
     constexpr int per = P::slots(G) / 64;
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      int c = k < per ? P::global_of(G, per * lane + k) : -1;
-      comp[G][k] = c;
-      cs[G][k] = c >= 0 ? (F64 ? (real)a.cscale64[c] : (real)a.cscale32[c]) : real(0);
-    }
+    for (int k = 0; k < 2; ++k) mslot[G][k] = k < per ? P::global_of(G, per * lane + k) : -1;
   });
 
   for (int i = lane; i < (LMAX + 1) * nb * nb; i += 64) part[i] = 0.0;
 
   int tile_n = 0, tile_cat = -1, part_cat = -1, cur_cat = -1;
   unsigned long long my_pairs = 0, my_cand = 0;
-
-  // Catalogue parameters (wave-uniform).
-  int sh = 0, K = 0, nc = 0, periodic = 0, st_base = 0, nst = 0;
-  uint32_t cell_base = 0;
-  float rmin_l = 0.f, inv_dl = 0.f;
+  CatU cu = {};
 
   auto flush_part = [&]() {
     if (part_cat >= 0) {
-      double* z = a.zeta + (size_t)part_cat * (LMAX + 1) * nb * nb;
+      double* zt = a.zeta + (size_t)part_cat * (LMAX + 1) * nb * nb;
       for (int i = lane; i < (LMAX + 1) * nb * nb; i += 64) {
-        double v = part[i];
-        if (v != 0.0) atomicAdd(&z[i], v);
+        const double v = part[i];
+        if (v != 0.0) atomicAdd(&zt[i], v);
         part[i] = 0.0;
       }
     }
@@ -500,15 +573,23 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sw
     }
     if (cat != cur_cat) {
       const CatDesc& cd = a.cats[cat];
-      sh = uniform(cd.sh);
-      K = uniform(cd.K);
-      nc = uniform(cd.nc);
-      periodic = uniform(cd.periodic);
-      st_base = uniform(cd.stencil_base);
-      nst = uniform(cd.nstencil);
-      cell_base = uniform(cd.cell_base);
-      rmin_l = cd.rmin_l;
-      inv_dl = cd.inv_delta_l;
+      cu.sh = uniform(cd.sh);
+      cu.K = uniform(cd.K);
+      cu.nc = uniform(cd.nc);
+      cu.periodic = uniform(cd.periodic);
+      cu.row_lo = uniform(cd.row_lo);
+      cu.row_w = uniform(cd.row_w);
+      cu.cell_base = uniform(cd.cell_base);
+      cu.cs = cd.cs;
+      cu.inv_cs = cd.inv_cs;
+      cu.span = cd.span;
+      cu.inv_span = 1.0f / cd.span;
+      cu.reach = cd.reach;
+      cu.margin = cd.margin;
+      cu.inv_dl = cd.inv_delta_l;
+      cu.u0 = cd.u0;
+      cu.eps = cd.eps;
+      cu.inv_w = 1.0f / (float)cu.row_w;
       if (lane <= nb) sT[lane] = cd.T[lane];
       cur_cat = cat;
       __syncthreads();
@@ -521,29 +602,94 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sw
     P0.qx = uniform(rp.x);
     P0.qy = uniform(rp.y);
     P0.qz = uniform(rp.z);
-    P0.sh = sh;
+    P0.sh = cu.sh;
     const real wp = F64 ? (real)a.w64[p] : (real)__uint_as_float(uniform(rp.w));
-    const int cx = (int)(((uint64_t)(P0.qx >> sh) * (uint64_t)nc) >> K);
-    const int cy = (int)(((uint64_t)(P0.qy >> sh) * (uint64_t)nc) >> K);
-    const int cz = (int)(((uint64_t)(P0.qz >> sh) * (uint64_t)nc) >> K);
+    const uint32_t ux = P0.qx >> cu.sh, uy = P0.qy >> cu.sh, uz = P0.qz >> cu.sh;
+    const int cx = (int)(((uint64_t)ux * (uint64_t)cu.nc) >> cu.K);
+    const int cy = (int)(((uint64_t)uy * (uint64_t)cu.nc) >> cu.K);
+    const int cz = (int)(((uint64_t)uz * (uint64_t)cu.nc) >> cu.K);
+    const float qxf = (float)ux, qyf = (float)uy, qzf = (float)uz;
 
     if (lane < 32) {
       bcnt[lane] = 0;
       btot[lane] = 0;
-      head[lane] = kEnd;
-      tail[lane] = kEnd;
+      bblk[lane] = 0;
     }
     __syncthreads();
-    int nblk = 0;
     uint32_t written = 0;  // bins whose shell already holds a stored value
-
     real* slot = tile + (size_t)tile_n * nb * NC;
 
-    // ---- replay the blocks of every bin and store the shells
-    auto process_blocks = [&](bool final_pass) {
+    // ---- stencil cursor. A chunk = 64 rows (one per lane); its non-empty runs are compacted
+    // through LDS into rb/re (run r held by lane r % 64 in register r / 64).
+    const int nrows = cu.row_w * cu.row_w;
+    int row_base = 0;
+    int nr = 0;         // runs in the current chunk
+    int rcur = 0;       // current run
+    uint32_t roff = 0;  // candidates of the current run already taken
+    uint32_t rb0 = 0, re0 = 0, rb1 = 0, re1 = 0;
+    auto load_chunk = [&]() {
+      const Row rw = make_row(a.cell_start, cu, row_base + lane, cx, cy, cz, qxf, qyf, qzf);
+      const bool h0 = rw.e0 > rw.b0, h1 = rw.e1 > rw.b1;
+      const uint64_t m0 = __ballot(h0), m1 = __ballot(h1);
+      const int below =
+          (int)(__builtin_amdgcn_mbcnt_hi((uint32_t)(m0 >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m0, 0u)) +
+                __builtin_amdgcn_mbcnt_hi((uint32_t)(m1 >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m1, 0u)));
+      if (h0) runs[below] = make_uint2(rw.b0, rw.e0);
+      if (h1) runs[below + (h0 ? 1 : 0)] = make_uint2(rw.b1, rw.e1);
+      nr = __popcll(m0) + __popcll(m1);
+      __syncthreads();
+      const uint2 r0 = lane < nr ? runs[lane] : make_uint2(0u, 0u);
+      const uint2 r1 = lane + 64 < nr ? runs[lane + 64] : make_uint2(0u, 0u);
+      rb0 = r0.x;
+      re0 = r0.y;
+      rb1 = r1.x;
+      re1 = r1.y;
+      __syncthreads();
+      rcur = 0;
+      roff = 0;
+      row_base += 64;
+    };
+    load_chunk();
+    // Maps the next up-to-256 candidates (four rounds: slot k of round u in lane k of idx[u]),
+    // packed across runs; returns the number of candidates mapped.
+    auto map_rounds = [&](uint32_t(&idx)[4]) -> int {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) idx[u] = kInvalid;
+      int filled = 0;
+      while (filled < 4 * kBlock) {
+        if (rcur == nr) {
+          if (row_base >= nrows) break;
+          load_chunk();
+          continue;
+        }
+        const uint32_t b =
+            uniform(rcur < 64 ? __builtin_amdgcn_readlane(rb0, rcur) : __builtin_amdgcn_readlane(rb1, rcur - 64));
+        const uint32_t e =
+            uniform(rcur < 64 ? __builtin_amdgcn_readlane(re0, rcur) : __builtin_amdgcn_readlane(re1, rcur - 64));
+        const uint32_t start = b + roff;
+        const int take = (int)min(e - start, (uint32_t)(4 * kBlock - filled));
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int slot = u * kBlock + lane;
+          if (slot >= filled && slot < filled + take) idx[u] = start + (uint32_t)(slot - filled);
+        }
+        filled += take;
+        if (start + (uint32_t)take == e) {
+          ++rcur;
+          roff = 0;
+        } else {
+          roff += (uint32_t)take;
+        }
+      }
+      return filled;
+    };
+
+    // ---- shells: replay every bin's blocks (one copy of this code)
+    auto process_blocks = [&]() {
       for (int b = 0; b < nb; ++b) {
-        const int first = uniform((int)head[b]);
-        if (first == kEnd) continue;
+        const int nblk_b = uniform((int)bblk[b]);
+        if (nblk_b == 0) continue;
+        const int k0 = uniform((int)reg[b]);
         static_for<0, P::NG>([&](auto G) {
           constexpr int SG = P::slots(G);
           constexpr int per = SG / 64;
@@ -558,8 +704,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sw
               if constexpr (F64) {
                 hi[k] += acc[k];
               } else {  // Kahan: hi holds the sum, lo the negated lost low part
-                real yk = acc[k] - lo[k];
-                real tk = hi[k] + yk;
+                const real yk = acc[k] - lo[k];
+                const real tk = hi[k] + yk;
                 lo[k] = (tk - hi[k]) - yk;
                 hi[k] = tk;
               }
@@ -569,22 +715,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sw
           };
           // Software pipeline: the record of the next round and the index of the round after
           // it are in flight while the current round is evaluated.
-          uint32_t j = scratch[first * kBlock + lane];
-          int kn = uniform((int)nxt[first]);
-          uint32_t jn = kn != kEnd ? scratch[kn * kBlock + lane] : kInvalid;
+          uint32_t j = scratch[k0 * kBlock + lane];
+          uint32_t jn = nblk_b > 1 ? scratch[(k0 + 1) * kBlock + lane] : kInvalid;
           uint4 r = a.rec[j != kInvalid ? j : p];
           double wd = (F64 && j != kInvalid) ? a.w64[j] : 0.0;
           int rounds = 0;
-          for (;;) {
+          for (int i = 0; i < nblk_b; ++i) {
             uint4 rn = r;
             double wdn = 0.0;
-            int knn = kEnd;
             uint32_t jnn = kInvalid;
-            if (kn != kEnd) {
+            if (i + 1 < nblk_b) {
               rn = a.rec[jn != kInvalid ? jn : p];
               if constexpr (F64) wdn = jn != kInvalid ? a.w64[jn] : 0.0;
-              knn = uniform((int)nxt[kn]);
-              if (knn != kEnd) jnn = scratch[knn * kBlock + lane];
+              if (i + 2 < nblk_b) jnn = scratch[(k0 + i + 2) * kBlock + lane];
             }
             int dx, dy, dz;
             displacement(P0, r, dx, dy, dz);
@@ -597,49 +740,55 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sw
               dz = 0;
               w = real(0);
             }
-            real ux, uy, uz;
-            unit(dx, dy, dz, ux, uy, uz);
-            add_harmonics<LMAX, F64, G>(acc, ux, uy, uz, w);
+            real vx, vy, vz;
+            unit(dx, dy, dz, vx, vy, vz);
+            add_moments<LMAX, F64, G>(acc, vx, vy, vz, w);
             if (++rounds == 64) {
               flush_acc();
               rounds = 0;
             }
-            if (kn == kEnd) break;
             r = rn;
             wd = wdn;
             j = jn;
             jn = jnn;
-            kn = knn;
           }
           if (rounds) flush_acc();
-          // store this group's components of the shell (normalised)
 #pragma unroll
-          for (int kk = 0; kk < per; ++kk) {
-            const int c = comp[G][kk];
-            if (c >= 0 && c < NC) {
-              real v = F64 ? hi[kk] : (hi[kk] - lo[kk]);
-              v *= cs[G][kk];
-              real* dst = slot + b * NC + c;
-              if (written & (1u << b)) v += *dst;
-              *dst = v;
-            }
+          for (int k = 0; k < per; ++k) {
+            const int ms = mslot[G][k];
+            if (ms >= 0 && ms < NC) mom[ms] = F64 ? hi[k] : (hi[k] - lo[k]);
           }
         });
+        __syncthreads();
+        // moments -> normalised a_lm of bin b
+        for (int c = lane; c < NC; c += 64) {
+          real v = real(0);
+#pragma unroll
+          for (int q = 0; q < kConvTerms; ++q) {
+            const int mi = a.conv_idx[c * kConvTerms + q];
+            if (mi >= 0) {
+              const real cf = F64 ? (real)a.conv_coef64[c * kConvTerms + q] : (real)a.conv_coef32[c * kConvTerms + q];
+              v += cf * mom[mi];
+            }
+          }
+          real* dst = slot + b * NC + c;
+          if (written & (1u << b)) v += *dst;
+          *dst = v;
+        }
+        __syncthreads();
         written |= 1u << b;
       }
-      if (lane < 32) {
-        head[lane] = kEnd;
-        tail[lane] = kEnd;
-      }
+      if (lane < 32) bblk[lane] = 0;
       __syncthreads();
-      (void)final_pass;
     };
 
-    // Appends bucket b (64 entries, or the final partial bucket padded with kInvalid) as one
-    // scratch block.
-    auto emit_block = [&](int b, uint32_t n) {
+    // Moves bucket b's first n entries (64, or the final partial bucket padded with kInvalid)
+    // into the next block of bin b's scratch region. Returns true when the region is full.
+    auto emit_block = [&](int b, uint32_t n) -> bool {
+      const int kb = uniform((int)bblk[b]);
+      const int k = uniform((int)reg[b]) + kb;
       const uint32_t v = lane < (int)n ? bucket[b * kBucketCap + lane] : kInvalid;
-      scratch[nblk * kBlock + lane] = v;
+      scratch[k * kBlock + lane] = v;
       const uint32_t c = bcnt[b];
       const uint32_t rem = c - n;
       const uint32_t carry = lane < (int)rem ? bucket[b * kBucketCap + n + lane] : 0u;
@@ -648,104 +797,84 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sw
       if (lane == 0) {
         bcnt[b] = rem;
         btot[b] += n;
-        nxt[nblk] = kEnd;
-        if (head[b] == kEnd) head[b] = (uint16_t)nblk;
-        else nxt[tail[b]] = (uint16_t)nblk;
-        tail[b] = (uint16_t)nblk;
+        bblk[b] = (uint32_t)(kb + 1);
       }
       __syncthreads();
-      ++nblk;
+      // one block of the region stays free for the final partial bucket
+      return kb + 2 >= uniform((int)reg[b + 1]) - uniform((int)reg[b]);
     };
 
-    // ---- pass over the stencil
-    for (int e = 0; e < nst; ++e) {
-      const StencilRow row = a.stencil[st_base + e];
-      const int ry = uniform(row.dy), rz = uniform(row.dz), half = uniform(row.half), full = uniform(row.full);
-      int y = cy + ry, z = cz + rz;
-      if (periodic) {
-        y = y < 0 ? y + nc : (y >= nc ? y - nc : y);
-        z = z < 0 ? z + nc : (z >= nc ? z - nc : z);
-      } else if (y < 0 || y >= nc || z < 0 || z >= nc) {
-        continue;
-      }
-      const uint32_t rowbase = cell_base + (uint32_t)((z * nc + y) * nc);
-      int xa[2], xb[2], nint = 0;
-      if (periodic && full) {
-        xa[0] = 0;
-        xb[0] = nc - 1;
-        nint = 1;
-      } else {
-        int x0 = cx - half, x1 = cx + half;
-        if (periodic) {
-          if (x0 < 0) {
-            xa[0] = x0 + nc; xb[0] = nc - 1; xa[1] = 0; xb[1] = x1; nint = 2;
-          } else if (x1 >= nc) {
-            xa[0] = x0; xb[0] = nc - 1; xa[1] = 0; xb[1] = x1 - nc; nint = 2;
-          } else {
-            xa[0] = x0; xb[0] = x1; nint = 1;
-          }
-        } else {
-          xa[0] = x0 < 0 ? 0 : x0;
-          xb[0] = x1 >= nc ? nc - 1 : x1;
-          nint = 1;
-        }
-      }
-      for (int s = 0; s < nint; ++s) {
-        const uint32_t beg = uniform(a.cell_start[rowbase + xa[s]]);
-        const uint32_t end = uniform(a.cell_start[rowbase + xb[s] + 1]);
-        // Rounds of 64 candidates, with the records of up to four rounds loaded ahead.
-        for (uint32_t o4 = beg; o4 < end; o4 += 4 * kBlock) {
-          uint4 rr[4];
+    // ---- pass over the stencil, chunked by the scratch regions
+    uint32_t idx4[4];
+    int nfill = map_rounds(idx4);
+    for (;;) {
+      bool region_full = false;
+      while (nfill > 0) {
+        my_cand += (unsigned long long)nfill;
+        uint4 rc[4];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const uint32_t j = o4 + u * kBlock + lane;
-            rr[u] = a.rec[j < end ? j : beg];
-          }
+        for (int u = 0; u < 4; ++u) rc[u] = a.rec[idx4[u] != kInvalid ? idx4[u] : p];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const uint32_t o = o4 + u * kBlock;
-            if (o >= end) break;
-            const uint32_t j = o + lane;
-            const bool ok = j < end;
-            int dx, dy, dz;
-            displacement(P0, rr[u], dx, dy, dz);
-            const double ddx = dx, ddy = dy, ddz = dz;
-            const double R2 = fma(ddx, ddx, fma(ddy, ddy, ddz * ddz));
-            if (ok && R2 > 0.0 && R2 >= T0 && R2 < Tn) {
-              int bb = (int)((sqrtf((float)R2) - rmin_l) * inv_dl);
-              bb = bb < 0 ? 0 : (bb >= nb ? nb - 1 : bb);
-              while (R2 < sT[bb]) --bb;
-              while (bb + 1 < nb && R2 >= sT[bb + 1]) ++bb;
-              const uint32_t pos = atomicAdd(&bcnt[bb], 1u);
-              bucket[bb * kBucketCap + pos] = j;
-            }
-            my_cand += (end - o < (uint32_t)kBlock) ? (end - o) : (uint32_t)kBlock;
-            __syncthreads();
-            uint64_t full_mask = __ballot(lane < nb && bcnt[lane] >= (uint32_t)kBlock);
-            while (full_mask) {
-              const int b = __ffsll((unsigned long long)full_mask) - 1;
-              full_mask &= full_mask - 1;
-              emit_block(b, kBlock);
-              if (nblk + nb >= S) {
-                process_blocks(false);
-                nblk = 0;
+        for (int u = 0; u < 4; ++u) {
+          if (u * kBlock >= nfill) break;
+          const uint32_t idx = idx4[u];
+          // bin decision: FP32 away from edges, exact near them
+          int dx, dy, dz;
+          displacement(P0, rc[u], dx, dy, dz);
+          const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
+          const float r2 = fx * fx + fy * fy + fz * fz;
+          const float uu = __builtin_amdgcn_sqrtf(r2) * cu.inv_dl + cu.u0;
+          const float fl = floorf(uu);
+          const float fr = uu - fl;
+          int bb = (int)fl;
+          const bool ok = idx != kInvalid;
+          const bool fast = fr >= cu.eps && fr <= 1.0f - cu.eps;
+          bool acc_ok = ok && fast && bb >= 0 && bb < nb;
+          const bool slow = ok && !fast;
+          if (__ballot(slow)) {
+            if (slow) {
+              const double ddx = dx, ddy = dy, ddz = dz;
+              const double R2 = fma(ddx, ddx, fma(ddy, ddy, ddz * ddz));
+              if (R2 > 0.0 && R2 >= T0 && R2 < Tn) {
+                bb = bb < 0 ? 0 : (bb >= nb ? nb - 1 : bb);
+                while (R2 < sT[bb]) --bb;
+                while (bb + 1 < nb && R2 >= sT[bb + 1]) ++bb;
+                acc_ok = true;
               }
             }
           }
+          uint32_t pos = 0;
+          if (acc_ok) {
+            pos = atomicAdd(&bcnt[bb], 1u);
+            bucket[bb * kBucketCap + pos] = idx;
+          }
+          uint64_t full_mask = __ballot(acc_ok && pos == (uint32_t)(kBlock - 1));
+          if (full_mask) {
+            __syncthreads();
+            while (full_mask) {
+              const int l = __ffsll((unsigned long long)full_mask) - 1;
+              full_mask &= full_mask - 1;
+              const int b = uniform(__builtin_amdgcn_readlane(bb, l));
+              region_full |= emit_block(b, kBlock);
+            }
+          }
+        }
+        nfill = map_rounds(idx4);
+        if (region_full) break;
+      }
+      const bool done = nfill == 0;
+      if (done) {
+        __syncthreads();
+        uint64_t part_mask = __ballot(lane < nb && bcnt[lane] > 0);
+        while (part_mask) {
+          const int b = __ffsll((unsigned long long)part_mask) - 1;
+          part_mask &= part_mask - 1;
+          emit_block(b, bcnt[b]);
         }
       }
+      process_blocks();
+      if (done) break;
     }
-    // final partial buckets
-    {
-      uint64_t part_mask = __ballot(lane < nb && bcnt[lane] > 0);
-      while (part_mask) {
-        const int b = __ffsll((unsigned long long)part_mask) - 1;
-        part_mask &= part_mask - 1;
-        emit_block(b, bcnt[b]);
-      }
-    }
-    process_blocks(true);
-    nblk = 0;
     // bins without any pair: zero shells
     for (int b = 0; b < nb; ++b)
       if (!(written & (1u << b)))
@@ -788,7 +917,10 @@ static hipError_t set_lds(size_t lds) {
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
-size_t sweep_lds_bytes(int scratch_blocks, int nb) { return (size_t)Lds::bytes(scratch_blocks, nb); }
+size_t sweep_lds_bytes(int scratch_blocks, int nb) {
+  (void)scratch_blocks;
+  return (size_t)Lds::bytes(nb);
+}
 
 // Doubles (FP64) or floats (mixed) of per-wave tile area, including the FP64 zeta partial.
 size_t sweep_tile_bytes_per_wave(int lmax, int nb, bool f64) {

@@ -24,20 +24,21 @@ struct CatDesc {
   int32_t K;             // lattice bits: coordinates are integers in [0, 2^K)
   int32_t sh;            // stored coordinate = q << sh (32-K when periodic, else 0)
   int32_t periodic;
-  int32_t stencil_base;  // first entry of this catalogue's stencil rows
-  int32_t nstencil;
+  int32_t row_lo;        // stencil rows: offsets (dy, dz) in [row_lo, row_lo + row_w)^2
+  int32_t row_w;
   int32_t pad_;
   double box;
   double scale;          // 2^K / box
   double T[kMaxBins + 1];  // exact integer squared-separation thresholds (lattice units)
-  float rmin_l;          // r_min in lattice units (FP32, first guess of the bin only)
-  float inv_delta_l;     // 1 / bin width in lattice units
-};
-
-// One stencil row: all cells at (dy, dz) from the primary cell with |dx| <= half (or the whole
-// x row when full != 0).
-struct StencilRow {
-  int32_t dy, dz, half, full;
+  // FP32 quantities of the per-primary stencil and of the fast bin decision (lattice units)
+  float cs;              // cell side 2^K / nc
+  float inv_cs;
+  float span;            // 2^K
+  float reach;           // r_max + margin
+  float margin;
+  float inv_delta_l;     // 1 / bin width
+  float u0;              // -r_min / bin width
+  float eps;             // fast bin decisions need a fractional bin position in [eps, 1 - eps]
 };
 
 // Arguments of the persistent sweep kernel.
@@ -45,7 +46,6 @@ struct SweepArgs {
   const uint4* rec;             // sorted records: (Qx, Qy, Qz, float bits of w)
   const double* w64;            // sorted FP64 weights
   const uint32_t* cell_start;   // per catalogue nc^3 + 1 entries
-  const StencilRow* stencil;
   const CatDesc* cats;
   int32_t ncat;
   int32_t nb;
@@ -54,14 +54,19 @@ struct SweepArgs {
   uint32_t* queue;              // [0] task ticket counter
   uint32_t* scratch;            // per-wave blocks of 64 sorted positions
   int32_t scratch_blocks;       // blocks per wave
+  const uint32_t* regions;      // [nb + 1]: bin b owns scratch blocks [regions[b], regions[b+1])
   void* tile;                   // per-wave a_lm tile area
   double* zeta;                 // [ncat][(lmax+1)][nb][nb]
   int32_t* counts;              // optional [total points][nb], by sorted position
   void* alm_debug;              // optional [total points][nb][NC] (float or double), by sorted position
   unsigned long long* stats;    // [0] pairs, [1] candidates
-  const float* cscale32;        // normalisation constant per real component
-  const double* cscale64;
+  // moments -> a_lm: component c = sum_t conv_coef[c][t] * moment[conv_idx[c][t]] (t < kConvTerms)
+  const int16_t* conv_idx;
+  const float* conv_coef32;
+  const double* conv_coef64;
 };
+
+constexpr int kConvTerms = 6;
 
 // Components per primary and bin: (lmax+1)^2 real numbers.
 __host__ __device__ constexpr int ncomp(int lmax) { return (lmax + 1) * (lmax + 1); }
