@@ -65,6 +65,12 @@ def _load() -> ctypes.CDLL:
     if not os.path.exists(_LIB_PATH):
         raise ImportError(
             f"{_LIB_PATH} is not built: run `python -m paper_2604_08855_amd.build` (needs hipcc)")
+    # torch wheels bundle their own HIP runtime. Loading torch first lets the library bind to
+    # that runtime (same soname), so a process never holds two HIP runtimes side by side.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(_LIB_PATH)
     vp, i, i64, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
     sig = {

@@ -326,8 +326,8 @@ int configure_grid(tpcf_ctx* c) {
   return TPCF_OK;
 }
 
-// Scratch regions per bin: two blocks each plus a share of the rest proportional to the bin's
-// shell volume.
+// Scratch regions per bin: kMinRegionBlocks blocks each plus a share of the rest proportional
+// to the bin's shell volume.
 std::vector<uint32_t> scratch_regions(int nb, double rmin, double rmax, int S) {
   std::vector<double> vol(nb);
   double tot = 0.0;
@@ -338,10 +338,10 @@ std::vector<uint32_t> scratch_regions(int nb, double rmin, double rmax, int S) {
     tot += vol[b];
   }
   std::vector<uint32_t> r(nb + 1, 0);
-  const int spare = S - 2 * nb;
+  const int spare = S - kMinRegionBlocks * nb;
   for (int b = 0; b < nb; ++b) {
     const uint32_t share = (uint32_t)floor(spare * vol[b] / tot);
-    r[b + 1] = r[b] + 2 + share;
+    r[b + 1] = r[b] + kMinRegionBlocks + share;
   }
   return r;
 }
@@ -488,8 +488,10 @@ int prepare_sweep(tpcf_ctx* c, const uint32_t* tasks_d, uint32_t ntask, SweepArg
   const int S = c->scratch_blocks;
   int rc;
   const size_t lds = sweep_lds_bytes(S, nb);
-  if (lds > 160 * 1024) return fail(c, TPCF_E_UNSUPPORTED, "scratch_blocks too large for LDS");
-  if ((rc = ensure(c, c->scratch, (size_t)waves * S * kBlock * 4, "scratch")) ||
+  if (lds > 160 * 1024) return fail(c, TPCF_E_UNSUPPORTED, "LDS layout too large");
+  if (S < kMinRegionBlocks * nb)
+    return fail(c, TPCF_E_INVALID_ARG, "scratch_blocks must be at least 5 x nbins");
+  if ((rc = ensure(c, c->scratch, (size_t)waves * (S + 1) * kBlock * 4, "scratch")) ||
       (rc = ensure(c, c->tile, (size_t)waves * sweep_tile_bytes_per_wave(L, nb, f64), "tiles")) ||
       (rc = ensure(c, c->zeta_d, (size_t)ncat * (L + 1) * nb * nb * 8, "zeta")) ||
       (rc = ensure(c, c->queue, 16, "queue")) || (rc = ensure(c, c->stats_d, 16, "stats")))

@@ -406,14 +406,14 @@ __device__ __forceinline__ T uniform(T v) {
 struct Lds {
   static constexpr int T = 0;                    // double[kMaxBins + 1] thresholds
   static constexpr int WT = 272;                 // real[32] tile weights
-  static constexpr int BCNT = WT + 256;          // uint32[32] bucket fill
-  static constexpr int BTOT = BCNT + 128;        // uint32[32] pairs per bin (this primary)
-  static constexpr int BBLK = BTOT + 128;        // uint32[32] blocks per bin (this chunk)
-  static constexpr int REG = BBLK + 128;         // uint32[33] scratch region start per bin
+  static constexpr int BTOT = WT + 256;          // uint32[32] pairs per bin (this primary)
+  static constexpr int BBLK = BTOT + 128;        // uint32[32] filled scratch blocks per bin
+  static constexpr int REG = BBLK + 128;         // uint32[33] scratch region start per bin (blocks)
   static constexpr int MOM = REG + 144;          // real[128] moments of one bin
   static constexpr int RUNS = MOM + 1024;        // uint2[128] non-empty runs of one row chunk
-  static constexpr int BUCKET = RUNS + 1024;     // uint32[nb][kBucketCap]
-  static __host__ __device__ int bytes(int nb) { return BUCKET + nb * kBucketCap * 4; }
+  static constexpr int CUR = RUNS + 1024;        // uint64[kMaxBins + 64]: bin cursors, lane dummies
+  static constexpr int END = CUR + 8 * (kMaxBins + 64);
+  static __host__ __device__ int bytes(int) { return END; }
 };
 
 // One row of the per-primary stencil: up to two runs [b, e) of sorted positions.
@@ -495,6 +495,14 @@ __device__ __forceinline__ Row make_row(const uint32_t* __restrict__ cell_start,
   return r;
 }
 
+// Compiler-only ordering point for LDS data exchanged between lanes of the one wavefront of a
+// workgroup: the hardware executes a wavefront's LDS instructions in order.
+__device__ __forceinline__ void lds_order() { __atomic_signal_fence(__ATOMIC_SEQ_CST); }
+
+__device__ __forceinline__ int lanes_below(uint64_t m) {
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
 template <int LMAX, bool F64>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sweep_kernel(SweepArgs a) {
   using real = std::conditional_t<F64, double, float>;
@@ -505,23 +513,23 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sw
   extern __shared__ __align__(16) unsigned char smem[];
   double* sT = reinterpret_cast<double*>(smem + Lds::T);
   real* swt = reinterpret_cast<real*>(smem + Lds::WT);
-  uint32_t* bcnt = reinterpret_cast<uint32_t*>(smem + Lds::BCNT);
   uint32_t* btot = reinterpret_cast<uint32_t*>(smem + Lds::BTOT);
   uint32_t* bblk = reinterpret_cast<uint32_t*>(smem + Lds::BBLK);
   uint32_t* reg = reinterpret_cast<uint32_t*>(smem + Lds::REG);
   real* mom = reinterpret_cast<real*>(smem + Lds::MOM);
   uint2* runs = reinterpret_cast<uint2*>(smem + Lds::RUNS);
-  uint32_t* bucket = reinterpret_cast<uint32_t*>(smem + Lds::BUCKET);
+  unsigned long long* cur = reinterpret_cast<unsigned long long*>(smem + Lds::CUR);
 
   const int lane = threadIdx.x;
   const int nb = a.nb;
   const int S = a.scratch_blocks;
   const uint32_t wave = blockIdx.x;
-  uint32_t* scratch = a.scratch + (size_t)wave * S * kBlock;
+  uint32_t* scratch = a.scratch + (size_t)wave * (S + 1) * kBlock;
+  uint32_t* dummy = scratch + (size_t)S * kBlock + lane;  // rejected lanes store here
   real* tile = reinterpret_cast<real*>(a.tile) + (size_t)wave * (TP * nb * NC + (LMAX + 1) * nb * nb * (F64 ? 1 : 2));
   double* part = reinterpret_cast<double*>(tile + TP * nb * NC);
 
-  // Scratch regions: bin b owns blocks [reg[b], reg[b+1]); a full region triggers the shells.
+  // Scratch regions: bin b owns blocks [reg[b], reg[b+1]).
   if (lane <= nb) reg[lane] = a.regions[lane];
 
   // Moment index held by each of this lane's reduction slots, per group.
@@ -610,78 +618,109 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sw
     const int cz = (int)(((uint64_t)uz * (uint64_t)cu.nc) >> cu.K);
     const float qxf = (float)ux, qyf = (float)uy, qzf = (float)uz;
 
+    // Bin cursors: low word = next free entry of the bin's region, high word = its soft limit.
+    auto reset_cursors = [&]() {
+      if (lane < nb) {
+        const uint32_t r0 = reg[lane], r1 = reg[lane + 1];
+        cur[lane] = (unsigned long long)(r0 * kBlock) |
+                    ((unsigned long long)(r1 * kBlock - kSoftReserve) << 32);
+      }
+      lds_order();
+    };
     if (lane < 32) {
-      bcnt[lane] = 0;
       btot[lane] = 0;
       bblk[lane] = 0;
     }
-    __syncthreads();
+    reset_cursors();
     uint32_t written = 0;  // bins whose shell already holds a stored value
     real* slot = tile + (size_t)tile_n * nb * NC;
 
-    // ---- stencil cursor. A chunk = 64 rows (one per lane); its non-empty runs are compacted
-    // through LDS into rb/re (run r held by lane r % 64 in register r / 64).
+    // ---- stencil generator. Rows are built 64 at a time (one per lane) and their non-empty
+    // runs compacted into LDS; runs are taken 64 at a time into a sub-chunk held in registers
+    // (lane r: first candidate position of run r and the offset from candidate position to
+    // sorted position). Rounds are 64 consecutive candidate positions of the sub-chunk.
     const int nrows = cu.row_w * cu.row_w;
-    int row_base = 0;
-    int nr = 0;         // runs in the current chunk
-    int rcur = 0;       // current run
-    uint32_t roff = 0;  // candidates of the current run already taken
-    uint32_t rb0 = 0, re0 = 0, rb1 = 0, re1 = 0;
-    auto load_chunk = [&]() {
+    int row_base = 0;      // first row of the next row chunk
+    int nrun = 0;          // runs of the current row chunk
+    int run_next = 0;      // first run of the row chunk not yet taken into a sub-chunk
+    uint32_t sub_T = 0;    // candidates of the sub-chunk
+    uint32_t o = 0;        // next candidate position
+    uint32_t delta_c = 0;  // sorted minus candidate position for the run holding position o - 1
+    uint32_t pre_v = kInvalid, dl_v = 0;
+
+    auto build_rows = [&]() {
       const Row rw = make_row(a.cell_start, cu, row_base + lane, cx, cy, cz, qxf, qyf, qzf);
       const bool h0 = rw.e0 > rw.b0, h1 = rw.e1 > rw.b1;
       const uint64_t m0 = __ballot(h0), m1 = __ballot(h1);
-      const int below =
-          (int)(__builtin_amdgcn_mbcnt_hi((uint32_t)(m0 >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m0, 0u)) +
-                __builtin_amdgcn_mbcnt_hi((uint32_t)(m1 >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m1, 0u)));
+      const int below = lanes_below(m0) + lanes_below(m1);
       if (h0) runs[below] = make_uint2(rw.b0, rw.e0);
       if (h1) runs[below + (h0 ? 1 : 0)] = make_uint2(rw.b1, rw.e1);
-      nr = __popcll(m0) + __popcll(m1);
-      __syncthreads();
-      const uint2 r0 = lane < nr ? runs[lane] : make_uint2(0u, 0u);
-      const uint2 r1 = lane + 64 < nr ? runs[lane + 64] : make_uint2(0u, 0u);
-      rb0 = r0.x;
-      re0 = r0.y;
-      rb1 = r1.x;
-      re1 = r1.y;
-      __syncthreads();
-      rcur = 0;
-      roff = 0;
+      lds_order();
+      nrun = __popcll(m0) + __popcll(m1);
+      run_next = 0;
       row_base += 64;
     };
-    load_chunk();
-    // Maps the next up-to-256 candidates (four rounds: slot k of round u in lane k of idx[u]),
-    // packed across runs; returns the number of candidates mapped.
-    auto map_rounds = [&](uint32_t(&idx)[4]) -> int {
+    auto load_sub = [&]() {
+      const int cnt = min(64, nrun - run_next);
+      uint2 rr = make_uint2(0u, 0u);
+      if (lane < cnt) rr = runs[run_next + lane];
+      const uint32_t len = rr.y - rr.x;
+      uint32_t incl = len;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) idx[u] = kInvalid;
-      int filled = 0;
-      while (filled < 4 * kBlock) {
-        if (rcur == nr) {
-          if (row_base >= nrows) break;
-          load_chunk();
-          continue;
-        }
-        const uint32_t b =
-            uniform(rcur < 64 ? __builtin_amdgcn_readlane(rb0, rcur) : __builtin_amdgcn_readlane(rb1, rcur - 64));
-        const uint32_t e =
-            uniform(rcur < 64 ? __builtin_amdgcn_readlane(re0, rcur) : __builtin_amdgcn_readlane(re1, rcur - 64));
-        const uint32_t start = b + roff;
-        const int take = (int)min(e - start, (uint32_t)(4 * kBlock - filled));
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int slot = u * kBlock + lane;
-          if (slot >= filled && slot < filled + take) idx[u] = start + (uint32_t)(slot - filled);
-        }
-        filled += take;
-        if (start + (uint32_t)take == e) {
-          ++rcur;
-          roff = 0;
+      for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t v = __shfl_up(incl, (unsigned)d);
+        if (lane >= d) incl += v;
+      }
+      const uint32_t pre = incl - len;
+      pre_v = lane < cnt ? pre : kInvalid;
+      dl_v = rr.x - pre;
+      sub_T = uniform(__builtin_amdgcn_readlane(incl, 63));
+      run_next += cnt;
+      o = 0;
+      lds_order();
+    };
+    // Next round: lane k gets the sorted position of candidate o + k (kInvalid past the end).
+    auto gen_round = [&]() -> uint32_t {
+      while (o >= sub_T) {
+        if (run_next >= nrun) {
+          if (row_base >= nrows) return kInvalid;
+          build_rows();
         } else {
-          roff += (uint32_t)take;
+          load_sub();
         }
       }
-      return filled;
+      const uint32_t g = o + (uint32_t)lane;
+      uint64_t starts = __ballot(pre_v >= o && pre_v < o + (uint32_t)kBlock);
+      uint32_t delta = delta_c;
+      while (starts) {
+        const int r = __ffsll((unsigned long long)starts) - 1;
+        starts &= starts - 1;
+        const uint32_t ps = uniform(__builtin_amdgcn_readlane(pre_v, r));
+        const uint32_t ds = uniform(__builtin_amdgcn_readlane(dl_v, r));
+        if (g >= ps) delta = ds;
+        delta_c = ds;
+      }
+      my_cand += (unsigned long long)min(sub_T - o, (uint32_t)kBlock);
+      const uint32_t idx = g < sub_T ? g + delta : kInvalid;
+      o += kBlock;
+      return idx;
+    };
+    // Next batch of rounds (shifted through registers so gen_round is expanded once).
+    auto gen_batch = [&](uint32_t(&id)[kBatch]) -> bool {
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) id[u] = kInvalid;
+#pragma unroll 1
+      for (int u = 0; u < kBatch; ++u) {
+        const uint32_t v = gen_round();
+#pragma unroll
+        for (int k = 0; k + 1 < kBatch; ++k) id[k] = id[k + 1];
+        id[kBatch - 1] = v;
+      }
+      return __ballot(id[0] != kInvalid) != 0;
+    };
+    auto load_batch = [&](const uint32_t(&id)[kBatch], uint4(&rc)[kBatch]) {
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) rc[u] = a.rec[id[u] != kInvalid ? id[u] : p];
     };
 
     // ---- shells: replay every bin's blocks (one copy of this code)
@@ -778,103 +817,111 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sw
         __syncthreads();
         written |= 1u << b;
       }
-      if (lane < 32) bblk[lane] = 0;
-      __syncthreads();
     };
 
-    // Moves bucket b's first n entries (64, or the final partial bucket padded with kInvalid)
-    // into the next block of bin b's scratch region. Returns true when the region is full.
-    auto emit_block = [&](int b, uint32_t n) -> bool {
-      const int kb = uniform((int)bblk[b]);
-      const int k = uniform((int)reg[b]) + kb;
-      const uint32_t v = lane < (int)n ? bucket[b * kBucketCap + lane] : kInvalid;
-      scratch[k * kBlock + lane] = v;
-      const uint32_t c = bcnt[b];
-      const uint32_t rem = c - n;
-      const uint32_t carry = lane < (int)rem ? bucket[b * kBucketCap + n + lane] : 0u;
-      __syncthreads();
-      if (lane < (int)rem) bucket[b * kBucketCap + lane] = carry;
-      if (lane == 0) {
-        bcnt[b] = rem;
-        btot[b] += n;
-        bblk[b] = (uint32_t)(kb + 1);
+    // Closes the regions (pads each bin's last block with kInvalid), replays the shells and
+    // empties the regions.
+    auto flush_shells = [&]() {
+      uint32_t c_b = 0, n_b = 0;
+      if (lane < nb) {
+        c_b = (uint32_t)cur[lane];
+        n_b = c_b - reg[lane] * kBlock;
+        btot[lane] += n_b;
+        bblk[lane] = (n_b + kBlock - 1) / kBlock;
       }
-      __syncthreads();
-      // one block of the region stays free for the final partial bucket
-      return kb + 2 >= uniform((int)reg[b + 1]) - uniform((int)reg[b]);
-    };
-
-    // ---- pass over the stencil, chunked by the scratch regions
-    uint32_t idx4[4];
-    int nfill = map_rounds(idx4);
-    for (;;) {
-      bool region_full = false;
-      while (nfill > 0) {
-        my_cand += (unsigned long long)nfill;
-        uint4 rc[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) rc[u] = a.rec[idx4[u] != kInvalid ? idx4[u] : p];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          if (u * kBlock >= nfill) break;
-          const uint32_t idx = idx4[u];
-          // bin decision: FP32 away from edges, exact near them
-          int dx, dy, dz;
-          displacement(P0, rc[u], dx, dy, dz);
-          const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
-          const float r2 = fx * fx + fy * fy + fz * fz;
-          const float uu = __builtin_amdgcn_sqrtf(r2) * cu.inv_dl + cu.u0;
-          const float fl = floorf(uu);
-          const float fr = uu - fl;
-          int bb = (int)fl;
-          const bool ok = idx != kInvalid;
-          const bool fast = fr >= cu.eps && fr <= 1.0f - cu.eps;
-          bool acc_ok = ok && fast && bb >= 0 && bb < nb;
-          const bool slow = ok && !fast;
-          if (__ballot(slow)) {
-            if (slow) {
-              const double ddx = dx, ddy = dy, ddz = dz;
-              const double R2 = fma(ddx, ddx, fma(ddy, ddy, ddz * ddz));
-              if (R2 > 0.0 && R2 >= T0 && R2 < Tn) {
-                bb = bb < 0 ? 0 : (bb >= nb ? nb - 1 : bb);
-                while (R2 < sT[bb]) --bb;
-                while (bb + 1 < nb && R2 >= sT[bb + 1]) ++bb;
-                acc_ok = true;
-              }
-            }
-          }
-          uint32_t pos = 0;
-          if (acc_ok) {
-            pos = atomicAdd(&bcnt[bb], 1u);
-            bucket[bb * kBucketCap + pos] = idx;
-          }
-          uint64_t full_mask = __ballot(acc_ok && pos == (uint32_t)(kBlock - 1));
-          if (full_mask) {
-            __syncthreads();
-            while (full_mask) {
-              const int l = __ffsll((unsigned long long)full_mask) - 1;
-              full_mask &= full_mask - 1;
-              const int b = uniform(__builtin_amdgcn_readlane(bb, l));
-              region_full |= emit_block(b, kBlock);
-            }
-          }
-        }
-        nfill = map_rounds(idx4);
-        if (region_full) break;
+      uint64_t tails = __ballot(lane < nb && (n_b & (kBlock - 1)) != 0);
+      while (tails) {
+        const int b = __ffsll((unsigned long long)tails) - 1;
+        tails &= tails - 1;
+        const uint32_t c = uniform(__builtin_amdgcn_readlane(c_b, b));
+        const uint32_t e = (c + kBlock - 1) & ~(uint32_t)(kBlock - 1);  // regions are block aligned
+        if (c + (uint32_t)lane < e) scratch[c + lane] = kInvalid;
       }
-      const bool done = nfill == 0;
-      if (done) {
-        __syncthreads();
-        uint64_t part_mask = __ballot(lane < nb && bcnt[lane] > 0);
-        while (part_mask) {
-          const int b = __ffsll((unsigned long long)part_mask) - 1;
-          part_mask &= part_mask - 1;
-          emit_block(b, bcnt[b]);
-        }
-      }
+      __syncthreads();  // the region stores complete before the replay loads them
       process_blocks();
-      if (done) break;
+      reset_cursors();
+    };
+
+    // Evaluates one batch of rounds: bin decision (FP32 away from bin edges, exact near them),
+    // then one LDS cursor increment per lane and one store of the sorted position into the
+    // bin's region. Rejected lanes use their own dummy cursor and store slot, so the batch has
+    // no divergent branch. Returns true when a region passed its soft limit.
+    auto process_batch = [&](const uint32_t(&id)[kBatch], const uint4(&rc)[kBatch]) -> bool {
+      int bbv[kBatch];
+      bool accv[kBatch], slowv[kBatch];
+      uint64_t anyslow = 0;
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        int dx, dy, dz;
+        displacement(P0, rc[u], dx, dy, dz);
+        const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
+        const float r2 = fx * fx + fy * fy + fz * fz;
+        const float uu = __builtin_amdgcn_sqrtf(r2) * cu.inv_dl + cu.u0;
+        const float fl = floorf(uu);
+        const float fr = uu - fl;
+        const int bb = (int)fl;
+        const bool ok = id[u] != kInvalid;
+        const bool fast = fr >= cu.eps && fr <= 1.0f - cu.eps;
+        accv[u] = ok && fast && (uint32_t)bb < (uint32_t)nb;
+        slowv[u] = ok && !fast;
+        bbv[u] = bb;
+        anyslow |= __ballot(slowv[u]);
+      }
+      if (anyslow) {
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+          if (slowv[u]) {
+            int dx, dy, dz;
+            displacement(P0, rc[u], dx, dy, dz);
+            const double ddx = dx, ddy = dy, ddz = dz;
+            const double R2 = fma(ddx, ddx, fma(ddy, ddy, ddz * ddz));
+            if (R2 > 0.0 && R2 >= T0 && R2 < Tn) {
+              int bb = bbv[u];
+              bb = bb < 0 ? 0 : (bb >= nb ? nb - 1 : bb);
+              while (R2 < sT[bb]) --bb;
+              while (bb + 1 < nb && R2 >= sT[bb + 1]) ++bb;
+              bbv[u] = bb;
+              accv[u] = true;
+            }
+          }
+        }
+      }
+      unsigned long long cw[kBatch];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const int slot_u = accv[u] ? bbv[u] : kMaxBins + lane;
+        cw[u] = atomicAdd(&cur[slot_u], 1ull);
+      }
+      bool soft = false;
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const uint32_t pos = (uint32_t)cw[u], lim = (uint32_t)(cw[u] >> 32);
+        soft |= accv[u] && pos >= lim;
+        uint32_t* dst = accv[u] ? scratch + pos : dummy;
+        *dst = id[u];
+      }
+      return __ballot(soft) != 0;
+    };
+
+    // ---- pass over the stencil: batch B is generated and its records loaded while batch A is
+    // evaluated.
+    uint32_t idA[kBatch], idB[kBatch];
+    uint4 rA[kBatch], rB[kBatch];
+    bool moreA = gen_batch(idA);
+    load_batch(idA, rA);
+    while (moreA) {
+      const bool moreB = gen_batch(idB);
+      load_batch(idB, rB);
+      if (process_batch(idA, rA)) flush_shells();
+      moreA = moreB;
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        idA[u] = idB[u];
+        rA[u] = rB[u];
+      }
     }
+    flush_shells();
+
     // bins without any pair: zero shells
     for (int b = 0; b < nb; ++b)
       if (!(written & (1u << b)))

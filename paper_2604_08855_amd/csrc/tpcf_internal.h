@@ -8,8 +8,12 @@ namespace tpcf {
 
 constexpr int kMaxBins = 32;   // bucket layout and the 32x32 MFMA output tile
 constexpr int kMaxLmax = 10;
-constexpr int kBucketCap = 128;  // per-bin LDS bucket: < 64 carried over + <= 64 new per round
 constexpr int kBlock = 64;       // secondaries per scratch block = one wavefront round
+constexpr int kBatch = 4;        // pass rounds evaluated together (one batch of loads in flight)
+// A bin's region takes new entries until it is within one batch of being full; the batch that
+// crosses that soft limit still fits, then the shells are replayed and the region emptied.
+constexpr int kSoftReserve = kBatch * kBlock;
+constexpr int kMinRegionBlocks = kBatch + 1;
 constexpr int kTileF32 = 32;     // primaries per contraction tile, mixed precision
 constexpr int kTileF64 = 16;     // primaries per contraction tile, FP64
 
@@ -52,8 +56,8 @@ struct SweepArgs {
   const uint32_t* task_list;    // NULL: task t is sorted position t
   uint32_t ntask;
   uint32_t* queue;              // [0] task ticket counter
-  uint32_t* scratch;            // per-wave blocks of 64 sorted positions
-  int32_t scratch_blocks;       // blocks per wave
+  uint32_t* scratch;            // per wave: scratch_blocks + 1 blocks of 64 sorted positions
+  int32_t scratch_blocks;       // blocks per wave in bin regions (the extra block takes rejected lanes' stores)
   const uint32_t* regions;      // [nb + 1]: bin b owns scratch blocks [regions[b], regions[b+1])
   void* tile;                   // per-wave a_lm tile area
   double* zeta;                 // [ncat][(lmax+1)][nb][nb]
