@@ -313,7 +313,8 @@ int configure_grid(tpcf_ctx* c) {
     d.span = (float)span;
     d.reach = (float)reach;
     d.margin = (float)margin;
-    d.inv_delta_l = (float)(1.0 / (delta * d.scale));
+    // bin scale per unit of the stored (shifted) coordinate difference: 2^-sh exactly
+    d.inv_delta_l = (float)(ldexp(1.0 / (delta * d.scale), -d.sh));
     d.u0 = (float)(-c->rmin / delta);
     // |u_fp32 - u_exact| <= 13 * 2^-24 * r_max / delta bins (see the kernel); a decision is
     // taken in FP32 only when the fractional bin position is 4x that far from an edge.
@@ -449,7 +450,8 @@ int prepare_grid(tpcf_ctx* c) {
       (rc = ensure(c, c->bsum, scan_block_count(c->ncell) * 4 + 4, "grid")) ||
       (rc = ensure(c, c->errflag, sizeof(int), "flags")) ||
       (rc = ensure(c, c->cell_start, ((size_t)c->ncell + 1) * 4, "grid")) ||
-      (rc = ensure(c, c->rec, n * sizeof(uint4), "records")) || (rc = ensure(c, c->w64, n * 8, "weights")) ||
+      (rc = ensure(c, c->rec, (n + 1) * sizeof(uint4), "records")) ||
+      (rc = ensure(c, c->w64, (n + 1) * 8, "weights")) ||
       (rc = ensure(c, c->perm, n * 4, "permutation")))
     return rc;
   HIP_TRY(c, hipMemcpyAsync(c->cats_d.p, c->cd.data(), c->cd.size() * sizeof(CatDesc), hipMemcpyHostToDevice,
@@ -524,6 +526,7 @@ int prepare_sweep(tpcf_ctx* c, const uint32_t* tasks_d, uint32_t ntask, SweepArg
   }
   memset(&a, 0, sizeof(a));
   a.rec = (const uint4*)c->rec.p;
+  a.sentinel = (uint32_t)c->ntot;
   a.w64 = (const double*)c->w64.p;
   a.cell_start = (const uint32_t*)c->cell_start.p;
   a.cats = (const CatDesc*)c->cats_d.p;

@@ -14,7 +14,7 @@
 //                 sorted layout (catalogue, cell, input index) and hence every summation order is
 //                 reproducible.
 //   k_gather    : writes the cell-sorted records (Qx, Qy, Qz, float w), FP64 weights and the
-//                 permutation back to input order.
+//                 permutation back to input order, then one zero-weight sentinel record.
 #include "tpcf_internal.h"
 
 namespace tpcf {
@@ -180,7 +180,12 @@ __global__ void k_gather(const uint32_t* __restrict__ order, const uint4* __rest
                          const double* __restrict__ w, uint4* __restrict__ rec, double* __restrict__ w64,
                          uint32_t* __restrict__ perm, uint32_t n) {
   const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= n) return;
+  if (s > n) return;
+  if (s == n) {  // sentinel record after the last point: weight 0, read by padding entries
+    rec[n] = make_uint4(0u, 0u, 0u, 0u);
+    w64[n] = 0.0;
+    return;
+  }
   const uint32_t i = order[s];
   rec[s] = qtmp[i];
   w64[s] = w ? w[i] : 1.0;
@@ -254,8 +259,8 @@ hipError_t build_grid(const double* x, const double* y, const double* z, const d
   if (n) {
     hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, s, cell, cell_start, hist, idx_a, n);
     hipLaunchKernelGGL(k_cellsort, dim3(ncell), dim3(64), 0, s, cell_start, idx_a, idx_b, ncell);
-    hipLaunchKernelGGL(k_gather, dim3(blocks_for(n, 256)), dim3(256), 0, s, idx_b, qtmp, w, rec, w64, perm, n);
   }
+  hipLaunchKernelGGL(k_gather, dim3(blocks_for(n + 1, 256)), dim3(256), 0, s, idx_b, qtmp, w, rec, w64, perm, n);
   return hipGetLastError();
 }
 

@@ -119,9 +119,9 @@ struct Plan {
   }
 };
 
-// Adds the group-G moments w T_k(z) (x - i y)^m of one pair into acc. Moment (m, k) occupies
-// the register slot of component (l = m + k, m) of the plan.
-template <int LMAX, bool F64, int G, class real, int S>
+// Adds (WRITE: stores) the group-G moments w T_k(z) (x - i y)^m of one pair into acc. Moment
+// (m, k) occupies the register slot of component (l = m + k, m) of the plan.
+template <int LMAX, bool F64, int G, bool WRITE, class real, int S>
 __device__ __forceinline__ void add_moments(real (&acc)[S], real x, real y, real z, real w) {
   using P = Plan<LMAX, F64>;
   real T[LMAX + 1];
@@ -141,12 +141,22 @@ __device__ __forceinline__ void add_moments(real (&acc)[S], real x, real y, real
     if constexpr (P::group_of(m) == G) {
       static_for<0, LMAX - m + 1>([&](auto Kk) {
         constexpr int k = Kk;
-        if constexpr (k == 0) {
-          acc[P::loc(m, m, 0)] += pr;
-          if constexpr (m > 0) acc[P::loc(m, m, 1)] += pi;
+        if constexpr (WRITE) {
+          if constexpr (k == 0) {
+            acc[P::loc(m, m, 0)] = pr;
+            if constexpr (m > 0) acc[P::loc(m, m, 1)] = pi;
+          } else {
+            acc[P::loc(m + k, m, 0)] = T[k] * pr;
+            if constexpr (m > 0) acc[P::loc(m + k, m, 1)] = T[k] * pi;
+          }
         } else {
-          acc[P::loc(m + k, m, 0)] += T[k] * pr;
-          if constexpr (m > 0) acc[P::loc(m + k, m, 1)] += T[k] * pi;
+          if constexpr (k == 0) {
+            acc[P::loc(m, m, 0)] += pr;
+            if constexpr (m > 0) acc[P::loc(m, m, 1)] += pi;
+          } else {
+            acc[P::loc(m + k, m, 0)] += T[k] * pr;
+            if constexpr (m > 0) acc[P::loc(m + k, m, 1)] += T[k] * pi;
+          }
         }
       });
     }
@@ -223,26 +233,25 @@ struct Primary {
   int sh;
 };
 
-// Lattice displacement of a secondary from the primary: the shifted coordinates wrap modulo
-// 2^32, so the arithmetic shift back gives the minimum image when periodic.
-__device__ __forceinline__ void displacement(const Primary& P, uint4 r, int& dx, int& dy, int& dz) {
-  dx = (int)(r.x - P.qx) >> P.sh;
-  dy = (int)(r.y - P.qy) >> P.sh;
-  dz = (int)(r.z - P.qz) >> P.sh;
-}
+// Stored-coordinate difference of a secondary and the primary: the lattice displacement times
+// 2^sh. Stored coordinates wrap modulo 2^32, so when periodic the signed difference is the
+// minimum image; an arithmetic shift by sh gives the lattice displacement itself.
+__device__ __forceinline__ int sdiff(uint32_t a, uint32_t b) { return (int)(a - b); }
 
-// Unit vector of a lattice displacement.
-__device__ __forceinline__ void unit(int dx, int dy, int dz, float& x, float& y, float& z) {
-  float fx = (float)dx, fy = (float)dy, fz = (float)dz;
-  float r2 = fx * fx + fy * fy + fz * fz;
-  float ri = __builtin_amdgcn_rsqf(r2);
+// Unit vector of a secondary's displacement, from the scaled difference (the scale cancels).
+// The tiny addend keeps the zero-weight sentinel record finite when it sits on the primary;
+// it cannot change the squared length of a real pair (>= 1 in lattice units).
+__device__ __forceinline__ void unit(const Primary& P, uint4 r, float& x, float& y, float& z) {
+  const float fx = (float)sdiff(r.x, P.qx), fy = (float)sdiff(r.y, P.qy), fz = (float)sdiff(r.z, P.qz);
+  const float r2 = __builtin_fmaf(fx, fx, __builtin_fmaf(fy, fy, __builtin_fmaf(fz, fz, 0x1p-100f)));
+  const float ri = __builtin_amdgcn_rsqf(r2);
   x = fx * ri;
   y = fy * ri;
   z = fz * ri;
 }
-__device__ __forceinline__ void unit(int dx, int dy, int dz, double& x, double& y, double& z) {
-  double fx = (double)dx, fy = (double)dy, fz = (double)dz;
-  double r2 = fma(fx, fx, fma(fy, fy, fz * fz));
+__device__ __forceinline__ void unit(const Primary& P, uint4 r, double& x, double& y, double& z) {
+  const double fx = (double)sdiff(r.x, P.qx), fy = (double)sdiff(r.y, P.qy), fz = (double)sdiff(r.z, P.qz);
+  const double r2 = fma(fx, fx, fma(fy, fy, fma(fz, fz, 0x1p-100)));
   double ri = __builtin_amdgcn_rsq(r2);
   // two Newton steps from the hardware estimate
   double h = r2 * ri;
@@ -525,7 +534,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sw
   const int S = a.scratch_blocks;
   const uint32_t wave = blockIdx.x;
   uint32_t* scratch = a.scratch + (size_t)wave * (S + 1) * kBlock;
-  uint32_t* dummy = scratch + (size_t)S * kBlock + lane;  // rejected lanes store here
   real* tile = reinterpret_cast<real*>(a.tile) + (size_t)wave * (TP * nb * NC + (LMAX + 1) * nb * nb * (F64 ? 1 : 2));
   double* part = reinterpret_cast<double*>(tile + TP * nb * NC);
 
@@ -729,12 +737,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sw
         const int nblk_b = uniform((int)bblk[b]);
         if (nblk_b == 0) continue;
         const int k0 = uniform((int)reg[b]);
+        // this lane's entry of block i of the bin is sb[i * kBlock]
+        const uint32_t* sb = scratch + (size_t)k0 * kBlock + lane;
         static_for<0, P::NG>([&](auto G) {
           constexpr int SG = P::slots(G);
           constexpr int per = SG / 64;
           real acc[SG];
+          // slots past the group's components are never written by the moments
 #pragma unroll
-          for (int i = 0; i < SG; ++i) acc[i] = real(0);
+          for (int i = P::gsize(G); i < SG; ++i) acc[i] = real(0);
           real hi[2] = {real(0), real(0)}, lo[2] = {real(0), real(0)};
           auto flush_acc = [&]() {
             transpose_reduce<SG>(acc, lane);
@@ -749,49 +760,40 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sw
                 hi[k] = tk;
               }
             }
-#pragma unroll
-            for (int i = 0; i < SG; ++i) acc[i] = real(0);
           };
           // Software pipeline: the record of the next round and the index of the round after
-          // it are in flight while the current round is evaluated.
-          uint32_t j = scratch[k0 * kBlock + lane];
-          uint32_t jn = nblk_b > 1 ? scratch[(k0 + 1) * kBlock + lane] : kInvalid;
-          uint4 r = a.rec[j != kInvalid ? j : p];
-          double wd = (F64 && j != kInvalid) ? a.w64[j] : 0.0;
-          int rounds = 0;
-          for (int i = 0; i < nblk_b; ++i) {
+          // it are in flight while the current round is evaluated. Padding entries hold the
+          // zero-weight sentinel record, so every entry is evaluated alike.
+          uint32_t jn = nblk_b > 1 ? sb[kBlock] : a.sentinel;
+          uint4 r = a.rec[sb[0]];
+          double wd = 0.0;
+          if constexpr (F64) wd = a.w64[sb[0]];
+          int i = 0;
+          auto step = [&](auto WRITE) {
             uint4 rn = r;
             double wdn = 0.0;
-            uint32_t jnn = kInvalid;
+            uint32_t jnn = a.sentinel;
             if (i + 1 < nblk_b) {
-              rn = a.rec[jn != kInvalid ? jn : p];
-              if constexpr (F64) wdn = jn != kInvalid ? a.w64[jn] : 0.0;
-              if (i + 2 < nblk_b) jnn = scratch[(k0 + i + 2) * kBlock + lane];
-            }
-            int dx, dy, dz;
-            displacement(P0, r, dx, dy, dz);
-            real w;
-            if (j != kInvalid) {
-              w = F64 ? (real)wd : (real)__uint_as_float(r.w);
-            } else {
-              dx = 1;
-              dy = 0;
-              dz = 0;
-              w = real(0);
+              rn = a.rec[jn];
+              if constexpr (F64) wdn = a.w64[jn];
+              if (i + 2 < nblk_b) jnn = sb[(i + 2) * kBlock];
             }
             real vx, vy, vz;
-            unit(dx, dy, dz, vx, vy, vz);
-            add_moments<LMAX, F64, G>(acc, vx, vy, vz, w);
-            if (++rounds == 64) {
-              flush_acc();
-              rounds = 0;
-            }
+            unit(P0, r, vx, vy, vz);
+            const real w = F64 ? (real)wd : (real)__uint_as_float(r.w);
+            add_moments<LMAX, F64, G, decltype(WRITE)::value>(acc, vx, vy, vz, w);
             r = rn;
             wd = wdn;
-            j = jn;
             jn = jnn;
+            ++i;
+          };
+          // chunks of <= 64 rounds: the first round of a chunk stores, the others add
+          while (i < nblk_b) {
+            const int n = min(64, nblk_b - i);
+            step(std::true_type{});
+            for (int q = 1; q < n; ++q) step(std::false_type{});
+            flush_acc();
           }
-          if (rounds) flush_acc();
 #pragma unroll
           for (int k = 0; k < per; ++k) {
             const int ms = mslot[G][k];
@@ -819,7 +821,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sw
       }
     };
 
-    // Closes the regions (pads each bin's last block with kInvalid), replays the shells and
+    // Closes the regions (pads each bin's last block with the sentinel), replays the shells and
     // empties the regions.
     auto flush_shells = [&]() {
       uint32_t c_b = 0, n_b = 0;
@@ -835,26 +837,30 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sw
         tails &= tails - 1;
         const uint32_t c = uniform(__builtin_amdgcn_readlane(c_b, b));
         const uint32_t e = (c + kBlock - 1) & ~(uint32_t)(kBlock - 1);  // regions are block aligned
-        if (c + (uint32_t)lane < e) scratch[c + lane] = kInvalid;
+        if (c + (uint32_t)lane < e) scratch[c + lane] = a.sentinel;
       }
       __syncthreads();  // the region stores complete before the replay loads them
       process_blocks();
       reset_cursors();
     };
 
-    // Evaluates one batch of rounds: bin decision (FP32 away from bin edges, exact near them),
-    // then one LDS cursor increment per lane and one store of the sorted position into the
-    // bin's region. Rejected lanes use their own dummy cursor and store slot, so the batch has
-    // no divergent branch. Returns true when a region passed its soft limit.
+    // Evaluates one batch of rounds. Bin decision in FP32 when the fractional bin position is
+    // farther than the proven error bound from an edge; every accepted lane takes the next entry
+    // of its bin's region from one LDS cursor increment and stores its sorted position there.
+    // Rejected lanes use their own dummy cursor and store slot, so the fast path has no
+    // divergent branch. Lanes near a bin edge are decided exactly afterwards (FP64 squared
+    // lattice separation against the integer thresholds). Returns true when a region passed
+    // its soft limit.
+    const uint32_t dummy_pos = (uint32_t)S * kBlock + lane;
     auto process_batch = [&](const uint32_t(&id)[kBatch], const uint4(&rc)[kBatch]) -> bool {
+      bool soft = false;
+      bool slowv[kBatch];
       int bbv[kBatch];
-      bool accv[kBatch], slowv[kBatch];
       uint64_t anyslow = 0;
 #pragma unroll
       for (int u = 0; u < kBatch; ++u) {
-        int dx, dy, dz;
-        displacement(P0, rc[u], dx, dy, dz);
-        const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
+        const float fx = (float)sdiff(rc[u].x, P0.qx), fy = (float)sdiff(rc[u].y, P0.qy),
+                    fz = (float)sdiff(rc[u].z, P0.qz);
         const float r2 = fx * fx + fy * fy + fz * fz;
         const float uu = __builtin_amdgcn_sqrtf(r2) * cu.inv_dl + cu.u0;
         const float fl = floorf(uu);
@@ -862,65 +868,60 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sw
         const int bb = (int)fl;
         const bool ok = id[u] != kInvalid;
         const bool fast = fr >= cu.eps && fr <= 1.0f - cu.eps;
-        accv[u] = ok && fast && (uint32_t)bb < (uint32_t)nb;
+        const bool acc = ok && fast && (uint32_t)bb < (uint32_t)nb;
         slowv[u] = ok && !fast;
         bbv[u] = bb;
         anyslow |= __ballot(slowv[u]);
+        const unsigned long long cw = atomicAdd(&cur[acc ? bb : kMaxBins + lane], 1ull);
+        soft |= acc && (uint32_t)cw >= (uint32_t)(cw >> 32);
+        scratch[acc ? (uint32_t)cw : dummy_pos] = id[u];
       }
       if (anyslow) {
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
           if (slowv[u]) {
-            int dx, dy, dz;
-            displacement(P0, rc[u], dx, dy, dz);
-            const double ddx = dx, ddy = dy, ddz = dz;
+            const double ddx = sdiff(rc[u].x, P0.qx) >> cu.sh, ddy = sdiff(rc[u].y, P0.qy) >> cu.sh,
+                         ddz = sdiff(rc[u].z, P0.qz) >> cu.sh;
             const double R2 = fma(ddx, ddx, fma(ddy, ddy, ddz * ddz));
             if (R2 > 0.0 && R2 >= T0 && R2 < Tn) {
               int bb = bbv[u];
               bb = bb < 0 ? 0 : (bb >= nb ? nb - 1 : bb);
               while (R2 < sT[bb]) --bb;
               while (bb + 1 < nb && R2 >= sT[bb + 1]) ++bb;
-              bbv[u] = bb;
-              accv[u] = true;
+              const unsigned long long cw = atomicAdd(&cur[bb], 1ull);
+              soft |= (uint32_t)cw >= (uint32_t)(cw >> 32);
+              scratch[(uint32_t)cw] = id[u];
             }
           }
         }
-      }
-      unsigned long long cw[kBatch];
-#pragma unroll
-      for (int u = 0; u < kBatch; ++u) {
-        const int slot_u = accv[u] ? bbv[u] : kMaxBins + lane;
-        cw[u] = atomicAdd(&cur[slot_u], 1ull);
-      }
-      bool soft = false;
-#pragma unroll
-      for (int u = 0; u < kBatch; ++u) {
-        const uint32_t pos = (uint32_t)cw[u], lim = (uint32_t)(cw[u] >> 32);
-        soft |= accv[u] && pos >= lim;
-        uint32_t* dst = accv[u] ? scratch + pos : dummy;
-        *dst = id[u];
       }
       return __ballot(soft) != 0;
     };
 
     // ---- pass over the stencil: batch B is generated and its records loaded while batch A is
     // evaluated.
+    // The shells are replayed from one place (keeps a single copy of their code).
     uint32_t idA[kBatch], idB[kBatch];
     uint4 rA[kBatch], rB[kBatch];
     bool moreA = gen_batch(idA);
     load_batch(idA, rA);
-    while (moreA) {
-      const bool moreB = gen_batch(idB);
-      load_batch(idB, rB);
-      if (process_batch(idA, rA)) flush_shells();
-      moreA = moreB;
+    for (;;) {
+      const bool last = !moreA;
+      bool flush = last;
+      if (!last) {
+        const bool moreB = gen_batch(idB);
+        load_batch(idB, rB);
+        flush = process_batch(idA, rA);
+        moreA = moreB;
 #pragma unroll
-      for (int u = 0; u < kBatch; ++u) {
-        idA[u] = idB[u];
-        rA[u] = rB[u];
+        for (int u = 0; u < kBatch; ++u) {
+          idA[u] = idB[u];
+          rA[u] = rB[u];
+        }
       }
+      if (flush) flush_shells();
+      if (last) break;
     }
-    flush_shells();
 
     // bins without any pair: zero shells
     for (int b = 0; b < nb; ++b)

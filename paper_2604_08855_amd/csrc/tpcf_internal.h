@@ -40,15 +40,16 @@ struct CatDesc {
   float span;            // 2^K
   float reach;           // r_max + margin
   float margin;
-  float inv_delta_l;     // 1 / bin width
+  float inv_delta_l;     // 2^-sh / bin width: bin position per unit of stored coordinate difference
   float u0;              // -r_min / bin width
   float eps;             // fast bin decisions need a fractional bin position in [eps, 1 - eps]
 };
 
 // Arguments of the persistent sweep kernel.
 struct SweepArgs {
-  const uint4* rec;             // sorted records: (Qx, Qy, Qz, float bits of w)
-  const double* w64;            // sorted FP64 weights
+  const uint4* rec;             // sorted records: (Qx, Qy, Qz, float bits of w), then the sentinel
+  const double* w64;            // sorted FP64 weights, then the sentinel's 0
+  uint32_t sentinel;            // index of the zero-weight sentinel record (total points)
   const uint32_t* cell_start;   // per catalogue nc^3 + 1 entries
   const CatDesc* cats;
   int32_t ncat;
