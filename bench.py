@@ -28,6 +28,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 NB, RMIN, RMAX, LMAX, BOX, N = 20, 10.0, 200.0, 10, 1000.0, 1_000_000
+# HBM counters of the sweep kernel (rocprofv3 FETCH_SIZE / WRITE_SIZE, calibrated on a plain copy)
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "sweep_kernel_lognormal1e6_hbm_traffic.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2604_08855_amd", "csrc", f) for f in ("sweep.hip", "tpcf_internal.h")]
 PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32, published
 F_PAIR = 4 * (LMAX + 1) ** 2  # algorithmic flops per in-range pair (2 to generate + 2 to add)
 F_PRIM = 2 * NB * NB * (LMAX + 1) ** 2  # algorithmic flops per primary for the contraction
@@ -73,6 +76,37 @@ def time_path(tpcf, torch, dev, precision, steps, warmup):
     zc = z.cpu().numpy()
     ctx.close()
     return ms, float(np.mean(sweep_ms)), st, zc
+
+
+def kernel_source_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(precision):
+    """HBM bytes per sweep launch from the committed counter profile, if it was taken on the
+    kernel source as it is now; None otherwise."""
+    if not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_PROFILE):
+        if line.startswith("- `") and "`: " in line:
+            k, v = line[3:].split("`: ", 1)
+            vals[k] = v.strip()
+    if vals.get("source_sha256") != kernel_source_hash():
+        return None
+    try:
+        fetch = float(vals[f"{precision}_fetch_bytes"])
+        write = float(vals[f"{precision}_write_bytes"])
+    except (KeyError, ValueError):
+        return None
+    return {"bytes": fetch + write, "fetch_bytes": fetch, "write_bytes": write,
+            "source": os.path.relpath(TRAFFIC_PROFILE, ROOT)}
 
 
 def cpu_baseline_parallel(cat, w, seconds):
@@ -148,6 +182,7 @@ def main():
 
     flops = pairs * F_PAIR + st["n_primaries"] * F_PRIM
     achieved = flops / (sweep_ms / 1000.0) / 1e12
+    traffic = measured_traffic("mixed")
     out = {
         "metric": "primary-secondary pairs/sec (l_max=10, 20 bins), mixed vs FP64 GPU at 1e-5 rel err",
         "value": value,
@@ -167,6 +202,7 @@ def main():
             "pairs_per_step": pairs,
             "candidates_per_step": st["n_candidates"],
             "cells_per_axis": st["cells_per_axis"],
+            "points_per_cell": N / st["cells_per_axis"] ** 3,
             "waves": st["waves"],
         },
         "fp64": {"value": value64, "unit": "pairs/s", "ms_per_step": ms64, "sweep_ms": sweep64},
@@ -180,7 +216,8 @@ def main():
             "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS,
-            "traffic": None,
+            "traffic": traffic["bytes"] if traffic else None,
+            "traffic_detail": traffic,
             "flops_per_launch": flops,
             "sweep_ms": sweep_ms,
         },

@@ -103,7 +103,7 @@ int tpcf_set_bins(tpcf_ctx* ctx, int nbins, double rmin, double rmax, int lmax);
 int tpcf_set_precision(tpcf_ctx* ctx, int precision);
 
 /*
- * Optional tuning: target mean points per grid cell (default 4; the grid side follows from it
+ * Optional tuning: target mean points per grid cell (default 8; the grid side follows from it
  * and the catalogue density), persistent waves per compute unit (default 8), and scratch blocks
  * of 64 secondaries per wave (default 1024). A value of 0 keeps the default.
  * Errors: TPCF_E_INVALID_ARG for negative values or scratch_blocks not a multiple of 64; a

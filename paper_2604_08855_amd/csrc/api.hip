@@ -63,7 +63,7 @@ struct tpcf_ctx {
   double rmin = 0, rmax = 0;
   int lmax = 0;
   int precision = TPCF_PREC_FP64;
-  double ppc = 4.0;
+  double ppc = 8.0;
   int waves_per_cu = 8;
   int scratch_blocks = 1024;
   bool debug = false;
