@@ -241,7 +241,8 @@ __device__ __forceinline__ int sdiff(uint32_t a, uint32_t b) { return (int)(a - 
 // Unit vector of a secondary's displacement, from the scaled difference (the scale cancels).
 // The tiny addend keeps the zero-weight sentinel record finite when it sits on the primary;
 // it cannot change the squared length of a real pair (>= 1 in lattice units).
-__device__ __forceinline__ void unit(const Primary& P, uint4 r, float& x, float& y, float& z) {
+template <class Rec>
+__device__ __forceinline__ void unit(const Primary& P, Rec r, float& x, float& y, float& z) {
   const float fx = (float)sdiff(r.x, P.qx), fy = (float)sdiff(r.y, P.qy), fz = (float)sdiff(r.z, P.qz);
   const float r2 = __builtin_fmaf(fx, fx, __builtin_fmaf(fy, fy, __builtin_fmaf(fz, fz, 0x1p-100f)));
   const float ri = __builtin_amdgcn_rsqf(r2);
@@ -249,7 +250,8 @@ __device__ __forceinline__ void unit(const Primary& P, uint4 r, float& x, float&
   y = fy * ri;
   z = fz * ri;
 }
-__device__ __forceinline__ void unit(const Primary& P, uint4 r, double& x, double& y, double& z) {
+template <class Rec>
+__device__ __forceinline__ void unit(const Primary& P, Rec r, double& x, double& y, double& z) {
   const double fx = (double)sdiff(r.x, P.qx), fy = (double)sdiff(r.y, P.qy), fz = (double)sdiff(r.z, P.qz);
   const double r2 = fma(fx, fx, fma(fy, fy, fma(fz, fz, 0x1p-100)));
   double ri = __builtin_amdgcn_rsq(r2);
@@ -533,7 +535,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sw
   const int nb = a.nb;
   const int S = a.scratch_blocks;
   const uint32_t wave = blockIdx.x;
-  uint32_t* scratch = a.scratch + (size_t)wave * (S + 1) * kBlock;
+  uint32_t* scratch = a.scratch + (size_t)wave * (S + kScratchTail) * kBlock;
   real* tile = reinterpret_cast<real*>(a.tile) + (size_t)wave * (TP * nb * NC + (LMAX + 1) * nb * nb * (F64 ? 1 : 2));
   double* part = reinterpret_cast<double*>(tile + TP * nb * NC);
 
@@ -761,38 +763,85 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sw
               }
             }
           };
-          // Software pipeline: the record of the next round and the index of the round after
-          // it are in flight while the current round is evaluated. Padding entries hold the
-          // zero-weight sentinel record, so every entry is evaluated alike.
-          uint32_t jn = nblk_b > 1 ? sb[kBlock] : a.sentinel;
-          uint4 r = a.rec[sb[0]];
-          double wd = 0.0;
-          if constexpr (F64) wd = a.w64[sb[0]];
-          int i = 0;
-          auto step = [&](auto WRITE) {
-            uint4 rn = r;
-            double wdn = 0.0;
-            uint32_t jnn = a.sentinel;
-            if (i + 1 < nblk_b) {
-              rn = a.rec[jn];
-              if constexpr (F64) wdn = a.w64[jn];
-              if (i + 2 < nblk_b) jnn = sb[(i + 2) * kBlock];
+          // Padding entries hold the zero-weight sentinel record, so every entry is evaluated
+          // alike.
+          if constexpr (F64) {
+            // FP64 replays every bin once per m-group and loads FP64 weights separately, which
+            // makes its rounds latency-bound: a two-round software pipeline with separate
+            // registers for even and odd rounds (no register copies, so each wait covers only its
+            // own load). As soon as round i has taken its unit vector and weight, the position
+            // and weight of round i + 2 and the index of round i + 4 are requested into that
+            // round's registers. Reads past a bin's last block stay inside the wave's scratch
+            // (kScratchTail spare blocks follow the regions); such entries are replaced by the
+            // sentinel before use.
+            auto idx_at = [&](int k) -> uint32_t { return k < nblk_b ? sb[k * kBlock] : a.sentinel; };
+            auto pos_at = [&](uint32_t j) -> uint3 {
+              const uint4* r = a.rec + j;
+              return make_uint3(r->x, r->y, r->z);
+            };
+            uint3 R0 = pos_at(idx_at(0)), R1 = pos_at(idx_at(1));
+            real W0 = a.w64[idx_at(0)], W1 = a.w64[idx_at(1)];
+            uint32_t J0 = idx_at(2), J1 = idx_at(3);
+            int i = 0;
+            auto step = [&](uint3& R, real& W, uint32_t& J, auto WRITE) {
+              // rounds stay in order, so each waits only for its own loads
+              __builtin_amdgcn_sched_barrier(0);
+              real vx, vy, vz;
+              unit(P0, R, vx, vy, vz);
+              real w = W;
+              // The next loads go into this round's registers: the empty asm statement makes the
+              // record address depend on this round's unit vector and weight, so the loads cannot
+              // be hoisted above their last use.
+              // J holds the raw entry of round i + 2 (read two rounds ago, possibly past the
+              // bin's end): it is range-checked here, at its use.
+              uint32_t jr = i + 2 < nblk_b ? J : a.sentinel;
+              asm volatile("" : "+v"(jr), "+v"(w) : "v"(vx));
+              R = pos_at(jr);
+              W = a.w64[jr];
+              J = sb[(i + 4) * kBlock];
+              add_moments<LMAX, F64, G, decltype(WRITE)::value>(acc, vx, vy, vz, w);
+              ++i;
+            };
+            // chunks of <= 64 rounds (they start at even rounds): the first round of a chunk
+            // stores, the others add
+            while (i < nblk_b) {
+              const int n = min(64, nblk_b - i);
+              step(R0, W0, J0, std::true_type{});
+              for (int q = 0; q < (n - 1) >> 1; ++q) {
+                step(R1, W1, J1, std::false_type{});
+                step(R0, W0, J0, std::false_type{});
+              }
+              if (!(n & 1)) step(R1, W1, J1, std::false_type{});
+              flush_acc();
             }
-            real vx, vy, vz;
-            unit(P0, r, vx, vy, vz);
-            const real w = F64 ? (real)wd : (real)__uint_as_float(r.w);
-            add_moments<LMAX, F64, G, decltype(WRITE)::value>(acc, vx, vy, vz, w);
-            r = rn;
-            wd = wdn;
-            jn = jnn;
-            ++i;
-          };
-          // chunks of <= 64 rounds: the first round of a chunk stores, the others add
-          while (i < nblk_b) {
-            const int n = min(64, nblk_b - i);
-            step(std::true_type{});
-            for (int q = 1; q < n; ++q) step(std::false_type{});
-            flush_acc();
+          } else {
+            // Mixed: one round of software pipeline (the record of the next round and the index
+            // of the round after it are in flight while the current round is evaluated); its
+            // rounds are long enough to cover the latency.
+            uint32_t jn = nblk_b > 1 ? sb[kBlock] : a.sentinel;
+            uint4 r = a.rec[sb[0]];
+            int i = 0;
+            auto step = [&](auto WRITE) {
+              uint4 rn = r;
+              uint32_t jnn = a.sentinel;
+              if (i + 1 < nblk_b) {
+                rn = a.rec[jn];
+                if (i + 2 < nblk_b) jnn = sb[(i + 2) * kBlock];
+              }
+              real vx, vy, vz;
+              unit(P0, r, vx, vy, vz);
+              add_moments<LMAX, F64, G, decltype(WRITE)::value>(acc, vx, vy, vz, __uint_as_float(r.w));
+              r = rn;
+              jn = jnn;
+              ++i;
+            };
+            // chunks of <= 64 rounds: the first round of a chunk stores, the others add
+            while (i < nblk_b) {
+              const int n = min(64, nblk_b - i);
+              step(std::true_type{});
+              for (int q = 1; q < n; ++q) step(std::false_type{});
+              flush_acc();
+            }
           }
 #pragma unroll
           for (int k = 0; k < per; ++k) {

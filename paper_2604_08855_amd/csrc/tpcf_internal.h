@@ -14,6 +14,9 @@ constexpr int kBatch = 4;        // pass rounds evaluated together (one batch of
 // crosses that soft limit still fits, then the shells are replayed and the region emptied.
 constexpr int kSoftReserve = kBatch * kBlock;
 constexpr int kMinRegionBlocks = kBatch + 1;
+// Blocks after a wave's regions: one takes rejected lanes' stores, and the shell replay may
+// read (and discard) up to four blocks past a region's last block.
+constexpr int kScratchTail = 5;
 constexpr int kTileF32 = 32;     // primaries per contraction tile, mixed precision
 constexpr int kTileF64 = 16;     // primaries per contraction tile, FP64
 
@@ -57,8 +60,8 @@ struct SweepArgs {
   const uint32_t* task_list;    // NULL: task t is sorted position t
   uint32_t ntask;
   uint32_t* queue;              // [0] task ticket counter
-  uint32_t* scratch;            // per wave: scratch_blocks + 1 blocks of 64 sorted positions
-  int32_t scratch_blocks;       // blocks per wave in bin regions (the extra block takes rejected lanes' stores)
+  uint32_t* scratch;            // per wave: scratch_blocks + kScratchTail blocks of 64 sorted positions
+  int32_t scratch_blocks;       // blocks per wave in bin regions
   const uint32_t* regions;      // [nb + 1]: bin b owns scratch blocks [regions[b], regions[b+1])
   void* tile;                   // per-wave a_lm tile area
   double* zeta;                 // [ncat][(lmax+1)][nb][nb]
