@@ -10,6 +10,9 @@ One step = the whole hot path on device-resident inputs: lattice snap + cell-gri
 sweep with the a_lm shells, contraction into zeta_l(r1, r2). The same catalogue is also timed on
 the FP64 path (FP64 sweep and FP64 MFMA contraction), and the mixed result is compared with it.
 
+Before the warmup, the library's autotuner picks the grid density and wave count on a 5% sample of
+primaries (outside the timed steps; --no-autotune keeps the defaults).
+
 Prints one JSON line. Options: --steps K --warmup W --gpus N (only 1 is supported)
 --cpu-seconds S (target wall time of the oracle sample; 0 skips the CPU baseline).
 """
@@ -50,8 +53,9 @@ def make_catalog():
     return cat, w
 
 
-def time_path(tpcf, torch, dev, precision, steps, warmup):
-    """Times `steps` hot-path steps; returns (ms_per_step, mean sweep ms, stats, zeta)."""
+def time_path(tpcf, torch, dev, precision, steps, warmup, autotune=True):
+    """Times `steps` hot-path steps; returns (ms_per_step, mean sweep ms, stats, zeta, tuning).
+    The autotuner (if on) runs once before the warmup, outside the timed steps."""
     ctx = tpcf.Context(0, torch.cuda.current_stream())
     ctx.set_bins(NB, RMIN, RMAX, LMAX)
     ctx.set_precision(precision)
@@ -59,6 +63,14 @@ def time_path(tpcf, torch, dev, precision, steps, warmup):
     def step():
         ctx.set_catalog(*dev[:3], dev[3], box=BOX, periodic=True)
         return ctx.compute_zeta(device_output=True)
+
+    tuning = None
+    if autotune:
+        ctx.set_catalog(*dev[:3], dev[3], box=BOX, periodic=True)
+        t0 = time.perf_counter()
+        tuning = ctx.autotune()
+        tuning["seconds"] = time.perf_counter() - t0
+        log(f"[bench] {precision} autotune: {tuning}")
 
     for i in range(warmup):
         step()
@@ -75,7 +87,7 @@ def time_path(tpcf, torch, dev, precision, steps, warmup):
     st = ctx.stats()
     zc = z.cpu().numpy()
     ctx.close()
-    return ms, float(np.mean(sweep_ms)), st, zc
+    return ms, float(np.mean(sweep_ms)), st, zc, tuning
 
 
 def kernel_source_hash():
@@ -141,6 +153,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--fp64-steps", type=int, default=None)
+    ap.add_argument("--no-autotune", action="store_true", help="keep the library's default tuning")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -166,13 +179,14 @@ def main():
         log(f"[bench] calibration copy of {args.copy_calibration_mib} MiB done")
         del src, dst
 
-    ms, sweep_ms, st, zmix = time_path(tpcf, torch, dev, "mixed", args.steps, args.warmup)
+    tune = not args.no_autotune
+    ms, sweep_ms, st, zmix, tmix = time_path(tpcf, torch, dev, "mixed", args.steps, args.warmup, tune)
     pairs = st["n_pairs"]
     value = pairs / (ms / 1000.0)
     log(f"[bench] mixed: {ms:.1f} ms/step, sweep {sweep_ms:.1f} ms, {pairs} pairs, {value:.3e} pairs/s")
 
     f64_steps = args.fp64_steps if args.fp64_steps is not None else max(1, min(args.steps, 3))
-    ms64, sweep64, st64, z64 = time_path(tpcf, torch, dev, "fp64", f64_steps, 1)
+    ms64, sweep64, st64, z64, t64 = time_path(tpcf, torch, dev, "fp64", f64_steps, 1, tune)
     value64 = st64["n_pairs"] / (ms64 / 1000.0)
     log(f"[bench] fp64: {ms64:.1f} ms/step, sweep {sweep64:.1f} ms, {value64:.3e} pairs/s")
     err = []
@@ -204,8 +218,10 @@ def main():
             "cells_per_axis": st["cells_per_axis"],
             "points_per_cell": N / st["cells_per_axis"] ** 3,
             "waves": st["waves"],
+            "tuning": tmix,
         },
-        "fp64": {"value": value64, "unit": "pairs/s", "ms_per_step": ms64, "sweep_ms": sweep64},
+        "fp64": {"value": value64, "unit": "pairs/s", "ms_per_step": ms64, "sweep_ms": sweep64,
+                 "tuning": t64},
         "mixed_over_fp64_speedup": value / value64,
         "max_rel_err_mixed_vs_fp64_per_l": max(err),
         "grid_ms": st["ms_grid"],

@@ -73,6 +73,16 @@ typedef struct tpcf_stats {
     int nbins;
 } tpcf_stats;
 
+/* Tuning picked by tpcf_autotune. */
+typedef struct tpcf_tuning {
+    double points_per_cell; /* grid density */
+    int waves_per_cu;       /* persistent waves per compute unit */
+    int scratch_blocks;     /* scratch blocks of 64 secondaries per wave (unchanged by the tuner) */
+    int candidates;         /* configurations timed */
+    double ms_best;         /* sweep time of the sample with the chosen configuration */
+    double ms_default;      /* sweep time of the sample with the configuration in force before */
+} tpcf_tuning;
+
 /* Library version string, e.g. "tpcf 1.0.0 gfx950". Never NULL. */
 const char* tpcf_version(void);
 
@@ -110,6 +120,21 @@ int tpcf_set_precision(tpcf_ctx* ctx, int precision);
  * compute call with scratch_blocks below 5 x nbins fails with TPCF_E_INVALID_ARG.
  */
 int tpcf_set_tuning(tpcf_ctx* ctx, double points_per_cell, int waves_per_cu, int scratch_blocks);
+
+/*
+ * Autotuner for the persistent sweep. On the catalogue(s) staged by the last tpcf_set_catalog or
+ * tpcf_compute_batch call, with the current bins and precision, it times the sweep over a sample
+ * of primaries (every k-th cell-sorted point, k = round(1 / sample_fraction), so the sample follows
+ * the catalogue's density) for grid densities of 3-24 points per cell and 6 or 8 waves per compute
+ * unit, then keeps the fastest as if set by tpcf_set_tuning. sample_fraction in (0, 1]; 0 means
+ * 0.05. Results of later compute calls do not depend on the tuning. The call synchronises the
+ * context's stream. Stats of the last compute call are kept; its debug output is dropped
+ * (tpcf_debug_pair_counts / tpcf_debug_alm return TPCF_E_STATE until the next compute call with
+ * debug output enabled). out may be NULL.
+ * Errors: TPCF_E_STATE (bins or catalogue missing), TPCF_E_INVALID_ARG (sample_fraction out of
+ * range), TPCF_E_OUT_OF_MEMORY, TPCF_E_DEVICE.
+ */
+int tpcf_autotune(tpcf_ctx* ctx, double sample_fraction, tpcf_tuning* out);
 
 /*
  * One catalogue of n points: positions x, y, z and weights w (w = NULL means unit weights), all

@@ -31,7 +31,7 @@ EXPORTS = [
     "tpcf_version", "tpcf_create", "tpcf_destroy", "tpcf_set_bins", "tpcf_set_precision",
     "tpcf_set_tuning", "tpcf_set_catalog", "tpcf_compute_zeta", "tpcf_compute_zeta_range",
     "tpcf_compute_batch", "tpcf_debug_pair_counts", "tpcf_debug_alm", "tpcf_set_debug",
-    "tpcf_get_stats", "tpcf_last_error",
+    "tpcf_get_stats", "tpcf_last_error", "tpcf_autotune",
 ]
 
 
@@ -39,6 +39,17 @@ class TpcfError(RuntimeError):
     def __init__(self, code: int, message: str):
         super().__init__(f"tpcf error {ERRORS.get(code, code)}: {message}")
         self.code = code
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [
+        ("points_per_cell", ctypes.c_double),
+        ("waves_per_cu", ctypes.c_int),
+        ("scratch_blocks", ctypes.c_int),
+        ("candidates", ctypes.c_int),
+        ("ms_best", ctypes.c_double),
+        ("ms_default", ctypes.c_double),
+    ]
 
 
 class Stats(ctypes.Structure):
@@ -64,7 +75,7 @@ def library_path() -> str:
 def _load() -> ctypes.CDLL:
     if not os.path.exists(_LIB_PATH):
         raise ImportError(
-            f"{_LIB_PATH} is not built: run `python -m paper_2604_08855_amd.build` (needs hipcc)")
+            f"{_LIB_PATH} is not built: run `python paper_2604_08855_amd/build.py` (needs hipcc)")
     # torch wheels bundle their own HIP runtime. Loading torch first lets the library bind to
     # that runtime (same soname), so a process never holds two HIP runtimes side by side.
     try:
@@ -89,7 +100,12 @@ def _load() -> ctypes.CDLL:
         "tpcf_set_debug": ([vp, i], i),
         "tpcf_get_stats": ([vp, ctypes.POINTER(Stats)], i),
         "tpcf_last_error": ([vp], ctypes.c_char_p),
+        "tpcf_autotune": ([vp, d, ctypes.POINTER(Tuning)], i),
     }
+    missing = [name for name in sig if not hasattr(lib, name)]
+    if missing:
+        raise ImportError(f"{_LIB_PATH} is stale (no {', '.join(missing)}): rebuild it with "
+                          "`python paper_2604_08855_amd/build.py`")
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
         f.argtypes = args
@@ -178,6 +194,13 @@ class Context:
     def set_tuning(self, points_per_cell: float = 0.0, waves_per_cu: int = 0, scratch_blocks: int = 0):
         self._check(_lib.tpcf_set_tuning(self._h, float(points_per_cell), int(waves_per_cu),
                                          int(scratch_blocks)))
+
+    def autotune(self, sample_fraction: float = 0.0) -> dict:
+        """Times the sweep on a sample of primaries of the staged catalogue(s) for several grid
+        densities and wave counts and keeps the fastest (see tpcf_autotune)."""
+        t = Tuning()
+        self._check(_lib.tpcf_autotune(self._h, float(sample_fraction), ctypes.byref(t)))
+        return {k: getattr(t, k) for k, _ in Tuning._fields_}
 
     def set_debug(self, enable: bool = True):
         self._check(_lib.tpcf_set_debug(self._h, int(bool(enable))))

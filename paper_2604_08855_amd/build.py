@@ -1,4 +1,5 @@
-"""Builds libtpcf.so (gfx950) in-tree with hipcc. Run: python -m paper_2604_08855_amd.build"""
+"""Builds libtpcf.so (gfx950) in-tree with hipcc. Run: python paper_2604_08855_amd/build.py
+(a standalone script: importing the package needs the library already built)."""
 from __future__ import annotations
 
 import os

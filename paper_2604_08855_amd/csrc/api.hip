@@ -441,6 +441,7 @@ bool grid_current(const tpcf_ctx* c) {
 // Host part of the grid build: grid geometry, stencil rows, buffers, tables on the device.
 int prepare_grid(tpcf_ctx* c) {
   int rc;
+  c->grid_valid = false;  // geometry and tables change: the built grid no longer matches them
   if ((rc = configure_grid(c))) return rc;
   const size_t n = (size_t)c->ntot;
   if ((rc = ensure(c, c->cats_d, c->cd.size() * sizeof(CatDesc), "catalogue table")) ||
@@ -780,6 +781,93 @@ int tpcf_set_tuning(tpcf_ctx* c, double points_per_cell, int waves_per_cu, int s
   if (points_per_cell > 0.0) c->ppc = points_per_cell;
   if (waves_per_cu > 0) c->waves_per_cu = waves_per_cu;
   if (scratch_blocks > 0) c->scratch_blocks = scratch_blocks;
+  c->err.clear();
+  return TPCF_OK;
+}
+
+int tpcf_autotune(tpcf_ctx* c, double sample_fraction, tpcf_tuning* out) {
+  if (!c) return TPCF_E_INVALID_ARG;
+  if (sample_fraction == 0.0) sample_fraction = 0.05;
+  if (!(sample_fraction > 0.0 && sample_fraction <= 1.0))
+    return fail(c, TPCF_E_INVALID_ARG, "sample_fraction must be in (0, 1]");
+  if (!c->bins_set) return fail(c, TPCF_E_STATE, "set_bins has not been called");
+  if (!c->cat_set) return fail(c, TPCF_E_STATE, "no catalogue set");
+  int rc;
+  if ((rc = check_periodic_range(c))) return rc;
+  if ((rc = ensure_device(c))) return rc;
+  const tpcf_stats saved_stats = c->stats;
+  const bool saved_debug = c->debug;
+  const double ppc0 = c->ppc;
+  const int wpc0 = c->waves_per_cu;
+  c->debug = false;
+
+  // Every k-th cell-sorted point. The positions are re-sorted per grid density; any such
+  // stride sample follows the catalogue's density.
+  const uint32_t stride = (uint32_t)std::max(1.0, floor(1.0 / sample_fraction + 0.5));
+  std::vector<uint32_t> list;
+  for (uint64_t s = 0; s < (uint64_t)c->ntot; s += stride) list.push_back((uint32_t)s);
+  const uint32_t ntask = (uint32_t)list.size();
+  if ((rc = ensure(c, c->tasks, std::max<size_t>(1, list.size()) * 4, "task list"))) return rc;
+  if (ntask) HIP_TRY(c, hipMemcpyAsync(c->tasks.p, list.data(), list.size() * 4, hipMemcpyHostToDevice, c->stream));
+
+  // Times one configuration: grid for it, one untimed and one timed sweep of the sample.
+  auto time_config = [&](double ppc, int wpc, double& ms) -> int {
+    c->ppc = ppc;
+    c->waves_per_cu = wpc;
+    int r;
+    if (!grid_current(c)) {
+      if ((r = prepare_grid(c)) || (r = record_grid(c))) return r;
+      mark_grid(c);
+    }
+    SweepArgs a;
+    int waves = 0;
+    if ((r = prepare_sweep(c, (const uint32_t*)c->tasks.p, ntask, a, waves))) return r;
+    if ((r = record_sweep(c, a, waves))) return r;
+    HIP_TRY(c, hipEventRecord(c->ev[2], c->stream));
+    if ((r = record_sweep(c, a, waves))) return r;
+    HIP_TRY(c, hipEventRecord(c->ev[3], c->stream));
+    HIP_TRY(c, hipEventSynchronize(c->ev[3]));
+    float f = 0.f;
+    HIP_TRY(c, hipEventElapsedTime(&f, c->ev[2], c->ev[3]));
+    ms = f;
+    return TPCF_OK;
+  };
+  double ms_default = 0.0;
+  rc = time_config(ppc0, wpc0, ms_default);
+  double best_ms = ms_default, best_ppc = ppc0;
+  int best_wpc = wpc0, tried = 1;
+  const double ppcs[] = {3.0, 4.0, 6.0, 8.0, 12.0, 16.0, 24.0};
+  const int wpcs[] = {8, 6};
+  for (int wi = 0; wi < 2 && rc == TPCF_OK; ++wi)
+    for (int pi = 0; pi < 7 && rc == TPCF_OK; ++pi) {
+      if (ppcs[pi] == ppc0 && wpcs[wi] == wpc0) continue;
+      double ms = 0.0;
+      rc = time_config(ppcs[pi], wpcs[wi], ms);
+      ++tried;
+      if (rc == TPCF_OK && ms < best_ms) {
+        best_ms = ms;
+        best_ppc = ppcs[pi];
+        best_wpc = wpcs[wi];
+      }
+    }
+  c->debug = saved_debug;
+  c->stats = saved_stats;
+  c->dbg_valid = false;  // debug output is kept by sorted position, and the grid was rebuilt
+  if (rc) {
+    c->ppc = ppc0;
+    c->waves_per_cu = wpc0;
+    return rc;
+  }
+  c->ppc = best_ppc;
+  c->waves_per_cu = best_wpc;
+  if (out) {
+    out->points_per_cell = best_ppc;
+    out->waves_per_cu = best_wpc;
+    out->scratch_blocks = c->scratch_blocks;
+    out->candidates = tried;
+    out->ms_best = best_ms;
+    out->ms_default = ms_default;
+  }
   c->err.clear();
   return TPCF_OK;
 }

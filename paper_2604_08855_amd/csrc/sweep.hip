@@ -54,7 +54,6 @@ __device__ __forceinline__ void static_for(F&& f) {
 }
 
 constexpr uint32_t kInvalid = 0xFFFFFFFFu;
-constexpr uint16_t kEnd = 0xFFFFu;
 
 // ------------------------------------------------------------------------------------------
 // Harmonic plan: which m-chains a group holds and where each real component lives.

@@ -69,6 +69,17 @@ def test_precision_and_tuning_validation():
     c.set_tuning(20.0, 4, 256)
 
 
+def test_autotune_validation_on_host():
+    c = _ctx()
+    assert _code(c.autotune, 1.5) == 1
+    assert _code(c.autotune, -0.1) == 1
+    assert _code(c.autotune, float("nan")) == 1
+    assert _code(c.autotune) == 2  # no bins
+    c.set_bins(4, 1.0, 10.0, 2)
+    assert _code(c.autotune, 0.5) == 2  # no catalogue
+    assert "catalogue" in tpcf._lib.tpcf_last_error(c._h).decode()
+
+
 def test_compute_before_setup_is_a_state_error():
     c = _ctx()
     out = np.zeros(1)

@@ -175,6 +175,59 @@ def test_tuning_does_not_change_results(tpcf, tuning):
         np.testing.assert_array_equal(ctx.pair_counts(), ref.counts)
 
 
+def test_settings_changed_between_calls_rebuild_the_grid(tpcf):
+    """One context, one catalogue: new tuning, then new bins, between compute calls. Every call
+    must match the oracle for the settings in force (the cell grid is rebuilt when its
+    geometry changes)."""
+    cat = catalogs.lognormal(5000, 200.0, 41, grid=32)
+    w = catalogs.gaussian_weights(cat.n, 42)
+    ctx = tpcf.Context(0)
+    ctx.set_precision("fp64")
+    ctx.set_debug(True)
+    ctx.set_bins(8, 4.0, 40.0, 5)
+    ctx.set_catalog(cat.x, cat.y, cat.z, w, box=cat.box, periodic=True)
+    ref = oracle.zeta(cat.x, cat.y, cat.z, w, cat.box, True, 8, 4.0, 40.0, 5, want_counts=True)
+    for ppc in (8.0, 2.0, 24.0):
+        ctx.set_tuning(ppc, 0, 0)
+        z = ctx.compute_zeta()
+        say(f"ppc={ppc}", rel_err_per_l(z, ref.zeta).max())
+        assert rel_err_per_l(z, ref.zeta).max() <= TOL["fp64"]
+        np.testing.assert_array_equal(ctx.pair_counts(), ref.counts)
+    ctx.set_bins(6, 2.0, 60.0, 4)
+    ref2 = oracle.zeta(cat.x, cat.y, cat.z, w, cat.box, True, 6, 2.0, 60.0, 4, want_counts=True)
+    z = ctx.compute_zeta()
+    assert rel_err_per_l(z, ref2.zeta).max() <= TOL["fp64"]
+    np.testing.assert_array_equal(ctx.pair_counts(), ref2.counts)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_autotune_keeps_results(tpcf, prec):
+    """The autotuner picks a configuration from its candidate set; results after it still match
+    the oracle, with exact pair counts. Stats of the last compute call are kept; its debug output
+    is dropped."""
+    cat = catalogs.lognormal(6000, 200.0, 31, grid=32)
+    w = catalogs.gaussian_weights(cat.n, 32)
+    ref = oracle.zeta(cat.x, cat.y, cat.z, w, cat.box, True, 10, 4.0, 50.0, 6, want_counts=True)
+    ctx, z0 = run_gpu(tpcf, cat, w, 10, 4.0, 50.0, 6, prec, debug=True)
+    counts0 = ctx.pair_counts()
+    st0 = ctx.stats()
+    t = ctx.autotune(0.25)
+    say("autotune", t)
+    assert t["points_per_cell"] in (3.0, 4.0, 6.0, 8.0, 12.0, 16.0, 24.0)
+    assert t["waves_per_cu"] in (6, 8)
+    assert t["candidates"] == 14
+    assert 0.0 < t["ms_best"] <= t["ms_default"]
+    assert ctx.stats() == st0
+    with pytest.raises(tpcf.TpcfError) as e:
+        ctx.pair_counts()
+    assert e.value.code == 2
+    np.testing.assert_array_equal(counts0, ref.counts)
+    z1 = ctx.compute_zeta()
+    assert rel_err_per_l(z1, ref.zeta).max() <= TOL[prec]
+    np.testing.assert_array_equal(ctx.pair_counts(), ref.counts)
+    assert rel_err_per_l(z0, ref.zeta).max() <= TOL[prec]
+
+
 def test_device_tensors_in_and_out(tpcf):
     import torch
 
