@@ -146,6 +146,114 @@ def cpu_baseline_parallel(cat, w, seconds):
     return r.npairs, k, el, threads
 
 
+def _mock(args):
+    """One batch mock (runs in a worker process, before the parent touches the GPU)."""
+    import catalogs
+
+    i, n = args
+    c = catalogs.lognormal(int(n), BOX, int(i), grid=256)
+    return c.x, c.y, c.z
+
+
+def run_batch(args):
+    """Batch form: independent log-normal mocks (seeds 0..M-1, sizes log-uniform in [2e5, 2e6]
+    from seed 1000), L = 1000 periodic, unit weights, 20 bins [10, 200), l_max = 10, mixed, one
+    persistent launch per call, captured as a HIP graph on a non-default stream and replayed."""
+    import multiprocessing as mp
+
+    import catalogs
+
+    sizes = catalogs.mock_sizes(args.mocks, 2e5, 2e6, 1000)
+    t0 = time.time()
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    with mp.get_context("fork").Pool(workers) as pool:
+        cats = pool.map(_mock, list(enumerate(sizes)), chunksize=1)
+    log(f"[bench] {len(cats)} mocks, {int(sizes.sum())} points generated in {time.time() - t0:.1f}s "
+        f"on {workers} processes")
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+
+    import torch
+
+    import paper_2604_08855_amd as tpcf
+
+    dev = [torch.from_numpy(np.concatenate([c[k] for c in cats])).cuda() for k in range(3)]
+    torch.cuda.synchronize()
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        ctx = tpcf.Context(0, stream)
+        ctx.set_bins(NB, RMIN, RMAX, LMAX)
+        ctx.set_precision("mixed")
+        tuning = None
+        if not args.no_autotune:
+            # tuned on the median-size mock
+            k = int(np.argsort(sizes)[len(sizes) // 2])
+            ctx.set_catalog(*[t[off[k]:off[k + 1]] for t in dev], None, box=BOX, periodic=True)
+            tuning = ctx.autotune()
+            log(f"[bench] batch autotune on mock {k} ({sizes[k]} points): {tuning}")
+        for i in range(args.warmup):
+            ctx.compute_batch(off, *dev, None, BOX, True, device_output=True)
+            stream.synchronize()
+            log(f"[bench] batch warmup {i + 1}/{args.warmup} done")
+        times, sweeps = [], []
+        for i in range(args.steps):
+            t1 = time.perf_counter()
+            zb = ctx.compute_batch(off, *dev, None, BOX, True, device_output=True)
+            stream.synchronize()
+            times.append(time.perf_counter() - t1)
+            sweeps.append(ctx.stats()["ms_sweep"])
+            log(f"[bench] batch step {i + 1}/{args.steps}: {times[-1]:.2f}s")
+        st = ctx.stats()
+        zb = zb.cpu().numpy()
+        # the smallest and largest mock, each run alone, against their batch slices
+        check = {}
+        for k in (int(np.argmin(sizes)), int(np.argmax(sizes))):
+            ctx.set_catalog(*[t[off[k]:off[k + 1]] for t in dev], None, box=BOX, periodic=True)
+            z1 = ctx.compute_zeta(device_output=True).cpu().numpy()
+            check[f"mock{k}_n{int(sizes[k])}"] = float(np.abs(z1 - zb[k]).max() / np.abs(z1).max())
+        ctx.close()
+    ms = float(np.mean(times)) * 1000.0
+    pairs = st["n_pairs"]
+    flops = pairs * F_PAIR + int(sizes.sum()) * F_PRIM
+    achieved = flops / (ms / 1000.0) / 1e12
+    out = {
+        "metric": "primary-secondary pairs/sec (l_max=10, 20 bins), mixed, batch form",
+        "value": pairs / (ms / 1000.0),
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"batch: {args.mocks} log-normal mocks (seeds 0..{args.mocks - 1}), sizes "
+                        "log-uniform [2e5, 2e6] (seed 1000), L=1000 periodic, w=1, 20 bins [10,200), "
+                        "l_max=10, mixed, one persistent launch replayed from a HIP graph",
+            "mocks": args.mocks,
+            "n_points": int(sizes.sum()),
+            "pairs_per_step": pairs,
+            "candidates_per_step": st["n_candidates"],
+            "tuning": tuning,
+        },
+        "graph_ms": float(np.mean(sweeps)),
+        "batch_vs_single_max_rel_diff": check,
+        "roofline": {
+            "bound": "alu",
+            "kernel": "sweep_kernel<10,false>",
+            "achieved": achieved,
+            "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_TFLOPS,
+            "traffic": None,
+            "flops_per_launch": flops,
+        },
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -156,11 +264,17 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="keep the library's default tuning")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (HBM counter calibration)")
+    ap.add_argument("--workload", choices=["single", "batch"], default="single",
+                    help="single: the 1e6-point catalogue (default); batch: the mock batch form")
+    ap.add_argument("--mocks", type=int, default=256, help="batch form: number of mocks")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
               f"(asked for --gpus {args.gpus}).", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch":
+        run_batch(args)
+        return
 
     import torch
 
