@@ -48,6 +48,8 @@ def _load():
         lib.oracle_ylm.restype = i
         lib.oracle_zeta.argtypes = [i64, p, p, p, p, d, i, i, d, d, i, i64, i64, p, p, p, p, i]
         lib.oracle_zeta.restype = i
+        lib.oracle_pair_sums.argtypes = [i64, p, p, p, p, d, i, i, d, d, i64, i64, p, p, i]
+        lib.oracle_pair_sums.restype = i
         _lib = lib
     return _lib
 
@@ -121,6 +123,27 @@ def zeta(x, y, z, w, box: float, periodic: bool, nbins: int, rmin: float, rmax: 
         raise ValueError("oracle_zeta: invalid arguments")
     a = None if alm is None else alm[..., 0] + 1j * alm[..., 1]
     return Result(zt, counts, a, int(npairs.value))
+
+
+def pair_sums(x, y, z, w, box: float, periodic: bool, nbins: int, rmin: float, rmax: float,
+              p_begin: int = 0, p_end: int | None = None, threads: int = 0):
+    """(npairs[nbins] int64, dd[nbins] FP64): ordered pairs per bin and sum of w_p w_j per bin,
+    for primaries [p_begin, p_end) against all secondaries (oracle_pair_sums)."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    n = x.shape[0]
+    w = np.ones(n) if w is None else np.ascontiguousarray(w, dtype=np.float64)
+    if p_end is None:
+        p_end = n
+    npairs = np.zeros(nbins, dtype=np.int64)
+    dd = np.zeros(nbins)
+    rc = _load().oracle_pair_sums(n, _ptr(x), _ptr(y), _ptr(z), _ptr(w), float(box), int(bool(periodic)),
+                                  int(nbins), float(rmin), float(rmax), int(p_begin), int(p_end),
+                                  _ptr(npairs), _ptr(dd), int(threads))
+    if rc:
+        raise ValueError("oracle_pair_sums: invalid arguments")
+    return npairs, dd
 
 
 def zeta_catalog(cat, nbins, rmin, rmax, lmax, **kw) -> Result:

@@ -302,3 +302,68 @@ int oracle_zeta(int64_t n, const double *x, const double *y, const double *z, co
     free(T);
     return 0;
 }
+
+/*
+ * Pair sums per radial bin, the two-point by-product of the same sweep (the paper's second
+ * statistic; Introduction and Features sections): for primaries [p_begin, p_end) and all
+ * secondaries j != p,
+ *     npairs[b] = number of (p, j) with (p, j) in bin b           (exact integer)
+ *     dd[b]     = sum over those pairs of w_p w_j                 (FP64)
+ * with the same lattice binning as oracle_zeta. Returns 0, or 1 on invalid arguments.
+ */
+int oracle_pair_sums(int64_t n, const double *x, const double *y, const double *z, const double *w,
+                     double box, int periodic, int nbins, double rmin, double rmax, int64_t p_begin,
+                     int64_t p_end, int64_t *npairs, double *dd, int nthreads)
+{
+    if (n < 0 || nbins < 1 || !(rmin >= 0.0) || !(rmax > rmin) || !(box > 0.0) || p_begin < 0 ||
+        p_end > n || p_begin > p_end)
+        return 1;
+    const int nb = nbins;
+    for (int b = 0; b < nb; b++) {
+        npairs[b] = 0;
+        dd[b] = 0.0;
+    }
+    if (n == 0 || p_begin == p_end) return 0;
+    int K = oracle_lattice_bits(box, rmax, periodic);
+    int64_t *q = (int64_t *)malloc(sizeof(int64_t) * 3 * (size_t)n);
+    uint64_t *T = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(nb + 1));
+    oracle_snap(n, x, box, K, periodic, q);
+    oracle_snap(n, y, box, K, periodic, q + n);
+    oracle_snap(n, z, box, K, periodic, q + 2 * n);
+    oracle_thresholds(nb, rmin, rmax, box, K, T);
+    problem P = {n, q, q + n, q + 2 * n, w, K, periodic, nb, 0, T};
+
+    /* fixed chunks of primaries, merged in order: the result does not depend on threads */
+    const int64_t np = p_end - p_begin;
+    const int64_t nchunk = np < ORACLE_CHUNKS ? np : ORACLE_CHUNKS;
+    int64_t *cpart = (int64_t *)calloc((size_t)nchunk * nb, sizeof(int64_t));
+    double *dpart = (double *)calloc((size_t)nchunk * nb, sizeof(double));
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t c = 0; c < nchunk; c++) {
+        int64_t lo = p_begin + np * c / nchunk, hi = p_begin + np * (c + 1) / nchunk;
+        for (int64_t p = lo; p < hi; p++)
+            for (int64_t j = 0; j < n; j++) {
+                if (j == p) continue;
+                int64_t d[3];
+                int b = pair_bin(&P, p, j, d);
+                if (b < 0) continue;
+                cpart[c * nb + b] += 1;
+                dpart[c * nb + b] += w[p] * w[j];
+            }
+    }
+    for (int64_t c = 0; c < nchunk; c++)
+        for (int b = 0; b < nb; b++) {
+            npairs[b] += cpart[c * nb + b];
+            dd[b] += dpart[c * nb + b];
+        }
+    free(cpart);
+    free(dpart);
+    free(q);
+    free(T);
+    return 0;
+}

@@ -99,3 +99,13 @@ def pair_counts(x, y, z, box, periodic, nbins, rmin, rmax, primaries=None):
     for p, j, b, u in pair_table(x, y, z, box, periodic, nbins, rmin, rmax, prim):
         counts[idx[p], b] += 1
     return counts
+
+
+def pair_sums(x, y, z, w, box, periodic, nbins, rmin, rmax):
+    """Ordered pairs and sum of w_p w_j per bin, from the pair table (independent route)."""
+    npairs = np.zeros(nbins, dtype=np.int64)
+    dd = np.zeros(nbins)
+    for p, j, b, u in pair_table(x, y, z, box, periodic, nbins, rmin, rmax):
+        npairs[b] += 1
+        dd[b] += w[p] * w[j]
+    return npairs, dd

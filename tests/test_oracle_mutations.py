@@ -35,6 +35,8 @@ MUTANTS = {
     "m = l term dropped": ("for (int m = -l; m <= l; m++) {", "for (int m = -l; m < l; m++) {"),
     "negative m phase": ("((m & 1) ? -1.0 : 1.0) * conj(y)", "conj(y)"),
     "secondary weight dropped": ("a[c] += P->w[j] * conj(Y[c]);", "a[c] += conj(Y[c]);"),
+    "pair sums: primary weight dropped": ("dpart[c * nb + b] += w[p] * w[j];",
+                                          "dpart[c * nb + b] += w[j];"),
 }
 
 
@@ -89,6 +91,13 @@ def _pins():
     z1 = oracle.zeta(Xt[:, 0], Xt[:, 1], Xt[:, 2], w[:60], 60.0, True, 4, 2.0, 20.0, 3).zeta
     if np.max(np.abs(z1 - z0)) > 1e-12 * np.max(np.abs(z0)):
         failed.append("translation")
+    # two-point by-product against the pair table
+    Pc = np.concatenate([P[:40], P[:3]])
+    wc = np.concatenate([w[:40], w[:3]])
+    n_o, d_o = oracle.pair_sums(Pc[:, 0], Pc[:, 1], Pc[:, 2], wc, 50.0, True, 4, 0.0, 20.0)
+    n_b, d_b = brute.pair_sums(Pc[:, 0], Pc[:, 1], Pc[:, 2], wc, 50.0, True, 4, 0.0, 20.0)
+    if not np.array_equal(n_o, n_b) or np.max(np.abs(d_o - d_b)) > 1e-12 * np.max(np.abs(d_b)):
+        failed.append("pair sums")
     return failed
 
 

@@ -115,6 +115,30 @@ def test_pair_counts_exact(periodic):
     assert r.npairs == int(ref.sum())
 
 
+@pytest.mark.parametrize("periodic", [True, False])
+def test_pair_sums_against_brute_force(periodic):
+    """The two-point by-product: ordered pairs per bin (exact) and sum of w_p w_j per bin,
+    against an independent numpy pair table; unit weights give dd == npairs; the totals agree
+    with the multipole oracle's pair count; every unordered pair counts twice."""
+    c = catalogs.lognormal(350, 70.0, 61, grid=16)
+    w = catalogs.gaussian_weights(c.n, 62, 1.0, 0.7)
+    nb, rmin, rmax = 6, 2.0, 25.0
+    npairs, dd = oracle.pair_sums(c.x, c.y, c.z, w, c.box, periodic, nb, rmin, rmax)
+    bn, bdd = brute.pair_sums(c.x, c.y, c.z, w, c.box, periodic, nb, rmin, rmax)
+    np.testing.assert_array_equal(npairs, bn)
+    assert _rel(dd, bdd) < 1e-13
+    assert np.all(npairs % 2 == 0)
+    n1, d1 = oracle.pair_sums(c.x, c.y, c.z, None, c.box, periodic, nb, rmin, rmax)
+    np.testing.assert_array_equal(n1, npairs)
+    np.testing.assert_array_equal(d1, npairs.astype(float))
+    assert oracle.zeta(c.x, c.y, c.z, w, c.box, periodic, nb, rmin, rmax, 0).npairs == int(npairs.sum())
+    # primary ranges add up
+    a = oracle.pair_sums(c.x, c.y, c.z, w, c.box, periodic, nb, rmin, rmax, 0, 100)
+    b = oracle.pair_sums(c.x, c.y, c.z, w, c.box, periodic, nb, rmin, rmax, 100, c.n)
+    np.testing.assert_array_equal(a[0] + b[0], npairs)
+    assert _rel(a[1] + b[1], dd) < 1e-13
+
+
 def test_bin_edges_are_half_open():
     # box 256 and bins [8, 64) of width 8: with K = 27 every edge is a whole number of lattice
     # steps, so separations can sit exactly on an edge. A separation of exactly 16 belongs to
