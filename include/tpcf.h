@@ -200,6 +200,22 @@ int tpcf_debug_pair_counts(tpcf_ctx* ctx, int64_t* counts);
  */
 int tpcf_debug_alm(tpcf_ctx* ctx, double* alm);
 
+/*
+ * Two-point by-product of the last compute call (tpcf_compute_zeta, _range or _batch), per
+ * catalogue c and radial bin b, over that call's primaries and all secondaries:
+ *     npairs[c][b] = ordered (primary, secondary) pairs in bin b, exact;
+ *     dd[c][b]     = sum over those pairs of w_p w_j (FP64 sum of per-primary bin sums, which
+ *                    are the M_00 moments of the shells: FP32 with compensation in the mixed
+ *                    path, FP64 in the FP64 path).
+ * This is the weighted pair count DD(r) of the two-point function the paper computes alongside
+ * the 3PCF (Introduction and Features sections). npairs and dd are host arrays of `capacity`
+ * elements each (either may be NULL); ncat x nbins of the last compute call are written, row-major.
+ * The call synchronises the context's stream.
+ * Errors: TPCF_E_STATE before the first compute call; TPCF_E_INVALID_ARG if capacity is below
+ * ncat x nbins.
+ */
+int tpcf_pair_sums(tpcf_ctx* ctx, int64_t capacity, int64_t* npairs, double* dd);
+
 /* 0 (default) or 1: keep per-primary pair counts and a_lm of the next compute calls. */
 int tpcf_set_debug(tpcf_ctx* ctx, int enable);
 

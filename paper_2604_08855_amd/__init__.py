@@ -31,7 +31,7 @@ EXPORTS = [
     "tpcf_version", "tpcf_create", "tpcf_destroy", "tpcf_set_bins", "tpcf_set_precision",
     "tpcf_set_tuning", "tpcf_set_catalog", "tpcf_compute_zeta", "tpcf_compute_zeta_range",
     "tpcf_compute_batch", "tpcf_debug_pair_counts", "tpcf_debug_alm", "tpcf_set_debug",
-    "tpcf_get_stats", "tpcf_last_error", "tpcf_autotune",
+    "tpcf_get_stats", "tpcf_last_error", "tpcf_autotune", "tpcf_pair_sums",
 ]
 
 
@@ -101,6 +101,7 @@ def _load() -> ctypes.CDLL:
         "tpcf_get_stats": ([vp, ctypes.POINTER(Stats)], i),
         "tpcf_last_error": ([vp], ctypes.c_char_p),
         "tpcf_autotune": ([vp, d, ctypes.POINTER(Tuning)], i),
+        "tpcf_pair_sums": ([vp, i64, vp, vp], i),
     }
     missing = [name for name in sig if not hasattr(lib, name)]
     if missing:
@@ -266,6 +267,15 @@ class Context:
                                             _ptr_np(per), p, mem))
         self.n, self.ncat = int(offsets[-1]), ncat
         return out
+
+    def pair_sums(self):
+        """Two-point by-product of the last compute call: (npairs int64 [ncat, nbins] ordered
+        pairs per bin, dd float64 [ncat, nbins] sum of w_p w_j per bin)."""
+        nb = self.stats()["nbins"]
+        npairs = np.zeros((max(self.ncat, 1), max(nb, 1)), dtype=np.int64)
+        dd = np.zeros(npairs.shape)
+        self._check(_lib.tpcf_pair_sums(self._h, npairs.size, _ptr_np(npairs), _ptr_np(dd)))
+        return npairs, dd
 
     # -- debug and statistics
     def pair_counts(self) -> np.ndarray:

@@ -85,6 +85,9 @@ struct tpcf_ctx {
 
   // sweep buffers
   DevBuf scratch, tile, zeta_d, queue, stats_d, tasks, counts32, alm_dbg, conv_idx, conv32, conv64, regions;
+  DevBuf bin_pairs, bin_dd;  // two-point by-product of the last compute call, [ncat][nbins]
+  bool sums_valid = false;
+  int sums_ncat = 0, sums_nb = 0;
   int conv_lmax = -1;
   int regions_key = -1;
 
@@ -130,7 +133,7 @@ size_t total_bytes(tpcf_ctx* c) {
   DevBuf* all[] = {&c->sx, &c->sy, &c->sz, &c->sw, &c->cats_d, &c->qtmp, &c->cellid, &c->hist,
                    &c->idx_a, &c->idx_b, &c->bsum, &c->errflag, &c->cell_start, &c->rec, &c->w64, &c->perm,
                    &c->scratch, &c->tile, &c->zeta_d, &c->queue, &c->stats_d, &c->tasks, &c->counts32,
-                   &c->alm_dbg, &c->conv_idx, &c->conv32, &c->conv64, &c->regions};
+                   &c->alm_dbg, &c->conv_idx, &c->conv32, &c->conv64, &c->regions, &c->bin_pairs, &c->bin_dd};
   size_t t = 0;
   for (DevBuf* b : all) t += b->bytes;
   return t;
@@ -497,7 +500,9 @@ int prepare_sweep(tpcf_ctx* c, const uint32_t* tasks_d, uint32_t ntask, SweepArg
   if ((rc = ensure(c, c->scratch, (size_t)waves * (S + kScratchTail) * kBlock * 4, "scratch")) ||
       (rc = ensure(c, c->tile, (size_t)waves * sweep_tile_bytes_per_wave(L, nb, f64), "tiles")) ||
       (rc = ensure(c, c->zeta_d, (size_t)ncat * (L + 1) * nb * nb * 8, "zeta")) ||
-      (rc = ensure(c, c->queue, 16, "queue")) || (rc = ensure(c, c->stats_d, 16, "stats")))
+      (rc = ensure(c, c->queue, 16, "queue")) || (rc = ensure(c, c->stats_d, 16, "stats")) ||
+      (rc = ensure(c, c->bin_pairs, (size_t)ncat * nb * 8, "pair sums")) ||
+      (rc = ensure(c, c->bin_dd, (size_t)ncat * nb * 8, "pair sums")))
     return rc;
   if (c->conv_lmax != L) {
     std::vector<int16_t> idx;
@@ -544,6 +549,8 @@ int prepare_sweep(tpcf_ctx* c, const uint32_t* tasks_d, uint32_t ntask, SweepArg
   a.counts = c->debug ? (int32_t*)c->counts32.p : nullptr;
   a.alm_debug = c->debug ? c->alm_dbg.p : nullptr;
   a.stats = (unsigned long long*)c->stats_d.p;
+  a.bin_pairs = (unsigned long long*)c->bin_pairs.p;
+  a.bin_dd = (double*)c->bin_dd.p;
   a.conv_idx = (const int16_t*)c->conv_idx.p;
   a.conv_coef32 = (const float*)c->conv32.p;
   a.conv_coef64 = (const double*)c->conv64.p;
@@ -561,6 +568,8 @@ int record_sweep(tpcf_ctx* c, const SweepArgs& a, int waves) {
   fill_f64((double*)c->zeta_d.p, 0.0, (size_t)a.ncat * (L + 1) * nb * nb, c->stream);
   fill_u32((uint32_t*)c->queue.p, 0u, 4, c->stream);
   fill_u32((uint32_t*)c->stats_d.p, 0u, 4, c->stream);
+  fill_u32((uint32_t*)c->bin_pairs.p, 0u, (size_t)a.ncat * nb * 2, c->stream);
+  fill_f64((double*)c->bin_dd.p, 0.0, (size_t)a.ncat * nb, c->stream);
   if (a.ntask > 0) HIP_TRY(c, launch_sweep(L, f64, a, waves, c->stream));
   return TPCF_OK;
 }
@@ -582,6 +591,9 @@ int finish_stats(tpcf_ctx* c, bool grid_built, uint32_t ntask) {
   c->stats.lmax = c->lmax;
   c->stats.nbins = c->nbins;
   c->dbg_valid = c->debug;
+  c->sums_valid = true;
+  c->sums_ncat = (int)c->cd.size();
+  c->sums_nb = c->nbins;
   c->dbg_f64 = c->precision == TPCF_PREC_FP64;
   c->dbg_nb = c->nbins;
   c->dbg_nc = (c->lmax + 1) * (c->lmax + 1);
@@ -735,7 +747,7 @@ void tpcf_destroy(tpcf_ctx* c) {
     DevBuf* all[] = {&c->sx, &c->sy, &c->sz, &c->sw, &c->cats_d, &c->qtmp, &c->cellid, &c->hist,
                      &c->idx_a, &c->idx_b, &c->bsum, &c->errflag, &c->cell_start, &c->rec, &c->w64, &c->perm,
                      &c->scratch, &c->tile, &c->zeta_d, &c->queue, &c->stats_d, &c->tasks, &c->counts32,
-                     &c->alm_dbg, &c->conv_idx, &c->conv32, &c->conv64, &c->regions};
+                     &c->alm_dbg, &c->conv_idx, &c->conv32, &c->conv64, &c->regions, &c->bin_pairs, &c->bin_dd};
     for (DevBuf* b : all) release(*b);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     for (auto& e : c->ev)
@@ -868,6 +880,18 @@ int tpcf_autotune(tpcf_ctx* c, double sample_fraction, tpcf_tuning* out) {
     out->ms_best = best_ms;
     out->ms_default = ms_default;
   }
+  c->err.clear();
+  return TPCF_OK;
+}
+
+int tpcf_pair_sums(tpcf_ctx* c, int64_t capacity, int64_t* npairs, double* dd) {
+  if (!c) return TPCF_E_INVALID_ARG;
+  if (!c->sums_valid) return fail(c, TPCF_E_STATE, "no compute call yet");
+  const size_t cnt = (size_t)c->sums_ncat * c->sums_nb;
+  if (capacity < (int64_t)cnt) return fail(c, TPCF_E_INVALID_ARG, "capacity below ncat x nbins of the last compute call");
+  if (npairs) HIP_TRY(c, hipMemcpyAsync(npairs, c->bin_pairs.p, cnt * 8, hipMemcpyDeviceToHost, c->stream));
+  if (dd) HIP_TRY(c, hipMemcpyAsync(dd, c->bin_dd.p, cnt * 8, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->err.clear();
   return TPCF_OK;
 }

@@ -553,6 +553,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sw
 
   int tile_n = 0, tile_cat = -1, part_cat = -1, cur_cat = -1;
   unsigned long long my_pairs = 0, my_cand = 0;
+  // Two-point by-product, per wave (lane b < nb: bin b) for catalogue bins_cat: ordered pairs
+  // and sum of w_p w_j. sdd (lane b): sum of w_j of bin b for the current primary.
+  unsigned long long bins_np = 0;
+  double bins_dd = 0.0, sdd = 0.0;
+  int bins_cat = -1;
+  auto flush_bins = [&]() {
+    if (bins_cat >= 0 && lane < nb) {
+      if (bins_np) atomicAdd(&a.bin_pairs[(size_t)bins_cat * nb + lane], bins_np);
+      if (bins_dd != 0.0) atomicAdd(&a.bin_dd[(size_t)bins_cat * nb + lane], bins_dd);
+    }
+    bins_np = 0;
+    bins_dd = 0.0;
+  };
   CatU cu = {};
 
   auto flush_part = [&]() {
@@ -849,6 +862,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sw
           }
         });
         __syncthreads();
+        if (lane == b) sdd += (double)mom[0];  // M_00 = sum of w_j over the bin
         // moments -> normalised a_lm of bin b
         for (int c = lane; c < NC; c += 64) {
           real v = real(0);
@@ -978,6 +992,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sw
 
     uint32_t pairs_p = lane < nb ? btot[lane] : 0u;
     if (a.counts && lane < nb) a.counts[(size_t)p * nb + lane] = (int32_t)pairs_p;
+    if (cat != bins_cat) {
+      flush_bins();
+      bins_cat = cat;
+    }
+    bins_np += pairs_p;
+    bins_dd += (double)wp * sdd;
+    sdd = 0.0;
     for (int off = 32; off > 0; off >>= 1) pairs_p += __shfl_xor(pairs_p, off);
     my_pairs += pairs_p;
     if (a.alm_debug) {
@@ -991,6 +1012,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sw
   }
   do_contract();
   flush_part();
+  flush_bins();
   if (lane == 0) {
     atomicAdd(&a.stats[0], my_pairs);
     atomicAdd(&a.stats[1], my_cand);

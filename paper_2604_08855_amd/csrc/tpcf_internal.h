@@ -68,6 +68,8 @@ struct SweepArgs {
   int32_t* counts;              // optional [total points][nb], by sorted position
   void* alm_debug;              // optional [total points][nb][NC] (float or double), by sorted position
   unsigned long long* stats;    // [0] pairs, [1] candidates
+  unsigned long long* bin_pairs;  // [ncat][nb] ordered pairs per bin
+  double* bin_dd;               // [ncat][nb] sum over pairs of w_p w_j per bin
   // moments -> a_lm: component c = sum_t conv_coef[c][t] * moment[conv_idx[c][t]] (t < kConvTerms)
   const int16_t* conv_idx;
   const float* conv_coef32;

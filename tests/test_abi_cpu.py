@@ -93,6 +93,8 @@ def test_compute_before_setup_is_a_state_error():
     assert rc == 2
     rc = tpcf._lib.tpcf_debug_pair_counts(c._h, out.ctypes.data_as(ctypes.c_void_p))
     assert rc == 2
+    rc = tpcf._lib.tpcf_pair_sums(c._h, 1, None, out.ctypes.data_as(ctypes.c_void_p))
+    assert rc == 2
 
 
 def test_catalog_validation_on_host():

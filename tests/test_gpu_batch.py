@@ -54,8 +54,14 @@ def test_batch_matches_oracle_per_catalogue(tpcf, prec):
     say(f"batch of {len(cats)} catalogues, {off[-1]} points, prec={prec}")
     zb = ctx.compute_batch(off, x, y, z, w, [c.box for c in cats], [c.periodic for c in cats])
     assert zb.shape == (len(cats), L + 1, NB, NB)
+    npairs, dd = ctx.pair_sums()
+    assert npairs.shape == (len(cats), NB)
     for k, c in enumerate(cats):
         ref = oracle.zeta(c.x, c.y, c.z, c.w, c.box, c.periodic, NB, RMIN, RMAX, L).zeta
+        rn, rdd = oracle.pair_sums(c.x, c.y, c.z, c.w, c.box, c.periodic, NB, RMIN, RMAX)
+        np.testing.assert_array_equal(npairs[k], rn)
+        if rn.any():
+            assert np.max(np.abs(dd[k] - rdd)) <= (1e-12 if prec == "fp64" else 2e-6) * np.max(np.abs(rdd))
         if c.n < 2:
             assert not zb[k].any()
             continue

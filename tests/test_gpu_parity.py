@@ -175,6 +175,28 @@ def test_tuning_does_not_change_results(tpcf, tuning):
         np.testing.assert_array_equal(ctx.pair_counts(), ref.counts)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("periodic", [True, False])
+def test_pair_sums_match_oracle(tpcf, prec, periodic):
+    """Two-point by-product: ordered pairs per bin (exact) and sum of w_p w_j per bin, for the
+    whole catalogue and for a primary range."""
+    cat = catalogs.lognormal(5000, 150.0, 71, grid=32, periodic=periodic)
+    w = catalogs.gaussian_weights(cat.n, 72, 1.0, 0.5)
+    tol = 1e-12 if prec == "fp64" else 2e-6
+    ctx, _ = run_gpu(tpcf, cat, w, 9, 3.0, 45.0, 5, prec)
+    for rng in (None, (700, 2345)):
+        if rng is not None:
+            ctx.compute_zeta_range(*rng)
+        npairs, dd = ctx.pair_sums()
+        assert npairs.shape == (1, 9)
+        b0, b1 = rng if rng else (0, cat.n)
+        rn, rdd = oracle.pair_sums(cat.x, cat.y, cat.z, w, cat.box, periodic, 9, 3.0, 45.0, b0, b1)
+        np.testing.assert_array_equal(npairs[0], rn)
+        err = np.max(np.abs(dd[0] - rdd)) / np.max(np.abs(rdd))
+        say(f"pair sums {prec} periodic={periodic} range={rng}: dd rel err {err:.2e}")
+        assert err <= tol
+
+
 def test_settings_changed_between_calls_rebuild_the_grid(tpcf):
     """One context, one catalogue: new tuning, then new bins, between compute calls. Every call
     must match the oracle for the settings in force (the cell grid is rebuilt when its
