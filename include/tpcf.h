@@ -125,7 +125,8 @@ int tpcf_set_tuning(tpcf_ctx* ctx, double points_per_cell, int waves_per_cu, int
  * Autotuner for the persistent sweep. On the catalogue(s) staged by the last tpcf_set_catalog or
  * tpcf_compute_batch call, with the current bins and precision, it times the sweep over a sample
  * of primaries (every k-th cell-sorted point, k = round(1 / sample_fraction), so the sample follows
- * the catalogue's density) for grid densities of 3-24 points per cell and 6 or 8 waves per compute
+ * the catalogue's density; each configuration timed twice after a warm-up, the faster run kept)
+ * for grid densities of 3-24 points per cell and 6 or 8 waves per compute
  * unit, then keeps the fastest as if set by tpcf_set_tuning. sample_fraction in (0, 1]; 0 means
  * 0.05. Results of later compute calls do not depend on the tuning. The call synchronises the
  * context's stream. Stats of the last compute call are kept; its debug output is dropped

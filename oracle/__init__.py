@@ -50,6 +50,8 @@ def _load():
         lib.oracle_zeta.restype = i
         lib.oracle_pair_sums.argtypes = [i64, p, p, p, p, d, i, i, d, d, i64, i64, p, p, i]
         lib.oracle_pair_sums.restype = i
+        lib.oracle_edge_correct.argtypes = [i, i, i, p, p, p]
+        lib.oracle_edge_correct.restype = i
         _lib = lib
     return _lib
 
@@ -144,6 +146,22 @@ def pair_sums(x, y, z, w, box: float, periodic: bool, nbins: int, rmin: float, r
     if rc:
         raise ValueError("oracle_pair_sums: invalid arguments")
     return npairs, dd
+
+
+def edge_correct(N, R):
+    """Edge-corrected multipoles zeta solving M(R) zeta = N / R_0 per bin pair
+    (oracle_edge_correct); N, R: [(lmax+1), nbins, nbins] or [ncat, (lmax+1), nbins, nbins]."""
+    N = np.ascontiguousarray(N, dtype=np.float64)
+    R = np.ascontiguousarray(R, dtype=np.float64)
+    if N.shape != R.shape:
+        raise ValueError("N and R must have the same shape")
+    single = N.ndim == 3
+    N4, R4 = (N[None], R[None]) if single else (N, R)
+    ncat, L1, nb, _ = N4.shape
+    out = np.zeros_like(N4)
+    if _load().oracle_edge_correct(ncat, L1 - 1, nb, _ptr(N4), _ptr(R4), _ptr(out)):
+        raise ValueError("oracle_edge_correct: invalid arguments")
+    return out[0] if single else out
 
 
 def zeta_catalog(cat, nbins, rmin, rmax, lmax, **kw) -> Result:

@@ -367,3 +367,107 @@ int oracle_pair_sums(int64_t n, const double *x, const double *y, const double *
     free(T);
     return 0;
 }
+
+/* Legendre polynomials P_0..P_lmax at x (Bonnet recurrence). */
+static void legendre_all(int lmax, double x, double *P)
+{
+    P[0] = 1.0;
+    if (lmax >= 1) P[1] = x;
+    for (int l = 2; l <= lmax; l++) P[l] = ((2.0 * l - 1.0) * x * P[l - 1] - (l - 1.0) * P[l - 2]) / l;
+}
+
+/* Gauss-Legendre nodes and weights on [-1, 1] (Newton iteration on P_n). */
+static void gauss_legendre(int n, double *x, double *wt)
+{
+    for (int i = 0; i < n; i++) {
+        double t = cos(3.14159265358979323846 * (i + 0.75) / (n + 0.5));
+        double dp = 1.0;
+        for (int it = 0; it < 100; it++) {
+            double p0 = 1.0, p1 = t;
+            for (int k = 2; k <= n; k++) {
+                double pk = ((2.0 * k - 1.0) * t * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = pk;
+            }
+            dp = n * (t * p1 - p0) / (t * t - 1.0);
+            double dt = p1 / dp;
+            t -= dt;
+            if (fabs(dt) < 1e-16) break;
+        }
+        x[i] = t;
+        wt[i] = 2.0 / ((1.0 - t * t) * dp * dp);
+    }
+}
+
+/*
+ * Edge correction of the Legendre multipoles (Slepian & Eisenstein 2015, cited in the paper's
+ * Features section; the paper gives no formula): with N the multipoles of the data-minus-randoms
+ * field and R those of the (weighted) randoms, the corrected 3PCF is zeta(mu) = N(mu) / R(mu)
+ * for every bin pair. In Legendre coefficients, N_L = sum_l'' M_{L l''} zeta_l'' R_0 with
+ *     M_{L l''} = (2L + 1)/2 * integral_{-1}^{1} P_L(mu) P_l''(mu) sum_l' f_l' P_l'(mu) dmu,
+ *     f_l' = R_l' / R_0,
+ * truncated at lmax, and zeta solves M zeta = N / R_0. The integral is taken here by 32-point
+ * Gauss-Legendre quadrature, exact for the integrand's degree (at most 3 lmax <= 48), and the
+ * system is solved by Gaussian elimination with partial pivoting. The zeta_l of the library are
+ * (2l + 1)/(4 pi) times the Legendre sums, the same factor for N and R, so they enter as they are.
+ * Arrays are [ncat][(lmax+1)][nbins][nbins]; bin pairs with R_0 = 0 give 0.
+ * Returns 0, or 1 on invalid arguments.
+ */
+int oracle_edge_correct(int ncat, int lmax, int nbins, const double *N, const double *R, double *zeta)
+{
+    if (ncat < 1 || lmax < 0 || lmax > ORACLE_LMAX_CAP || nbins < 1) return 1;
+    enum { NQ = 32 }; /* exact for polynomial integrands of degree <= 63 */
+    double xq[NQ], wq[NQ], Pq[NQ][ORACLE_LMAX_CAP + 1];
+    gauss_legendre(NQ, xq, wq);
+    for (int i = 0; i < NQ; i++) legendre_all(lmax, xq[i], Pq[i]);
+    const int L1 = lmax + 1, nb = nbins;
+    double M[ORACLE_LMAX_CAP + 1][ORACLE_LMAX_CAP + 2];
+    for (int c = 0; c < ncat; c++)
+        for (int b1 = 0; b1 < nb; b1++)
+            for (int b2 = 0; b2 < nb; b2++) {
+                const size_t base = (size_t)c * L1 * nb * nb + (size_t)b1 * nb + b2;
+#define AT(arr, l) arr[base + (size_t)(l) * nb * nb]
+                const double R0 = AT(R, 0);
+                if (R0 == 0.0) {
+                    for (int l = 0; l < L1; l++) AT(zeta, l) = 0.0;
+                    continue;
+                }
+                /* R(mu) / R_0 at the nodes */
+                double g[NQ];
+                for (int i = 0; i < NQ; i++) {
+                    double s = 0.0;
+                    for (int l = 0; l < L1; l++) s += AT(R, l) / R0 * Pq[i][l];
+                    g[i] = s;
+                }
+                for (int L = 0; L < L1; L++) {
+                    for (int l2 = 0; l2 < L1; l2++) {
+                        double s = 0.0;
+                        for (int i = 0; i < NQ; i++) s += wq[i] * Pq[i][L] * Pq[i][l2] * g[i];
+                        M[L][l2] = 0.5 * (2.0 * L + 1.0) * s;
+                    }
+                    M[L][L1] = AT(N, L) / R0;
+                }
+                /* Gaussian elimination with partial pivoting on the augmented matrix */
+                for (int k = 0; k < L1; k++) {
+                    int piv = k;
+                    for (int r = k + 1; r < L1; r++)
+                        if (fabs(M[r][k]) > fabs(M[piv][k])) piv = r;
+                    for (int j = 0; j <= L1; j++) {
+                        double t = M[k][j];
+                        M[k][j] = M[piv][j];
+                        M[piv][j] = t;
+                    }
+                    for (int r = k + 1; r < L1; r++) {
+                        double f = M[r][k] / M[k][k];
+                        for (int j = k; j <= L1; j++) M[r][j] -= f * M[k][j];
+                    }
+                }
+                for (int k = L1 - 1; k >= 0; k--) {
+                    double s = M[k][L1];
+                    for (int j = k + 1; j < L1; j++) s -= M[k][j] * AT(zeta, j);
+                    AT(zeta, k) = s / M[k][k];
+                }
+#undef AT
+            }
+    return 0;
+}

@@ -822,7 +822,8 @@ int tpcf_autotune(tpcf_ctx* c, double sample_fraction, tpcf_tuning* out) {
   if ((rc = ensure(c, c->tasks, std::max<size_t>(1, list.size()) * 4, "task list"))) return rc;
   if (ntask) HIP_TRY(c, hipMemcpyAsync(c->tasks.p, list.data(), list.size() * 4, hipMemcpyHostToDevice, c->stream));
 
-  // Times one configuration: grid for it, one untimed and one timed sweep of the sample.
+  // Times one configuration: grid for it, one untimed sweep of the sample, then the faster
+  // of two timed sweeps.
   auto time_config = [&](double ppc, int wpc, double& ms) -> int {
     c->ppc = ppc;
     c->waves_per_cu = wpc;
@@ -835,13 +836,16 @@ int tpcf_autotune(tpcf_ctx* c, double sample_fraction, tpcf_tuning* out) {
     int waves = 0;
     if ((r = prepare_sweep(c, (const uint32_t*)c->tasks.p, ntask, a, waves))) return r;
     if ((r = record_sweep(c, a, waves))) return r;
-    HIP_TRY(c, hipEventRecord(c->ev[2], c->stream));
-    if ((r = record_sweep(c, a, waves))) return r;
-    HIP_TRY(c, hipEventRecord(c->ev[3], c->stream));
-    HIP_TRY(c, hipEventSynchronize(c->ev[3]));
-    float f = 0.f;
-    HIP_TRY(c, hipEventElapsedTime(&f, c->ev[2], c->ev[3]));
-    ms = f;
+    ms = 1e30;
+    for (int rep = 0; rep < 2; ++rep) {
+      HIP_TRY(c, hipEventRecord(c->ev[2], c->stream));
+      if ((r = record_sweep(c, a, waves))) return r;
+      HIP_TRY(c, hipEventRecord(c->ev[3], c->stream));
+      HIP_TRY(c, hipEventSynchronize(c->ev[3]));
+      float f = 0.f;
+      HIP_TRY(c, hipEventElapsedTime(&f, c->ev[2], c->ev[3]));
+      ms = std::min(ms, (double)f);
+    }
     return TPCF_OK;
   };
   double ms_default = 0.0;

@@ -37,6 +37,8 @@ MUTANTS = {
     "secondary weight dropped": ("a[c] += P->w[j] * conj(Y[c]);", "a[c] += conj(Y[c]);"),
     "pair sums: primary weight dropped": ("dpart[c * nb + b] += w[p] * w[j];",
                                           "dpart[c * nb + b] += w[j];"),
+    "edge correction: projection factor": ("M[L][l2] = 0.5 * (2.0 * L + 1.0) * s;",
+                                           "M[L][l2] = 0.5 * (2.0 * l2 + 1.0) * s;"),
 }
 
 
@@ -98,6 +100,15 @@ def _pins():
     n_b, d_b = brute.pair_sums(Pc[:, 0], Pc[:, 1], Pc[:, 2], wc, 50.0, True, 4, 0.0, 20.0)
     if not np.array_equal(n_o, n_b) or np.max(np.abs(d_o - d_b)) > 1e-12 * np.max(np.abs(d_b)):
         failed.append("pair sums")
+    # edge correction at l_max = 2 against the hand-written squared-3j coupling matrix
+    f1, f2 = 0.3, -0.2
+    Re = np.zeros((3, 1, 1))
+    Re[:, 0, 0] = [1.0, f1, f2]
+    Me = np.array([[1.0, f1 / 3, f2 / 5], [f1, 3 * (1 / 3 + 2 * f2 / 15), 2 * f1 / 5],
+                   [f2, 2 * f1 / 3, 1 + 2 * f2 / 7]])
+    zt = np.array([0.7, -0.4, 0.25])
+    if np.abs(oracle.edge_correct((Me @ zt)[:, None, None], Re)[:, 0, 0] - zt).max() > 1e-12:
+        failed.append("edge correction")
     return failed
 
 

@@ -139,6 +139,39 @@ def test_pair_sums_against_brute_force(periodic):
     assert _rel(a[1] + b[1], dd) < 1e-13
 
 
+def test_edge_correction_closed_forms():
+    """Edge correction (zeta solves M(R) zeta = N / R_0): an isotropic R gives N / R_0; at
+    l_max = 2 the coupling matrix written out from the standard values of the squared 3j
+    symbols, (0 1 1) = 1/3, (0 2 2) = 1/5, (1 1 2) = 2/15, (2 2 2) = 2/35, inverts a known
+    zeta; scaling N and R scales zeta by their ratio; catalogues are independent."""
+    rng = np.random.default_rng(5)
+    R = np.zeros((4, 3, 3))
+    R[0] = rng.uniform(1.0, 3.0, (3, 3))
+    N = rng.normal(size=(4, 3, 3))
+    assert _rel(oracle.edge_correct(N, R), N / R[0]) < 1e-14
+    f1, f2 = 0.3, -0.2
+    R = np.zeros((3, 1, 1))
+    R[:, 0, 0] = [2.0, 2.0 * f1, 2.0 * f2]
+    M = np.array([[1.0, f1 / 3, f2 / 5],
+                  [f1, 3 * (1 / 3 + 2 * f2 / 15), 3 * 2 * f1 / 15],
+                  [f2, 5 * 2 * f1 / 15, 5 * (1 / 5 + 2 * f2 / 35)]])
+    zt = np.array([0.7, -0.4, 0.25])
+    N = (2.0 * M @ zt)[:, None, None]
+    assert np.abs(oracle.edge_correct(N, R)[:, 0, 0] - zt).max() < 1e-14
+    # scaling and batches
+    R = np.concatenate([R, R], axis=1).repeat(2, axis=2)
+    R[1:] *= 0.5
+    N = rng.normal(size=R.shape)
+    z = oracle.edge_correct(N, R)
+    assert _rel(oracle.edge_correct(3.0 * N, 2.0 * R), 1.5 * z) < 1e-13
+    zb = oracle.edge_correct(np.stack([N, 2 * N]), np.stack([R, R]))
+    assert _rel(zb[0], z) < 1e-15 and _rel(zb[1], 2 * z) < 1e-14
+    # bin pairs without randoms give 0
+    R0 = R.copy()
+    R0[:, 0, 1] = 0.0
+    assert not oracle.edge_correct(N, R0)[:, 0, 1].any()
+
+
 def test_bin_edges_are_half_open():
     # box 256 and bins [8, 64) of width 8: with K = 27 every edge is a whole number of lattice
     # steps, so separations can sit exactly on an edge. A separation of exactly 16 belongs to
