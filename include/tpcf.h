@@ -217,6 +217,22 @@ int tpcf_debug_alm(tpcf_ctx* ctx, double* alm);
  */
 int tpcf_pair_sums(tpcf_ctx* ctx, int64_t capacity, int64_t* npairs, double* dd);
 
+/*
+ * Edge correction for data-minus-randoms fields (Slepian & Eisenstein 2015, the estimator the
+ * paper's Features section cites): N holds the multipoles of the data-minus-randoms field and R
+ * those of the randoms alone (weighted as in N, with the opposite sign), both as returned by the
+ * compute calls with the current bins and l_max, [ncat][(lmax+1)][nbins][nbins]. For every
+ * catalogue and bin pair, zeta receives the Legendre coefficients of N(mu) / R(mu) truncated at
+ * l_max: the solution of M zeta = N / R_0 with M_{L l''} = (2L+1) sum_l' (L l' l''; 0 0 0)^2
+ * R_l' / R_0. Bin pairs with R_0 = 0 give 0. All three arrays are in `memspace`; zeta may alias N
+ * or R. Device arrays are processed in order on the context's stream; host arrays are copied
+ * through the device and the call returns when zeta is written.
+ * Errors: TPCF_E_INVALID_ARG (ncat < 1, NULL arrays, unknown memory space), TPCF_E_STATE (bins
+ * not set), TPCF_E_OUT_OF_MEMORY, TPCF_E_DEVICE.
+ */
+int tpcf_edge_correct(tpcf_ctx* ctx, int ncat, const double* N, const double* R, double* zeta,
+                      int memspace);
+
 /* 0 (default) or 1: keep per-primary pair counts and a_lm of the next compute calls. */
 int tpcf_set_debug(tpcf_ctx* ctx, int enable);
 

@@ -31,7 +31,7 @@ EXPORTS = [
     "tpcf_version", "tpcf_create", "tpcf_destroy", "tpcf_set_bins", "tpcf_set_precision",
     "tpcf_set_tuning", "tpcf_set_catalog", "tpcf_compute_zeta", "tpcf_compute_zeta_range",
     "tpcf_compute_batch", "tpcf_debug_pair_counts", "tpcf_debug_alm", "tpcf_set_debug",
-    "tpcf_get_stats", "tpcf_last_error", "tpcf_autotune", "tpcf_pair_sums",
+    "tpcf_get_stats", "tpcf_last_error", "tpcf_autotune", "tpcf_pair_sums", "tpcf_edge_correct",
 ]
 
 
@@ -102,6 +102,7 @@ def _load() -> ctypes.CDLL:
         "tpcf_last_error": ([vp], ctypes.c_char_p),
         "tpcf_autotune": ([vp, d, ctypes.POINTER(Tuning)], i),
         "tpcf_pair_sums": ([vp, i64, vp, vp], i),
+        "tpcf_edge_correct": ([vp, i, vp, vp, vp, i], i),
     }
     missing = [name for name in sig if not hasattr(lib, name)]
     if missing:
@@ -276,6 +277,30 @@ class Context:
         dd = np.zeros(npairs.shape)
         self._check(_lib.tpcf_pair_sums(self._h, npairs.size, _ptr_np(npairs), _ptr_np(dd)))
         return npairs, dd
+
+    def edge_correct(self, N, R):
+        """Edge-corrected multipoles N(mu)/R(mu) per bin pair (see tpcf_edge_correct). N, R:
+        [(lmax+1), nbins, nbins] or [ncat, (lmax+1), nbins, nbins], numpy (host) or torch
+        CUDA tensors (device); the result has the same shape and kind."""
+        if _is_torch(N):
+            import torch
+            Nt = N.contiguous().to(torch.float64)
+            Rt = R.contiguous().to(torch.float64)
+            if Nt.shape != Rt.shape:
+                raise ValueError("N and R must have the same shape")
+            out = torch.empty_like(Nt)
+            ncat = 1 if Nt.dim() == 3 else Nt.shape[0]
+            self._check(_lib.tpcf_edge_correct(self._h, ncat, ctypes.c_void_p(Nt.data_ptr()),
+                                               ctypes.c_void_p(Rt.data_ptr()),
+                                               ctypes.c_void_p(out.data_ptr()), MEM_DEVICE))
+            return out
+        Na, Ra = _host_f64(N), _host_f64(R)
+        if Na.shape != Ra.shape:
+            raise ValueError("N and R must have the same shape")
+        out = np.zeros_like(Na)
+        ncat = 1 if Na.ndim == 3 else Na.shape[0]
+        self._check(_lib.tpcf_edge_correct(self._h, ncat, _ptr_np(Na), _ptr_np(Ra), _ptr_np(out), MEM_HOST))
+        return out
 
     # -- debug and statistics
     def pair_counts(self) -> np.ndarray:

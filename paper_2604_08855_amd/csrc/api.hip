@@ -28,6 +28,9 @@ void unsort_alm(const void* in, bool f64, const uint32_t* perm, double* out, uin
 hipError_t launch_sweep(int lmax, bool f64, const SweepArgs& args, int waves, hipStream_t stream);
 size_t sweep_lds_bytes(int scratch_blocks, int nb);
 size_t sweep_tile_bytes_per_wave(int lmax, int nb, bool f64);
+std::vector<double> threej_squared_table(int lmax);
+hipError_t launch_edge_correct(int ncat, int lmax, int nb, const double* N, const double* R, const double* t3,
+                               double* out, hipStream_t s);
 }  // namespace tpcf
 
 using namespace tpcf;
@@ -86,6 +89,8 @@ struct tpcf_ctx {
   // sweep buffers
   DevBuf scratch, tile, zeta_d, queue, stats_d, tasks, counts32, alm_dbg, conv_idx, conv32, conv64, regions;
   DevBuf bin_pairs, bin_dd;  // two-point by-product of the last compute call, [ncat][nbins]
+  DevBuf edge_tab, edge_io;  // squared 3j table (for edge_lmax) and host-call staging
+  int edge_lmax = -1;
   bool sums_valid = false;
   int sums_ncat = 0, sums_nb = 0;
   int conv_lmax = -1;
@@ -133,7 +138,8 @@ size_t total_bytes(tpcf_ctx* c) {
   DevBuf* all[] = {&c->sx, &c->sy, &c->sz, &c->sw, &c->cats_d, &c->qtmp, &c->cellid, &c->hist,
                    &c->idx_a, &c->idx_b, &c->bsum, &c->errflag, &c->cell_start, &c->rec, &c->w64, &c->perm,
                    &c->scratch, &c->tile, &c->zeta_d, &c->queue, &c->stats_d, &c->tasks, &c->counts32,
-                   &c->alm_dbg, &c->conv_idx, &c->conv32, &c->conv64, &c->regions, &c->bin_pairs, &c->bin_dd};
+                   &c->alm_dbg, &c->conv_idx, &c->conv32, &c->conv64, &c->regions, &c->bin_pairs, &c->bin_dd,
+                   &c->edge_tab, &c->edge_io};
   size_t t = 0;
   for (DevBuf* b : all) t += b->bytes;
   return t;
@@ -747,7 +753,8 @@ void tpcf_destroy(tpcf_ctx* c) {
     DevBuf* all[] = {&c->sx, &c->sy, &c->sz, &c->sw, &c->cats_d, &c->qtmp, &c->cellid, &c->hist,
                      &c->idx_a, &c->idx_b, &c->bsum, &c->errflag, &c->cell_start, &c->rec, &c->w64, &c->perm,
                      &c->scratch, &c->tile, &c->zeta_d, &c->queue, &c->stats_d, &c->tasks, &c->counts32,
-                     &c->alm_dbg, &c->conv_idx, &c->conv32, &c->conv64, &c->regions, &c->bin_pairs, &c->bin_dd};
+                     &c->alm_dbg, &c->conv_idx, &c->conv32, &c->conv64, &c->regions, &c->bin_pairs, &c->bin_dd,
+                   &c->edge_tab, &c->edge_io};
     for (DevBuf* b : all) release(*b);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     for (auto& e : c->ev)
@@ -896,6 +903,42 @@ int tpcf_pair_sums(tpcf_ctx* c, int64_t capacity, int64_t* npairs, double* dd) {
   if (npairs) HIP_TRY(c, hipMemcpyAsync(npairs, c->bin_pairs.p, cnt * 8, hipMemcpyDeviceToHost, c->stream));
   if (dd) HIP_TRY(c, hipMemcpyAsync(dd, c->bin_dd.p, cnt * 8, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->err.clear();
+  return TPCF_OK;
+}
+
+int tpcf_edge_correct(tpcf_ctx* c, int ncat, const double* N, const double* R, double* zeta, int memspace) {
+  if (!c) return TPCF_E_INVALID_ARG;
+  if (ncat < 1) return fail(c, TPCF_E_INVALID_ARG, "ncat must be >= 1");
+  if (!N || !R || !zeta) return fail(c, TPCF_E_INVALID_ARG, "NULL array");
+  if (memspace != TPCF_MEM_HOST && memspace != TPCF_MEM_DEVICE)
+    return fail(c, TPCF_E_INVALID_ARG, "unknown memory space");
+  if (!c->bins_set) return fail(c, TPCF_E_STATE, "set_bins has not been called");
+  int rc;
+  if ((rc = ensure_device(c))) return rc;
+  const int L = c->lmax, nb = c->nbins;
+  const size_t cnt = (size_t)ncat * (L + 1) * nb * nb;
+  if (c->edge_lmax != L) {
+    const std::vector<double> t = threej_squared_table(L);
+    if ((rc = ensure(c, c->edge_tab, t.size() * 8, "3j table"))) return rc;
+    HIP_TRY(c, hipMemcpyAsync(c->edge_tab.p, t.data(), t.size() * 8, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->edge_lmax = L;
+  }
+  const double* t3 = (const double*)c->edge_tab.p;
+  if (memspace == TPCF_MEM_DEVICE) {
+    HIP_TRY(c, launch_edge_correct(ncat, L, nb, N, R, t3, zeta, c->stream));
+  } else {
+    if ((rc = ensure(c, c->edge_io, cnt * 3 * 8, "edge correction staging"))) return rc;
+    double* dN = (double*)c->edge_io.p;
+    double* dR = dN + cnt;
+    double* dZ = dR + cnt;
+    HIP_TRY(c, hipMemcpyAsync(dN, N, cnt * 8, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(dR, R, cnt * 8, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, launch_edge_correct(ncat, L, nb, dN, dR, t3, dZ, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(zeta, dZ, cnt * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+  }
   c->err.clear();
   return TPCF_OK;
 }

@@ -80,6 +80,16 @@ def test_autotune_validation_on_host():
     assert "catalogue" in tpcf._lib.tpcf_last_error(c._h).decode()
 
 
+def test_edge_correct_validation_on_host():
+    c = _ctx()
+    a = np.zeros((3, 2, 2))
+    p = a.ctypes.data_as(ctypes.c_void_p)
+    assert tpcf._lib.tpcf_edge_correct(c._h, 0, p, p, p, 0) == 1
+    assert tpcf._lib.tpcf_edge_correct(c._h, 1, None, p, p, 0) == 1
+    assert tpcf._lib.tpcf_edge_correct(c._h, 1, p, p, p, 7) == 1
+    assert tpcf._lib.tpcf_edge_correct(c._h, 1, p, p, p, 0) == 2  # bins not set
+
+
 def test_compute_before_setup_is_a_state_error():
     c = _ctx()
     out = np.zeros(1)

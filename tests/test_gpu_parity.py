@@ -197,6 +197,55 @@ def test_pair_sums_match_oracle(tpcf, prec, periodic):
         assert err <= tol
 
 
+def test_edge_correct_matches_oracle_on_random_multipoles(tpcf):
+    """The coupling-matrix solve against the oracle's quadrature route, l_max = 10, two
+    catalogues, host and device arrays, a bin pair without randoms."""
+    import torch
+
+    rng = np.random.default_rng(81)
+    L, nb = 10, 5
+    R = rng.normal(0.0, 0.15, (2, L + 1, nb, nb))
+    R[:, 0] = rng.uniform(0.5, 2.0, (2, nb, nb))
+    R *= R[:, :1]  # f_l = R_l / R_0 stays small
+    R[1, :, 2, 3] = 0.0
+    N = rng.normal(size=(2, L + 1, nb, nb))
+    ref = oracle.edge_correct(N, R)
+    ctx = tpcf.Context(0)
+    ctx.set_bins(nb, 1.0, 10.0, L)
+    z = ctx.edge_correct(N, R)
+    assert np.max(np.abs(z - ref)) <= 1e-12 * np.max(np.abs(ref))
+    assert not z[1, :, 2, 3].any()
+    zd = ctx.edge_correct(torch.from_numpy(N).cuda(), torch.from_numpy(R).cuda())
+    assert zd.is_cuda
+    assert np.max(np.abs(zd.cpu().numpy() - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_edge_corrected_data_minus_randoms(tpcf):
+    """End to end: N from the data-minus-randoms field, R from the randoms alone (weight
+    +N_d/N_r), both on the GPU (FP64), corrected on the GPU; against the oracle's N and R
+    corrected by the oracle."""
+    cat = catalogs.data_minus_randoms(1500, 4500, 120.0, 91, 92, grid=32)
+    nd = 1500
+    nb, rmin, rmax, L = 6, 4.0, 30.0, 6
+    rand = slice(nd, cat.n)
+    wr = -cat.w[rand]
+    ctx = tpcf.Context(0)
+    ctx.set_bins(nb, rmin, rmax, L)
+    ctx.set_precision("fp64")
+    ctx.set_catalog(cat.x, cat.y, cat.z, cat.w, box=cat.box, periodic=False)
+    Ng = ctx.compute_zeta()
+    ctx.set_catalog(cat.x[rand], cat.y[rand], cat.z[rand], wr, box=cat.box, periodic=False)
+    Rg = ctx.compute_zeta()
+    zg = ctx.edge_correct(Ng, Rg)
+    No = oracle.zeta(cat.x, cat.y, cat.z, cat.w, cat.box, False, nb, rmin, rmax, L).zeta
+    Ro = oracle.zeta(cat.x[rand], cat.y[rand], cat.z[rand], wr, cat.box, False, nb, rmin, rmax, L).zeta
+    zo = oracle.edge_correct(No, Ro)
+    assert Ro[0].min() > 0
+    err = rel_err_per_l(zg, zo)
+    say("edge-corrected rel err per l", err)
+    assert err.max() <= 1e-9
+
+
 def test_settings_changed_between_calls_rebuild_the_grid(tpcf):
     """One context, one catalogue: new tuning, then new bins, between compute calls. Every call
     must match the oracle for the settings in force (the cell grid is rebuilt when its
