@@ -285,12 +285,33 @@ def run_dmr(args):
         for i in range(steps):
             t1 = time.perf_counter()
             ctx.set_catalog(*dev, box=cat.box, periodic=False)
-            ctx.compute_zeta(device_output=True)
+            zN = ctx.compute_zeta(device_output=True)
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t1)
             sweeps.append(ctx.stats()["ms_sweep"])
             log(f"[bench] dmr {prec} step {i + 1}/{steps}: {times[-1]:.2f}s")
         st = ctx.stats()
+        npairs, _ = ctx.pair_sums()
+        extra = {"pair_sums_total_equals_pair_count": int(npairs.sum()) == st["n_pairs"]}
+        if prec == "mixed":
+            # randoms alone (weight +N_d/N_r) and the edge-corrected multipoles N / R
+            nd = 4_000_000
+            t1 = time.perf_counter()
+            ctx.set_catalog(dev[0][nd:], dev[1][nd:], dev[2][nd:], -dev[3][nd:], box=cat.box, periodic=False)
+            zR = ctx.compute_zeta(device_output=True)
+            torch.cuda.synchronize()
+            extra["randoms_only_s"] = time.perf_counter() - t1
+            t1 = time.perf_counter()
+            zc = ctx.edge_correct(zN, zR)
+            torch.cuda.synchronize()
+            extra["edge_correct_ms"] = (time.perf_counter() - t1) * 1000.0
+            zrr = ctx.edge_correct(zR, zR).cpu().numpy()
+            unit = np.zeros_like(zrr)
+            unit[0] = 1.0
+            extra["edge_correct_R_over_R_max_abs_dev_from_1"] = float(np.abs(zrr - unit).max())
+            zc = zc.cpu().numpy()
+            extra["edge_corrected_zeta0_diag_first_bins"] = [float(zc[0, b, b]) for b in range(3)]
+            ctx.set_catalog(*dev, box=cat.box, periodic=False)
         errs = []
         for b0, b1 in ranges:
             zg = ctx.compute_zeta_range(b0, b1)
@@ -301,7 +322,7 @@ def run_dmr(args):
         ms = float(np.mean(times)) * 1000.0
         res[prec] = {"value": st["n_pairs"] / (ms / 1000.0), "ms_per_step": ms, "sweep_ms": float(np.mean(sweeps)),
                      "pairs_per_step": st["n_pairs"], "candidates_per_step": st["n_candidates"],
-                     "tuning": tuning, "max_rel_err_vs_oracle_on_sampled_ranges": max(errs)}
+                     "tuning": tuning, "max_rel_err_vs_oracle_on_sampled_ranges": max(errs), **extra}
         log(f"[bench] dmr {prec}: {res[prec]}")
     m = res["mixed"]
     flops = m["pairs_per_step"] * F_PAIR + cat.n * F_PRIM
