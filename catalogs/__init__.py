@@ -84,7 +84,7 @@ def lognormal_field(grid: int, box: float, seed: int, slope: float = -1.5,
         amp = np.where(k2 > 0, k2 ** (slope / 4.0), 0.0)  # sqrt(k^slope) = (k^2)^(slope/4)
     fk *= amp
     del amp, k2
-    g = np.fft.irfftn(fk, s=(grid, grid, grid))
+    g = np.fft.irfftn(fk, s=(grid, grid, grid), axes=(0, 1, 2))
     del fk
     g -= g.mean()
     g *= sigma / g.std()

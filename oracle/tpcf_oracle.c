@@ -471,3 +471,126 @@ int oracle_edge_correct(int ncat, int lmax, int nbins, const double *N, const do
             }
     return 0;
 }
+
+/* ---------------------------------------------------------------- projected fields on the sphere */
+
+/*
+ * Projected scalar fields on the unit sphere, the geometry of the paper's main application
+ * (convergence maps; Statement of need and Features sections) with the triangle's position angle
+ * decomposed in multipoles (Implementation section). Readings where the paper is silent:
+ *   - Positions (ra, dec) in radians become unit vectors n = (cos dec cos ra, cos dec sin ra,
+ *     sin dec) in FP64, are shifted by +2 and snapped to the lattice of the non-periodic cube
+ *     [0, 4)^3, K = 25 + floor(log2(4 / c_max)) capped at 31, c = 2 sin(theta / 2) the chord.
+ *   - Angular bins are linear in theta: theta_k = theta_min + k dtheta, theta_nb = theta_max,
+ *     with chord thresholds T_k = ceil(fl64(fl64(c_k 2^K / 4)^2)), c_k = 2 sin(theta_k / 2);
+ *     a pair is in bin k iff T_k <= R^2 < T_{k+1}, R^2 the exact squared lattice separation.
+ *   - Position angle of j around p: phi = atan2(d.e2, d.e1) with d = q_j - q_p (lattice) and the
+ *     tangent basis at n_p = unit(q_p s - 2): e1 = unit(z x n_p) (unit(x x n_p) within 1e-6 rad
+ *     of the poles), e2 = n_p x e1. zeta_m does not depend on this basis (a rotation of the
+ *     basis multiplies both a_m of a product by the same phase).
+ *   - a_m(p, b) = sum_{j in b} w_j exp(-i m phi_j),
+ *     zeta_m(b1, b2) = sum_p w_p Re[a_m(p, b1) conj(a_m(p, b2))],  0 <= m <= mmax.
+ * Output zeta[(mmax+1)][nbins][nbins]; counts (optional) [p_end-p_begin][nbins].
+ * Returns 0, or 1 on invalid arguments.
+ */
+int oracle_zeta_sphere(int64_t n, const double *ra, const double *dec, const double *w, int nbins,
+                       double theta_min, double theta_max, int mmax, int64_t p_begin, int64_t p_end,
+                       double *zeta, int64_t *counts, int64_t *npairs_out, int nthreads)
+{
+    if (n < 0 || nbins < 1 || mmax < 0 || !(theta_min >= 0.0) || !(theta_max > theta_min) ||
+        !(theta_max <= 3.14159265358979323846) || p_begin < 0 || p_end > n || p_begin > p_end)
+        return 1;
+    const int nb = nbins, M1 = mmax + 1;
+    const size_t zsize = (size_t)M1 * nb * nb;
+    memset(zeta, 0, sizeof(double) * zsize);
+    if (npairs_out) *npairs_out = 0;
+    if (n == 0 || p_begin == p_end) return 0;
+    const double box = 4.0;
+    const int K = oracle_lattice_bits(box, 2.0 * sin(0.5 * theta_max), 0);
+    const double sc = lattice_scale(box, K), s = 1.0 / sc;
+    int64_t *q = (int64_t *)malloc(sizeof(int64_t) * 3 * (size_t)n);
+    for (int64_t i = 0; i < n; i++) {
+        const double v[3] = {cos(dec[i]) * cos(ra[i]), cos(dec[i]) * sin(ra[i]), sin(dec[i])};
+        for (int a = 0; a < 3; a++) q[a * n + i] = snap(v[a] + 2.0, sc, K, 0);
+    }
+    uint64_t *T = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(nb + 1));
+    const double dth = (theta_max - theta_min) / nb;
+    for (int k = 0; k <= nb; k++) {
+        const double th = (k == nb) ? theta_max : theta_min + k * dth;
+        const double v = 2.0 * sin(0.5 * th) * sc;
+        T[k] = (uint64_t)ceil(v * v);
+    }
+    const int64_t np = p_end - p_begin;
+    const int64_t nchunk = np < ORACLE_CHUNKS ? np : ORACLE_CHUNKS;
+    double *part = (double *)calloc((size_t)nchunk * zsize, sizeof(double));
+    int64_t *pairs = (int64_t *)calloc((size_t)nchunk, sizeof(int64_t));
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel
+    {
+        double complex *am = (double complex *)malloc(sizeof(double complex) * (size_t)nb * M1);
+        int64_t *cnt = (int64_t *)malloc(sizeof(int64_t) * (size_t)nb);
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t c = 0; c < nchunk; c++) {
+            int64_t lo = p_begin + np * c / nchunk, hi = p_begin + np * (c + 1) / nchunk;
+            for (int64_t p = lo; p < hi; p++) {
+                memset(am, 0, sizeof(double complex) * (size_t)nb * M1);
+                for (int b = 0; b < nb; b++) cnt[b] = 0;
+                /* tangent basis at the primary's lattice position */
+                double np_[3] = {q[p] * s - 2.0, q[n + p] * s - 2.0, q[2 * n + p] * s - 2.0};
+                const double nn = sqrt(np_[0] * np_[0] + np_[1] * np_[1] + np_[2] * np_[2]);
+                for (int a = 0; a < 3; a++) np_[a] /= nn;
+                double e1[3] = {-np_[1], np_[0], 0.0}; /* z x n */
+                double l1 = sqrt(e1[0] * e1[0] + e1[1] * e1[1]);
+                if (l1 < 1e-6) { /* x x n */
+                    e1[0] = 0.0;
+                    e1[1] = -np_[2];
+                    e1[2] = np_[1];
+                    l1 = sqrt(e1[1] * e1[1] + e1[2] * e1[2]);
+                }
+                for (int a = 0; a < 3; a++) e1[a] /= l1;
+                const double e2[3] = {np_[1] * e1[2] - np_[2] * e1[1], np_[2] * e1[0] - np_[0] * e1[2],
+                                      np_[0] * e1[1] - np_[1] * e1[0]};
+                for (int64_t j = 0; j < n; j++) {
+                    if (j == p) continue;
+                    int64_t d[3];
+                    for (int a = 0; a < 3; a++) d[a] = q[a * n + j] - q[a * n + p];
+                    const uint64_t R2 = (uint64_t)(d[0] * d[0]) + (uint64_t)(d[1] * d[1]) + (uint64_t)(d[2] * d[2]);
+                    if (R2 == 0 || R2 < T[0] || R2 >= T[nb]) continue;
+                    int b = 0;
+                    while (b + 1 < nb && R2 >= T[b + 1]) b++;
+                    const double t1 = d[0] * e1[0] + d[1] * e1[1] + d[2] * e1[2];
+                    const double t2 = d[0] * e2[0] + d[1] * e2[1] + d[2] * e2[2];
+                    const double phi = atan2(t2, t1);
+                    for (int m = 0; m <= mmax; m++) am[b * M1 + m] += w[j] * cexp(-I * (m * phi));
+                    cnt[b]++;
+                    pairs[c]++;
+                }
+                double *z = part + (size_t)c * zsize;
+                for (int m = 0; m <= mmax; m++)
+                    for (int b1 = 0; b1 < nb; b1++)
+                        for (int b2 = 0; b2 < nb; b2++)
+                            z[((size_t)m * nb + b1) * nb + b2] +=
+                                w[p] * creal(am[b1 * M1 + m] * conj(am[b2 * M1 + m]));
+                if (counts)
+                    for (int b = 0; b < nb; b++) counts[(p - p_begin) * nb + b] = cnt[b];
+            }
+        }
+        free(am);
+        free(cnt);
+    }
+    int64_t total = 0;
+    for (int64_t c = 0; c < nchunk; c++) {
+        for (size_t k = 0; k < zsize; k++) zeta[k] += part[(size_t)c * zsize + k];
+        total += pairs[c];
+    }
+    if (npairs_out) *npairs_out = total;
+    free(part);
+    free(pairs);
+    free(q);
+    free(T);
+    return 0;
+}

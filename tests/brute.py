@@ -109,3 +109,71 @@ def pair_sums(x, y, z, w, box, periodic, nbins, rmin, rmax):
         npairs[b] += 1
         dd[b] += w[p] * w[j]
     return npairs, dd
+
+
+# ---------------------------------------------------------------- projected fields on the sphere
+
+def sphere_lattice(ra, dec):
+    """Unit vectors (cos dec cos ra, cos dec sin ra, sin dec) shifted by +2 into the cube
+    [0, 4)^3, before snapping."""
+    v = np.stack([np.cos(dec) * np.cos(ra), np.cos(dec) * np.sin(ra), np.sin(dec)], 1)
+    return v + 2.0
+
+
+def zeta_sphere_triangles(ra, dec, w, nbins, theta_min, theta_max, mmax, primaries=None):
+    """zeta_m on the sphere in the basis-free triangle form
+
+        zeta_m(b1, b2) = sum_p w_p sum_{j in b1} sum_{k in b2} w_j w_k cos(m (phi_j - phi_k)),
+
+    where phi_j - phi_k is the angle between the projections of d_j and d_k on the tangent
+    plane at the primary, so no tangent basis is needed; cos(m x) = T_m(cos x). Also returns
+    the per-primary counts and sums S_p(b) = sum_{j in b} w_j."""
+    from scipy.special import eval_chebyt
+    ra = np.asarray(ra, dtype=np.float64)
+    dec = np.asarray(dec, dtype=np.float64)
+    n = len(ra)
+    w = np.ones(n) if w is None else np.asarray(w, dtype=np.float64)
+    cmax = 2.0 * math.sin(0.5 * theta_max)
+    K = lattice_bits(4.0, cmax, False)
+    X = sphere_lattice(ra, dec)
+    q = np.stack([snap(X[:, a], 4.0, K, False) for a in range(3)], 1)
+    sc = math.ldexp(1.0, K) / 4.0
+    dth = (theta_max - theta_min) / nbins
+    T = []
+    for k in range(nbins + 1):
+        th = theta_max if k == nbins else theta_min + k * dth
+        v = 2.0 * math.sin(0.5 * th) * sc
+        T.append(int(math.ceil(v * v)))
+    zeta = np.zeros((mmax + 1, nbins, nbins))
+    counts = np.zeros((n, nbins), dtype=np.int64)
+    sums = np.zeros((n, nbins))
+    for p in (range(n) if primaries is None else primaries):
+        npv = q[p] / sc - 2.0
+        npv = npv / np.linalg.norm(npv)
+        js, bs, P = [], [], []
+        for j in range(n):
+            if j == p:
+                continue
+            d = [int(a) - int(b) for a, b in zip(q[j], q[p])]
+            R2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2]
+            if R2 == 0 or R2 < T[0] or R2 >= T[-1]:
+                continue
+            b = max(k for k in range(nbins) if T[k] <= R2)
+            dv = np.array(d, dtype=np.float64)
+            perp = dv - (dv @ npv) * npv
+            js.append(j)
+            bs.append(b)
+            P.append(perp / np.linalg.norm(perp))
+            counts[p, b] += 1
+            sums[p, b] += w[j]
+        if not js:
+            continue
+        js, bs, P = np.array(js), np.array(bs), np.array(P)
+        cosd = np.clip(P @ P.T, -1.0, 1.0)
+        ww = np.outer(w[js], w[js])
+        for m in range(mmax + 1):
+            acc = np.zeros((nbins, nbins))
+            np.add.at(acc, (bs[:, None].repeat(len(js), 1), bs[None, :].repeat(len(js), 0)),
+                      eval_chebyt(m, cosd) * ww)
+            zeta[m] += w[p] * acc
+    return zeta, counts, sums

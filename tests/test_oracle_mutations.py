@@ -39,6 +39,13 @@ MUTANTS = {
                                           "dpart[c * nb + b] += w[j];"),
     "edge correction: projection factor": ("M[L][l2] = 0.5 * (2.0 * L + 1.0) * s;",
                                            "M[L][l2] = 0.5 * (2.0 * l2 + 1.0) * s;"),
+    "sphere: angle used as chord": ("const double v = 2.0 * sin(0.5 * th) * sc;",
+                                    "const double v = th * sc;"),
+    "sphere: second tangent vector": ("np_[0] * e1[1] - np_[1] * e1[0]};",
+                                      "np_[0] * e1[1] + np_[1] * e1[0]};"),
+    "sphere: no basis at the pole": ("if (l1 < 1e-6) { /* x x n */", "if (l1 < 0.0) { /* x x n */"),
+    "sphere: primary weight dropped": ("w[p] * creal(am[b1 * M1 + m] * conj(am[b2 * M1 + m]));",
+                                       "creal(am[b1 * M1 + m] * conj(am[b2 * M1 + m]));"),
 }
 
 
@@ -109,6 +116,15 @@ def _pins():
     zt = np.array([0.7, -0.4, 0.25])
     if np.abs(oracle.edge_correct((Me @ zt)[:, None, None], Re)[:, 0, 0] - zt).max() > 1e-12:
         failed.append("edge correction")
+    # sphere: basis-free triangle form, and the pivot at the pole
+    ra = np.concatenate([1.0 + 0.15 * rng.standard_normal(40), rng.random(29) * 2 * np.pi, [0.0]])
+    dec = np.concatenate([0.3 + 0.15 * rng.standard_normal(40), np.pi / 2 - 0.2 * rng.random(29),
+                          [np.pi / 2]])
+    ws = rng.normal(1.0, 0.5, 70)
+    zs = oracle.zeta_sphere(ra, dec, ws, 4, 0.01, 0.3, 5).zeta
+    ref, _, _ = brute.zeta_sphere_triangles(ra, dec, ws, 4, 0.01, 0.3, 5)
+    if not np.all(np.isfinite(zs)) or np.max(np.abs(zs - ref)) > 1e-12 * np.max(np.abs(ref)):
+        failed.append("sphere triangles")
     return failed
 
 
