@@ -242,7 +242,7 @@ def run_batch(args):
         "batch_vs_single_max_rel_diff": check,
         "roofline": {
             "bound": "alu",
-            "kernel": "sweep_kernel<10,false>",
+            "kernel": "sweep_kernel<10,false,false>",
             "achieved": achieved,
             "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s",
@@ -340,10 +340,104 @@ def run_dmr(args):
         "mixed_over_fp64_speedup": m["value"] / res["fp64"]["value"],
         "max_rel_err_vs_oracle_on_sampled_ranges": {k: v["max_rel_err_vs_oracle_on_sampled_ranges"]
                                                     for k, v in res.items()},
-        "roofline": {"bound": "alu", "kernel": "sweep_kernel<10,false>", "achieved": achieved,
+        "roofline": {"bound": "alu", "kernel": "sweep_kernel<10,false,false>", "achieved": achieved,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
                      "traffic": None, "flops_per_launch": flops},
     }
+    print(json.dumps(out), flush=True)
+
+
+def run_sphere(args):
+    """The paper's own geometry: a full-sky HEALPix map, nside 1024 (12,582,912 pixels), map values
+    rho - 1 of a log-normal field (sigma_lnrho 0.5) sampled on the sphere, 20 angular bins in
+    [10, 200) arcmin, m_max = 8; mixed and FP64; three primary ranges checked against the oracle."""
+    import catalogs
+    import oracle
+
+    nside, nb, mmax = 1024, 20, 8
+    arcmin = math.pi / (180.0 * 60.0)
+    tmin, tmax = 10 * arcmin, 200 * arcmin
+    t0 = time.time()
+    m = catalogs.sphere_map(nside, 2604)
+    log(f"[bench] HEALPix nside {nside} map ({m.n} pixels) generated in {time.time() - t0:.1f}s")
+
+    import torch
+
+    import paper_2604_08855_amd as tpcf
+
+    dev = [torch.from_numpy(a).cuda() for a in (m.x, m.y, m.z, m.w)]
+    torch.cuda.synchronize()
+    res = {}
+    ranges = [(0, 24), (m.n // 2, m.n // 2 + 24), (m.n - 24, m.n)]
+    for prec, steps in (("mixed", args.steps), ("fp64", max(1, min(args.steps, 2)))):
+        ctx = tpcf.Context(0, torch.cuda.current_stream())
+        ctx.set_bins(nb, tmin, tmax, mmax)
+        ctx.set_precision(prec)
+        ctx.set_sphere_catalog(*dev)
+        tuning = None if args.no_autotune else ctx.autotune()
+        log(f"[bench] sphere {prec} tuning {tuning}")
+        ctx.compute_zeta(device_output=True)  # warmup
+        torch.cuda.synchronize()
+        times, sweeps = [], []
+        for i in range(steps):
+            t1 = time.perf_counter()
+            ctx.set_sphere_catalog(*dev)
+            ctx.compute_zeta(device_output=True)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t1)
+            sweeps.append(ctx.stats()["ms_sweep"])
+            log(f"[bench] sphere {prec} step {i + 1}/{steps}: {times[-1] * 1000:.1f} ms")
+        st = ctx.stats()
+        npairs, _ = ctx.pair_sums()
+        errs = []
+        for b0, b1 in ranges:
+            zg = ctx.compute_zeta_range(b0, b1)
+            ref = oracle.zeta_sphere(m.x, m.y, m.z, m.w, nb, tmin, tmax, mmax, b0, b1).zeta
+            scale = np.abs(ref).reshape(mmax + 1, -1).max(axis=1)
+            errs.append(float((np.abs(zg - ref).reshape(mmax + 1, -1).max(axis=1) / scale).max()))
+        ctx.close()
+        ms = float(np.mean(times)) * 1000.0
+        res[prec] = {"value": st["n_pairs"] / (ms / 1000.0), "ms_per_step": ms, "sweep_ms": float(np.mean(sweeps)),
+                     "pairs_per_step": st["n_pairs"], "candidates_per_step": st["n_candidates"],
+                     "cells_per_axis": st["cells_per_axis"], "tuning": tuning,
+                     "pair_sums_total_equals_pair_count": int(npairs.sum()) == st["n_pairs"],
+                     "max_rel_err_vs_oracle_on_sampled_ranges": max(errs)}
+        log(f"[bench] sphere {prec}: {res[prec]}")
+    mx = res["mixed"]
+    f_pair = 4 * (2 * mmax + 1)
+    f_prim = 2 * nb * nb * (2 * mmax + 1)
+    flops = mx["pairs_per_step"] * f_pair + m.n * f_prim
+    achieved = flops / (mx["sweep_ms"] / 1000.0) / 1e12
+    out = {
+        "metric": "primary-secondary pairs/sec (m_max=8, 20 angular bins), mixed, full-sky map",
+        "value": mx["value"], "unit": "pairs/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": mx["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "HEALPix nside 1024 full sky (12,582,912 pixels), log-normal map values, "
+                               "20 bins [10,200) arcmin, m_max=8, mixed", "n_points": m.n,
+                   "pairs_per_step": mx["pairs_per_step"], "candidates_per_step": mx["candidates_per_step"],
+                   "cells_per_axis": mx["cells_per_axis"], "tuning": mx["tuning"]},
+        "fp64": res["fp64"],
+        "mixed_over_fp64_speedup": mx["value"] / res["fp64"]["value"],
+        "max_rel_err_vs_oracle_on_sampled_ranges": {k: v["max_rel_err_vs_oracle_on_sampled_ranges"]
+                                                    for k, v in res.items()},
+        "roofline": {"bound": "alu", "kernel": "sweep_kernel<8,false,true>", "achieved": achieved,
+                     "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
+                     "traffic": None, "flops_per_launch": flops, "flops_per_pair": f_pair,
+                     "flops_per_primary": f_prim},
+    }
+    if args.cpu_seconds > 0:
+        threads = len(os.sched_getaffinity(0))
+        t1 = time.perf_counter()
+        r = oracle.zeta_sphere(m.x, m.y, m.z, m.w, nb, tmin, tmax, mmax, 0, threads, threads=threads)
+        per = (time.perf_counter() - t1) / threads
+        k = int(min(m.n, max(threads, args.cpu_seconds / max(per, 1e-6))))
+        t1 = time.perf_counter()
+        r = oracle.zeta_sphere(m.x, m.y, m.z, m.w, nb, tmin, tmax, mmax, 0, k, threads=threads)
+        el = time.perf_counter() - t1
+        out["cpu_baseline"] = {"value": r.npairs / el, "unit": "pairs/s", "cores": threads, "kind": "oracle",
+                               "sample": f"primaries [0, {k}) of the same map against all pixels (brute force "
+                                         f"over all secondaries), FP64, {r.npairs} pairs in {el:.1f}s"}
     print(json.dumps(out), flush=True)
 
 
@@ -357,9 +451,10 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="keep the library's default tuning")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (HBM counter calibration)")
-    ap.add_argument("--workload", choices=["single", "batch", "dmr"], default="single",
+    ap.add_argument("--workload", choices=["single", "batch", "dmr", "sphere"], default="single",
                     help="single: the 1e6-point catalogue (default); batch: the mock batch form; "
-                         "dmr: 4e6 data + 1.6e7 randoms, non-periodic")
+                         "dmr: 4e6 data + 1.6e7 randoms, non-periodic; sphere: a full-sky HEALPix "
+                         "nside 1024 map with angular bins")
     ap.add_argument("--mocks", type=int, default=256, help="batch form: number of mocks")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -371,6 +466,9 @@ def main():
         return
     if args.workload == "dmr":
         run_dmr(args)
+        return
+    if args.workload == "sphere":
+        run_sphere(args)
         return
 
     import torch
@@ -438,7 +536,7 @@ def main():
         "grid_ms": st["ms_grid"],
         "roofline": {
             "bound": "alu",
-            "kernel": "sweep_kernel<10,false>",
+            "kernel": "sweep_kernel<10,false,false>",
             "achieved": achieved,
             "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s",

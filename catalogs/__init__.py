@@ -14,6 +14,15 @@ Workloads (all positions in FP64, box side ``box``):
 * ``mock_sizes``  -- catalogue sizes drawn log-uniform in [lo, hi].
 * ``data_minus_randoms`` -- clustered data plus uniform randoms in a non-periodic cube, the
   randoms weighted -N_d/N_r so that the combined field has zero mean.
+* ``healpix_centres`` -- unit vectors of the pixel centres of a HEALPix map (RING scheme,
+  Gorski et al. 2005): the pixel layout of the maps the paper measures on.
+* ``sphere_field``    -- a log-normal density contrast (rho - 1) sampled at points on the unit
+  sphere from a 3D log-normal field (trilinear interpolation), as map values (convergence-like:
+  zero mean, skewed).
+* ``sphere_map``      -- ``healpix_centres`` with ``sphere_field`` values: a full-sky map.
+* ``sphere_cluster``  -- clustered points on the sphere (Gaussian caps around random centres,
+  the poles included), for small-size parity cases.
+* ``radec_to_unit``   -- (ra, dec) in radians to unit vectors.
 
 The paper measures on HEALPix maps and N-body simulation products that are not available
 here; these generators stand in for them with the shapes, sizes and clustering of the
@@ -31,6 +40,12 @@ __all__ = [
     "mock_sizes",
     "data_minus_randoms",
     "Catalog",
+    "radec_to_unit",
+    "healpix_centres",
+    "sphere_field",
+    "sphere_map",
+    "sphere_cluster",
+    "SphereMap",
 ]
 
 
@@ -149,3 +164,117 @@ def data_minus_randoms(n_data: int, n_rand: int, box: float, seed_data: int, see
     w = np.concatenate([np.ones(n_data), np.full(n_rand, -n_data / n_rand)])
     return Catalog(x, y, z, w, box, False,
                    f"data_minus_randoms(nd={n_data},nr={n_rand},box={box})")
+
+
+# ---------------------------------------------------------------- the unit sphere
+
+class SphereMap:
+    """Plain container of a field on the unit sphere: unit vectors x, y, z and values w."""
+
+    def __init__(self, x, y, z, w, name=""):
+        self.x = np.ascontiguousarray(x, dtype=np.float64)
+        self.y = np.ascontiguousarray(y, dtype=np.float64)
+        self.z = np.ascontiguousarray(z, dtype=np.float64)
+        self.w = np.ascontiguousarray(w, dtype=np.float64)
+        self.name = name
+
+    @property
+    def n(self) -> int:
+        return int(self.x.shape[0])
+
+
+def radec_to_unit(ra, dec):
+    """(cos dec cos ra, cos dec sin ra, sin dec) as three float64 arrays."""
+    ra = np.asarray(ra, dtype=np.float64)
+    dec = np.asarray(dec, dtype=np.float64)
+    c = np.cos(dec)
+    return (np.ascontiguousarray(c * np.cos(ra)), np.ascontiguousarray(c * np.sin(ra)),
+            np.ascontiguousarray(np.sin(dec)))
+
+
+def healpix_centres(nside: int):
+    """Unit vectors of the 12 nside^2 pixel centres of a HEALPix map, RING order.
+
+    Rings i = 1..4 nside - 1 from the north pole. Polar caps (i < nside, and the mirror rings
+    i > 3 nside): z = +-(1 - k^2 / (3 nside^2)) with k = i or 4 nside - i, 4k pixels at
+    phi = (pi / (2k)) (j - 1/2). Equatorial belt (nside <= i <= 3 nside): z = 4/3 - 2i / (3 nside),
+    4 nside pixels at phi = (pi / (2 nside)) (j - s/2), s = (i - nside + 1) mod 2, j = 1..4 nside.
+    """
+    ns = int(nside)
+    zs, phis = [], []
+    for i in range(1, 4 * ns):
+        if i < ns or i > 3 * ns:
+            k = i if i < ns else 4 * ns - i
+            z = 1.0 - k * k / (3.0 * ns * ns)
+            if i > 3 * ns:
+                z = -z
+            j = np.arange(1, 4 * k + 1, dtype=np.float64)
+            phi = (np.pi / (2.0 * k)) * (j - 0.5)
+        else:
+            z = 4.0 / 3.0 - 2.0 * i / (3.0 * ns)
+            sft = (i - ns + 1) % 2
+            j = np.arange(1, 4 * ns + 1, dtype=np.float64)
+            phi = (np.pi / (2.0 * ns)) * (j - 0.5 * sft)
+        zs.append(np.full(phi.shape, z))
+        phis.append(phi)
+    z = np.concatenate(zs)
+    phi = np.concatenate(phis)
+    st = np.sqrt(np.maximum(0.0, (1.0 - z) * (1.0 + z)))
+    x, y = st * np.cos(phi), st * np.sin(phi)
+    # unit length to rounding: renormalise so |v|^2 = 1 within a few ulp
+    r = np.sqrt(x * x + y * y + z * z)
+    return (np.ascontiguousarray(x / r), np.ascontiguousarray(y / r), np.ascontiguousarray(z / r))
+
+
+def sphere_field(x, y, z, seed: int, grid: int = 256, slope: float = -1.5, sigma: float = 0.5) -> np.ndarray:
+    """rho - 1 of a log-normal field (``lognormal_field`` on a periodic grid^3 mesh of side 2.5
+    centred on the origin) at the unit vectors (x, y, z), trilinear interpolation."""
+    side = 2.5
+    rho = lognormal_field(grid, side, seed, slope, sigma)
+    h = side / grid
+    out = np.empty(len(x))
+    step = 1 << 22
+    for a in range(0, len(x), step):
+        b = min(len(x), a + step)
+        u = np.stack([x[a:b], y[a:b], z[a:b]], 1) * (1.0 / h) + (0.5 * side / h - 0.5)
+        i0 = np.floor(u).astype(np.int64)
+        f = u - i0
+        i0 %= grid
+        i1 = (i0 + 1) % grid
+        acc = np.zeros(b - a)
+        for cx in (0, 1):
+            ix = i1[:, 0] if cx else i0[:, 0]
+            wx = f[:, 0] if cx else 1.0 - f[:, 0]
+            for cy in (0, 1):
+                iy = i1[:, 1] if cy else i0[:, 1]
+                wy = f[:, 1] if cy else 1.0 - f[:, 1]
+                for cz in (0, 1):
+                    iz = i1[:, 2] if cz else i0[:, 2]
+                    wz = f[:, 2] if cz else 1.0 - f[:, 2]
+                    acc += wx * wy * wz * rho[ix, iy, iz]
+        out[a:b] = acc - 1.0
+    return out
+
+
+def sphere_map(nside: int, seed: int, grid: int = 256, sigma: float = 0.5) -> SphereMap:
+    """A full-sky HEALPix map (``healpix_centres``) with ``sphere_field`` values."""
+    x, y, z = healpix_centres(nside)
+    w = sphere_field(x, y, z, seed, grid=grid, sigma=sigma)
+    return SphereMap(x, y, z, w, f"healpix(nside={nside},seed={seed})")
+
+
+def sphere_cluster(n: int, seed: int, ncentre: int = 8, spread: float = 0.1) -> SphereMap:
+    """n points in Gaussian caps (angular sd ``spread``) around ``ncentre`` random centres, the
+    two poles among them, and the exact north pole as the last point; weights N(1, 0.5^2)."""
+    rng = np.random.default_rng(seed)
+    c = rng.normal(size=(ncentre, 3))
+    c[0] = (0.0, 0.0, 1.0)
+    c[1 % ncentre] = (0.0, 0.0, -1.0) if ncentre > 1 else c[1 % ncentre]
+    c /= np.linalg.norm(c, axis=1)[:, None]
+    k = rng.integers(0, ncentre, n - 1)
+    v = c[k] + spread * rng.normal(size=(n - 1, 3))
+    v = np.concatenate([v, [[0.0, 0.0, 1.0]]])
+    v /= np.linalg.norm(v, axis=1)[:, None]
+    w = rng.normal(1.0, 0.5, n)
+    return SphereMap(v[:, 0], v[:, 1], v[:, 2], w, f"sphere_cluster(n={n},seed={seed})")
+

@@ -100,7 +100,8 @@ void tpcf_destroy(tpcf_ctx* ctx);
 
 /*
  * Radial bins and multipole order. nbins in [1, TPCF_MAX_NBINS], 0 <= rmin < rmax (finite),
- * lmax in [0, TPCF_MAX_LMAX]. Errors: TPCF_E_INVALID_ARG.
+ * lmax in [0, TPCF_MAX_LMAX]. With a catalogue on the sphere (tpcf_set_sphere_catalog) rmin and
+ * rmax are angles in radians (rmax <= pi) and lmax is m_max. Errors: TPCF_E_INVALID_ARG.
  */
 int tpcf_set_bins(tpcf_ctx* ctx, int nbins, double rmin, double rmax, int lmax);
 
@@ -150,6 +151,33 @@ int tpcf_autotune(tpcf_ctx* ctx, double sample_fraction, tpcf_tuning* out);
  */
 int tpcf_set_catalog(tpcf_ctx* ctx, int64_t n, const double* x, const double* y, const double* z,
                      const double* w, double box, int periodic, int memspace);
+
+/*
+ * One projected scalar field on the unit sphere (the paper's own geometry: pixels or galaxies of
+ * a map; Statement of need, Features and Performance sections): n unit vectors x, y, z (FP64,
+ * |v|^2 within 1e-6 of 1) with field values w (NULL = unit weights), in `memspace`. Replaces the
+ * catalogue of the context; the compute calls then return the 2D multipoles of the position
+ * angle phi of each secondary around its primary,
+ *
+ *     a_m(p, b)      = sum_{j in bin b} w_j exp(-i m phi_pj),                 0 <= m <= m_max,
+ *     zeta_m(b1, b2) = sum_p w_p Re[a_m(p, b1) conj(a_m(p, b2))],
+ *
+ * as double [(m_max+1)][nbins][nbins], with the bins of tpcf_set_bins read as angles: linear,
+ * half-open [theta_min + k D, theta_min + (k+1) D) in radians. Conventions: the unit vectors are
+ * shifted by +2 and snapped to the lattice of the non-periodic cube [0, 4)^3 with
+ * K = 25 + floor(log2(4 / c_max)) (capped at 31) bits, c = 2 sin(theta / 2) the chord; a pair is
+ * in bin k iff T_k <= R^2 < T_{k+1}, R^2 the exact squared lattice separation and
+ * T_k = ceil(fl(fl(2 sin(theta_k / 2) 2^K / 4)^2)), so pair counts are exact; phi is measured
+ * from a tangent basis at the primary's lattice position, which zeta_m does not depend on.
+ * Debug a_m (tpcf_debug_alm) has 2 m_max + 1 components per bin: Re a_0, then Re a_m, Im a_m
+ * (index 2m - 1, 2m). tpcf_pair_sums reports the angular bins; tpcf_edge_correct (3D coupling)
+ * is refused. The call synchronises the context's stream.
+ * Errors: TPCF_E_INVALID_ARG (n < 0, n >= 2^31, NULL arrays with n > 0, a non-finite value, a
+ * vector that is not a unit vector, rmax > pi when bins are already set), TPCF_E_OUT_OF_MEMORY,
+ * TPCF_E_DEVICE.
+ */
+int tpcf_set_sphere_catalog(tpcf_ctx* ctx, int64_t n, const double* x, const double* y,
+                            const double* z, const double* w, int memspace);
 
 /*
  * zeta for the catalogue set by tpcf_set_catalog: every point is a primary and a secondary.
@@ -228,7 +256,8 @@ int tpcf_pair_sums(tpcf_ctx* ctx, int64_t capacity, int64_t* npairs, double* dd)
  * or R. Device arrays are processed in order on the context's stream; host arrays are copied
  * through the device and the call returns when zeta is written.
  * Errors: TPCF_E_INVALID_ARG (ncat < 1, NULL arrays, unknown memory space), TPCF_E_STATE (bins
- * not set), TPCF_E_OUT_OF_MEMORY, TPCF_E_DEVICE.
+ * not set), TPCF_E_UNSUPPORTED (the context holds a catalogue on the sphere),
+ * TPCF_E_OUT_OF_MEMORY, TPCF_E_DEVICE.
  */
 int tpcf_edge_correct(tpcf_ctx* ctx, int ncat, const double* N, const double* R, double* zeta,
                       int memspace);

@@ -52,7 +52,7 @@ def _load():
         lib.oracle_pair_sums.restype = i
         lib.oracle_edge_correct.argtypes = [i, i, i, p, p, p]
         lib.oracle_edge_correct.restype = i
-        lib.oracle_zeta_sphere.argtypes = [i64, p, p, p, i, d, d, i, i64, i64, p, p, p, i]
+        lib.oracle_zeta_sphere.argtypes = [i64, p, p, p, p, i, d, d, i, i64, i64, p, p, p, i]
         lib.oracle_zeta_sphere.restype = i
         _lib = lib
     return _lib
@@ -166,21 +166,20 @@ def edge_correct(N, R):
     return out[0] if single else out
 
 
-def zeta_sphere(ra, dec, w, nbins: int, theta_min: float, theta_max: float, mmax: int,
+def zeta_sphere(x, y, z, w, nbins: int, theta_min: float, theta_max: float, mmax: int,
                 p_begin: int = 0, p_end: int | None = None, want_counts: bool = False,
                 threads: int = 0) -> Result:
-    """zeta_m(b1, b2), m = 0..mmax, of a projected field on the unit sphere (angles in
-    radians), primaries [p_begin, p_end) against all points (oracle_zeta_sphere)."""
-    ra = np.ascontiguousarray(ra, dtype=np.float64)
-    dec = np.ascontiguousarray(dec, dtype=np.float64)
-    n = ra.shape[0]
+    """zeta_m(b1, b2), m = 0..mmax, of a projected field on the unit sphere (unit vectors x, y, z;
+    angles in radians), primaries [p_begin, p_end) against all points (oracle_zeta_sphere)."""
+    x, y, z = (np.ascontiguousarray(a, dtype=np.float64) for a in (x, y, z))
+    n = x.shape[0]
     w = np.ones(n) if w is None else np.ascontiguousarray(w, dtype=np.float64)
     if p_end is None:
         p_end = n
     zt = np.zeros((mmax + 1, nbins, nbins))
     counts = np.zeros((p_end - p_begin, nbins), dtype=np.int64) if want_counts else None
     npairs = ctypes.c_int64(0)
-    rc = _load().oracle_zeta_sphere(n, _ptr(ra), _ptr(dec), _ptr(w), int(nbins), float(theta_min),
+    rc = _load().oracle_zeta_sphere(n, _ptr(x), _ptr(y), _ptr(z), _ptr(w), int(nbins), float(theta_min),
                                     float(theta_max), int(mmax), int(p_begin), int(p_end), _ptr(zt),
                                     _ptr(counts) if counts is not None else None, ctypes.byref(npairs),
                                     int(threads))

@@ -478,9 +478,9 @@ int oracle_edge_correct(int ncat, int lmax, int nbins, const double *N, const do
  * Projected scalar fields on the unit sphere, the geometry of the paper's main application
  * (convergence maps; Statement of need and Features sections) with the triangle's position angle
  * decomposed in multipoles (Implementation section). Readings where the paper is silent:
- *   - Positions (ra, dec) in radians become unit vectors n = (cos dec cos ra, cos dec sin ra,
- *     sin dec) in FP64, are shifted by +2 and snapped to the lattice of the non-periodic cube
- *     [0, 4)^3, K = 25 + floor(log2(4 / c_max)) capped at 31, c = 2 sin(theta / 2) the chord.
+ *   - Positions are unit vectors n (FP64), shifted by +2 and snapped to the lattice of the
+ *     non-periodic cube [0, 4)^3, K = 25 + floor(log2(4 / c_max)) capped at 31, c = 2 sin(theta / 2)
+ *     the chord.
  *   - Angular bins are linear in theta: theta_k = theta_min + k dtheta, theta_nb = theta_max,
  *     with chord thresholds T_k = ceil(fl64(fl64(c_k 2^K / 4)^2)), c_k = 2 sin(theta_k / 2);
  *     a pair is in bin k iff T_k <= R^2 < T_{k+1}, R^2 the exact squared lattice separation.
@@ -493,7 +493,7 @@ int oracle_edge_correct(int ncat, int lmax, int nbins, const double *N, const do
  * Output zeta[(mmax+1)][nbins][nbins]; counts (optional) [p_end-p_begin][nbins].
  * Returns 0, or 1 on invalid arguments.
  */
-int oracle_zeta_sphere(int64_t n, const double *ra, const double *dec, const double *w, int nbins,
+int oracle_zeta_sphere(int64_t n, const double *x, const double *y, const double *z, const double *w, int nbins,
                        double theta_min, double theta_max, int mmax, int64_t p_begin, int64_t p_end,
                        double *zeta, int64_t *counts, int64_t *npairs_out, int nthreads)
 {
@@ -510,7 +510,7 @@ int oracle_zeta_sphere(int64_t n, const double *ra, const double *dec, const dou
     const double sc = lattice_scale(box, K), s = 1.0 / sc;
     int64_t *q = (int64_t *)malloc(sizeof(int64_t) * 3 * (size_t)n);
     for (int64_t i = 0; i < n; i++) {
-        const double v[3] = {cos(dec[i]) * cos(ra[i]), cos(dec[i]) * sin(ra[i]), sin(dec[i])};
+        const double v[3] = {x[i], y[i], z[i]};
         for (int a = 0; a < 3; a++) q[a * n + i] = snap(v[a] + 2.0, sc, K, 0);
     }
     uint64_t *T = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(nb + 1));

@@ -32,6 +32,7 @@ EXPORTS = [
     "tpcf_set_tuning", "tpcf_set_catalog", "tpcf_compute_zeta", "tpcf_compute_zeta_range",
     "tpcf_compute_batch", "tpcf_debug_pair_counts", "tpcf_debug_alm", "tpcf_set_debug",
     "tpcf_get_stats", "tpcf_last_error", "tpcf_autotune", "tpcf_pair_sums", "tpcf_edge_correct",
+    "tpcf_set_sphere_catalog",
 ]
 
 
@@ -103,6 +104,7 @@ def _load() -> ctypes.CDLL:
         "tpcf_autotune": ([vp, d, ctypes.POINTER(Tuning)], i),
         "tpcf_pair_sums": ([vp, i64, vp, vp], i),
         "tpcf_edge_correct": ([vp, i, vp, vp, vp, i], i),
+        "tpcf_set_sphere_catalog": ([vp, i64, vp, vp, vp, vp, i], i),
     }
     missing = [name for name in sig if not hasattr(lib, name)]
     if missing:
@@ -159,6 +161,7 @@ class Context:
         self.nbins = self.lmax = None
         self.n = 0
         self.ncat = 0
+        self.sphere = False
         self._keep = []
 
     # -- plumbing
@@ -233,7 +236,18 @@ class Context:
             raise ValueError("x, y, z, w must have the same length")
         ptrs, mem, keep = self._arrays(x, y, z, w)
         self._check(_lib.tpcf_set_catalog(self._h, int(n), *ptrs, float(box), int(bool(periodic)), mem))
-        self.n, self.ncat = n, 1
+        self.n, self.ncat, self.sphere = n, 1, False
+
+    def set_sphere_catalog(self, x, y, z, w=None):
+        """A projected field on the unit sphere: unit vectors x, y, z and field values w (see
+        tpcf_set_sphere_catalog). The bins of set_bins are then angles in radians and lmax is
+        m_max; compute_zeta returns zeta_m(b1, b2), m = 0..m_max."""
+        n = len(x)
+        if len(y) != n or len(z) != n or (w is not None and len(w) != n):
+            raise ValueError("x, y, z, w must have the same length")
+        ptrs, mem, keep = self._arrays(x, y, z, w)
+        self._check(_lib.tpcf_set_sphere_catalog(self._h, int(n), *ptrs, mem))
+        self.n, self.ncat, self.sphere = n, 1, True
 
     # -- compute
     def _out(self, like_device: bool, shape):
@@ -266,7 +280,7 @@ class Context:
             raise ValueError("batch inputs and output must be in the same memory space")
         self._check(_lib.tpcf_compute_batch(self._h, ncat, _ptr_np(offsets), *ptrs, _ptr_np(box),
                                             _ptr_np(per), p, mem))
-        self.n, self.ncat = int(offsets[-1]), ncat
+        self.n, self.ncat, self.sphere = int(offsets[-1]), ncat, False
         return out
 
     def pair_sums(self):
@@ -309,15 +323,22 @@ class Context:
         return out
 
     def alm_real(self) -> np.ndarray:
-        nc = (self.lmax + 1) ** 2
+        nc = 2 * self.lmax + 1 if self.sphere else (self.lmax + 1) ** 2
         out = np.zeros((self.n, self.nbins, nc))
         self._check(_lib.tpcf_debug_alm(self._h, _ptr_np(out)))
         return out
 
     def alm(self) -> np.ndarray:
-        """a_lm for m >= 0 as complex [n, nbins, lmax+1, lmax+1] (index [.., l, m])."""
+        """a_lm for m >= 0 as complex [n, nbins, lmax+1, lmax+1] (index [.., l, m]); on the sphere
+        a_m as complex [n, nbins, m_max+1]."""
         r = self.alm_real()
         L = self.lmax
+        if self.sphere:
+            out = np.zeros(r.shape[:2] + (L + 1,), dtype=np.complex128)
+            out[..., 0] = r[..., 0]
+            for m in range(1, L + 1):
+                out[..., m] = r[..., 2 * m - 1] + 1j * r[..., 2 * m]
+            return out
         out = np.zeros(r.shape[:2] + (L + 1, L + 1), dtype=np.complex128)
         for l in range(L + 1):
             out[..., l, 0] = r[..., l * l]
@@ -329,6 +350,17 @@ class Context:
         s = Stats()
         self._check(_lib.tpcf_get_stats(self._h, ctypes.byref(s)))
         return {k: getattr(s, k) for k, _ in Stats._fields_}
+
+
+def zeta_sphere(x, y, z, w=None, *, theta_min: float, theta_max: float, nbins: int, mmax: int,
+                precision="fp64", device: int = 0, stream=None):
+    """zeta_m(b1, b2) of a field on the unit sphere (unit vectors x, y, z; angles in radians),
+    float64 [(mmax+1), nbins, nbins]."""
+    with Context(device, stream) as ctx:
+        ctx.set_bins(nbins, theta_min, theta_max, mmax)
+        ctx.set_precision(precision)
+        ctx.set_sphere_catalog(x, y, z, w)
+        return ctx.compute_zeta(device_output=_is_torch(x) and x.is_cuda)
 
 
 def zeta(x, y, z, w=None, *, box: float, periodic: bool = True, rmin: float, rmax: float,

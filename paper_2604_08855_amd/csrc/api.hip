@@ -25,9 +25,9 @@ void fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s);
 void fill_f64(double* p, double v, size_t n, hipStream_t s);
 void unsort_counts(const int32_t* in, const uint32_t* perm, int64_t* out, uint32_t n, int nb, hipStream_t s);
 void unsort_alm(const void* in, bool f64, const uint32_t* perm, double* out, uint32_t n, int row, hipStream_t s);
-hipError_t launch_sweep(int lmax, bool f64, const SweepArgs& args, int waves, hipStream_t stream);
+hipError_t launch_sweep(int lmax, bool f64, bool sphere, const SweepArgs& args, int waves, hipStream_t stream);
 size_t sweep_lds_bytes(int scratch_blocks, int nb);
-size_t sweep_tile_bytes_per_wave(int lmax, int nb, bool f64);
+size_t sweep_tile_bytes_per_wave(int lmax, int nb, bool f64, bool sphere);
 std::vector<double> threej_squared_table(int lmax);
 hipError_t launch_edge_correct(int ncat, int lmax, int nb, const double* N, const double* R, const double* t3,
                                double* out, hipStream_t s);
@@ -49,7 +49,10 @@ struct HostCat {
   int64_t first, n;
   double box;
   int periodic;
+  int sphere;  // unit vectors on the sphere (box 4, not periodic, shifted by +2 on the device)
 };
+
+constexpr double kPi = 3.14159265358979323846;
 
 }  // namespace
 
@@ -185,6 +188,9 @@ int ensure_device(tpcf_ctx* c) {
 
 bool is_finite(double v) { return isfinite(v) != 0; }
 
+// The context holds a catalogue on the sphere: bins are angles and lmax is m_max.
+bool is_sphere(const tpcf_ctx* c) { return c->cat_set && !c->cats.empty() && c->cats[0].sphere; }
+
 // Lattice bits K: the largest K <= 25 + log2(L / r_max), capped at 32 (periodic) / 31.
 int lattice_bits(double box, double rmax, int periodic) {
   int e = 0;
@@ -263,6 +269,63 @@ void conversion(int lmax, std::vector<int16_t>& idx, std::vector<double>& coef) 
 
 typedef unsigned __int128 u128;
 
+// Catalogue on the unit sphere (bins in the angle theta, radians). Points are unit vectors
+// shifted by +2 into the non-periodic cube [0, 4)^3; a pair at angle theta has chord
+// 2 sin(theta / 2). Lattice and thresholds as in 3D with chord edges: K from the largest chord,
+// T_k = ceil(fl(fl(2 sin(theta_k / 2) 2^K / 4)^2)). The grid side follows the surface density
+// (a plane through a cubic grid cuts 1.5 / cs^2 cells per unit area on average, so cells on the
+// sphere hold about n cs^2 / (6 pi) points).
+void configure_sphere(const tpcf_ctx* c, const HostCat& h, CatDesc& d) {
+  const int nb = c->nbins;
+  const double dth = (c->rmax - c->rmin) / nb;
+  const double cmax = 2.0 * sin(0.5 * c->rmax);
+  d.sphere = 1;
+  d.periodic = 0;
+  d.box = 4.0;
+  d.K = lattice_bits(4.0, cmax, 0);
+  d.sh = 0;
+  d.scale = ldexp(1.0, d.K) / 4.0;
+  for (int b = 0; b <= nb; ++b) {
+    const double th = (b == nb) ? c->rmax : c->rmin + b * dth;
+    const double v = 2.0 * sin(0.5 * th) * d.scale;
+    d.T[b] = ceil(v * v);
+  }
+  int ncx = 1;
+  if (h.n > 0) ncx = (int)floor(4.0 / sqrt(6.0 * kPi * c->ppc / (double)h.n));
+  ncx = std::max(1, std::min(ncx, 512));
+  d.nc = ncx;
+  const double span = ldexp(1.0, d.K);
+  const double margin = ldexp(1.0, d.K - 14);
+  const double reach = cmax * d.scale + margin;
+  const double cs_min = floor(span / ncx);
+  const int R = std::min((int)ceil(reach / cs_min) + 1, ncx - 1);
+  d.row_lo = -R;
+  d.row_w = 2 * R + 1;
+  d.cs = (float)(span / ncx);
+  d.inv_cs = (float)(ncx / span);
+  d.span = (float)span;
+  d.reach = (float)reach;
+  d.margin = (float)margin;
+  // fast decision: u = 2 asin(sqrt(R^2) / (2 scale)) / dtheta - theta_min / dtheta
+  d.inv_delta_l = (float)(2.0 / dth);
+  d.u0 = (float)(-c->rmin / dth);
+  d.half_inv_scale = (float)(0.5 / d.scale);
+  // |u_fp32 - u_exact| <= (theta_max / dtheta + 1) (4.5 kappa + 20) 2^-24, kappa the condition
+  // number of asin at the largest argument (the chord's relative error is at most 4.5 2^-24, the
+  // arcsine's own 16 2^-24, the scaling and offset 4 2^-24); integer thresholds move an edge by
+  // at most 1 / (2 c scale^2 cos(theta / 2) dtheta) bins. Decisions are taken in FP32 only 4x that
+  // far from an edge.
+  const double xmax = 0.5 * cmax;
+  double kappa = 1.0;
+  if (xmax >= 0.999) kappa = 1e30;
+  else if (xmax > 1e-4) kappa = xmax / (sqrt(1.0 - xmax * xmax) * asin(xmax));
+  const double c1 = 2.0 * sin(0.5 * (c->rmin > 0.0 ? c->rmin : dth));
+  const double edge = 1.0 / (2.0 * c1 * d.scale * d.scale * sqrt(1.0 - std::min(xmax * xmax, 0.998)) * dth);
+  double eps = 4.0 * ((c->rmax / dth + 1.0) * (4.5 * kappa + 24.0) * ldexp(1.0, -24) + edge);
+  if (!(eps <= 0.2)) eps = 2.0;  // every candidate takes the exact path
+  d.eps = (float)eps;
+}
+
 // Grid side, lattice, thresholds, stencil geometry and FP32 bin-decision bound of every
 // catalogue.
 int configure_grid(tpcf_ctx* c) {
@@ -278,6 +341,14 @@ int configure_grid(tpcf_ctx* c) {
     d.npoints = (uint32_t)h.n;
     d.periodic = h.periodic;
     d.box = h.box;
+    if (h.sphere) {
+      configure_sphere(c, h, d);
+      d.cell_base = (uint32_t)cells;
+      cells += (uint64_t)d.nc * d.nc * d.nc;
+      if (cells >= ((uint64_t)1 << 31)) return fail(c, TPCF_E_UNSUPPORTED, "too many grid cells");
+      c->cd.push_back(d);
+      continue;
+    }
     d.K = lattice_bits(h.box, c->rmax, h.periodic);
     d.sh = h.periodic ? 32 - d.K : 0;
     d.scale = ldexp(1.0, d.K) / h.box;
@@ -338,13 +409,14 @@ int configure_grid(tpcf_ctx* c) {
 
 // Scratch regions per bin: kMinRegionBlocks blocks each plus a share of the rest proportional
 // to the bin's shell volume.
-std::vector<uint32_t> scratch_regions(int nb, double rmin, double rmax, int S) {
+// On the sphere the share follows the area of the bin's annulus, cos theta_0 - cos theta_1.
+std::vector<uint32_t> scratch_regions(int nb, double rmin, double rmax, int S, bool sphere) {
   std::vector<double> vol(nb);
   double tot = 0.0;
   const double delta = (rmax - rmin) / nb;
   for (int b = 0; b < nb; ++b) {
     const double e0 = rmin + b * delta, e1 = (b + 1 == nb) ? rmax : rmin + (b + 1) * delta;
-    vol[b] = e1 * e1 * e1 - e0 * e0 * e0;
+    vol[b] = sphere ? cos(e0) - cos(e1) : e1 * e1 * e1 - e0 * e0 * e0;
     tot += vol[b];
   }
   std::vector<uint32_t> r(nb + 1, 0);
@@ -357,18 +429,30 @@ std::vector<uint32_t> scratch_regions(int nb, double rmin, double rmax, int S) {
 }
 
 int check_periodic_range(tpcf_ctx* c) {
-  for (const HostCat& h : c->cats)
+  for (const HostCat& h : c->cats) {
     if (h.periodic && !(c->rmax < 0.5 * h.box))
       return fail(c, TPCF_E_INVALID_ARG, "periodic catalogue needs rmax < box/2");
+    if (h.sphere && !(c->rmax <= kPi))
+      return fail(c, TPCF_E_INVALID_ARG, "angular bins on the sphere need theta_max <= pi");
+  }
   return TPCF_OK;
 }
 
 // Host-side validation of one catalogue's host arrays.
 int validate_host(tpcf_ctx* c, const double* x, const double* y, const double* z, const double* w, int64_t n,
-                  double box, int periodic) {
+                  double box, int periodic, int sphere) {
   const double lim = box * 1048576.0;
   for (int64_t i = 0; i < n; ++i) {
     const double p[3] = {x[i], y[i], z[i]};
+    if (sphere) {
+      if (!is_finite(p[0]) || !is_finite(p[1]) || !is_finite(p[2]))
+        return fail(c, TPCF_E_INVALID_ARG, "non-finite position at index " + std::to_string(i));
+      const double r2 = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
+      if (!(r2 >= 1.0 - 1e-6 && r2 <= 1.0 + 1e-6))
+        return fail(c, TPCF_E_INVALID_ARG, "point on the sphere is not a unit vector at index " + std::to_string(i));
+      if (w && !is_finite(w[i])) return fail(c, TPCF_E_INVALID_ARG, "non-finite weight at index " + std::to_string(i));
+      continue;
+    }
     for (double v : p) {
       if (!is_finite(v)) return fail(c, TPCF_E_INVALID_ARG, "non-finite position at index " + std::to_string(i));
       if (periodic) {
@@ -388,7 +472,7 @@ int stage(tpcf_ctx* c, const std::vector<HostCat>& cats, int64_t ntot, const dou
   if (memspace == TPCF_MEM_HOST) {
     for (const HostCat& h : cats) {
       int rc = validate_host(c, x + h.first, y + h.first, z + h.first, w ? w + h.first : nullptr, h.n, h.box,
-                             h.periodic);
+                             h.periodic, h.sphere);
       if (rc) return rc;
     }
   }
@@ -414,6 +498,7 @@ int stage(tpcf_ctx* c, const std::vector<HostCat>& cats, int64_t ntot, const dou
       tmp[k].point_base = (uint32_t)cats[k].first;
       tmp[k].box = cats[k].box;
       tmp[k].periodic = cats[k].periodic;
+      tmp[k].sphere = cats[k].sphere;
     }
     if ((rc = ensure(c, c->cats_d, tmp.size() * sizeof(CatDesc), "catalogue table")) ||
         (rc = ensure(c, c->errflag, sizeof(int), "flags")))
@@ -430,6 +515,7 @@ int stage(tpcf_ctx* c, const std::vector<HostCat>& cats, int64_t ntot, const dou
     if (flag & 1) return fail(c, TPCF_E_INVALID_ARG, "non-finite position or weight");
     if (flag & 2) return fail(c, TPCF_E_INVALID_ARG, "non-periodic position outside [0, box)");
     if (flag & 4) return fail(c, TPCF_E_INVALID_ARG, "periodic position beyond 2^20 box sides");
+    if (flag & 8) return fail(c, TPCF_E_INVALID_ARG, "point on the sphere is not a unit vector");
   } else {
     HIP_TRY(c, hipStreamSynchronize(c->stream));
   }
@@ -493,7 +579,8 @@ void mark_grid(tpcf_ctx* c) {
 // Host part of the sweep: buffers, normalisation constants and the kernel arguments.
 int prepare_sweep(tpcf_ctx* c, const uint32_t* tasks_d, uint32_t ntask, SweepArgs& a, int& waves) {
   const bool f64 = c->precision == TPCF_PREC_FP64;
-  const int nb = c->nbins, L = c->lmax, NC = (L + 1) * (L + 1);
+  const bool sph = is_sphere(c);
+  const int nb = c->nbins, L = c->lmax, NC = ncomp(L, sph);
   const int ncat = (int)c->cd.size();
   waves = std::max(1, c->ncu * c->waves_per_cu);
   if ((uint32_t)waves > ntask) waves = (int)std::max<uint32_t>(1, ntask);
@@ -504,7 +591,7 @@ int prepare_sweep(tpcf_ctx* c, const uint32_t* tasks_d, uint32_t ntask, SweepArg
   if (S < kMinRegionBlocks * nb)
     return fail(c, TPCF_E_INVALID_ARG, "scratch_blocks must be at least 5 x nbins");
   if ((rc = ensure(c, c->scratch, (size_t)waves * (S + kScratchTail) * kBlock * 4, "scratch")) ||
-      (rc = ensure(c, c->tile, (size_t)waves * sweep_tile_bytes_per_wave(L, nb, f64), "tiles")) ||
+      (rc = ensure(c, c->tile, (size_t)waves * sweep_tile_bytes_per_wave(L, nb, f64, sph), "tiles")) ||
       (rc = ensure(c, c->zeta_d, (size_t)ncat * (L + 1) * nb * nb * 8, "zeta")) ||
       (rc = ensure(c, c->queue, 16, "queue")) || (rc = ensure(c, c->stats_d, 16, "stats")) ||
       (rc = ensure(c, c->bin_pairs, (size_t)ncat * nb * 8, "pair sums")) ||
@@ -526,7 +613,7 @@ int prepare_sweep(tpcf_ctx* c, const uint32_t* tasks_d, uint32_t ntask, SweepArg
     c->conv_lmax = L;
   }
   {
-    std::vector<uint32_t> regs = scratch_regions(nb, c->rmin, c->rmax, S);
+    std::vector<uint32_t> regs = scratch_regions(nb, c->rmin, c->rmax, S, sph);
     if ((rc = ensure(c, c->regions, regs.size() * 4, "regions"))) return rc;
     HIP_TRY(c, hipMemcpyAsync(c->regions.p, regs.data(), regs.size() * 4, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -566,7 +653,8 @@ int prepare_sweep(tpcf_ctx* c, const uint32_t* tasks_d, uint32_t ntask, SweepArg
 // Device part of the sweep: clears (fill kernels, never memset nodes) and the persistent launch.
 int record_sweep(tpcf_ctx* c, const SweepArgs& a, int waves) {
   const bool f64 = c->precision == TPCF_PREC_FP64;
-  const int nb = c->nbins, L = c->lmax, NC = (L + 1) * (L + 1);
+  const bool sph = is_sphere(c);
+  const int nb = c->nbins, L = c->lmax, NC = ncomp(L, sph);
   if (c->debug) {
     fill_u32((uint32_t*)c->counts32.p, 0u, (size_t)c->ntot * nb, c->stream);
     fill_u32((uint32_t*)c->alm_dbg.p, 0u, (size_t)c->ntot * nb * NC * (f64 ? 2 : 1), c->stream);
@@ -576,7 +664,7 @@ int record_sweep(tpcf_ctx* c, const SweepArgs& a, int waves) {
   fill_u32((uint32_t*)c->stats_d.p, 0u, 4, c->stream);
   fill_u32((uint32_t*)c->bin_pairs.p, 0u, (size_t)a.ncat * nb * 2, c->stream);
   fill_f64((double*)c->bin_dd.p, 0.0, (size_t)a.ncat * nb, c->stream);
-  if (a.ntask > 0) HIP_TRY(c, launch_sweep(L, f64, a, waves, c->stream));
+  if (a.ntask > 0) HIP_TRY(c, launch_sweep(L, f64, sph, a, waves, c->stream));
   return TPCF_OK;
 }
 
@@ -602,7 +690,7 @@ int finish_stats(tpcf_ctx* c, bool grid_built, uint32_t ntask) {
   c->sums_nb = c->nbins;
   c->dbg_f64 = c->precision == TPCF_PREC_FP64;
   c->dbg_nb = c->nbins;
-  c->dbg_nc = (c->lmax + 1) * (c->lmax + 1);
+  c->dbg_nc = ncomp(c->lmax, is_sphere(c));
   return TPCF_OK;
 }
 
@@ -771,9 +859,12 @@ int tpcf_set_bins(tpcf_ctx* c, int nbins, double rmin, double rmax, int lmax) {
   if (!is_finite(rmin) || !is_finite(rmax) || rmin < 0.0 || !(rmax > rmin))
     return fail(c, TPCF_E_INVALID_ARG, "need finite 0 <= rmin < rmax");
   if (c->cat_set)
-    for (const HostCat& h : c->cats)
+    for (const HostCat& h : c->cats) {
       if (h.periodic && !(rmax < 0.5 * h.box))
         return fail(c, TPCF_E_INVALID_ARG, "periodic catalogue needs rmax < box/2");
+      if (h.sphere && !(rmax <= kPi))
+        return fail(c, TPCF_E_INVALID_ARG, "angular bins on the sphere need theta_max <= pi");
+    }
   c->nbins = nbins;
   c->rmin = rmin;
   c->rmax = rmax;
@@ -914,6 +1005,8 @@ int tpcf_edge_correct(tpcf_ctx* c, int ncat, const double* N, const double* R, d
   if (memspace != TPCF_MEM_HOST && memspace != TPCF_MEM_DEVICE)
     return fail(c, TPCF_E_INVALID_ARG, "unknown memory space");
   if (!c->bins_set) return fail(c, TPCF_E_STATE, "set_bins has not been called");
+  if (is_sphere(c))
+    return fail(c, TPCF_E_UNSUPPORTED, "the edge correction couples 3D multipoles; the context holds a sphere catalogue");
   int rc;
   if ((rc = ensure_device(c))) return rc;
   const int L = c->lmax, nb = c->nbins;
@@ -964,6 +1057,27 @@ int tpcf_set_catalog(tpcf_ctx* c, int64_t n, const double* x, const double* y, c
   cats[0].n = n;
   cats[0].box = box;
   cats[0].periodic = periodic ? 1 : 0;
+  cats[0].sphere = 0;
+  int rc = stage(c, cats, n, x, y, z, w, memspace);
+  if (!rc) c->err.clear();
+  return rc;
+}
+
+int tpcf_set_sphere_catalog(tpcf_ctx* c, int64_t n, const double* x, const double* y, const double* z,
+                            const double* w, int memspace) {
+  if (!c) return TPCF_E_INVALID_ARG;
+  if (n < 0 || n >= kMaxPoints) return fail(c, TPCF_E_INVALID_ARG, "n must be in [0, 2^31)");
+  if (n > 0 && (!x || !y || !z)) return fail(c, TPCF_E_INVALID_ARG, "NULL position array");
+  if (memspace != TPCF_MEM_HOST && memspace != TPCF_MEM_DEVICE)
+    return fail(c, TPCF_E_INVALID_ARG, "unknown memory space");
+  if (c->bins_set && !(c->rmax <= kPi))
+    return fail(c, TPCF_E_INVALID_ARG, "angular bins on the sphere need theta_max <= pi");
+  std::vector<HostCat> cats(1);
+  cats[0].first = 0;
+  cats[0].n = n;
+  cats[0].box = 4.0;
+  cats[0].periodic = 0;
+  cats[0].sphere = 1;
   int rc = stage(c, cats, n, x, y, z, w, memspace);
   if (!rc) c->err.clear();
   return rc;
@@ -1006,6 +1120,7 @@ int tpcf_compute_batch(tpcf_ctx* c, int ncat, const int64_t* offsets, const doub
     cats[k].n = offsets[k + 1] - offsets[k];
     cats[k].box = box_side[k];
     cats[k].periodic = periodic[k] ? 1 : 0;
+    cats[k].sphere = 0;
   }
   const int64_t ntot = offsets[ncat];
   if (ntot >= kMaxPoints) return fail(c, TPCF_E_INVALID_ARG, "total points must be < 2^31");

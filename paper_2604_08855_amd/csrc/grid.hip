@@ -7,6 +7,7 @@
 //   k_snap      : FP64 positions -> lattice coordinates q (FP64 multiply by 2^K/L, floor, wrap
 //                 or clamp), stored shifted as q << sh; cell id; cell histogram (atomics);
 //                 validation flags for non-finite values and non-periodic points outside the box.
+//                 Points on the sphere are unit vectors, shifted by +2 into the cube [0, 4)^3.
 //   k_scan_*    : exclusive scan of the histogram -> cell_start (three small kernels).
 //   k_scatter   : each point claims a slot of its cell (atomic, so the order inside a cell is
 //                 arbitrary at this point).
@@ -29,6 +30,12 @@ __device__ __forceinline__ int cat_of_point(const CatDesc* cats, int ncat, uint3
     else hi = mid - 1;
   }
   return lo;
+}
+
+// Points on the sphere must be unit vectors to within 1e-6 in |v|^2 (flag bit 8).
+__device__ __forceinline__ int unit_norm_flag(double px, double py, double pz) {
+  const double r2 = px * px + py * py + pz * pz;
+  return (r2 >= 1.0 - 1e-6 && r2 <= 1.0 + 1e-6) ? 0 : 8;
 }
 
 // Lattice coordinate of one position (periodic: mod 2^K; else clamped to [0, 2^K)).
@@ -56,6 +63,12 @@ __global__ void k_snap(const double* __restrict__ x, const double* __restrict__ 
   const double pw = w ? w[i] : 1.0;
   int bad = 0;
   if (!isfinite(px) || !isfinite(py) || !isfinite(pz) || !isfinite(pw)) bad |= 1;
+  if (cd.sphere) {
+    bad |= unit_norm_flag(px, py, pz);
+    px += 2.0;
+    py += 2.0;
+    pz += 2.0;
+  }
   if (cd.periodic) {
     const double lim = cd.box * 1048576.0;
     if (fabs(px) > lim || fabs(py) > lim || fabs(pz) > lim) bad |= 4;
@@ -155,24 +168,27 @@ __global__ void k_scatter(const uint32_t* __restrict__ cell, const uint32_t* __r
   slot_idx[cell_start[c] + k] = i;
 }
 
-// One wavefront per cell: rank every entry by its input index (cells of up to kCellSortMax
-// points; larger cells keep the scatter order).
+// One wavefront per cell at a time (cells strided over the grid, which may be far smaller than
+// the cell count of a sparsely filled grid): rank every entry by its input index (cells of up to
+// kCellSortMax points; larger cells keep the scatter order).
+constexpr uint32_t kCellSortGrid = 65536;
+
 __global__ __launch_bounds__(64) void k_cellsort(const uint32_t* __restrict__ cell_start,
                                                  const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
                                                  uint32_t ncell) {
-  const uint32_t c = blockIdx.x;
-  if (c >= ncell) return;
-  const uint32_t beg = cell_start[c], end = cell_start[c + 1];
-  const uint32_t n = end - beg;
-  if (n <= 1 || n > (uint32_t)kCellSortMax) {
-    for (uint32_t k = threadIdx.x; k < n; k += 64) out[beg + k] = in[beg + k];
-    return;
-  }
-  for (uint32_t k = threadIdx.x; k < n; k += 64) {
-    const uint32_t v = in[beg + k];
-    uint32_t rank = 0;
-    for (uint32_t m = 0; m < n; ++m) rank += in[beg + m] < v ? 1u : 0u;
-    out[beg + rank] = v;
+  for (uint32_t c = blockIdx.x; c < ncell; c += gridDim.x) {
+    const uint32_t beg = cell_start[c], end = cell_start[c + 1];
+    const uint32_t n = end - beg;
+    if (n <= 1 || n > (uint32_t)kCellSortMax) {
+      for (uint32_t k = threadIdx.x; k < n; k += 64) out[beg + k] = in[beg + k];
+      continue;
+    }
+    for (uint32_t k = threadIdx.x; k < n; k += 64) {
+      const uint32_t v = in[beg + k];
+      uint32_t rank = 0;
+      for (uint32_t m = 0; m < n; ++m) rank += in[beg + m] < v ? 1u : 0u;
+      out[beg + rank] = v;
+    }
   }
 }
 
@@ -193,7 +209,8 @@ __global__ void k_gather(const uint32_t* __restrict__ order, const uint4* __rest
 }
 
 // Validation of device-resident inputs: bit 1 non-finite value, bit 2 non-periodic point outside
-// [0, box), bit 4 periodic coordinate beyond 2^20 box sides.
+// [0, box), bit 4 periodic coordinate beyond 2^20 box sides, bit 8 a point on the sphere that is
+// not a unit vector.
 __global__ void k_validate(const double* __restrict__ x, const double* __restrict__ y,
                            const double* __restrict__ z, const double* __restrict__ w, uint32_t n,
                            const CatDesc* __restrict__ cats, int ncat, int* __restrict__ err) {
@@ -203,7 +220,9 @@ __global__ void k_validate(const double* __restrict__ x, const double* __restric
   const double px = x[i], py = y[i], pz = z[i], pw = w ? w[i] : 1.0;
   int bad = 0;
   if (!isfinite(px) || !isfinite(py) || !isfinite(pz) || !isfinite(pw)) bad |= 1;
-  else if (cd.periodic) {
+  else if (cd.sphere) {
+    bad |= unit_norm_flag(px, py, pz);
+  } else if (cd.periodic) {
     const double lim = cd.box * 1048576.0;
     if (fabs(px) > lim || fabs(py) > lim || fabs(pz) > lim) bad |= 4;
   } else if (px < 0.0 || px >= cd.box || py < 0.0 || py >= cd.box || pz < 0.0 || pz >= cd.box) {
@@ -258,7 +277,8 @@ hipError_t build_grid(const double* x, const double* y, const double* z, const d
                      ncell, n);
   if (n) {
     hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, s, cell, cell_start, hist, idx_a, n);
-    hipLaunchKernelGGL(k_cellsort, dim3(ncell), dim3(64), 0, s, cell_start, idx_a, idx_b, ncell);
+    hipLaunchKernelGGL(k_cellsort, dim3(ncell < kCellSortGrid ? ncell : kCellSortGrid), dim3(64), 0, s,
+                       cell_start, idx_a, idx_b, ncell);
   }
   hipLaunchKernelGGL(k_gather, dim3(blocks_for(n + 1, 256)), dim3(256), 0, s, idx_b, qtmp, w, rec, w64, perm, n);
   return hipGetLastError();

@@ -32,6 +32,15 @@
 //             accumulation within the tile. FP64: v_mfma_f64_16x16x4. Tile results are added into
 //             a per-wave FP64 partial; partials are added into zeta (FP64 atomics) when the wave
 //             changes catalogue and when it finishes.
+//
+// Projected fields on the unit sphere (the paper's own geometry, Statement of need, Features and
+// Performance sections) run through the same skeleton with 2D multipoles of the position angle:
+// points are unit vectors shifted into a cube of side 4, bins are linear in the angle theta
+// (integer thresholds on the squared chord 2 sin(theta/2)), and per pair the displacement is
+// projected on a tangent basis (e1, e2) of the primary, (c, s) = unit(d.e1, d.e2), so that
+//     a_m = sum_j w_j (c_j - i s_j)^m = sum_j w_j exp(-i m phi_j),   0 <= m <= m_max,
+// one complex multiply per m and no trigonometric call (the Chebyshev form of cos m phi and
+// sin m phi the paper uses); zeta_m(b1, b2) = sum_p w_p Re[a_m(b1) conj(a_m(b2))].
 #include <type_traits>
 
 #include "tpcf_internal.h"
@@ -162,6 +171,40 @@ __device__ __forceinline__ void add_moments(real (&acc)[S], real x, real y, real
   });
 }
 
+// Sphere plan: component 0 is Re a_0, components 2m - 1 and 2m are Re a_m and Im a_m; one group
+// of 64 reduction slots (2 m_max + 1 <= 21 are used).
+template <int M>
+struct PlanSph {
+  static constexpr int NC = 2 * M + 1;
+  static constexpr int NG = 1;
+  static constexpr int slots(int) { return 64; }
+  static constexpr int gsize(int) { return NC; }
+  __host__ __device__ static constexpr int global_of(int, int s) { return s < NC ? s : -1; }
+};
+
+// Adds (WRITE: stores) w (c - i s)^m, m = 0..M, of one pair into acc.
+template <int M, bool WRITE, class real, int S>
+__device__ __forceinline__ void add_moments_sph(real (&acc)[S], real c, real s, real w) {
+  real pr = w, pi = real(0);
+  static_for<0, M + 1>([&](auto Mi) {
+    constexpr int m = Mi;
+    if constexpr (m > 0) {
+      const real nr = pr * c + pi * s;
+      const real ni = pi * c - pr * s;
+      pr = nr;
+      pi = ni;
+    }
+    constexpr int re = m == 0 ? 0 : 2 * m - 1;
+    if constexpr (WRITE) {
+      acc[re] = pr;
+      if constexpr (m > 0) acc[re + 1] = pi;
+    } else {
+      acc[re] += pr;
+      if constexpr (m > 0) acc[re + 1] += pi;
+    }
+  });
+}
+
 // ------------------------------------------------------------------------------------------
 // Cross-lane transpose-reduction. Input: S values per lane (S = 64 or 128). Output: slot k of
 // lane L (k < S/64) holds the wave-wide sum of component (S/64)*L + k.
@@ -264,21 +307,142 @@ __device__ __forceinline__ void unit(const Primary& P, Rec r, double& x, double&
   z = fz * ri;
 }
 
+// Tangent basis at a primary on the sphere: n = unit(q s - 2) from its lattice position (s = 1 /
+// scale), e1 = unit(z x n) (unit(x x n) within 1e-6 of the poles), e2 = n x e1. zeta_m does not
+// depend on the choice: turning the basis by alpha multiplies every a_m of the primary by
+// exp(i m alpha).
+template <class real>
+struct Tangent {
+  real e1x, e1y, e1z, e2x, e2y, e2z;
+};
+
+__device__ __forceinline__ double uniform_d(double v) {
+  const uint64_t u = __double_as_longlong(v);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+  return __longlong_as_double((int64_t)(((uint64_t)hi << 32) | lo));
+}
+
+template <class real>
+__device__ __forceinline__ Tangent<real> tangent_basis(uint32_t ux, uint32_t uy, uint32_t uz, double inv_scale) {
+  double nx = (double)ux * inv_scale - 2.0, ny = (double)uy * inv_scale - 2.0, nz = (double)uz * inv_scale - 2.0;
+  const double nn = sqrt(nx * nx + ny * ny + nz * nz);
+  nx /= nn;
+  ny /= nn;
+  nz /= nn;
+  double ax = -ny, ay = nx, az = 0.0;
+  double l1 = sqrt(ax * ax + ay * ay);
+  if (l1 < 1e-6) {
+    ax = 0.0;
+    ay = -nz;
+    az = ny;
+    l1 = sqrt(ay * ay + az * az);
+  }
+  ax /= l1;
+  ay /= l1;
+  az /= l1;
+  Tangent<real> t;
+  t.e1x = (real)uniform_d(ax);
+  t.e1y = (real)uniform_d(ay);
+  t.e1z = (real)uniform_d(az);
+  t.e2x = (real)uniform_d(ny * az - nz * ay);
+  t.e2y = (real)uniform_d(nz * ax - nx * az);
+  t.e2z = (real)uniform_d(nx * ay - ny * ax);
+  return t;
+}
+
+// Position angle of a secondary around the primary as (c, s) = (cos phi, sin phi): the lattice
+// displacement projected on the tangent basis, normalised.
+template <class Rec>
+__device__ __forceinline__ void unit_sph(const Primary& P, const Tangent<float>& tb, Rec r, float& c, float& s) {
+  const float fx = (float)sdiff(r.x, P.qx), fy = (float)sdiff(r.y, P.qy), fz = (float)sdiff(r.z, P.qz);
+  const float t1 = __builtin_fmaf(fx, tb.e1x, __builtin_fmaf(fy, tb.e1y, fz * tb.e1z));
+  const float t2 = __builtin_fmaf(fx, tb.e2x, __builtin_fmaf(fy, tb.e2y, fz * tb.e2z));
+  const float r2 = __builtin_fmaf(t1, t1, __builtin_fmaf(t2, t2, 0x1p-100f));
+  const float ri = __builtin_amdgcn_rsqf(r2);
+  c = t1 * ri;
+  s = t2 * ri;
+}
+template <class Rec>
+__device__ __forceinline__ void unit_sph(const Primary& P, const Tangent<double>& tb, Rec r, double& c, double& s) {
+  const double fx = (double)sdiff(r.x, P.qx), fy = (double)sdiff(r.y, P.qy), fz = (double)sdiff(r.z, P.qz);
+  const double t1 = fma(fx, tb.e1x, fma(fy, tb.e1y, fz * tb.e1z));
+  const double t2 = fma(fx, tb.e2x, fma(fy, tb.e2y, fz * tb.e2z));
+  const double r2 = fma(t1, t1, fma(t2, t2, 0x1p-100));
+  double ri = __builtin_amdgcn_rsq(r2);
+  double h = r2 * ri;
+  ri = fma(ri * 0.5, fma(-h, ri, 1.0), ri);
+  h = r2 * ri;
+  ri = fma(ri * 0.5, fma(-h, ri, 1.0), ri);
+  c = t1 * ri;
+  s = t2 * ri;
+}
+
+// Direction of a pair and its moments, for either geometry (3D: unit vector; sphere: (c, s)).
+template <bool SPH, class real, class Rec>
+__device__ __forceinline__ void direction(const Primary& P, const Tangent<real>& tb, Rec r, real& x, real& y,
+                                          real& z) {
+  if constexpr (SPH) {
+    unit_sph(P, tb, r, x, y);
+    z = real(0);
+  } else {
+    unit(P, r, x, y, z);
+  }
+}
+template <int LMAX, bool F64, bool SPH, int G, bool WRITE, class real, int S>
+__device__ __forceinline__ void accumulate(real (&acc)[S], real x, real y, real z, real w) {
+  if constexpr (SPH) add_moments_sph<LMAX, WRITE>(acc, x, y, w);
+  else add_moments<LMAX, F64, G, WRITE>(acc, x, y, z, w);
+}
+
+// Arcsine of x in [0, 1] in FP32 for the fast angular bin decision: the Taylor series about 0,
+// asin y = sum_n c_n y^(2n+1), c_0 = 1, c_n = c_(n-1) (2n-1)^2 / (2n (2n+1)), through n = 10 for
+// y <= 1/2 (truncation below 2^-28 relative), and asin x = pi/2 - 2 asin(sqrt((1 - x) / 2)) above
+// 1/2. Relative error below 16 * 2^-24 for exact x (rounding of the Horner steps, the square root
+// and the final subtraction).
+__device__ __forceinline__ float asin01(float x) {
+  const bool up = x > 0.5f;
+  const float y = up ? __builtin_amdgcn_sqrtf((1.0f - x) * 0.5f) : x;
+  const float y2 = y * y;
+  float p = 8.390335810e-03f;
+  p = __builtin_fmaf(p, y2, 9.761609529e-03f);
+  p = __builtin_fmaf(p, y2, 1.155180090e-02f);
+  p = __builtin_fmaf(p, y2, 1.396484375e-02f);
+  p = __builtin_fmaf(p, y2, 1.735276442e-02f);
+  p = __builtin_fmaf(p, y2, 2.237215909e-02f);
+  p = __builtin_fmaf(p, y2, 3.038194444e-02f);
+  p = __builtin_fmaf(p, y2, 4.464285714e-02f);
+  p = __builtin_fmaf(p, y2, 7.500000000e-02f);
+  p = __builtin_fmaf(p, y2, 1.666666667e-01f);
+  const float a = __builtin_fmaf(y * y2, p, y);
+  return up ? __builtin_fmaf(-2.0f, a, 1.5707963268f) : a;
+}
+
 // ------------------------------------------------------------------------------------------
 // Contraction of one tile of shells on MFMA.
 // tile: [TP][nb][NC] normalised a_lm (real components), wt: [TP] weights in LDS, nt valid
 // primaries. Adds zeta_l(b1, b2) of the tile into part[(l*nb + b1)*nb + b2] (FP64, per wave).
+// 3D: the 2l+1 components of l start at l*l; components m != 0 stand for +m and -m (factor 2).
+// Sphere: the components of m start at 0 (m = 0, Re only) or 2m - 1 (Re, Im), factor 1.
 // ------------------------------------------------------------------------------------------
-template <int LMAX>
+template <bool SPH>
+__device__ __forceinline__ int comp_base(int l) { return SPH ? (l == 0 ? 0 : 2 * l - 1) : l * l; }
+template <bool SPH>
+__device__ __forceinline__ int comp_count(int l) { return SPH ? (l == 0 ? 1 : 2) : 2 * l + 1; }
+template <bool SPH, class real>
+__device__ __forceinline__ real comp_factor(int cc) { return (SPH || cc == 0) ? real(1) : real(2); }
+
+template <int LMAX, bool SPH>
 __device__ __noinline__ void contract_tile(const float* __restrict__ tile, const float* wt, int nt,
                                            int nb, double* __restrict__ part, int lane) {
-  constexpr int NC = (LMAX + 1) * (LMAX + 1);
+  constexpr int NC = ncomp(LMAX, SPH);
   const int b = lane & 31;
   const int kh = (lane >> 5) * 8;
   const bool brow = b < nb;
 #pragma unroll 1
   for (int l = 0; l <= LMAX; ++l) {
-    const int n2 = 2 * l + 1;
+    const int n2 = comp_count<SPH>(l);
+    const int lb = comp_base<SPH>(l);
     const int K = nt * n2;
     floatx16 acc = {};
     // (t, cc) of this lane's first k, advanced incrementally
@@ -292,8 +456,8 @@ __device__ __noinline__ void contract_tile(const float* __restrict__ tile, const
         const int k = k0 + kh + j;
         float xv = 0.f, wv = 0.f;
         if (brow && k < K) {
-          xv = tile[(t * nb + b) * NC + l * l + cc];
-          wv = wt[t] * (cc == 0 ? 1.f : 2.f);
+          xv = tile[(t * nb + b) * NC + lb + cc];
+          wv = wt[t] * comp_factor<SPH, float>(cc);
         }
         const float yv = xv * wv;
         // three-piece BF16 split: v = v0 + v1 + v2 to within 2^-27 |v|
@@ -339,16 +503,17 @@ __device__ __noinline__ void contract_tile(const float* __restrict__ tile, const
   }
 }
 
-template <int LMAX>
+template <int LMAX, bool SPH>
 __device__ __noinline__ void contract_tile(const double* __restrict__ tile, const double* wt, int nt,
                                            int nb, double* __restrict__ part, int lane) {
-  constexpr int NC = (LMAX + 1) * (LMAX + 1);
+  constexpr int NC = ncomp(LMAX, SPH);
   const int rl = lane & 15;
   const int kq = lane >> 4;
   const bool two = nb > 16;
 #pragma unroll 1
   for (int l = 0; l <= LMAX; ++l) {
-    const int n2 = 2 * l + 1;
+    const int n2 = comp_count<SPH>(l);
+    const int lb = comp_base<SPH>(l);
     const int K = nt * n2;
     doublex4 acc00 = {}, acc01 = {}, acc10 = {}, acc11 = {};
     int t = kq / n2, cc = kq - (kq / n2) * n2;  // (primary, component) of k = k0 + kq
@@ -357,8 +522,8 @@ __device__ __noinline__ void contract_tile(const double* __restrict__ tile, cons
       const int k = k0 + kq;
       double x0 = 0.0, x1 = 0.0, y0 = 0.0, y1 = 0.0;
       if (k < K) {
-        const double wf = wt[t] * (cc == 0 ? 1.0 : 2.0);
-        const double* src = tile + (size_t)t * nb * NC + l * l + cc;
+        const double wf = wt[t] * comp_factor<SPH, double>(cc);
+        const double* src = tile + (size_t)t * nb * NC + lb + cc;
         if (rl < nb) {
           x0 = src[rl * NC];
           y0 = x0 * wf;
@@ -435,7 +600,7 @@ struct Row {
 struct CatU {
   int sh, K, nc, periodic, row_lo, row_w;
   uint32_t cell_base;
-  float cs, inv_cs, span, inv_span, reach, margin, inv_dl, u0, eps, inv_w;
+  float cs, inv_cs, span, inv_span, reach, margin, inv_dl, u0, eps, inv_w, hinv;
 };
 
 // Builds row t of the primary's stencil (rows are offsets (dy, dz) from the primary's cell):
@@ -513,10 +678,10 @@ __device__ __forceinline__ int lanes_below(uint64_t m) {
   return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
-template <int LMAX, bool F64>
+template <int LMAX, bool F64, bool SPH>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sweep_kernel(SweepArgs a) {
   using real = std::conditional_t<F64, double, float>;
-  using P = Plan<LMAX, F64>;
+  using P = std::conditional_t<SPH, PlanSph<LMAX>, Plan<LMAX, F64>>;
   constexpr int NC = P::NC;
   constexpr int TP = F64 ? kTileF64 : kTileF32;
 
@@ -585,7 +750,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sw
       part_cat = tile_cat;
     }
     __syncthreads();
-    contract_tile<LMAX>(tile, swt, tile_n, nb, part, lane);
+    contract_tile<LMAX, SPH>(tile, swt, tile_n, nb, part, lane);
     __syncthreads();
     tile_n = 0;
   };
@@ -620,6 +785,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sw
       cu.u0 = cd.u0;
       cu.eps = cd.eps;
       cu.inv_w = 1.0f / (float)cu.row_w;
+      cu.hinv = cd.half_inv_scale;
       if (lane <= nb) sT[lane] = cd.T[lane];
       cur_cat = cat;
       __syncthreads();
@@ -639,6 +805,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sw
     const int cy = (int)(((uint64_t)uy * (uint64_t)cu.nc) >> cu.K);
     const int cz = (int)(((uint64_t)uz * (uint64_t)cu.nc) >> cu.K);
     const float qxf = (float)ux, qyf = (float)uy, qzf = (float)uz;
+    Tangent<real> tb = {};
+    if constexpr (SPH) tb = tangent_basis<real>(ux, uy, uz, 2.0 * (double)cu.hinv);
 
     // Bin cursors: low word = next free entry of the bin's region, high word = its soft limit.
     auto reset_cursors = [&]() {
@@ -799,7 +967,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sw
               // rounds stay in order, so each waits only for its own loads
               __builtin_amdgcn_sched_barrier(0);
               real vx, vy, vz;
-              unit(P0, R, vx, vy, vz);
+              direction<SPH>(P0, tb, R, vx, vy, vz);
               real w = W;
               // The next loads go into this round's registers: the empty asm statement makes the
               // record address depend on this round's unit vector and weight, so the loads cannot
@@ -811,7 +979,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sw
               R = pos_at(jr);
               W = a.w64[jr];
               J = sb[(i + 4) * kBlock];
-              add_moments<LMAX, F64, G, decltype(WRITE)::value>(acc, vx, vy, vz, w);
+              accumulate<LMAX, F64, SPH, G, decltype(WRITE)::value>(acc, vx, vy, vz, w);
               ++i;
             };
             // chunks of <= 64 rounds (they start at even rounds): the first round of a chunk
@@ -841,8 +1009,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sw
                 if (i + 2 < nblk_b) jnn = sb[(i + 2) * kBlock];
               }
               real vx, vy, vz;
-              unit(P0, r, vx, vy, vz);
-              add_moments<LMAX, F64, G, decltype(WRITE)::value>(acc, vx, vy, vz, __uint_as_float(r.w));
+              direction<SPH>(P0, tb, r, vx, vy, vz);
+              accumulate<LMAX, F64, SPH, G, decltype(WRITE)::value>(acc, vx, vy, vz, __uint_as_float(r.w));
               r = rn;
               jn = jnn;
               ++i;
@@ -863,15 +1031,20 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sw
         });
         __syncthreads();
         if (lane == b) sdd += (double)mom[0];  // M_00 = sum of w_j over the bin
-        // moments -> normalised a_lm of bin b
+        // moments -> normalised a_lm of bin b (on the sphere the moments are the a_m)
         for (int c = lane; c < NC; c += 64) {
           real v = real(0);
+          if constexpr (SPH) {
+            v = mom[c];
+          } else {
 #pragma unroll
-          for (int q = 0; q < kConvTerms; ++q) {
-            const int mi = a.conv_idx[c * kConvTerms + q];
-            if (mi >= 0) {
-              const real cf = F64 ? (real)a.conv_coef64[c * kConvTerms + q] : (real)a.conv_coef32[c * kConvTerms + q];
-              v += cf * mom[mi];
+            for (int q = 0; q < kConvTerms; ++q) {
+              const int mi = a.conv_idx[c * kConvTerms + q];
+              if (mi >= 0) {
+                const real cf =
+                    F64 ? (real)a.conv_coef64[c * kConvTerms + q] : (real)a.conv_coef32[c * kConvTerms + q];
+                v += cf * mom[mi];
+              }
             }
           }
           real* dst = slot + b * NC + c;
@@ -924,7 +1097,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sw
         const float fx = (float)sdiff(rc[u].x, P0.qx), fy = (float)sdiff(rc[u].y, P0.qy),
                     fz = (float)sdiff(rc[u].z, P0.qz);
         const float r2 = fx * fx + fy * fy + fz * fz;
-        const float uu = __builtin_amdgcn_sqrtf(r2) * cu.inv_dl + cu.u0;
+        // 3D: linear in the separation; sphere: linear in theta = 2 asin(chord / 2)
+        const float uu = SPH ? asin01(__builtin_amdgcn_sqrtf(r2) * cu.hinv) * cu.inv_dl + cu.u0
+                             : __builtin_amdgcn_sqrtf(r2) * cu.inv_dl + cu.u0;
         const float fl = floorf(uu);
         const float fr = uu - fl;
         const int bb = (int)fl;
@@ -1022,17 +1197,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sw
 // ------------------------------------------------------------------------------------------
 // Host-side launch table.
 // ------------------------------------------------------------------------------------------
-typedef void (*SweepFn)(SweepArgs);
-
-template <int LMAX, bool F64>
-static void launch_one(SweepArgs args, int waves, size_t lds, hipStream_t stream) {
-  hipLaunchKernelGGL((sweep_kernel<LMAX, F64>), dim3(waves), dim3(64), lds, stream, args);
-}
-
-template <int LMAX, bool F64>
-static hipError_t set_lds(size_t lds) {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&sweep_kernel<LMAX, F64>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+template <int LMAX, bool F64, bool SPH>
+static hipError_t launch_one(SweepArgs args, int waves, size_t lds, hipStream_t stream) {
+  const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&sweep_kernel<LMAX, F64, SPH>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((sweep_kernel<LMAX, F64, SPH>), dim3(waves), dim3(64), lds, stream, args);
+  return hipSuccess;
 }
 
 size_t sweep_lds_bytes(int scratch_blocks, int nb) {
@@ -1040,43 +1211,37 @@ size_t sweep_lds_bytes(int scratch_blocks, int nb) {
   return (size_t)Lds::bytes(nb);
 }
 
-// Doubles (FP64) or floats (mixed) of per-wave tile area, including the FP64 zeta partial.
-size_t sweep_tile_bytes_per_wave(int lmax, int nb, bool f64) {
-  const int NC = (lmax + 1) * (lmax + 1);
+// Bytes of per-wave tile area, including the FP64 zeta partial.
+size_t sweep_tile_bytes_per_wave(int lmax, int nb, bool f64, bool sphere) {
+  const int NC = ncomp(lmax, sphere);
   const size_t tp = f64 ? kTileF64 : kTileF32;
   const size_t elem = f64 ? 8 : 4;
   return tp * nb * NC * elem + (size_t)(lmax + 1) * nb * nb * 8;
 }
 
-hipError_t launch_sweep(int lmax, bool f64, const SweepArgs& args, int waves, hipStream_t stream) {
+template <int L>
+static hipError_t launch_l(bool f64, bool sphere, const SweepArgs& args, int waves, size_t lds, hipStream_t s) {
+  if (sphere) return f64 ? launch_one<L, true, true>(args, waves, lds, s) : launch_one<L, false, true>(args, waves, lds, s);
+  return f64 ? launch_one<L, true, false>(args, waves, lds, s) : launch_one<L, false, false>(args, waves, lds, s);
+}
+
+hipError_t launch_sweep(int lmax, bool f64, bool sphere, const SweepArgs& args, int waves, hipStream_t stream) {
   const size_t lds = sweep_lds_bytes(args.scratch_blocks, args.nb);
-  hipError_t err = hipSuccess;
-#define TPCF_CASE(L)                                   \
-  case L:                                              \
-    if (f64) {                                         \
-      err = set_lds<L, true>(lds);                     \
-      if (err == hipSuccess) launch_one<L, true>(args, waves, lds, stream); \
-    } else {                                           \
-      err = set_lds<L, false>(lds);                    \
-      if (err == hipSuccess) launch_one<L, false>(args, waves, lds, stream); \
-    }                                                  \
-    break;
+  hipError_t err = hipErrorInvalidValue;
   switch (lmax) {
-    TPCF_CASE(0)
-    TPCF_CASE(1)
-    TPCF_CASE(2)
-    TPCF_CASE(3)
-    TPCF_CASE(4)
-    TPCF_CASE(5)
-    TPCF_CASE(6)
-    TPCF_CASE(7)
-    TPCF_CASE(8)
-    TPCF_CASE(9)
-    TPCF_CASE(10)
-    default:
-      return hipErrorInvalidValue;
+    case 0: err = launch_l<0>(f64, sphere, args, waves, lds, stream); break;
+    case 1: err = launch_l<1>(f64, sphere, args, waves, lds, stream); break;
+    case 2: err = launch_l<2>(f64, sphere, args, waves, lds, stream); break;
+    case 3: err = launch_l<3>(f64, sphere, args, waves, lds, stream); break;
+    case 4: err = launch_l<4>(f64, sphere, args, waves, lds, stream); break;
+    case 5: err = launch_l<5>(f64, sphere, args, waves, lds, stream); break;
+    case 6: err = launch_l<6>(f64, sphere, args, waves, lds, stream); break;
+    case 7: err = launch_l<7>(f64, sphere, args, waves, lds, stream); break;
+    case 8: err = launch_l<8>(f64, sphere, args, waves, lds, stream); break;
+    case 9: err = launch_l<9>(f64, sphere, args, waves, lds, stream); break;
+    case 10: err = launch_l<10>(f64, sphere, args, waves, lds, stream); break;
+    default: return hipErrorInvalidValue;
   }
-#undef TPCF_CASE
   if (err != hipSuccess) return err;
   return hipGetLastError();
 }

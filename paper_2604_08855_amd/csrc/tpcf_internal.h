@@ -33,7 +33,7 @@ struct CatDesc {
   int32_t periodic;
   int32_t row_lo;        // stencil rows: offsets (dy, dz) in [row_lo, row_lo + row_w)^2
   int32_t row_w;
-  int32_t pad_;
+  int32_t sphere;        // 1: unit vectors on the sphere, stored shifted by +2 in a cube of side 4
   double box;
   double scale;          // 2^K / box
   double T[kMaxBins + 1];  // exact integer squared-separation thresholds (lattice units)
@@ -46,6 +46,8 @@ struct CatDesc {
   float inv_delta_l;     // 2^-sh / bin width: bin position per unit of stored coordinate difference
   float u0;              // -r_min / bin width
   float eps;             // fast bin decisions need a fractional bin position in [eps, 1 - eps]
+  float half_inv_scale;  // sphere: 0.5 / scale, so that sqrt(R^2) * half_inv_scale = sin(theta / 2)
+  float pad_;
 };
 
 // Arguments of the persistent sweep kernel.
@@ -78,7 +80,10 @@ struct SweepArgs {
 
 constexpr int kConvTerms = 6;
 
-// Components per primary and bin: (lmax+1)^2 real numbers.
-__host__ __device__ constexpr int ncomp(int lmax) { return (lmax + 1) * (lmax + 1); }
+// Components per primary and bin: (lmax+1)^2 real numbers in 3D; on the sphere 2 m_max + 1
+// (Re a_0, then Re and Im of a_m for m = 1..m_max).
+__host__ __device__ constexpr int ncomp(int lmax, bool sphere = false) {
+  return sphere ? 2 * lmax + 1 : (lmax + 1) * (lmax + 1);
+}
 
 }  // namespace tpcf

@@ -113,14 +113,7 @@ def pair_sums(x, y, z, w, box, periodic, nbins, rmin, rmax):
 
 # ---------------------------------------------------------------- projected fields on the sphere
 
-def sphere_lattice(ra, dec):
-    """Unit vectors (cos dec cos ra, cos dec sin ra, sin dec) shifted by +2 into the cube
-    [0, 4)^3, before snapping."""
-    v = np.stack([np.cos(dec) * np.cos(ra), np.cos(dec) * np.sin(ra), np.sin(dec)], 1)
-    return v + 2.0
-
-
-def zeta_sphere_triangles(ra, dec, w, nbins, theta_min, theta_max, mmax, primaries=None):
+def zeta_sphere_triangles(x, y, z, w, nbins, theta_min, theta_max, mmax, primaries=None):
     """zeta_m on the sphere in the basis-free triangle form
 
         zeta_m(b1, b2) = sum_p w_p sum_{j in b1} sum_{k in b2} w_j w_k cos(m (phi_j - phi_k)),
@@ -129,13 +122,11 @@ def zeta_sphere_triangles(ra, dec, w, nbins, theta_min, theta_max, mmax, primari
     plane at the primary, so no tangent basis is needed; cos(m x) = T_m(cos x). Also returns
     the per-primary counts and sums S_p(b) = sum_{j in b} w_j."""
     from scipy.special import eval_chebyt
-    ra = np.asarray(ra, dtype=np.float64)
-    dec = np.asarray(dec, dtype=np.float64)
-    n = len(ra)
+    X = np.stack([np.asarray(a, dtype=np.float64) for a in (x, y, z)], 1) + 2.0
+    n = len(X)
     w = np.ones(n) if w is None else np.asarray(w, dtype=np.float64)
     cmax = 2.0 * math.sin(0.5 * theta_max)
     K = lattice_bits(4.0, cmax, False)
-    X = sphere_lattice(ra, dec)
     q = np.stack([snap(X[:, a], 4.0, K, False) for a in range(3)], 1)
     sc = math.ldexp(1.0, K) / 4.0
     dth = (theta_max - theta_min) / nbins

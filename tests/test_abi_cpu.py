@@ -151,3 +151,22 @@ def test_null_context_is_rejected():
     assert tpcf._lib.tpcf_set_bins(None, 4, 1.0, 2.0, 2) == 1
     assert tpcf._lib.tpcf_last_error(None) is not None
     tpcf._lib.tpcf_destroy(None)
+
+
+def test_sphere_catalog_validation_on_host():
+    c = _ctx()
+    v = np.array([[1.0, 0.0, 0.0], [0.0, 1.0, 0.0], [0.0, 0.6, 0.8]])
+    x, y, z = v[:, 0].copy(), v[:, 1].copy(), v[:, 2].copy()
+    assert _code(c.set_sphere_catalog, x * 1.001, y, z) == 1  # not unit vectors
+    assert "unit vector" in tpcf._lib.tpcf_last_error(c._h).decode()
+    assert _code(c.set_sphere_catalog, np.array([1.0, np.nan, 0.0]), y, z) == 1
+    assert _code(c.set_sphere_catalog, x, y, z, np.array([1.0, np.inf, 1.0])) == 1
+    with pytest.raises(ValueError):
+        c.set_sphere_catalog(x, y, z[:2])
+    assert tpcf._lib.tpcf_set_sphere_catalog(c._h, -1, None, None, None, None, 0) == 1
+    assert tpcf._lib.tpcf_set_sphere_catalog(c._h, 3, None, None, None, None, 0) == 1
+    assert tpcf._lib.tpcf_set_sphere_catalog(c._h, 0, None, None, None, None, 5) == 1
+    # angular bins beyond pi
+    c.set_bins(4, 0.0, 3.5, 2)
+    assert _code(c.set_sphere_catalog, x, y, z) == 1
+    assert "pi" in tpcf._lib.tpcf_last_error(c._h).decode()

@@ -14,6 +14,7 @@ import numpy as np
 import pytest
 from scipy.special import eval_legendre, sph_harm_y
 
+import catalogs
 import oracle
 from tests import brute
 
@@ -121,8 +122,9 @@ def _pins():
     dec = np.concatenate([0.3 + 0.15 * rng.standard_normal(40), np.pi / 2 - 0.2 * rng.random(29),
                           [np.pi / 2]])
     ws = rng.normal(1.0, 0.5, 70)
-    zs = oracle.zeta_sphere(ra, dec, ws, 4, 0.01, 0.3, 5).zeta
-    ref, _, _ = brute.zeta_sphere_triangles(ra, dec, ws, 4, 0.01, 0.3, 5)
+    u = catalogs.radec_to_unit(ra, dec)
+    zs = oracle.zeta_sphere(*u, ws, 4, 0.01, 0.3, 5).zeta
+    ref, _, _ = brute.zeta_sphere_triangles(*u, ws, 4, 0.01, 0.3, 5)
     if not np.all(np.isfinite(zs)) or np.max(np.abs(zs - ref)) > 1e-12 * np.max(np.abs(ref)):
         failed.append("sphere triangles")
     return failed

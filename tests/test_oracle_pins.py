@@ -386,24 +386,25 @@ def test_degenerate_sizes():
 # ---------------------------------------------------------------- projected fields on the sphere
 
 def _sphere_points(n, seed):
-    """A clustered cap, a polar cap (tangent basis switches near the pole) and the exact pole."""
+    """A clustered cap, a polar cap (tangent basis switches near the pole) and the exact pole;
+    unit vectors (x, y, z) and weights."""
     rng = np.random.default_rng(seed)
     h = n // 2
     ra = np.concatenate([1.0 + 0.15 * rng.standard_normal(h), rng.random(n - h - 1) * 2 * np.pi, [0.0]])
     dec = np.concatenate([0.3 + 0.15 * rng.standard_normal(h), np.pi / 2 - 0.2 * rng.random(n - h - 1),
                           [np.pi / 2]])
-    return ra, dec, rng.normal(1.0, 0.5, n)
+    return (*catalogs.radec_to_unit(ra, dec), rng.normal(1.0, 0.5, n))
 
 
 def test_sphere_bruteforce_triangles():
     """zeta_m against the basis-free triangle form (cos of the angle between tangent-plane
     projections, no atan2 and no tangent basis); per-primary counts exact."""
-    ra, dec, w = _sphere_points(160, 1)
-    r = oracle.zeta_sphere(ra, dec, w, 5, 0.01, 0.3, 8, want_counts=True)
-    z, c, _ = brute.zeta_sphere_triangles(ra, dec, w, 5, 0.01, 0.3, 8)
+    x, y, z, w = _sphere_points(160, 1)
+    r = oracle.zeta_sphere(x, y, z, w, 5, 0.01, 0.3, 8, want_counts=True)
+    zb, c, _ = brute.zeta_sphere_triangles(x, y, z, w, 5, 0.01, 0.3, 8)
     assert r.npairs > 5000
     assert np.array_equal(r.counts, c)
-    assert _rel(r.zeta, z) < 1e-12
+    assert _rel(r.zeta, zb) < 1e-12
 
 
 def test_sphere_worked_example_at_the_pole():
@@ -414,7 +415,7 @@ def test_sphere_worked_example_at_the_pole():
     ang = np.array([0.0, 2 * np.pi / 3, 4 * np.pi / 3])
     ra = np.concatenate([[0.0], ang, [0.5]])
     dec = np.pi / 2 - np.array([0.0, 0.12, 0.12, 0.12, 0.22])
-    r = oracle.zeta_sphere(ra, dec, None, 4, 0.05, 0.25, 7, 0, 1, want_counts=True)
+    r = oracle.zeta_sphere(*catalogs.radec_to_unit(ra, dec), None, 4, 0.05, 0.25, 7, 0, 1, want_counts=True)
     assert list(r.counts[0]) == [0, 3, 0, 1]
     for m in range(8):
         assert abs(r.zeta[m, 1, 1] - (9.0 if m % 3 == 0 else 0.0)) < 1e-6
@@ -427,39 +428,40 @@ def test_sphere_worked_example_at_the_pole():
 def test_sphere_m0_is_product_of_pair_sums():
     """zeta_0(b1, b2) = sum_p w_p S_p(b1) S_p(b2) with S_p(b) = sum_{j in b} w_j taken from the
     numpy pair table; with unit weights the integer pair counts, exactly."""
-    ra, dec, w = _sphere_points(200, 2)
-    r = oracle.zeta_sphere(ra, dec, None, 6, 0.0, 0.4, 2, want_counts=True)
+    x, y, z, w = _sphere_points(200, 2)
+    r = oracle.zeta_sphere(x, y, z, None, 6, 0.0, 0.4, 2, want_counts=True)
     c = r.counts.astype(np.float64)
     assert np.array_equal(r.zeta[0], c.T @ c)
-    _, _, S = brute.zeta_sphere_triangles(ra, dec, w, 6, 0.0, 0.4, 0)
-    rw = oracle.zeta_sphere(ra, dec, w, 6, 0.0, 0.4, 0)
+    _, _, S = brute.zeta_sphere_triangles(x, y, z, w, 6, 0.0, 0.4, 0)
+    rw = oracle.zeta_sphere(x, y, z, w, 6, 0.0, 0.4, 0)
     assert _rel(rw.zeta[0], np.einsum("p,pa,pb->ab", w, S, S)) < 1e-12
 
 
 def test_sphere_rotation_invariance():
     """A rigid rotation of the sphere changes every tangent basis but not zeta_m (up to the
     lattice snapping of the rotated points)."""
-    ra, dec, w = _sphere_points(160, 3)
-    v = np.stack([np.cos(dec) * np.cos(ra), np.cos(dec) * np.sin(ra), np.sin(dec)], 1)
+    x, y, z, w = _sphere_points(160, 3)
+    v = np.stack([x, y, z], 1)
     Q, _ = np.linalg.qr(np.random.default_rng(9).normal(size=(3, 3)))
     u = v @ Q.T
-    ra2, dec2 = np.arctan2(u[:, 1], u[:, 0]), np.arcsin(np.clip(u[:, 2], -1, 1))
-    z0 = oracle.zeta_sphere(ra, dec, w, 5, 0.01, 0.3, 8)
-    z1 = oracle.zeta_sphere(ra2, dec2, w, 5, 0.01, 0.3, 8)
+    z0 = oracle.zeta_sphere(x, y, z, w, 5, 0.01, 0.3, 8)
+    z1 = oracle.zeta_sphere(u[:, 0], u[:, 1], u[:, 2], w, 5, 0.01, 0.3, 8)
     assert z0.npairs == z1.npairs
     assert _rel(z1.zeta, z0.zeta) < 1e-6
 
 
 def test_sphere_degenerate_and_invalid():
-    r = oracle.zeta_sphere(np.zeros(0), np.zeros(0), None, 3, 0.0, 0.1, 4)
+    e = np.zeros(0)
+    r = oracle.zeta_sphere(e, e, e, None, 3, 0.0, 0.1, 4)
     assert r.npairs == 0 and not r.zeta.any()
-    r = oracle.zeta_sphere(np.array([0.3]), np.array([0.2]), None, 3, 0.0, 0.1, 4)
+    r = oracle.zeta_sphere(*catalogs.radec_to_unit(np.array([0.3]), np.array([0.2])), None, 3, 0.0, 0.1, 4)
     assert r.npairs == 0 and not r.zeta.any()
     # antipodal pair at the largest angle: in range only below theta_max = pi
-    r = oracle.zeta_sphere(np.array([0.0, np.pi]), np.array([0.0, 0.0]), None, 2, 0.0, np.pi, 1)
+    one, zero = np.array([1.0, -1.0]), np.zeros(2)
+    r = oracle.zeta_sphere(one, zero, zero, None, 2, 0.0, np.pi, 1)
     assert r.npairs == 0
-    r = oracle.zeta_sphere(np.array([0.0, 3.0]), np.array([0.0, 0.0]), None, 2, 0.0, np.pi, 1)
+    r = oracle.zeta_sphere(*catalogs.radec_to_unit(np.array([0.0, 3.0]), zero), None, 2, 0.0, np.pi, 1)
     assert r.npairs == 2 and r.zeta[0, 1, 1] == 2.0
     for bad in [(3, 0.2, 0.1, 4), (0, 0.0, 0.1, 4), (3, 0.0, 4.0, 4), (3, 0.0, 0.1, -1)]:
         with pytest.raises(ValueError):
-            oracle.zeta_sphere(np.zeros(2), np.zeros(2), None, *bad)
+            oracle.zeta_sphere(one, zero, zero, None, *bad)
