@@ -374,7 +374,12 @@ def run_sphere(args):
         ctx.set_bins(nb, tmin, tmax, mmax)
         ctx.set_precision(prec)
         ctx.set_sphere_catalog(*dev)
-        tuning = None if args.no_autotune else ctx.autotune()
+        if args.tuning:
+            ppc, wpc = (float(v) for v in args.tuning.split(","))
+            ctx.set_tuning(ppc, int(wpc))
+            tuning = {"points_per_cell": ppc, "waves_per_cu": int(wpc), "source": "--tuning"}
+        else:
+            tuning = None if args.no_autotune else ctx.autotune()
         log(f"[bench] sphere {prec} tuning {tuning}")
         ctx.compute_zeta(device_output=True)  # warmup
         torch.cuda.synchronize()
@@ -449,6 +454,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--fp64-steps", type=int, default=None)
     ap.add_argument("--no-autotune", action="store_true", help="keep the library's default tuning")
+    ap.add_argument("--tuning", default="", help="sphere form: 'PPC,WPC' points per cell and waves per CU "
+                                                 "instead of the autotuner (profiling runs)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (HBM counter calibration)")
     ap.add_argument("--workload", choices=["single", "batch", "dmr", "sphere"], default="single",

@@ -128,7 +128,8 @@ int tpcf_set_tuning(tpcf_ctx* ctx, double points_per_cell, int waves_per_cu, int
  * of primaries (every k-th cell-sorted point, k = round(1 / sample_fraction), so the sample follows
  * the catalogue's density; each configuration timed twice after a warm-up, the faster run kept)
  * for grid densities of 3-24 points per cell and 6 or 8 waves per compute
- * unit, then keeps the fastest as if set by tpcf_set_tuning. sample_fraction in (0, 1]; 0 means
+ * unit (8 or 12 with a catalogue on the sphere), then keeps the fastest as if set by
+ * tpcf_set_tuning. sample_fraction in (0, 1]; 0 means
  * 0.05. Results of later compute calls do not depend on the tuning. The call synchronises the
  * context's stream. Stats of the last compute call are kept; its debug output is dropped
  * (tpcf_debug_pair_counts / tpcf_debug_alm return TPCF_E_STATE until the next compute call with

@@ -951,7 +951,8 @@ int tpcf_autotune(tpcf_ctx* c, double sample_fraction, tpcf_tuning* out) {
   double best_ms = ms_default, best_ppc = ppc0;
   int best_wpc = wpc0, tried = 1;
   const double ppcs[] = {3.0, 4.0, 6.0, 8.0, 12.0, 16.0, 24.0};
-  const int wpcs[] = {8, 6};
+  // The sphere's kernels hold fewer registers (three waves fit on a SIMD): 12 waves per CU too.
+  const int wpcs[] = {8, is_sphere(c) ? 12 : 6};
   for (int wi = 0; wi < 2 && rc == TPCF_OK; ++wi)
     for (int pi = 0; pi < 7 && rc == TPCF_OK; ++pi) {
       if (ppcs[pi] == ppc0 && wpcs[wi] == wpc0) continue;

@@ -945,30 +945,41 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sw
           };
           // Padding entries hold the zero-weight sentinel record, so every entry is evaluated
           // alike.
-          if constexpr (F64) {
-            // FP64 replays every bin once per m-group and loads FP64 weights separately, which
-            // makes its rounds latency-bound: a two-round software pipeline with separate
-            // registers for even and odd rounds (no register copies, so each wait covers only its
-            // own load). As soon as round i has taken its unit vector and weight, the position
-            // and weight of round i + 2 and the index of round i + 4 are requested into that
-            // round's registers. Reads past a bin's last block stay inside the wave's scratch
-            // (kScratchTail spare blocks follow the regions); such entries are replaced by the
-            // sentinel before use.
+          if constexpr (F64 || SPH) {
+            // FP64 replays every bin once per m-group and loads FP64 weights separately, and the
+            // sphere's rounds are short (2 m_max + 1 components): both are latency-bound with one
+            // round of look-ahead. A two-round software pipeline with separate registers for even
+            // and odd rounds (no register copies, so each wait covers only its own load): as soon
+            // as round i has taken its direction and weight, the record (and FP64 weight) of
+            // round i + 2 and the index of round i + 4 are requested into that round's registers.
+            // Reads past a bin's last block stay inside the wave's scratch (kScratchTail spare
+            // blocks follow the regions); such entries are replaced by the sentinel before use.
+            using RecT = std::conditional_t<F64, uint3, uint4>;
             auto idx_at = [&](int k) -> uint32_t { return k < nblk_b ? sb[k * kBlock] : a.sentinel; };
-            auto pos_at = [&](uint32_t j) -> uint3 {
-              const uint4* r = a.rec + j;
-              return make_uint3(r->x, r->y, r->z);
+            auto pos_at = [&](uint32_t j) -> RecT {
+              if constexpr (F64) {
+                const uint4* r = a.rec + j;
+                return make_uint3(r->x, r->y, r->z);
+              } else {
+                return a.rec[j];
+              }
             };
-            uint3 R0 = pos_at(idx_at(0)), R1 = pos_at(idx_at(1));
-            real W0 = a.w64[idx_at(0)], W1 = a.w64[idx_at(1)];
+            auto wt_at = [&](uint32_t j) -> real {
+              if constexpr (F64) return a.w64[j];
+              else return real(0);  // mixed: the weight travels in the record
+            };
+            RecT R0 = pos_at(idx_at(0)), R1 = pos_at(idx_at(1));
+            real W0 = wt_at(idx_at(0)), W1 = wt_at(idx_at(1));
             uint32_t J0 = idx_at(2), J1 = idx_at(3);
             int i = 0;
-            auto step = [&](uint3& R, real& W, uint32_t& J, auto WRITE) {
+            auto step = [&](RecT& R, real& W, uint32_t& J, auto WRITE) {
               // rounds stay in order, so each waits only for its own loads
               __builtin_amdgcn_sched_barrier(0);
               real vx, vy, vz;
               direction<SPH>(P0, tb, R, vx, vy, vz);
-              real w = W;
+              real w;
+              if constexpr (F64) w = W;
+              else w = __uint_as_float(R.w);
               // The next loads go into this round's registers: the empty asm statement makes the
               // record address depend on this round's unit vector and weight, so the loads cannot
               // be hoisted above their last use.
@@ -977,7 +988,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sw
               uint32_t jr = i + 2 < nblk_b ? J : a.sentinel;
               asm volatile("" : "+v"(jr), "+v"(w) : "v"(vx));
               R = pos_at(jr);
-              W = a.w64[jr];
+              if constexpr (F64) W = a.w64[jr];
               J = sb[(i + 4) * kBlock];
               accumulate<LMAX, F64, SPH, G, decltype(WRITE)::value>(acc, vx, vy, vz, w);
               ++i;
@@ -995,9 +1006,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sw
               flush_acc();
             }
           } else {
-            // Mixed: one round of software pipeline (the record of the next round and the index
-            // of the round after it are in flight while the current round is evaluated); its
-            // rounds are long enough to cover the latency.
+            // Mixed 3D: one round of software pipeline (the record of the next round and the
+            // index of the round after it are in flight while the current round is evaluated);
+            // its rounds are long enough to cover the latency.
             uint32_t jn = nblk_b > 1 ? sb[kBlock] : a.sentinel;
             uint4 r = a.rec[sb[0]];
             int i = 0;
