@@ -347,6 +347,18 @@ def run_dmr(args):
     print(json.dumps(out), flush=True)
 
 
+def calibration_copy(torch, mib):
+    """A plain device copy of `mib` MiB: its FETCH_SIZE / WRITE_SIZE calibrate the HBM counters."""
+    if mib <= 0:
+        return
+    src = torch.ones(mib * 2**20 // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"[bench] calibration copy of {mib} MiB done")
+
+
 def run_sphere(args):
     """The paper's own geometry: a full-sky HEALPix map, nside 1024 (12,582,912 pixels), map values
     rho - 1 of a log-normal field (sigma_lnrho 0.5) sampled on the sphere, 20 angular bins in
@@ -367,6 +379,7 @@ def run_sphere(args):
 
     dev = [torch.from_numpy(a).cuda() for a in (m.x, m.y, m.z, m.w)]
     torch.cuda.synchronize()
+    calibration_copy(torch, args.copy_calibration_mib)
     res = {}
     ranges = [(0, 24), (m.n // 2, m.n // 2 + 24), (m.n - 24, m.n)]
     for prec, steps in (("mixed", args.steps), ("fp64", max(1, min(args.steps, 2)))):
@@ -485,15 +498,7 @@ def main():
     cat, w = make_catalog()
     dev = [torch.from_numpy(a).cuda() for a in (cat.x, cat.y, cat.z, w)]
     torch.cuda.synchronize()
-    if args.copy_calibration_mib > 0:
-        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE calibrate the HBM counters
-        src = torch.ones(args.copy_calibration_mib * 2**20 // 4, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        log(f"[bench] calibration copy of {args.copy_calibration_mib} MiB done")
-        del src, dst
+    calibration_copy(torch, args.copy_calibration_mib)
 
     tune = not args.no_autotune
     ms, sweep_ms, st, zmix, tmix = time_path(tpcf, torch, dev, "mixed", args.steps, args.warmup, tune)

@@ -310,6 +310,7 @@ void configure_sphere(const tpcf_ctx* c, const HostCat& h, CatDesc& d) {
   d.inv_delta_l = (float)(2.0 / dth);
   d.u0 = (float)(-c->rmin / dth);
   d.half_inv_scale = (float)(0.5 / d.scale);
+  d.asin_small = 0.5 * cmax <= 0.06 ? 1 : 0;
   // |u_fp32 - u_exact| <= (theta_max / dtheta + 1) (4.5 kappa + 20) 2^-24, kappa the condition
   // number of asin at the largest argument (the chord's relative error is at most 4.5 2^-24, the
   // arcsine's own 16 2^-24, the scaling and offset 4 2^-24); integer thresholds move an edge by

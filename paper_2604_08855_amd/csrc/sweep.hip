@@ -38,9 +38,9 @@
 // points are unit vectors shifted into a cube of side 4, bins are linear in the angle theta
 // (integer thresholds on the squared chord 2 sin(theta/2)), and per pair the displacement is
 // projected on a tangent basis (e1, e2) of the primary, (c, s) = unit(d.e1, d.e2), so that
-//     a_m = sum_j w_j (c_j - i s_j)^m = sum_j w_j exp(-i m phi_j),   0 <= m <= m_max,
-// one complex multiply per m and no trigonometric call (the Chebyshev form of cos m phi and
-// sin m phi the paper uses); zeta_m(b1, b2) = sum_p w_p Re[a_m(b1) conj(a_m(b2))].
+//     a_m = sum_j w_j exp(-i m phi_j) = sum_j w_j (T_m(c_j) - i s_j U_(m-1)(c_j)),  0 <= m <= m_max,
+// with the Chebyshev recurrence in place of trigonometric calls, as the paper does (two FMAs per
+// m); zeta_m(b1, b2) = sum_p w_p Re[a_m(b1) conj(a_m(b2))].
 #include <type_traits>
 
 #include "tpcf_internal.h"
@@ -172,42 +172,55 @@ __device__ __forceinline__ void add_moments(real (&acc)[S], real x, real y, real
 }
 
 // Sphere plan: component 0 is Re a_0, components 2m - 1 and 2m are Re a_m and Im a_m; one group
-// of 64 reduction slots (2 m_max + 1 <= 21 are used).
+// of 32 reduction slots (2 m_max + 1 <= 21 are used).
 template <int M>
 struct PlanSph {
   static constexpr int NC = 2 * M + 1;
   static constexpr int NG = 1;
-  static constexpr int slots(int) { return 64; }
+  static constexpr int slots(int) { return 32; }
   static constexpr int gsize(int) { return NC; }
   __host__ __device__ static constexpr int global_of(int, int s) { return s < NC ? s : -1; }
 };
 
-// Adds (WRITE: stores) w (c - i s)^m, m = 0..M, of one pair into acc.
+// Adds (WRITE: stores) w exp(-i m phi) = w (cos m phi - i sin m phi), m = 0..M, of one pair into
+// acc, from (c, s) = (cos phi, sin phi) with the Chebyshev recurrence the paper uses in place of
+// trigonometric calls: A_m = w T_m(c) = w cos m phi and B_m = w s U_(m-1)(c) = w sin m phi both
+// obey X_m = 2c X_(m-1) - X_(m-2), so each m costs two FMAs and two adds.
 template <int M, bool WRITE, class real, int S>
 __device__ __forceinline__ void add_moments_sph(real (&acc)[S], real c, real s, real w) {
-  real pr = w, pi = real(0);
-  static_for<0, M + 1>([&](auto Mi) {
-    constexpr int m = Mi;
-    if constexpr (m > 0) {
-      const real nr = pr * c + pi * s;
-      const real ni = pi * c - pr * s;
-      pr = nr;
-      pi = ni;
-    }
-    constexpr int re = m == 0 ? 0 : 2 * m - 1;
-    if constexpr (WRITE) {
-      acc[re] = pr;
-      if constexpr (m > 0) acc[re + 1] = pi;
-    } else {
-      acc[re] += pr;
-      if constexpr (m > 0) acc[re + 1] += pi;
-    }
-  });
+  auto put = [&](int k, real v) {
+    if constexpr (WRITE) acc[k] = v;
+    else acc[k] += v;
+  };
+  auto put_neg = [&](int k, real v) {
+    if constexpr (WRITE) acc[k] = -v;
+    else acc[k] -= v;
+  };
+  put(0, w);
+  if constexpr (M >= 1) {
+    const real c2 = c + c;
+    real Ap = w, A = w * c;         // A_0, A_1
+    real Bp = real(0), B = w * s;   // B_0, B_1
+    put(1, A);
+    put_neg(2, B);
+    static_for<2, M + 1>([&](auto Mi) {
+      constexpr int m = Mi;
+      const real An = c2 * A - Ap;
+      const real Bn = c2 * B - Bp;
+      Ap = A;
+      A = An;
+      Bp = B;
+      B = Bn;
+      put(2 * m - 1, A);
+      put_neg(2 * m, B);
+    });
+  }
 }
 
 // ------------------------------------------------------------------------------------------
-// Cross-lane transpose-reduction. Input: S values per lane (S = 64 or 128). Output: slot k of
-// lane L (k < S/64) holds the wave-wide sum of component (S/64)*L + k.
+// Cross-lane transpose-reduction. Input: S values per lane (S = 32, 64 or 128). Output: slot k of
+// lane L (k < S/64) holds the wave-wide sum of component (S/64)*L + k; for S = 32, slot 0 of
+// lanes 2c and 2c + 1 both hold the sum of component c.
 // Stage pairs: lanes 32 apart (permlane32 swap), 16 apart (permlane16 swap), then within rows
 // of 16 by DPP row_mirror, row_half_mirror and quad permutations. At each stage a lane keeps
 // the half of its values selected by one lane-index bit and receives the partner's copy of it.
@@ -264,7 +277,13 @@ __device__ __forceinline__ void transpose_reduce(real (&v)[S], int lane) {
   static_for<0, S / 8>([&](auto k) { v[k] = dpp_pair<kRowMirror>(v[k], v[k + S / 8], b3); });
   static_for<0, S / 16>([&](auto k) { v[k] = dpp_pair<kHalfMirror>(v[k], v[k + S / 16], b2); });
   static_for<0, S / 32>([&](auto k) { v[k] = dpp_pair<kQuadXor2>(v[k], v[k + S / 32], b1); });
-  static_for<0, S / 64>([&](auto k) { v[k] = dpp_pair<kQuadXor1>(v[k], v[k + S / 64], b0); });
+  if constexpr (S >= 64) {
+    static_for<0, S / 64>([&](auto k) { v[k] = dpp_pair<kQuadXor1>(v[k], v[k + S / 64], b0); });
+  } else {
+    // the stages so far summed over the 32 lanes of equal (bit 2 xor bit 0); the neighbour
+    // (lane bit 0 flipped) holds the other half of the same component
+    v[0] = v[0] + dpp<kQuadXor1>(v[0]);
+  }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -416,6 +435,13 @@ __device__ __forceinline__ float asin01(float x) {
   p = __builtin_fmaf(p, y2, 1.666666667e-01f);
   const float a = __builtin_fmaf(y * y2, p, y);
   return up ? __builtin_fmaf(-2.0f, a, 1.5707963268f) : a;
+}
+
+// The same series through n = 2 (x + x^3/6 + 3 x^5/40), for x <= 0.06: the truncation is below
+// c_3 x^6 / (1 - x^2) < 2.1e-9 (about 2^-28.8) relative.
+__device__ __forceinline__ float asin_small(float x) {
+  const float x2 = x * x;
+  return __builtin_fmaf(x * x2, __builtin_fmaf(x2, 7.500000000e-02f, 1.666666667e-01f), x);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -601,6 +627,7 @@ struct CatU {
   int sh, K, nc, periodic, row_lo, row_w;
   uint32_t cell_base;
   float cs, inv_cs, span, inv_span, reach, margin, inv_dl, u0, eps, inv_w, hinv;
+  int asin_small;
 };
 
 // Builds row t of the primary's stencil (rows are offsets (dy, dz) from the primary's cell):
@@ -706,12 +733,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sw
   // Scratch regions: bin b owns blocks [reg[b], reg[b+1]).
   if (lane <= nb) reg[lane] = a.regions[lane];
 
-  // Moment index held by each of this lane's reduction slots, per group.
+  // Moment index held by each of this lane's reduction slots, per group (32 slots: the even
+  // lane of each pair writes).
   int mslot[P::NG][2];
   static_for<0, P::NG>([&](auto G) {
-    constexpr int per = P::slots(G) / 64;
+    constexpr int SG = P::slots(G);
+    constexpr int per = SG >= 64 ? SG / 64 : 1;
 #pragma unroll
-    for (int k = 0; k < 2; ++k) mslot[G][k] = k < per ? P::global_of(G, per * lane + k) : -1;
+    for (int k = 0; k < 2; ++k) {
+      int ms = -1;
+      if (k < per) ms = SG >= 64 ? P::global_of(G, per * lane + k) : ((lane & 1) ? -1 : P::global_of(G, lane >> 1));
+      mslot[G][k] = ms;
+    }
   });
 
   for (int i = lane; i < (LMAX + 1) * nb * nb; i += 64) part[i] = 0.0;
@@ -786,6 +819,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sw
       cu.eps = cd.eps;
       cu.inv_w = 1.0f / (float)cu.row_w;
       cu.hinv = cd.half_inv_scale;
+      cu.asin_small = uniform(cd.asin_small);
       if (lane <= nb) sT[lane] = cd.T[lane];
       cur_cat = cat;
       __syncthreads();
@@ -923,7 +957,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sw
         const uint32_t* sb = scratch + (size_t)k0 * kBlock + lane;
         static_for<0, P::NG>([&](auto G) {
           constexpr int SG = P::slots(G);
-          constexpr int per = SG / 64;
+          constexpr int per = SG >= 64 ? SG / 64 : 1;
           real acc[SG];
           // slots past the group's components are never written by the moments
 #pragma unroll
@@ -1109,8 +1143,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sw
                     fz = (float)sdiff(rc[u].z, P0.qz);
         const float r2 = fx * fx + fy * fy + fz * fz;
         // 3D: linear in the separation; sphere: linear in theta = 2 asin(chord / 2)
-        const float uu = SPH ? asin01(__builtin_amdgcn_sqrtf(r2) * cu.hinv) * cu.inv_dl + cu.u0
-                             : __builtin_amdgcn_sqrtf(r2) * cu.inv_dl + cu.u0;
+        float uu;
+        if constexpr (SPH) {
+          const float x = __builtin_amdgcn_sqrtf(r2) * cu.hinv;
+          uu = (cu.asin_small ? asin_small(x) : asin01(x)) * cu.inv_dl + cu.u0;
+        } else {
+          uu = __builtin_amdgcn_sqrtf(r2) * cu.inv_dl + cu.u0;
+        }
         const float fl = floorf(uu);
         const float fr = uu - fl;
         const int bb = (int)fl;

@@ -47,7 +47,7 @@ struct CatDesc {
   float u0;              // -r_min / bin width
   float eps;             // fast bin decisions need a fractional bin position in [eps, 1 - eps]
   float half_inv_scale;  // sphere: 0.5 / scale, so that sqrt(R^2) * half_inv_scale = sin(theta / 2)
-  float pad_;
+  int32_t asin_small;    // sphere: sin(theta_max / 2) <= 0.06, the three-term arcsine suffices
 };
 
 // Arguments of the persistent sweep kernel.

@@ -78,6 +78,20 @@ def test_clustered_points_parity(tpcf, prec, mmax):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_small_angles(tpcf, prec):
+    """4,001 tightly clustered points, 12 bins in [0.002, 0.1) rad (sin(theta_max/2) <= 0.06: the
+    three-term arcsine decides bins), m_max = 8."""
+    m = catalogs.sphere_cluster(4001, 21, ncentre=5, spread=0.03)
+    say(f"small angles prec={prec}")
+    ctx, z = run_sphere(tpcf, m, 12, 0.002, 0.1, 8, prec, debug=True)
+    ref = oracle.zeta_sphere(m.x, m.y, m.z, m.w, 12, 0.002, 0.1, 8, want_counts=True)
+    err = rel_err_per_l(z, ref.zeta)
+    say("rel err per m", err)
+    assert err.max() <= TOL[prec]
+    np.testing.assert_array_equal(ctx.pair_counts(), ref.counts)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_wide_angles(tpcf, prec):
     """Uniform points, bins reaching 2 rad (the arcsine's upper branch decides bins) and pi
     (every decision exact: antipodal pairs stay out of range)."""
