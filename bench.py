@@ -33,6 +33,7 @@ sys.path.insert(0, ROOT)
 NB, RMIN, RMAX, LMAX, BOX, N = 20, 10.0, 200.0, 10, 1000.0, 1_000_000
 # HBM counters of the sweep kernel (rocprofv3 FETCH_SIZE / WRITE_SIZE, calibrated on a plain copy)
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "sweep_kernel_lognormal1e6_hbm_traffic.md")
+SPHERE_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "sweep_kernel_sphere_nside1024_hbm_traffic.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2604_08855_amd", "csrc", f) for f in ("sweep.hip", "tpcf_internal.h")]
 PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32, published
 F_PAIR = 4 * (LMAX + 1) ** 2  # algorithmic flops per in-range pair (2 to generate + 2 to add)
@@ -100,13 +101,13 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(precision):
+def measured_traffic(precision, profile=TRAFFIC_PROFILE):
     """HBM bytes per sweep launch from the committed counter profile, if it was taken on the
     kernel source as it is now; None otherwise."""
-    if not os.path.exists(TRAFFIC_PROFILE):
+    if not os.path.exists(profile):
         return None
     vals = {}
-    for line in open(TRAFFIC_PROFILE):
+    for line in open(profile):
         if line.startswith("- `") and "`: " in line:
             k, v = line[3:].split("`: ", 1)
             vals[k] = v.strip()
@@ -118,7 +119,7 @@ def measured_traffic(precision):
     except (KeyError, ValueError):
         return None
     return {"bytes": fetch + write, "fetch_bytes": fetch, "write_bytes": write,
-            "source": os.path.relpath(TRAFFIC_PROFILE, ROOT)}
+            "source": os.path.relpath(profile, ROOT)}
 
 
 def cpu_baseline_parallel(cat, w, seconds):
@@ -422,6 +423,7 @@ def run_sphere(args):
                      "max_rel_err_vs_oracle_on_sampled_ranges": max(errs)}
         log(f"[bench] sphere {prec}: {res[prec]}")
     mx = res["mixed"]
+    traffic = measured_traffic("mixed", SPHERE_TRAFFIC_PROFILE)
     f_pair = 4 * (2 * mmax + 1)
     f_prim = 2 * nb * nb * (2 * mmax + 1)
     flops = mx["pairs_per_step"] * f_pair + m.n * f_prim
@@ -441,8 +443,9 @@ def run_sphere(args):
                                                     for k, v in res.items()},
         "roofline": {"bound": "alu", "kernel": "sweep_kernel<8,false,true>", "achieved": achieved,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
-                     "traffic": None, "flops_per_launch": flops, "flops_per_pair": f_pair,
-                     "flops_per_primary": f_prim},
+                     "traffic": traffic["bytes"] if traffic else None, "traffic_detail": traffic,
+                     "flops_per_launch": flops, "flops_per_pair": f_pair, "flops_per_primary": f_prim,
+                     "sweep_ms": mx["sweep_ms"]},
     }
     if args.cpu_seconds > 0:
         threads = len(os.sched_getaffinity(0))

@@ -1134,9 +1134,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sw
     const uint32_t dummy_pos = (uint32_t)S * kBlock + lane;
     auto process_batch = [&](const uint32_t(&id)[kBatch], const uint4(&rc)[kBatch]) -> bool {
       bool soft = false;
-      bool slowv[kBatch];
+      bool slowv[kBatch], accv[kBatch];
       int bbv[kBatch];
+      unsigned long long cwv[kBatch];
       uint64_t anyslow = 0;
+      // all cursor increments of the batch are issued before the first result is used, so their
+      // LDS round trips overlap
 #pragma unroll
       for (int u = 0; u < kBatch; ++u) {
         const float fx = (float)sdiff(rc[u].x, P0.qx), fy = (float)sdiff(rc[u].y, P0.qy),
@@ -1159,9 +1162,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sw
         slowv[u] = ok && !fast;
         bbv[u] = bb;
         anyslow |= __ballot(slowv[u]);
-        const unsigned long long cw = atomicAdd(&cur[acc ? bb : kMaxBins + lane], 1ull);
-        soft |= acc && (uint32_t)cw >= (uint32_t)(cw >> 32);
-        scratch[acc ? (uint32_t)cw : dummy_pos] = id[u];
+        accv[u] = acc;
+        cwv[u] = atomicAdd(&cur[acc ? bb : kMaxBins + lane], 1ull);
+      }
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const unsigned long long cw = cwv[u];
+        soft |= accv[u] && (uint32_t)cw >= (uint32_t)(cw >> 32);
+        scratch[accv[u] ? (uint32_t)cw : dummy_pos] = id[u];
       }
       if (anyslow) {
 #pragma unroll
