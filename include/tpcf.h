@@ -123,10 +123,12 @@ int tpcf_set_precision(tpcf_ctx* ctx, int precision);
 int tpcf_set_tuning(tpcf_ctx* ctx, double points_per_cell, int waves_per_cu, int scratch_blocks);
 
 /*
- * Autotuner for the persistent sweep. On the catalogue(s) staged by the last tpcf_set_catalog or
- * tpcf_compute_batch call, with the current bins and precision, it times the sweep over a sample
- * of primaries (every k-th cell-sorted point, k = round(1 / sample_fraction), so the sample follows
- * the catalogue's density; each configuration timed twice after a warm-up, the faster run kept)
+ * Autotuner for the persistent sweep. On the catalogue(s) staged by the last tpcf_set_catalog,
+ * tpcf_set_sphere_catalog or tpcf_compute_batch call, with the current bins and precision, it times
+ * the sweep over a sample of primaries (a fraction sample_fraction of all, taken as up to 16 evenly
+ * spaced runs of consecutive cell-sorted points, so the sample follows the catalogue's density and
+ * keeps the full sweep's neighbour sharing; each configuration timed twice after a warm-up, the
+ * faster run kept)
  * for grid densities of 3-24 points per cell and 6 or 8 waves per compute
  * unit (8 or 12 with a catalogue on the sphere), then keeps the fastest as if set by
  * tpcf_set_tuning. sample_fraction in (0, 1]; 0 means

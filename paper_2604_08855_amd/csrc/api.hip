@@ -912,11 +912,20 @@ int tpcf_autotune(tpcf_ctx* c, double sample_fraction, tpcf_tuning* out) {
   const int wpc0 = c->waves_per_cu;
   c->debug = false;
 
-  // Every k-th cell-sorted point. The positions are re-sorted per grid density; any such
-  // stride sample follows the catalogue's density.
-  const uint32_t stride = (uint32_t)std::max(1.0, floor(1.0 / sample_fraction + 0.5));
+  // Up to 16 evenly spaced runs of consecutive cell-sorted points, sample_fraction of all: the
+  // runs follow the catalogue's density (the positions are re-sorted per grid density), and
+  // consecutive primaries keep the neighbour sharing in cache that the full sweep sees.
   std::vector<uint32_t> list;
-  for (uint64_t s = 0; s < (uint64_t)c->ntot; s += stride) list.push_back((uint32_t)s);
+  {
+    const uint64_t n = (uint64_t)c->ntot;
+    const uint64_t want = std::max<uint64_t>(1, (uint64_t)llround((double)n * sample_fraction));
+    const uint64_t runs = std::max<uint64_t>(1, std::min<uint64_t>(16, want / 2048));
+    for (uint64_t r = 0; r < runs && n > 0; ++r) {
+      const uint64_t start = n * r / runs;
+      const uint64_t len = want * (r + 1) / runs - want * r / runs;
+      for (uint64_t s = start; s < std::min(n, start + len); ++s) list.push_back((uint32_t)s);
+    }
+  }
   const uint32_t ntask = (uint32_t)list.size();
   if ((rc = ensure(c, c->tasks, std::max<size_t>(1, list.size()) * 4, "task list"))) return rc;
   if (ntask) HIP_TRY(c, hipMemcpyAsync(c->tasks.p, list.data(), list.size() * 4, hipMemcpyHostToDevice, c->stream));
