@@ -54,6 +54,8 @@ def _load():
         lib.oracle_edge_correct.restype = i
         lib.oracle_zeta_sphere.argtypes = [i64, p, p, p, p, i, d, d, i, i64, i64, p, p, p, i]
         lib.oracle_zeta_sphere.restype = i
+        lib.oracle_zeta_pivots.argtypes = [i64, p, p, p, p, d, i, i, d, d, i, d, p, p, p, p, p, i]
+        lib.oracle_zeta_pivots.restype = i
         _lib = lib
     return _lib
 
@@ -186,6 +188,33 @@ def zeta_sphere(x, y, z, w, nbins: int, theta_min: float, theta_max: float, mmax
     if rc:
         raise ValueError("oracle_zeta_sphere: invalid arguments")
     return Result(zt, counts, None, int(npairs.value))
+
+
+class PivotResult:
+    """Result of zeta_pivots: zeta, number of pivot groups, pairs, and the group pivots (lattice
+    positions [G, 3] and weights [G])."""
+
+    def __init__(self, zeta, ngroups, npairs, gq, gw):
+        self.zeta, self.ngroups, self.npairs, self.gq, self.gw = zeta, ngroups, npairs, gq, gw
+
+
+def zeta_pivots(x, y, z, w, box: float, periodic: bool, nbins: int, rmin: float, rmax: float,
+                lmax: int, h: float, threads: int = 0) -> PivotResult:
+    """Approximate zeta with pivots shared over cubic pivot cells of side h (oracle_zeta_pivots)."""
+    x, y, z = (np.ascontiguousarray(a, dtype=np.float64) for a in (x, y, z))
+    n = x.shape[0]
+    w = np.ones(n) if w is None else np.ascontiguousarray(w, dtype=np.float64)
+    zt = np.zeros((lmax + 1, nbins, nbins))
+    gq = np.zeros((3, max(n, 1)), dtype=np.int64)
+    gw = np.zeros(max(n, 1))
+    ng, npairs = ctypes.c_int64(0), ctypes.c_int64(0)
+    rc = _load().oracle_zeta_pivots(n, _ptr(x), _ptr(y), _ptr(z), _ptr(w), float(box), int(bool(periodic)),
+                                    int(nbins), float(rmin), float(rmax), int(lmax), float(h), _ptr(zt),
+                                    ctypes.byref(ng), ctypes.byref(npairs), _ptr(gq), _ptr(gw), int(threads))
+    if rc:
+        raise ValueError("oracle_zeta_pivots: invalid arguments")
+    G = int(ng.value)
+    return PivotResult(zt, G, int(npairs.value), gq[:, :G].T.copy(), gw[:G].copy())
 
 
 def zeta_catalog(cat, nbins, rmin, rmax, lmax, **kw) -> Result:

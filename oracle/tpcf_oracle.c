@@ -179,12 +179,13 @@ static int64_t displacement(int64_t qj, int64_t qp, int K, int periodic)
     return d;
 }
 
-/* Bin of the pair (p, j): -1 when out of range. Also returns the displacement. */
-static int pair_bin(const problem *P, int64_t p, int64_t j, int64_t d[3])
+/* Bin of the pair (pivot at lattice point qp, secondary j): -1 when out of range. Also returns
+ * the displacement. */
+static int pair_bin_at(const problem *P, const int64_t qp[3], int64_t j, int64_t d[3])
 {
-    d[0] = displacement(P->qx[j], P->qx[p], P->K, P->periodic);
-    d[1] = displacement(P->qy[j], P->qy[p], P->K, P->periodic);
-    d[2] = displacement(P->qz[j], P->qz[p], P->K, P->periodic);
+    d[0] = displacement(P->qx[j], qp[0], P->K, P->periodic);
+    d[1] = displacement(P->qy[j], qp[1], P->K, P->periodic);
+    d[2] = displacement(P->qz[j], qp[2], P->K, P->periodic);
     const int64_t lim = (int64_t)1 << 26; /* beyond this on one axis, R^2 > 2^52 > T_nb */
     for (int a = 0; a < 3; a++)
         if (d[a] > lim || d[a] < -lim) return -1;
@@ -196,17 +197,24 @@ static int pair_bin(const problem *P, int64_t p, int64_t j, int64_t d[3])
     return b;
 }
 
-/* One primary: a_lm over all secondaries, then its contribution to zeta (added into zacc). */
-static void one_primary(const problem *P, int64_t p, double complex *alm, double complex *Y,
-                        double *zacc, int64_t *counts, int64_t *npairs)
+static int pair_bin(const problem *P, int64_t p, int64_t j, int64_t d[3])
+{
+    const int64_t qp[3] = {P->qx[p], P->qy[p], P->qz[p]};
+    return pair_bin_at(P, qp, j, d);
+}
+
+/* One pivot at lattice point qp with weight wp: a_lm over all secondaries other than `skip`, then
+ * its contribution to zeta (added into zacc). */
+static void one_pivot(const problem *P, const int64_t qp[3], double wp, int64_t skip, double complex *alm,
+                      double complex *Y, double *zacc, int64_t *counts, int64_t *npairs)
 {
     const int nb = P->nbins, lmax = P->lmax, nc = (lmax + 1) * (lmax + 1);
     memset(alm, 0, sizeof(double complex) * (size_t)nb * nc);
     for (int b = 0; b < nb; b++) counts[b] = 0;
     for (int64_t j = 0; j < P->n; j++) {
-        if (j == p) continue;
+        if (j == skip) continue;
         int64_t d[3];
-        int b = pair_bin(P, p, j, d);
+        int b = pair_bin_at(P, qp, j, d);
         if (b < 0) continue;
         double r = sqrt((double)d[0] * d[0] + (double)d[1] * d[1] + (double)d[2] * d[2]);
         ylm_unit(lmax, d[0] / r, d[1] / r, d[2] / r, Y);
@@ -215,7 +223,6 @@ static void one_primary(const problem *P, int64_t p, double complex *alm, double
         counts[b]++;
         (*npairs)++;
     }
-    const double wp = P->w[p];
     for (int l = 0; l <= lmax; l++)
         for (int b1 = 0; b1 < nb; b1++)
             for (int b2 = 0; b2 < nb; b2++) {
@@ -226,6 +233,14 @@ static void one_primary(const problem *P, int64_t p, double complex *alm, double
                 }
                 zacc[((size_t)l * nb + b1) * nb + b2] += wp * s;
             }
+}
+
+/* One primary of the catalogue (input index p). */
+static void one_primary(const problem *P, int64_t p, double complex *alm, double complex *Y,
+                        double *zacc, int64_t *counts, int64_t *npairs)
+{
+    const int64_t qp[3] = {P->qx[p], P->qy[p], P->qz[p]};
+    one_pivot(P, qp, P->w[p], p, alm, Y, zacc, counts, npairs);
 }
 
 /*
@@ -594,3 +609,138 @@ int oracle_zeta_sphere(int64_t n, const double *x, const double *y, const double
     free(T);
     return 0;
 }
+
+
+/* ---------------------------------------------------------------- shared pivots (approximate) */
+
+/*
+ * Approximate pivot sharing (Implementation section: spatially close pivots share one neighbour
+ * list, closeness set by a pivot length scale that defaults to the mean separation). Reading,
+ * since the paper gives no formula:
+ *   - pivots are grouped by a cubic pivot cell of Hq = max(1, floor(h * 2^K / L)) lattice units:
+ *     the group of lattice point q is (floor(qx/Hq), floor(qy/Hq), floor(qz/Hq));
+ *   - every non-empty group g becomes one pivot at X_g = round-half-up of the mean lattice position
+ *     of its members, per axis (2 sum q + n_g) div (2 n_g), with weight W_g = sum of its members'
+ *     weights (input order);
+ *   - the pivot's multipoles use every point as a secondary (pairs at zero separation skipped):
+ *         zeta~_l(b1, b2) = sum_g W_g sum_m a_lm(X_g, b1) conj(a_lm(X_g, b2)).
+ * Groups are visited in (gz, gy, gx) order. Outputs: zeta as oracle_zeta; ngroups; optionally the
+ * group pivots (gq[3][n], gw[n], first ngroups entries). Returns 0, or 1 on invalid arguments.
+ */
+typedef struct {
+    int64_t gx, gy, gz, idx;
+} group_key;
+
+static int cmp_group_key(const void *a, const void *b)
+{
+    const group_key *u = (const group_key *)a, *v = (const group_key *)b;
+    if (u->gz != v->gz) return u->gz < v->gz ? -1 : 1;
+    if (u->gy != v->gy) return u->gy < v->gy ? -1 : 1;
+    if (u->gx != v->gx) return u->gx < v->gx ? -1 : 1;
+    return u->idx < v->idx ? -1 : (u->idx > v->idx);
+}
+
+int oracle_zeta_pivots(int64_t n, const double *x, const double *y, const double *z, const double *w,
+                       double box, int periodic, int nbins, double rmin, double rmax, int lmax, double h,
+                       double *zeta, int64_t *ngroups_out, int64_t *npairs_out, int64_t *gq, double *gw,
+                       int nthreads)
+{
+    if (n < 0 || nbins < 1 || lmax < 0 || lmax > ORACLE_LMAX_CAP || !(rmin >= 0.0) || !(rmax > rmin) ||
+        !(box > 0.0) || !(h > 0.0))
+        return 1;
+    const int nb = nbins, nc = (lmax + 1) * (lmax + 1);
+    const size_t zsize = (size_t)(lmax + 1) * nb * nb;
+    memset(zeta, 0, sizeof(double) * zsize);
+    *ngroups_out = 0;
+    if (npairs_out) *npairs_out = 0;
+    if (n == 0) return 0;
+    const int K = oracle_lattice_bits(box, rmax, periodic);
+    int64_t *q = (int64_t *)malloc(sizeof(int64_t) * 3 * (size_t)n);
+    uint64_t *T = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(nb + 1));
+    oracle_snap(n, x, box, K, periodic, q);
+    oracle_snap(n, y, box, K, periodic, q + n);
+    oracle_snap(n, z, box, K, periodic, q + 2 * n);
+    oracle_thresholds(nb, rmin, rmax, box, K, T);
+    problem P = {n, q, q + n, q + 2 * n, w, K, periodic, nb, lmax, T};
+
+    int64_t Hq = (int64_t)floor(h * lattice_scale(box, K));
+    if (Hq < 1) Hq = 1;
+    group_key *keys = (group_key *)malloc(sizeof(group_key) * (size_t)n);
+    for (int64_t i = 0; i < n; i++) {
+        keys[i].gx = q[i] / Hq;
+        keys[i].gy = q[n + i] / Hq;
+        keys[i].gz = q[2 * n + i] / Hq;
+        keys[i].idx = i;
+    }
+    qsort(keys, (size_t)n, sizeof(group_key), cmp_group_key);
+    /* group pivots */
+    int64_t *pq = (int64_t *)malloc(sizeof(int64_t) * 3 * (size_t)n);
+    double *pw = (double *)malloc(sizeof(double) * (size_t)n);
+    int64_t G = 0;
+    for (int64_t a = 0; a < n;) {
+        int64_t b = a;
+        int64_t sum[3] = {0, 0, 0};
+        double W = 0.0;
+        while (b < n && keys[b].gx == keys[a].gx && keys[b].gy == keys[a].gy && keys[b].gz == keys[a].gz) {
+            const int64_t i = keys[b].idx;
+            sum[0] += q[i];
+            sum[1] += q[n + i];
+            sum[2] += q[2 * n + i];
+            b++;
+        }
+        /* weights in input order: members were sorted by index within the group */
+        for (int64_t k = a; k < b; k++) W += w[keys[k].idx];
+        const int64_t cnt = b - a;
+        for (int ax = 0; ax < 3; ax++) pq[ax * n + G] = (2 * sum[ax] + cnt) / (2 * cnt);
+        pw[G] = W;
+        G++;
+        a = b;
+    }
+    free(keys);
+    *ngroups_out = G;
+    if (gq)
+        for (int64_t g = 0; g < G; g++)
+            for (int ax = 0; ax < 3; ax++) gq[ax * n + g] = pq[ax * n + g];
+    if (gw)
+        for (int64_t g = 0; g < G; g++) gw[g] = pw[g];
+
+    const int64_t nchunk = G < ORACLE_CHUNKS ? G : ORACLE_CHUNKS;
+    double *part = (double *)calloc((size_t)nchunk * zsize, sizeof(double));
+    int64_t *pairs = (int64_t *)calloc((size_t)nchunk, sizeof(int64_t));
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel
+    {
+        double complex *alm = (double complex *)malloc(sizeof(double complex) * (size_t)nb * nc);
+        double complex *Y = (double complex *)malloc(sizeof(double complex) * (size_t)nc);
+        int64_t *cnt = (int64_t *)malloc(sizeof(int64_t) * (size_t)nb);
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t c = 0; c < nchunk; c++) {
+            const int64_t lo = G * c / nchunk, hi = G * (c + 1) / nchunk;
+            for (int64_t g = lo; g < hi; g++) {
+                const int64_t qp[3] = {pq[g], pq[n + g], pq[2 * n + g]};
+                one_pivot(&P, qp, pw[g], -1, alm, Y, part + (size_t)c * zsize, cnt, &pairs[c]);
+            }
+        }
+        free(alm);
+        free(Y);
+        free(cnt);
+    }
+    int64_t total = 0;
+    for (int64_t c = 0; c < nchunk; c++) {
+        for (size_t k = 0; k < zsize; k++) zeta[k] += part[(size_t)c * zsize + k];
+        total += pairs[c];
+    }
+    if (npairs_out) *npairs_out = total;
+    free(part);
+    free(pairs);
+    free(pq);
+    free(pw);
+    free(q);
+    free(T);
+    return 0;
+}
+

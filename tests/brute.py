@@ -168,3 +168,53 @@ def zeta_sphere_triangles(x, y, z, w, nbins, theta_min, theta_max, mmax, primari
                       eval_chebyt(m, cosd) * ww)
             zeta[m] += w[p] * acc
     return zeta, counts, sums
+
+
+# ---------------------------------------------------------------- shared pivots
+
+def pivot_groups(x, y, z, w, box, periodic, rmax, h):
+    """Group pivots of the shared-pivot approximation, from its stated definition: groups by
+    integer division of the lattice coordinates by Hq = max(1, floor(h 2^K / L)), ordered by
+    (gz, gy, gx); pivot at the round-half-up mean lattice position, weight the members' sum."""
+    K = lattice_bits(box, rmax, periodic)
+    q = np.stack([snap(a, box, K, periodic) for a in (x, y, z)], 1)
+    Hq = max(1, int(math.floor(h * (math.ldexp(1.0, K) / box))))
+    g = q // Hq
+    keys, inv = np.unique(g[:, ::-1], axis=0, return_inverse=True)
+    inv = inv.ravel()
+    G = len(keys)
+    cnt = np.bincount(inv, minlength=G).astype(np.int64)
+    sums = np.zeros((G, 3), dtype=np.int64)
+    np.add.at(sums, inv, q)
+    W = np.zeros(G)
+    np.add.at(W, inv, np.asarray(w, dtype=np.float64))
+    X = (2 * sums + cnt[:, None]) // (2 * cnt[:, None])
+    return X, W, q, K
+
+
+def zeta_triangles_lattice(qp, wp, qs, ws, K, periodic, T, nbins, lmax):
+    """Legendre form of zeta with explicit pivots (lattice points qp, weights wp) and secondaries
+    (qs, ws), binning by the integer thresholds T, pairs at zero separation skipped."""
+    M = 1 << K
+    zeta = np.zeros((lmax + 1, nbins, nbins))
+    Tlo, Thi = int(T[0]), int(T[-1])
+    for p in range(len(qp)):
+        d = qs - qp[p]
+        if periodic:
+            d = np.where(d >= M // 2, d - M, d)
+            d = np.where(d < -(M // 2), d + M, d)
+        R2 = (d.astype(object) ** 2).sum(axis=1)
+        sel = [j for j in range(len(qs)) if R2[j] != 0 and Tlo <= R2[j] < Thi]
+        if not sel:
+            continue
+        bs = np.array([max(k for k in range(nbins) if int(T[k]) <= R2[j]) for j in sel])
+        U = d[sel].astype(np.float64)
+        U /= np.linalg.norm(U, axis=1)[:, None]
+        cosg = np.clip(U @ U.T, -1.0, 1.0)
+        ww = np.outer(ws[sel], ws[sel])
+        for l in range(lmax + 1):
+            acc = np.zeros((nbins, nbins))
+            np.add.at(acc, (bs[:, None].repeat(len(sel), 1), bs[None, :].repeat(len(sel), 0)),
+                      eval_legendre(l, cosg) * ww)
+            zeta[l] += wp[p] * (2 * l + 1) / (4 * math.pi) * acc
+    return zeta

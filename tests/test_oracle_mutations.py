@@ -47,6 +47,10 @@ MUTANTS = {
     "sphere: no basis at the pole": ("if (l1 < 1e-6) { /* x x n */", "if (l1 < 0.0) { /* x x n */"),
     "sphere: primary weight dropped": ("w[p] * creal(am[b1 * M1 + m] * conj(am[b2 * M1 + m]));",
                                        "creal(am[b1 * M1 + m] * conj(am[b2 * M1 + m]));"),
+    "pivots: mean rounded down": ("pq[ax * n + G] = (2 * sum[ax] + cnt) / (2 * cnt);",
+                                  "pq[ax * n + G] = sum[ax] / cnt;"),
+    "pivots: group weight is the mean": ("pw[G] = W;", "pw[G] = W / (double)cnt;"),
+    "pivots: group key ignores y": ("keys[i].gy = q[n + i] / Hq;", "keys[i].gy = 0;"),
 }
 
 
@@ -127,6 +131,17 @@ def _pins():
     ref, _, _ = brute.zeta_sphere_triangles(*u, ws, 4, 0.01, 0.3, 5)
     if not np.all(np.isfinite(zs)) or np.max(np.abs(zs - ref)) > 1e-12 * np.max(np.abs(ref)):
         failed.append("sphere triangles")
+    # shared pivots: group pivots and zeta against the numpy grouping and Legendre form
+    cP = (rng.random((4, 3))[rng.integers(0, 4, 150)] * 40.0 + rng.normal(0, 2.0, (150, 3))) % 40.0
+    cw = rng.normal(1.0, 0.4, 150)
+    rp = oracle.zeta_pivots(cP[:, 0], cP[:, 1], cP[:, 2], cw, 40.0, True, 4, 1.0, 10.0, 3, 2.5)
+    X, W, q, K = brute.pivot_groups(cP[:, 0], cP[:, 1], cP[:, 2], cw, 40.0, True, 10.0, 2.5)
+    ok = rp.ngroups == len(X) and np.array_equal(rp.gq, X) and np.allclose(rp.gw, W, rtol=0, atol=1e-13)
+    if ok:
+        ref = brute.zeta_triangles_lattice(X, W, q, cw, K, True, brute.thresholds(4, 1.0, 10.0, 40.0, K), 4, 3)
+        ok = np.max(np.abs(rp.zeta - ref)) <= 1e-12 * np.max(np.abs(ref))
+    if not ok:
+        failed.append("shared pivots")
     return failed
 
 

@@ -465,3 +465,60 @@ def test_sphere_degenerate_and_invalid():
     for bad in [(3, 0.2, 0.1, 4), (0, 0.0, 0.1, 4), (3, 0.0, 4.0, 4), (3, 0.0, 0.1, -1)]:
         with pytest.raises(ValueError):
             oracle.zeta_sphere(one, zero, zero, None, *bad)
+
+
+# ---------------------------------------------------------------- shared pivots (approximate)
+
+def test_pivot_groups_and_zeta_against_brute_force():
+    """Clustered points whose pivot cells hold several points: the oracle's group pivots (exact
+    lattice positions, weights) and zeta against the numpy grouping and Legendre form."""
+    rng = np.random.default_rng(5)
+    centres = rng.random((6, 3)) * 60.0
+    P = (centres[rng.integers(0, 6, 300)] + rng.normal(0, 2.5, (300, 3))) % 60.0
+    w = rng.normal(1.0, 0.4, 300)
+    for periodic in (True, False):
+        r = oracle.zeta_pivots(P[:, 0], P[:, 1], P[:, 2], w, 60.0, periodic, 5, 1.0, 15.0, 4, 3.0)
+        X, W, q, K = brute.pivot_groups(P[:, 0], P[:, 1], P[:, 2], w, 60.0, periodic, 15.0, 3.0)
+        assert r.ngroups == len(X) < 300
+        np.testing.assert_array_equal(r.gq, X)
+        np.testing.assert_allclose(r.gw, W, rtol=0, atol=1e-13)
+        assert abs(r.gw.sum() - w.sum()) < 1e-11
+        T = brute.thresholds(5, 1.0, 15.0, 60.0, K)
+        ref = brute.zeta_triangles_lattice(X, W, q, w, K, periodic, T, 5, 4)
+        assert _rel(r.zeta, ref) < 1e-12
+
+
+def test_pivots_with_one_point_per_group_are_exact():
+    """When every pivot cell holds one point, each group pivot is that point and the approximation
+    is the exact estimator (to summation order)."""
+    rng = np.random.default_rng(6)
+    side, h = 50.0, 2.5
+    cells = rng.choice(20 ** 3, 400, replace=False)
+    ijk = np.stack(np.unravel_index(cells, (20, 20, 20)), 1)
+    P = (ijk + 0.1 + 0.8 * rng.random((400, 3))) * h
+    w = rng.normal(1.0, 0.3, 400)
+    r = oracle.zeta_pivots(P[:, 0], P[:, 1], P[:, 2], w, side, True, 6, 1.0, 12.0, 6, h * (1 + 1e-12))
+    ex = oracle.zeta(P[:, 0], P[:, 1], P[:, 2], w, side, True, 6, 1.0, 12.0, 6)
+    assert r.ngroups == 400
+    assert r.npairs == ex.npairs
+    assert _rel(r.zeta, ex.zeta) < 1e-12
+
+
+def test_pivots_converge_to_exact():
+    """The approximation error shrinks with the pivot cell (clustered catalogue, l_max = 4)."""
+    cat = catalogs.lognormal(3000, 100.0, 3, grid=32)
+    ex = oracle.zeta(cat.x, cat.y, cat.z, None, 100.0, True, 8, 4.0, 20.0, 4).zeta
+    errs = []
+    for h in (4.0, 2.0, 1.0, 0.5):
+        r = oracle.zeta_pivots(cat.x, cat.y, cat.z, None, 100.0, True, 8, 4.0, 20.0, 4, h)
+        errs.append(_rel(r.zeta, ex))
+    assert errs[0] > errs[1] > errs[2] > errs[3]
+    assert errs[-1] < 0.02 and errs[0] > 1e-3
+
+
+def test_pivots_invalid():
+    one = np.zeros(2)
+    with pytest.raises(ValueError):
+        oracle.zeta_pivots(one, one, one, None, 10.0, True, 2, 0.0, 2.0, 1, 0.0)
+    r = oracle.zeta_pivots(np.zeros(0), np.zeros(0), np.zeros(0), None, 10.0, True, 2, 0.0, 2.0, 1, 1.0)
+    assert r.ngroups == 0 and not r.zeta.any()
