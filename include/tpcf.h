@@ -265,6 +265,24 @@ int tpcf_pair_sums(tpcf_ctx* ctx, int64_t capacity, int64_t* npairs, double* dd)
 int tpcf_edge_correct(tpcf_ctx* ctx, int ncat, const double* N, const double* R, double* zeta,
                       int memspace);
 
+/*
+ * Shared pivots, an approximation with a speed knob (the paper's Implementation section: spatially
+ * close pivots share one neighbour list, closeness set by a pivot length scale that defaults to the
+ * mean separation). side > 0: pivots are grouped by cubic pivot cells of Hq = max(1, floor(side *
+ * 2^K / L)) lattice units (K and the lattice as for the exact estimator); every occupied cell
+ * becomes one pivot at the round-half-up mean lattice position of its members, (2 sum q + n)
+ * div (2 n) per axis, with weight W = sum of their weights, and every point stays a secondary:
+ *     zeta~_l(b1, b2) = sum_cells W sum_m a_lm(X, b1) conj(a_lm(X, b2)),
+ * pairs at zero separation skipped. side < 0 uses the mean separation L / n^(1/3); side = 0
+ * (default) is the exact estimator. The error falls with the cell side (the tests and the
+ * benchmark measure it against the exact estimator); stats report the pivot count as
+ * n_primaries. Applies to tpcf_compute_zeta on a 3D catalogue set by tpcf_set_catalog.
+ * Errors: TPCF_E_INVALID_ARG (side not finite). A compute call fails with TPCF_E_UNSUPPORTED for
+ * ranges, batches and catalogues on the sphere, and with TPCF_E_INVALID_ARG when the pivot cells
+ * number more than 2^26. Debug output (per-point counts, a_lm) is not kept.
+ */
+int tpcf_set_pivot_cell(tpcf_ctx* ctx, double side);
+
 /* 0 (default) or 1: keep per-primary pair counts and a_lm of the next compute calls. */
 int tpcf_set_debug(tpcf_ctx* ctx, int enable);
 

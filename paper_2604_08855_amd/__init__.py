@@ -32,7 +32,7 @@ EXPORTS = [
     "tpcf_set_tuning", "tpcf_set_catalog", "tpcf_compute_zeta", "tpcf_compute_zeta_range",
     "tpcf_compute_batch", "tpcf_debug_pair_counts", "tpcf_debug_alm", "tpcf_set_debug",
     "tpcf_get_stats", "tpcf_last_error", "tpcf_autotune", "tpcf_pair_sums", "tpcf_edge_correct",
-    "tpcf_set_sphere_catalog",
+    "tpcf_set_sphere_catalog", "tpcf_set_pivot_cell",
 ]
 
 
@@ -105,6 +105,7 @@ def _load() -> ctypes.CDLL:
         "tpcf_pair_sums": ([vp, i64, vp, vp], i),
         "tpcf_edge_correct": ([vp, i, vp, vp, vp, i], i),
         "tpcf_set_sphere_catalog": ([vp, i64, vp, vp, vp, vp, i], i),
+        "tpcf_set_pivot_cell": ([vp, d], i),
     }
     missing = [name for name in sig if not hasattr(lib, name)]
     if missing:
@@ -206,6 +207,11 @@ class Context:
         t = Tuning()
         self._check(_lib.tpcf_autotune(self._h, float(sample_fraction), ctypes.byref(t)))
         return {k: getattr(t, k) for k, _ in Tuning._fields_}
+
+    def set_pivot_cell(self, side: float):
+        """Shared pivots (approximate): pivot cells of this side (catalogue units); a negative value
+        means the mean separation, 0 the exact estimator (see tpcf_set_pivot_cell)."""
+        self._check(_lib.tpcf_set_pivot_cell(self._h, float(side)))
 
     def set_debug(self, enable: bool = True):
         self._check(_lib.tpcf_set_debug(self._h, int(bool(enable))))

@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtpcf.so")
-SOURCES = ["api.hip", "grid.hip", "sweep.hip", "edge.hip"]
+SOURCES = ["api.hip", "grid.hip", "sweep.hip", "edge.hip", "pivots.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

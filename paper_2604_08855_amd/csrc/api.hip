@@ -31,6 +31,9 @@ size_t sweep_tile_bytes_per_wave(int lmax, int nb, bool f64, bool sphere);
 std::vector<double> threej_squared_table(int lmax);
 hipError_t launch_edge_correct(int ncat, int lmax, int nb, const double* N, const double* R, const double* t3,
                                double* out, hipStream_t s);
+hipError_t build_pivots(const uint4* rec, const double* w64, uint32_t n, int sh, uint64_t Hq, uint32_t ng,
+                        uint32_t* count, unsigned long long* sum, double* wsum, uint32_t* flag, uint32_t* slot,
+                        uint32_t* block_sum, uint4* prim_rec, double* prim_w, hipStream_t s);
 }  // namespace tpcf
 
 using namespace tpcf;
@@ -93,6 +96,9 @@ struct tpcf_ctx {
   DevBuf scratch, tile, zeta_d, queue, stats_d, tasks, counts32, alm_dbg, conv_idx, conv32, conv64, regions;
   DevBuf bin_pairs, bin_dd;  // two-point by-product of the last compute call, [ncat][nbins]
   DevBuf edge_tab, edge_io;  // squared 3j table (for edge_lmax) and host-call staging
+  // shared pivots: pivot cell side (0 = exact, < 0 = the mean separation), cell tables, pivots
+  double pivot_h = 0.0;
+  DevBuf pv_count, pv_sum, pv_w, pv_flag, pv_slot, pv_bsum, pv_rec, pv_w64;
   int edge_lmax = -1;
   bool sums_valid = false;
   int sums_ncat = 0, sums_nb = 0;
@@ -142,7 +148,8 @@ size_t total_bytes(tpcf_ctx* c) {
                    &c->idx_a, &c->idx_b, &c->bsum, &c->errflag, &c->cell_start, &c->rec, &c->w64, &c->perm,
                    &c->scratch, &c->tile, &c->zeta_d, &c->queue, &c->stats_d, &c->tasks, &c->counts32,
                    &c->alm_dbg, &c->conv_idx, &c->conv32, &c->conv64, &c->regions, &c->bin_pairs, &c->bin_dd,
-                   &c->edge_tab, &c->edge_io};
+                   &c->edge_tab, &c->edge_io, &c->pv_count, &c->pv_sum, &c->pv_w, &c->pv_flag,
+                   &c->pv_slot, &c->pv_bsum, &c->pv_rec, &c->pv_w64};
   size_t t = 0;
   for (DevBuf* b : all) t += b->bytes;
   return t;
@@ -725,6 +732,38 @@ bool graphs_enabled() {
   return !(s && s[0] == '0');
 }
 
+// Shared pivots of the (single, 3D) catalogue: pivot cells of Hq = max(1, floor(h * scale))
+// lattice units, h the pivot cell side (the mean separation L / n^(1/3) when pivot_h < 0). Builds
+// the pivots on the stream and returns their number G (synchronises).
+int prepare_pivots(tpcf_ctx* c, uint32_t& G) {
+  const CatDesc& d = c->cd[0];
+  const HostCat& h = c->cats[0];
+  const double side = c->pivot_h > 0.0 ? c->pivot_h : (h.n > 0 ? h.box / cbrt((double)h.n) : h.box);
+  const uint64_t span = (uint64_t)1 << d.K;
+  double hq = floor(side * d.scale);
+  if (!(hq >= 1.0)) hq = 1.0;
+  if (hq > (double)span) hq = (double)span;
+  const uint64_t Hq = (uint64_t)hq;
+  const uint64_t ng = (span + Hq - 1) / Hq;
+  if (ng * ng * ng > ((uint64_t)1 << 26))
+    return fail(c, TPCF_E_INVALID_ARG, "pivot cell too small: more than 2^26 pivot cells");
+  const size_t nc3 = (size_t)(ng * ng * ng), n = (size_t)c->ntot;
+  int rc;
+  if ((rc = ensure(c, c->pv_count, nc3 * 4, "pivot cells")) || (rc = ensure(c, c->pv_sum, nc3 * 24, "pivot cells")) ||
+      (rc = ensure(c, c->pv_w, nc3 * 8, "pivot cells")) || (rc = ensure(c, c->pv_flag, nc3 * 4, "pivot cells")) ||
+      (rc = ensure(c, c->pv_slot, (nc3 + 1) * 4, "pivot cells")) ||
+      (rc = ensure(c, c->pv_bsum, scan_block_count((uint32_t)nc3) * 4 + 4, "pivot cells")) ||
+      (rc = ensure(c, c->pv_rec, (n + 1) * 16, "pivots")) || (rc = ensure(c, c->pv_w64, (n + 1) * 8, "pivots")))
+    return rc;
+  HIP_TRY(c, build_pivots((const uint4*)c->rec.p, (const double*)c->w64.p, (uint32_t)n, d.sh, Hq,
+                          (uint32_t)ng, (uint32_t*)c->pv_count.p, (unsigned long long*)c->pv_sum.p,
+                          (double*)c->pv_w.p, (uint32_t*)c->pv_flag.p, (uint32_t*)c->pv_slot.p,
+                          (uint32_t*)c->pv_bsum.p, (uint4*)c->pv_rec.p, (double*)c->pv_w64.p, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(&G, (uint32_t*)c->pv_slot.p + nc3, 4, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return TPCF_OK;
+}
+
 int compute(tpcf_ctx* c, int64_t p_begin, int64_t p_end, double* zeta, int memspace, bool use_graph) {
   if (!c) return TPCF_E_INVALID_ARG;
   if (!c->bins_set) return fail(c, TPCF_E_STATE, "set_bins has not been called");
@@ -736,10 +775,23 @@ int compute(tpcf_ctx* c, int64_t p_begin, int64_t p_end, double* zeta, int memsp
   if ((rc = check_periodic_range(c))) return rc;
   if ((rc = ensure_device(c))) return rc;
   const bool rebuild = !grid_current(c);
+  const bool pivots = c->pivot_h != 0.0;
+  if (pivots) {
+    if (use_graph || c->cats.size() != 1 || c->cats[0].sphere)
+      return fail(c, TPCF_E_UNSUPPORTED, "shared pivots need a single 3D catalogue set by tpcf_set_catalog");
+    if (p_begin != 0 || p_end != c->ntot)
+      return fail(c, TPCF_E_UNSUPPORTED, "shared pivots cover the whole catalogue: no primary ranges");
+  }
   if (rebuild && (rc = prepare_grid(c))) return rc;
   const uint32_t* tasks = nullptr;
   uint32_t ntask = (uint32_t)c->ntot;
-  if (p_begin != 0 || p_end != c->ntot) {
+  if (pivots) {
+    if (rebuild) {
+      if ((rc = record_grid(c))) return rc;
+      mark_grid(c);
+    }
+    if ((rc = prepare_pivots(c, ntask))) return rc;
+  } else if (p_begin != 0 || p_end != c->ntot) {
     // primaries by input index -> sorted positions (needs the grid: build it eagerly first)
     if (rebuild) {
       if ((rc = record_grid(c))) return rc;
@@ -763,6 +815,12 @@ int compute(tpcf_ctx* c, int64_t p_begin, int64_t p_end, double* zeta, int memsp
   SweepArgs a;
   int waves = 0;
   if ((rc = prepare_sweep(c, tasks, ntask, a, waves))) return rc;
+  if (pivots) {
+    a.prim_rec = (const uint4*)c->pv_rec.p;
+    a.prim_w64 = (const double*)c->pv_w64.p;
+    a.counts = nullptr;  // per-point debug rows do not apply to pivots
+    a.alm_debug = nullptr;
+  }
   c->stats.waves = waves;
   // The null stream cannot be captured: batches on it launch eagerly.
   const bool graph = use_graph && graphs_enabled() && c->stream != nullptr;
@@ -812,7 +870,9 @@ int compute(tpcf_ctx* c, int64_t p_begin, int64_t p_end, double* zeta, int memsp
   }
   const size_t cnt = (size_t)c->cd.size() * (c->lmax + 1) * c->nbins * c->nbins;
   if ((rc = copy_out(c, zeta, cnt, memspace))) return rc;
-  return finish_stats(c, grid_in_run && !graph, ntask);
+  rc = finish_stats(c, grid_in_run && !graph, ntask);
+  if (pivots) c->dbg_valid = false;
+  return rc;
 }
 
 }  // namespace
@@ -843,7 +903,8 @@ void tpcf_destroy(tpcf_ctx* c) {
                      &c->idx_a, &c->idx_b, &c->bsum, &c->errflag, &c->cell_start, &c->rec, &c->w64, &c->perm,
                      &c->scratch, &c->tile, &c->zeta_d, &c->queue, &c->stats_d, &c->tasks, &c->counts32,
                      &c->alm_dbg, &c->conv_idx, &c->conv32, &c->conv64, &c->regions, &c->bin_pairs, &c->bin_dd,
-                   &c->edge_tab, &c->edge_io};
+                     &c->edge_tab, &c->edge_io, &c->pv_count, &c->pv_sum, &c->pv_w, &c->pv_flag,
+                     &c->pv_slot, &c->pv_bsum, &c->pv_rec, &c->pv_w64};
     for (DevBuf* b : all) release(*b);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     for (auto& e : c->ev)
@@ -1047,6 +1108,14 @@ int tpcf_edge_correct(tpcf_ctx* c, int ncat, const double* N, const double* R, d
   return TPCF_OK;
 }
 
+int tpcf_set_pivot_cell(tpcf_ctx* c, double side) {
+  if (!c) return TPCF_E_INVALID_ARG;
+  if (!is_finite(side)) return fail(c, TPCF_E_INVALID_ARG, "pivot cell side must be finite");
+  c->pivot_h = side < 0.0 ? -1.0 : side;
+  c->err.clear();
+  return TPCF_OK;
+}
+
 int tpcf_set_debug(tpcf_ctx* c, int enable) {
   if (!c) return TPCF_E_INVALID_ARG;
   c->debug = enable != 0;
@@ -1119,6 +1188,7 @@ int tpcf_compute_batch(tpcf_ctx* c, int ncat, const int64_t* offsets, const doub
   if (!c) return TPCF_E_INVALID_ARG;
   if (ncat < 1 || !offsets || !box_side || !periodic) return fail(c, TPCF_E_INVALID_ARG, "invalid batch description");
   if (!c->bins_set) return fail(c, TPCF_E_STATE, "set_bins has not been called");
+  if (c->pivot_h != 0.0) return fail(c, TPCF_E_UNSUPPORTED, "shared pivots are not available for batches");
   if (offsets[0] != 0) return fail(c, TPCF_E_INVALID_ARG, "offsets[0] must be 0");
   std::vector<HostCat> cats(ncat);
   for (int k = 0; k < ncat; ++k) {

@@ -259,6 +259,24 @@ void validate_inputs(const double* x, const double* y, const double* z, const do
 
 size_t scan_block_count(uint32_t ncell) { return (ncell + kScanTile - 1) / kScanTile; }
 
+// out[n] = out[n-1] + in[n-1] (the total), after the exclusive scan of in[0..n).
+__global__ void k_scan_total(const uint32_t* __restrict__ in, uint32_t* __restrict__ out, uint32_t n) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) out[n] = n ? out[n - 1] + in[n - 1] : 0u;
+}
+
+// Exclusive scan of in[0..n) into out[0..n], out[n] = total. block_sum holds scan_block_count(n)
+// entries.
+hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* block_sum, hipStream_t s) {
+  const uint32_t nb = (uint32_t)scan_block_count(n);
+  if (n) {
+    hipLaunchKernelGGL(k_scan_blocks, dim3(nb), dim3(kScanThreads), 0, s, in, out, block_sum, n);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(64), 0, s, block_sum, nb);
+    hipLaunchKernelGGL(k_scan_add, dim3(blocks_for(n, 256)), dim3(256), 0, s, out, block_sum, n, 0u);
+  }
+  hipLaunchKernelGGL(k_scan_total, dim3(1), dim3(64), 0, s, in, out, n);
+  return hipGetLastError();
+}
+
 // Builds the cell-sorted layout. Buffers: qtmp[n], cell[n], hist[ncell], idx_a[n], idx_b[n],
 // block_sum[scan_block_count(ncell)], err[1] (all device). Outputs: cell_start[ncell+1],
 // rec[n], w64[n], perm[n].

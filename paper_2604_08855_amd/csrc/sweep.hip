@@ -826,14 +826,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sw
     }
     const double T0 = sT[0], Tn = sT[nb];
 
-    // ---- primary
-    const uint4 rp = a.rec[p];
+    // ---- primary (a point, or a shared pivot)
+    const uint4 rp = a.prim_rec ? a.prim_rec[p] : a.rec[p];
     Primary P0;
     P0.qx = uniform(rp.x);
     P0.qy = uniform(rp.y);
     P0.qz = uniform(rp.z);
     P0.sh = cu.sh;
-    const real wp = F64 ? (real)a.w64[p] : (real)__uint_as_float(uniform(rp.w));
+    const real wp = F64 ? (real)(a.prim_rec ? a.prim_w64[p] : a.w64[p]) : (real)__uint_as_float(uniform(rp.w));
     const uint32_t ux = P0.qx >> cu.sh, uy = P0.qy >> cu.sh, uz = P0.qz >> cu.sh;
     const int cx = (int)(((uint64_t)ux * (uint64_t)cu.nc) >> cu.K);
     const int cy = (int)(((uint64_t)uy * (uint64_t)cu.nc) >> cu.K);

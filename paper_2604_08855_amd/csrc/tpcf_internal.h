@@ -60,6 +60,8 @@ struct SweepArgs {
   int32_t ncat;
   int32_t nb;
   const uint32_t* task_list;    // NULL: task t is sorted position t
+  const uint4* prim_rec;        // optional: task t is the pivot prim_rec[t] (shared pivots), not a point
+  const double* prim_w64;       // FP64 weights of those pivots
   uint32_t ntask;
   uint32_t* queue;              // [0] task ticket counter
   uint32_t* scratch;            // per wave: scratch_blocks + kScratchTail blocks of 64 sorted positions

@@ -170,3 +170,13 @@ def test_sphere_catalog_validation_on_host():
     c.set_bins(4, 0.0, 3.5, 2)
     assert _code(c.set_sphere_catalog, x, y, z) == 1
     assert "pi" in tpcf._lib.tpcf_last_error(c._h).decode()
+
+
+def test_pivot_cell_validation_on_host():
+    c = _ctx()
+    assert _code(c.set_pivot_cell, float("nan")) == 1
+    assert _code(c.set_pivot_cell, float("inf")) == 1
+    c.set_pivot_cell(2.5)
+    c.set_pivot_cell(-1.0)
+    c.set_pivot_cell(0.0)
+    assert tpcf._lib.tpcf_set_pivot_cell(None, 1.0) == 1

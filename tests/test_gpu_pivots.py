@@ -1,0 +1,126 @@
+"""GPU parity of the shared-pivot approximation (tpcf_set_pivot_cell) against the FP64 oracle's
+definition of it (oracle_zeta_pivots), at the same bars as the exact estimator: 1e-10 (FP64) and
+1e-5 (mixed) of max|zeta_l| per l; pivot and pair counts exact."""
+import numpy as np
+import pytest
+
+import catalogs
+import oracle
+from tests import brute
+from tests.gpu_util import rel_err_per_l, say
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-10, "mixed": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def tpcf():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2604_08855_amd as mod
+
+    return mod
+
+
+def run(tpcf, cat, w, nb, rmin, rmax, lmax, prec, side, periodic=None):
+    ctx = tpcf.Context(0)
+    ctx.set_bins(nb, rmin, rmax, lmax)
+    ctx.set_precision(prec)
+    ctx.set_pivot_cell(side)
+    ctx.set_catalog(cat.x, cat.y, cat.z, w, box=cat.box, periodic=cat.periodic if periodic is None else periodic)
+    return ctx, ctx.compute_zeta()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("periodic", [True, False])
+def test_pivots_match_oracle(tpcf, prec, periodic):
+    """6,000 log-normal points, pivot cells of 3 (several points per cell in clusters), signed
+    weights, 10 bins in [3, 30), l_max = 6."""
+    cat = catalogs.lognormal(6000, 150.0, 4, grid=64)
+    cat.periodic = periodic
+    w = catalogs.gaussian_weights(cat.n, 9, 0.4, 1.0)
+    say(f"pivots periodic={periodic} prec={prec}")
+    ctx, z = run(tpcf, cat, w, 10, 3.0, 30.0, 6, prec, 3.0)
+    ref = oracle.zeta_pivots(cat.x, cat.y, cat.z, w, 150.0, periodic, 10, 3.0, 30.0, 6, 3.0)
+    st = ctx.stats()
+    say("groups", ref.ngroups, "pairs", ref.npairs, "rel err", rel_err_per_l(z, ref.zeta).max())
+    assert st["n_primaries"] == ref.ngroups < cat.n
+    assert st["n_pairs"] == ref.npairs
+    assert rel_err_per_l(z, ref.zeta).max() <= TOL[prec]
+    npairs, _ = ctx.pair_sums()
+    assert npairs.sum() == ref.npairs
+
+
+def test_one_point_per_cell_is_exact(tpcf):
+    """Pivot cells so small that each holds one point: the shared-pivot result is the exact one."""
+    rng = np.random.default_rng(2)
+    cells = rng.choice(40 ** 3, 3000, replace=False)
+    ijk = np.stack(np.unravel_index(cells, (40, 40, 40)), 1)
+    P = (ijk + 0.1 + 0.8 * rng.random((3000, 3))) * 2.5
+    cat = catalogs.Catalog(P[:, 0], P[:, 1], P[:, 2], np.ones(3000), 100.0, True)
+    w = catalogs.gaussian_weights(cat.n, 3, 1.0, 0.2)
+    ctx, z = run(tpcf, cat, w, 8, 2.0, 20.0, 5, "fp64", 2.5 * (1 + 1e-12))
+    ex = tpcf.Context(0)
+    ex.set_bins(8, 2.0, 20.0, 5)
+    ex.set_catalog(cat.x, cat.y, cat.z, w, box=100.0, periodic=True)
+    ze = ex.compute_zeta()
+    assert ctx.stats()["n_primaries"] == cat.n
+    assert rel_err_per_l(z, ze).max() < 1e-12
+
+
+def test_mean_separation_default_and_errors(tpcf):
+    """side < 0 uses the mean separation L / n^(1/3); ranges, batches, sphere catalogues and
+    too many pivot cells are refused."""
+    cat = catalogs.lognormal(4000, 120.0, 6, grid=64)
+    ctx, z = run(tpcf, cat, None, 6, 4.0, 24.0, 3, "fp64", -1.0)
+    h = 120.0 / np.cbrt(4000.0)
+    ref = oracle.zeta_pivots(cat.x, cat.y, cat.z, None, 120.0, True, 6, 4.0, 24.0, 3, h)
+    assert ctx.stats()["n_primaries"] == ref.ngroups
+    assert rel_err_per_l(z, ref.zeta).max() <= TOL["fp64"]
+    with pytest.raises(tpcf.TpcfError) as e:
+        ctx.compute_zeta_range(0, 10)
+    assert e.value.code == 5
+    x = np.concatenate([cat.x, cat.x])
+    with pytest.raises(tpcf.TpcfError) as e:
+        ctx.compute_batch([0, cat.n, 2 * cat.n], x, np.concatenate([cat.y, cat.y]), np.concatenate([cat.z, cat.z]),
+                          None, 120.0, True)
+    assert e.value.code == 5
+    with pytest.raises(tpcf.TpcfError) as e:
+        ctx.set_pivot_cell(float("nan"))
+    assert e.value.code == 1
+    ctx.set_pivot_cell(1e-4)  # 120 / 1e-4 cells per axis
+    ctx.set_catalog(cat.x, cat.y, cat.z, None, box=120.0, periodic=True)
+    with pytest.raises(tpcf.TpcfError) as e:
+        ctx.compute_zeta()
+    assert e.value.code == 1
+    m = catalogs.sphere_cluster(500, 1)
+    sp = tpcf.Context(0)
+    sp.set_bins(4, 0.0, 0.2, 2)
+    sp.set_pivot_cell(0.05)
+    sp.set_sphere_catalog(m.x, m.y, m.z, m.w)
+    with pytest.raises(tpcf.TpcfError) as e:
+        sp.compute_zeta()
+    assert e.value.code == 5
+
+
+def test_full_size_pivots(tpcf):
+    """The benchmark catalogue (10^6 log-normal points, L = 1000, 20 bins [10, 200), l_max = 10)
+    with pivot cells of the mean separation (10): pivot count against the numpy grouping, and
+    zeta within 2% of the exact estimator per l (mixed)."""
+    cat = catalogs.lognormal(10**6, 1000.0, 0, grid=256)
+    w = catalogs.gaussian_weights(cat.n, 10**6, 1.0, 0.1)
+    ctx, z = run(tpcf, cat, w, 20, 10.0, 200.0, 10, "mixed", 10.0)
+    st = ctx.stats()
+    X, W, _, _ = brute.pivot_groups(cat.x, cat.y, cat.z, w, 1000.0, True, 200.0, 10.0)
+    say(f"pivots: {st['n_primaries']} (numpy {len(X)}), sweep {st['ms_sweep']:.1f} ms")
+    assert st["n_primaries"] == len(X)
+    ex = tpcf.Context(0)
+    ex.set_bins(20, 10.0, 200.0, 10)
+    ex.set_precision("mixed")
+    ex.set_catalog(cat.x, cat.y, cat.z, w, box=1000.0, periodic=True)
+    ze = ex.compute_zeta()
+    err = rel_err_per_l(z, ze)
+    say("rel err vs exact per l", err, "exact sweep", ex.stats()["ms_sweep"])
+    assert err.max() < 0.02
