@@ -440,7 +440,7 @@ def run_sphere(args):
     dev = [torch.from_numpy(a).cuda() for a in (m.x, m.y, m.z, m.w)]
     torch.cuda.synchronize()
     calibration_copy(torch, args.copy_calibration_mib)
-    res = {}
+    res, zfull, tunings = {}, {}, {}
     ranges = [(0, 24), (m.n // 2, m.n // 2 + 24), (m.n - 24, m.n)]
     for prec, steps in (("mixed", args.steps), ("fp64", max(1, min(args.steps, 2)))):
         ctx = tpcf.Context(0, torch.cuda.current_stream())
@@ -460,11 +460,13 @@ def run_sphere(args):
         for i in range(steps):
             t1 = time.perf_counter()
             ctx.set_sphere_catalog(*dev)
-            ctx.compute_zeta(device_output=True)
+            zs = ctx.compute_zeta(device_output=True)
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t1)
             sweeps.append(ctx.stats()["ms_sweep"])
             log(f"[bench] sphere {prec} step {i + 1}/{steps}: {times[-1] * 1000:.1f} ms")
+        zfull[prec] = zs.cpu().numpy()
+        tunings[prec] = tuning
         st = ctx.stats()
         npairs, _ = ctx.pair_sums()
         errs = []
@@ -481,6 +483,33 @@ def run_sphere(args):
                      "pair_sums_total_equals_pair_count": int(npairs.sum()) == st["n_pairs"],
                      "max_rel_err_vs_oracle_on_sampled_ranges": max(errs)}
         log(f"[bench] sphere {prec}: {res[prec]}")
+    # shared pivots (approximate) at 1, 2 and 4 mean pixel separations, mixed
+    sep = math.sqrt(4.0 * math.pi / m.n)
+    z64 = zfull["fp64"]
+    piv = []
+    for f in (1.0, 2.0, 4.0):
+        ctx = tpcf.Context(0, torch.cuda.current_stream())
+        ctx.set_bins(nb, tmin, tmax, mmax)
+        ctx.set_precision("mixed")
+        t = tunings["mixed"] or {}
+        ctx.set_tuning(float(t.get("points_per_cell", 0.0)), int(t.get("waves_per_cu", 0)))
+        ctx.set_pivot_cell(f * sep)
+        ctx.set_sphere_catalog(*dev)
+        ctx.compute_zeta(device_output=True)  # warmup
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            ctx.set_sphere_catalog(*dev)
+            zp = ctx.compute_zeta(device_output=True)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t1) * 1000.0 / args.steps
+        st = ctx.stats()
+        zp = zp.cpu().numpy()
+        e = float(max(np.abs(zp[k] - z64[k]).max() / np.abs(z64[k]).max() for k in range(mmax + 1)))
+        piv.append({"pivot_cell": f * sep, "pivots": st["n_primaries"], "ms_per_step": ms,
+                    "speedup_vs_exact_mixed": res["mixed"]["ms_per_step"] / ms, "max_rel_err_vs_exact_fp64": e})
+        log(f"[bench] sphere shared pivots {piv[-1]}")
+        ctx.close()
     mx = res["mixed"]
     traffic = measured_traffic("mixed", SPHERE_TRAFFIC_PROFILE)
     f_pair = 4 * (2 * mmax + 1)
@@ -500,6 +529,7 @@ def run_sphere(args):
         "mixed_over_fp64_speedup": mx["value"] / res["fp64"]["value"],
         "max_rel_err_vs_oracle_on_sampled_ranges": {k: v["max_rel_err_vs_oracle_on_sampled_ranges"]
                                                     for k, v in res.items()},
+        "shared_pivots": piv,
         "roofline": {"bound": "alu", "kernel": "sweep_kernel<8,false,true>", "achieved": achieved,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
                      "traffic": traffic["bytes"] if traffic else None, "traffic_detail": traffic,

@@ -273,13 +273,18 @@ int tpcf_edge_correct(tpcf_ctx* ctx, int ncat, const double* N, const double* R,
  * becomes one pivot at the round-half-up mean lattice position of its members, (2 sum q + n)
  * div (2 n) per axis, with weight W = sum of their weights, and every point stays a secondary:
  *     zeta~_l(b1, b2) = sum_cells W sum_m a_lm(X, b1) conj(a_lm(X, b2)),
- * pairs at zero separation skipped. side < 0 uses the mean separation L / n^(1/3); side = 0
- * (default) is the exact estimator. The error falls with the cell side (the tests and the
+ * pairs at zero separation skipped. side < 0 uses the mean separation, L / n^(1/3) in a box and
+ * sqrt(4 pi / n) on the sphere; side = 0 (default) is the exact estimator. On the sphere the
+ * cells are those of the unit-vector cube (side in its units, about radians at small angles), a
+ * pivot sits at its members' rounded mean lattice position (just inside the sphere) and its
+ * position angles are measured in the tangent plane at that point's direction. The error falls with the cell side (the tests and the
  * benchmark measure it against the exact estimator); stats report the pivot count as
- * n_primaries. Applies to tpcf_compute_zeta on a 3D catalogue set by tpcf_set_catalog.
+ * n_primaries. Applies to tpcf_compute_zeta on a catalogue set by tpcf_set_catalog or
+ * tpcf_set_sphere_catalog.
  * Errors: TPCF_E_INVALID_ARG (side not finite). A compute call fails with TPCF_E_UNSUPPORTED for
- * ranges, batches and catalogues on the sphere, and with TPCF_E_INVALID_ARG when the pivot cells
- * number more than 2^26. Debug output (per-point counts, a_lm) is not kept.
+ * ranges and batches, and with TPCF_E_INVALID_ARG when the pivot cells number more than 2^21 per
+ * axis (cells of at least 2^-21 of the cube's side).
+ * Debug output (per-point counts, a_lm) is not kept.
  */
 int tpcf_set_pivot_cell(tpcf_ctx* ctx, double side);
 

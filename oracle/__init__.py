@@ -56,6 +56,8 @@ def _load():
         lib.oracle_zeta_sphere.restype = i
         lib.oracle_zeta_pivots.argtypes = [i64, p, p, p, p, d, i, i, d, d, i, d, p, p, p, p, p, i]
         lib.oracle_zeta_pivots.restype = i
+        lib.oracle_zeta_sphere_pivots.argtypes = [i64, p, p, p, p, i, d, d, i, d, p, p, p, i]
+        lib.oracle_zeta_sphere_pivots.restype = i
         _lib = lib
     return _lib
 
@@ -215,6 +217,23 @@ def zeta_pivots(x, y, z, w, box: float, periodic: bool, nbins: int, rmin: float,
         raise ValueError("oracle_zeta_pivots: invalid arguments")
     G = int(ng.value)
     return PivotResult(zt, G, int(npairs.value), gq[:, :G].T.copy(), gw[:G].copy())
+
+
+def zeta_sphere_pivots(x, y, z, w, nbins: int, theta_min: float, theta_max: float, mmax: int, h: float,
+                       threads: int = 0) -> PivotResult:
+    """Approximate zeta_m on the sphere with pivots shared over cubic pivot cells of side h (in the
+    units of the unit-vector cube) (oracle_zeta_sphere_pivots)."""
+    x, y, z = (np.ascontiguousarray(a, dtype=np.float64) for a in (x, y, z))
+    n = x.shape[0]
+    w = np.ones(n) if w is None else np.ascontiguousarray(w, dtype=np.float64)
+    zt = np.zeros((mmax + 1, nbins, nbins))
+    ng, npairs = ctypes.c_int64(0), ctypes.c_int64(0)
+    rc = _load().oracle_zeta_sphere_pivots(n, _ptr(x), _ptr(y), _ptr(z), _ptr(w), int(nbins), float(theta_min),
+                                           float(theta_max), int(mmax), float(h), _ptr(zt), ctypes.byref(ng),
+                                           ctypes.byref(npairs), int(threads))
+    if rc:
+        raise ValueError("oracle_zeta_sphere_pivots: invalid arguments")
+    return PivotResult(zt, int(ng.value), int(npairs.value), None, None)
 
 
 def zeta_catalog(cat, nbins, rmin, rmax, lmax, **kw) -> Result:

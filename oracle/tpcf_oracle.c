@@ -508,6 +508,72 @@ int oracle_edge_correct(int ncat, int lmax, int nbins, const double *N, const do
  * Output zeta[(mmax+1)][nbins][nbins]; counts (optional) [p_end-p_begin][nbins].
  * Returns 0, or 1 on invalid arguments.
  */
+/* Snaps unit vectors (shifted by +2) and sets the chord thresholds; returns K. */
+static int sphere_setup(int64_t n, const double *x, const double *y, const double *z, int nb, double theta_min,
+                        double theta_max, int64_t *q, uint64_t *T)
+{
+    const double box = 4.0;
+    const int K = oracle_lattice_bits(box, 2.0 * sin(0.5 * theta_max), 0);
+    const double sc = lattice_scale(box, K);
+    for (int64_t i = 0; i < n; i++) {
+        const double v[3] = {x[i], y[i], z[i]};
+        for (int a = 0; a < 3; a++) q[a * n + i] = snap(v[a] + 2.0, sc, K, 0);
+    }
+    const double dth = (theta_max - theta_min) / nb;
+    for (int k = 0; k <= nb; k++) {
+        const double th = (k == nb) ? theta_max : theta_min + k * dth;
+        const double v = 2.0 * sin(0.5 * th) * sc;
+        T[k] = (uint64_t)ceil(v * v);
+    }
+    return K;
+}
+
+/* One pivot on the sphere at lattice point qp (weight wp) against every point but `skip`: its
+ * a_m over all bins and its contribution to zeta (added into z); counts and pairs as in 3D.
+ * s = 1 / scale. */
+static void sphere_pivot(int64_t n, const int64_t *q, const double *w, const uint64_t *T, int nb, int mmax,
+                         double s, const int64_t qp[3], double wp, int64_t skip, double complex *am,
+                         int64_t *cnt, double *z, int64_t *pairs)
+{
+    const int M1 = mmax + 1;
+    memset(am, 0, sizeof(double complex) * (size_t)nb * M1);
+    for (int b = 0; b < nb; b++) cnt[b] = 0;
+    /* tangent basis at the pivot's lattice position */
+    double np_[3] = {qp[0] * s - 2.0, qp[1] * s - 2.0, qp[2] * s - 2.0};
+    const double nn = sqrt(np_[0] * np_[0] + np_[1] * np_[1] + np_[2] * np_[2]);
+    for (int a = 0; a < 3; a++) np_[a] /= nn;
+    double e1[3] = {-np_[1], np_[0], 0.0}; /* z x n */
+    double l1 = sqrt(e1[0] * e1[0] + e1[1] * e1[1]);
+    if (l1 < 1e-6) { /* x x n */
+        e1[0] = 0.0;
+        e1[1] = -np_[2];
+        e1[2] = np_[1];
+        l1 = sqrt(e1[1] * e1[1] + e1[2] * e1[2]);
+    }
+    for (int a = 0; a < 3; a++) e1[a] /= l1;
+    const double e2[3] = {np_[1] * e1[2] - np_[2] * e1[1], np_[2] * e1[0] - np_[0] * e1[2],
+                          np_[0] * e1[1] - np_[1] * e1[0]};
+    for (int64_t j = 0; j < n; j++) {
+        if (j == skip) continue;
+        int64_t d[3];
+        for (int a = 0; a < 3; a++) d[a] = q[a * n + j] - qp[a];
+        const uint64_t R2 = (uint64_t)(d[0] * d[0]) + (uint64_t)(d[1] * d[1]) + (uint64_t)(d[2] * d[2]);
+        if (R2 == 0 || R2 < T[0] || R2 >= T[nb]) continue;
+        int b = 0;
+        while (b + 1 < nb && R2 >= T[b + 1]) b++;
+        const double t1 = d[0] * e1[0] + d[1] * e1[1] + d[2] * e1[2];
+        const double t2 = d[0] * e2[0] + d[1] * e2[1] + d[2] * e2[2];
+        const double phi = atan2(t2, t1);
+        for (int m = 0; m <= mmax; m++) am[b * M1 + m] += w[j] * cexp(-I * (m * phi));
+        cnt[b]++;
+        (*pairs)++;
+    }
+    for (int m = 0; m <= mmax; m++)
+        for (int b1 = 0; b1 < nb; b1++)
+            for (int b2 = 0; b2 < nb; b2++)
+                z[((size_t)m * nb + b1) * nb + b2] += wp * creal(am[b1 * M1 + m] * conj(am[b2 * M1 + m]));
+}
+
 int oracle_zeta_sphere(int64_t n, const double *x, const double *y, const double *z, const double *w, int nbins,
                        double theta_min, double theta_max, int mmax, int64_t p_begin, int64_t p_end,
                        double *zeta, int64_t *counts, int64_t *npairs_out, int nthreads)
@@ -520,21 +586,10 @@ int oracle_zeta_sphere(int64_t n, const double *x, const double *y, const double
     memset(zeta, 0, sizeof(double) * zsize);
     if (npairs_out) *npairs_out = 0;
     if (n == 0 || p_begin == p_end) return 0;
-    const double box = 4.0;
-    const int K = oracle_lattice_bits(box, 2.0 * sin(0.5 * theta_max), 0);
-    const double sc = lattice_scale(box, K), s = 1.0 / sc;
     int64_t *q = (int64_t *)malloc(sizeof(int64_t) * 3 * (size_t)n);
-    for (int64_t i = 0; i < n; i++) {
-        const double v[3] = {x[i], y[i], z[i]};
-        for (int a = 0; a < 3; a++) q[a * n + i] = snap(v[a] + 2.0, sc, K, 0);
-    }
     uint64_t *T = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(nb + 1));
-    const double dth = (theta_max - theta_min) / nb;
-    for (int k = 0; k <= nb; k++) {
-        const double th = (k == nb) ? theta_max : theta_min + k * dth;
-        const double v = 2.0 * sin(0.5 * th) * sc;
-        T[k] = (uint64_t)ceil(v * v);
-    }
+    const int K = sphere_setup(n, x, y, z, nb, theta_min, theta_max, q, T);
+    const double s = 1.0 / lattice_scale(4.0, K);
     const int64_t np = p_end - p_begin;
     const int64_t nchunk = np < ORACLE_CHUNKS ? np : ORACLE_CHUNKS;
     double *part = (double *)calloc((size_t)nchunk * zsize, sizeof(double));
@@ -552,44 +607,8 @@ int oracle_zeta_sphere(int64_t n, const double *x, const double *y, const double
         for (int64_t c = 0; c < nchunk; c++) {
             int64_t lo = p_begin + np * c / nchunk, hi = p_begin + np * (c + 1) / nchunk;
             for (int64_t p = lo; p < hi; p++) {
-                memset(am, 0, sizeof(double complex) * (size_t)nb * M1);
-                for (int b = 0; b < nb; b++) cnt[b] = 0;
-                /* tangent basis at the primary's lattice position */
-                double np_[3] = {q[p] * s - 2.0, q[n + p] * s - 2.0, q[2 * n + p] * s - 2.0};
-                const double nn = sqrt(np_[0] * np_[0] + np_[1] * np_[1] + np_[2] * np_[2]);
-                for (int a = 0; a < 3; a++) np_[a] /= nn;
-                double e1[3] = {-np_[1], np_[0], 0.0}; /* z x n */
-                double l1 = sqrt(e1[0] * e1[0] + e1[1] * e1[1]);
-                if (l1 < 1e-6) { /* x x n */
-                    e1[0] = 0.0;
-                    e1[1] = -np_[2];
-                    e1[2] = np_[1];
-                    l1 = sqrt(e1[1] * e1[1] + e1[2] * e1[2]);
-                }
-                for (int a = 0; a < 3; a++) e1[a] /= l1;
-                const double e2[3] = {np_[1] * e1[2] - np_[2] * e1[1], np_[2] * e1[0] - np_[0] * e1[2],
-                                      np_[0] * e1[1] - np_[1] * e1[0]};
-                for (int64_t j = 0; j < n; j++) {
-                    if (j == p) continue;
-                    int64_t d[3];
-                    for (int a = 0; a < 3; a++) d[a] = q[a * n + j] - q[a * n + p];
-                    const uint64_t R2 = (uint64_t)(d[0] * d[0]) + (uint64_t)(d[1] * d[1]) + (uint64_t)(d[2] * d[2]);
-                    if (R2 == 0 || R2 < T[0] || R2 >= T[nb]) continue;
-                    int b = 0;
-                    while (b + 1 < nb && R2 >= T[b + 1]) b++;
-                    const double t1 = d[0] * e1[0] + d[1] * e1[1] + d[2] * e1[2];
-                    const double t2 = d[0] * e2[0] + d[1] * e2[1] + d[2] * e2[2];
-                    const double phi = atan2(t2, t1);
-                    for (int m = 0; m <= mmax; m++) am[b * M1 + m] += w[j] * cexp(-I * (m * phi));
-                    cnt[b]++;
-                    pairs[c]++;
-                }
-                double *z = part + (size_t)c * zsize;
-                for (int m = 0; m <= mmax; m++)
-                    for (int b1 = 0; b1 < nb; b1++)
-                        for (int b2 = 0; b2 < nb; b2++)
-                            z[((size_t)m * nb + b1) * nb + b2] +=
-                                w[p] * creal(am[b1 * M1 + m] * conj(am[b2 * M1 + m]));
+                const int64_t qp[3] = {q[p], q[n + p], q[2 * n + p]};
+                sphere_pivot(n, q, w, T, nb, mmax, s, qp, w[p], p, am, cnt, part + (size_t)c * zsize, &pairs[c]);
                 if (counts)
                     for (int b = 0; b < nb; b++) counts[(p - p_begin) * nb + b] = cnt[b];
             }
@@ -640,6 +659,43 @@ static int cmp_group_key(const void *a, const void *b)
     return u->idx < v->idx ? -1 : (u->idx > v->idx);
 }
 
+/* Groups the lattice points q[3][n] by pivot cells of Hq lattice units, in (gz, gy, gx) order;
+ * writes each group's pivot (round-half-up mean lattice position, pq[3][n]) and summed weight
+ * (members in input order, pw[n]); returns the number of groups. */
+static int64_t build_groups(int64_t n, const int64_t *q, const double *w, int64_t Hq, int64_t *pq, double *pw)
+{
+    group_key *keys = (group_key *)malloc(sizeof(group_key) * (size_t)n);
+    for (int64_t i = 0; i < n; i++) {
+        keys[i].gx = q[i] / Hq;
+        keys[i].gy = q[n + i] / Hq;
+        keys[i].gz = q[2 * n + i] / Hq;
+        keys[i].idx = i;
+    }
+    qsort(keys, (size_t)n, sizeof(group_key), cmp_group_key);
+    int64_t G = 0;
+    for (int64_t a = 0; a < n;) {
+        int64_t b = a;
+        int64_t sum[3] = {0, 0, 0};
+        double W = 0.0;
+        while (b < n && keys[b].gx == keys[a].gx && keys[b].gy == keys[a].gy && keys[b].gz == keys[a].gz) {
+            const int64_t i = keys[b].idx;
+            sum[0] += q[i];
+            sum[1] += q[n + i];
+            sum[2] += q[2 * n + i];
+            b++;
+        }
+        /* weights in input order: members were sorted by index within the group */
+        for (int64_t k = a; k < b; k++) W += w[keys[k].idx];
+        const int64_t cnt = b - a;
+        for (int ax = 0; ax < 3; ax++) pq[ax * n + G] = (2 * sum[ax] + cnt) / (2 * cnt);
+        pw[G] = W;
+        G++;
+        a = b;
+    }
+    free(keys);
+    return G;
+}
+
 int oracle_zeta_pivots(int64_t n, const double *x, const double *y, const double *z, const double *w,
                        double box, int periodic, int nbins, double rmin, double rmax, int lmax, double h,
                        double *zeta, int64_t *ngroups_out, int64_t *npairs_out, int64_t *gq, double *gw,
@@ -665,38 +721,9 @@ int oracle_zeta_pivots(int64_t n, const double *x, const double *y, const double
 
     int64_t Hq = (int64_t)floor(h * lattice_scale(box, K));
     if (Hq < 1) Hq = 1;
-    group_key *keys = (group_key *)malloc(sizeof(group_key) * (size_t)n);
-    for (int64_t i = 0; i < n; i++) {
-        keys[i].gx = q[i] / Hq;
-        keys[i].gy = q[n + i] / Hq;
-        keys[i].gz = q[2 * n + i] / Hq;
-        keys[i].idx = i;
-    }
-    qsort(keys, (size_t)n, sizeof(group_key), cmp_group_key);
-    /* group pivots */
     int64_t *pq = (int64_t *)malloc(sizeof(int64_t) * 3 * (size_t)n);
     double *pw = (double *)malloc(sizeof(double) * (size_t)n);
-    int64_t G = 0;
-    for (int64_t a = 0; a < n;) {
-        int64_t b = a;
-        int64_t sum[3] = {0, 0, 0};
-        double W = 0.0;
-        while (b < n && keys[b].gx == keys[a].gx && keys[b].gy == keys[a].gy && keys[b].gz == keys[a].gz) {
-            const int64_t i = keys[b].idx;
-            sum[0] += q[i];
-            sum[1] += q[n + i];
-            sum[2] += q[2 * n + i];
-            b++;
-        }
-        /* weights in input order: members were sorted by index within the group */
-        for (int64_t k = a; k < b; k++) W += w[keys[k].idx];
-        const int64_t cnt = b - a;
-        for (int ax = 0; ax < 3; ax++) pq[ax * n + G] = (2 * sum[ax] + cnt) / (2 * cnt);
-        pw[G] = W;
-        G++;
-        a = b;
-    }
-    free(keys);
+    const int64_t G = build_groups(n, q, w, Hq, pq, pw);
     *ngroups_out = G;
     if (gq)
         for (int64_t g = 0; g < G; g++)
@@ -727,6 +754,75 @@ int oracle_zeta_pivots(int64_t n, const double *x, const double *y, const double
         }
         free(alm);
         free(Y);
+        free(cnt);
+    }
+    int64_t total = 0;
+    for (int64_t c = 0; c < nchunk; c++) {
+        for (size_t k = 0; k < zsize; k++) zeta[k] += part[(size_t)c * zsize + k];
+        total += pairs[c];
+    }
+    if (npairs_out) *npairs_out = total;
+    free(part);
+    free(pairs);
+    free(pq);
+    free(pw);
+    free(q);
+    free(T);
+    return 0;
+}
+
+/*
+ * Shared pivots on the sphere: the grouping of oracle_zeta_pivots applied to the sphere's lattice
+ * (unit vectors shifted by +2, cube of side 4, K from the largest chord), pivot cell h in the
+ * cube's units (the mean pixel separation sqrt(4 pi / n) for a full-sky map); each group's pivot
+ * sits at the rounded mean lattice position of its members (just inside the sphere), its tangent
+ * basis is taken at unit(X s - 2) and its angles and chord bins from the lattice displacements,
+ * exactly as for a point; zeta~_m = sum_g W_g Re[a_m(X_g, b1) conj(a_m(X_g, b2))].
+ */
+int oracle_zeta_sphere_pivots(int64_t n, const double *x, const double *y, const double *z, const double *w,
+                              int nbins, double theta_min, double theta_max, int mmax, double h, double *zeta,
+                              int64_t *ngroups_out, int64_t *npairs_out, int nthreads)
+{
+    if (n < 0 || nbins < 1 || mmax < 0 || !(theta_min >= 0.0) || !(theta_max > theta_min) ||
+        !(theta_max <= 3.14159265358979323846) || !(h > 0.0))
+        return 1;
+    const int nb = nbins, M1 = mmax + 1;
+    const size_t zsize = (size_t)M1 * nb * nb;
+    memset(zeta, 0, sizeof(double) * zsize);
+    *ngroups_out = 0;
+    if (npairs_out) *npairs_out = 0;
+    if (n == 0) return 0;
+    int64_t *q = (int64_t *)malloc(sizeof(int64_t) * 3 * (size_t)n);
+    uint64_t *T = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(nb + 1));
+    const int K = sphere_setup(n, x, y, z, nb, theta_min, theta_max, q, T);
+    const double sc = lattice_scale(4.0, K), s = 1.0 / sc;
+    int64_t Hq = (int64_t)floor(h * sc);
+    if (Hq < 1) Hq = 1;
+    int64_t *pq = (int64_t *)malloc(sizeof(int64_t) * 3 * (size_t)n);
+    double *pw = (double *)malloc(sizeof(double) * (size_t)n);
+    const int64_t G = build_groups(n, q, w, Hq, pq, pw);
+    *ngroups_out = G;
+    const int64_t nchunk = G < ORACLE_CHUNKS ? G : ORACLE_CHUNKS;
+    double *part = (double *)calloc((size_t)nchunk * zsize, sizeof(double));
+    int64_t *pairs = (int64_t *)calloc((size_t)nchunk, sizeof(int64_t));
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel
+    {
+        double complex *am = (double complex *)malloc(sizeof(double complex) * (size_t)nb * M1);
+        int64_t *cnt = (int64_t *)malloc(sizeof(int64_t) * (size_t)nb);
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t c = 0; c < nchunk; c++) {
+            const int64_t lo = G * c / nchunk, hi = G * (c + 1) / nchunk;
+            for (int64_t g = lo; g < hi; g++) {
+                const int64_t qp[3] = {pq[g], pq[n + g], pq[2 * n + g]};
+                sphere_pivot(n, q, w, T, nb, mmax, s, qp, pw[g], -1, am, cnt, part + (size_t)c * zsize, &pairs[c]);
+            }
+        }
+        free(am);
         free(cnt);
     }
     int64_t total = 0;

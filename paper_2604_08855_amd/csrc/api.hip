@@ -31,9 +31,11 @@ size_t sweep_tile_bytes_per_wave(int lmax, int nb, bool f64, bool sphere);
 std::vector<double> threej_squared_table(int lmax);
 hipError_t launch_edge_correct(int ncat, int lmax, int nb, const double* N, const double* R, const double* t3,
                                double* out, hipStream_t s);
-hipError_t build_pivots(const uint4* rec, const double* w64, uint32_t n, int sh, uint64_t Hq, uint32_t ng,
-                        uint32_t* count, unsigned long long* sum, double* wsum, uint32_t* flag, uint32_t* slot,
-                        uint32_t* block_sum, uint4* prim_rec, double* prim_w, hipStream_t s);
+size_t pivot_sort_bytes(uint32_t n);
+hipError_t build_pivots(const uint4* rec, const double* w64, uint32_t n, int sh, uint64_t Hq,
+                        unsigned long long* key_a, unsigned long long* key_b, uint32_t* idx_a, uint32_t* idx_b,
+                        uint32_t* head, uint32_t* slot, uint32_t* block_sum, void* sort_tmp, size_t sort_bytes,
+                        uint4* prim_rec, double* prim_w, hipStream_t s);
 }  // namespace tpcf
 
 using namespace tpcf;
@@ -98,7 +100,7 @@ struct tpcf_ctx {
   DevBuf edge_tab, edge_io;  // squared 3j table (for edge_lmax) and host-call staging
   // shared pivots: pivot cell side (0 = exact, < 0 = the mean separation), cell tables, pivots
   double pivot_h = 0.0;
-  DevBuf pv_count, pv_sum, pv_w, pv_flag, pv_slot, pv_bsum, pv_rec, pv_w64;
+  DevBuf pv_keys, pv_idx, pv_head, pv_slot, pv_bsum, pv_tmp, pv_rec, pv_w64;
   int edge_lmax = -1;
   bool sums_valid = false;
   int sums_ncat = 0, sums_nb = 0;
@@ -148,8 +150,8 @@ size_t total_bytes(tpcf_ctx* c) {
                    &c->idx_a, &c->idx_b, &c->bsum, &c->errflag, &c->cell_start, &c->rec, &c->w64, &c->perm,
                    &c->scratch, &c->tile, &c->zeta_d, &c->queue, &c->stats_d, &c->tasks, &c->counts32,
                    &c->alm_dbg, &c->conv_idx, &c->conv32, &c->conv64, &c->regions, &c->bin_pairs, &c->bin_dd,
-                   &c->edge_tab, &c->edge_io, &c->pv_count, &c->pv_sum, &c->pv_w, &c->pv_flag,
-                   &c->pv_slot, &c->pv_bsum, &c->pv_rec, &c->pv_w64};
+                   &c->edge_tab, &c->edge_io, &c->pv_keys, &c->pv_idx, &c->pv_head, &c->pv_slot,
+                   &c->pv_bsum, &c->pv_tmp, &c->pv_rec, &c->pv_w64};
   size_t t = 0;
   for (DevBuf* b : all) t += b->bytes;
   return t;
@@ -732,34 +734,41 @@ bool graphs_enabled() {
   return !(s && s[0] == '0');
 }
 
-// Shared pivots of the (single, 3D) catalogue: pivot cells of Hq = max(1, floor(h * scale))
-// lattice units, h the pivot cell side (the mean separation L / n^(1/3) when pivot_h < 0). Builds
-// the pivots on the stream and returns their number G (synchronises).
+// Shared pivots of the (single) catalogue: pivot cells of Hq = max(1, floor(h * scale)) lattice
+// units, h the pivot cell side; when pivot_h < 0 the mean separation, L / n^(1/3) in a box and
+// sqrt(4 pi / n) on the sphere. Builds the pivots on the stream and returns their number G
+// (synchronises).
 int prepare_pivots(tpcf_ctx* c, uint32_t& G) {
   const CatDesc& d = c->cd[0];
   const HostCat& h = c->cats[0];
-  const double side = c->pivot_h > 0.0 ? c->pivot_h : (h.n > 0 ? h.box / cbrt((double)h.n) : h.box);
+  double side = c->pivot_h;
+  if (side < 0.0) {
+    if (h.n == 0) side = h.box;
+    else side = h.sphere ? sqrt(4.0 * kPi / (double)h.n) : h.box / cbrt((double)h.n);
+  }
   const uint64_t span = (uint64_t)1 << d.K;
   double hq = floor(side * d.scale);
   if (!(hq >= 1.0)) hq = 1.0;
   if (hq > (double)span) hq = (double)span;
   const uint64_t Hq = (uint64_t)hq;
-  const uint64_t ng = (span + Hq - 1) / Hq;
-  if (ng * ng * ng > ((uint64_t)1 << 26))
-    return fail(c, TPCF_E_INVALID_ARG, "pivot cell too small: more than 2^26 pivot cells");
-  const size_t nc3 = (size_t)(ng * ng * ng), n = (size_t)c->ntot;
+  if ((span + Hq - 1) / Hq > ((uint64_t)1 << 21))
+    return fail(c, TPCF_E_INVALID_ARG, "pivot cell too small: more than 2^21 pivot cells per axis");
+  const size_t n = (size_t)c->ntot;
+  const size_t sort_bytes = pivot_sort_bytes((uint32_t)n);
   int rc;
-  if ((rc = ensure(c, c->pv_count, nc3 * 4, "pivot cells")) || (rc = ensure(c, c->pv_sum, nc3 * 24, "pivot cells")) ||
-      (rc = ensure(c, c->pv_w, nc3 * 8, "pivot cells")) || (rc = ensure(c, c->pv_flag, nc3 * 4, "pivot cells")) ||
-      (rc = ensure(c, c->pv_slot, (nc3 + 1) * 4, "pivot cells")) ||
-      (rc = ensure(c, c->pv_bsum, scan_block_count((uint32_t)nc3) * 4 + 4, "pivot cells")) ||
+  if ((rc = ensure(c, c->pv_keys, (n + 1) * 16, "pivot keys")) || (rc = ensure(c, c->pv_idx, (n + 1) * 8, "pivot keys")) ||
+      (rc = ensure(c, c->pv_head, (n + 1) * 4, "pivot keys")) || (rc = ensure(c, c->pv_slot, (n + 1) * 4, "pivot keys")) ||
+      (rc = ensure(c, c->pv_bsum, scan_block_count((uint32_t)n) * 4 + 4, "pivot keys")) ||
+      (rc = ensure(c, c->pv_tmp, sort_bytes, "pivot sort")) ||
       (rc = ensure(c, c->pv_rec, (n + 1) * 16, "pivots")) || (rc = ensure(c, c->pv_w64, (n + 1) * 8, "pivots")))
     return rc;
-  HIP_TRY(c, build_pivots((const uint4*)c->rec.p, (const double*)c->w64.p, (uint32_t)n, d.sh, Hq,
-                          (uint32_t)ng, (uint32_t*)c->pv_count.p, (unsigned long long*)c->pv_sum.p,
-                          (double*)c->pv_w.p, (uint32_t*)c->pv_flag.p, (uint32_t*)c->pv_slot.p,
-                          (uint32_t*)c->pv_bsum.p, (uint4*)c->pv_rec.p, (double*)c->pv_w64.p, c->stream));
-  HIP_TRY(c, hipMemcpyAsync(&G, (uint32_t*)c->pv_slot.p + nc3, 4, hipMemcpyDeviceToHost, c->stream));
+  unsigned long long* keys = (unsigned long long*)c->pv_keys.p;
+  uint32_t* idx = (uint32_t*)c->pv_idx.p;
+  HIP_TRY(c, build_pivots((const uint4*)c->rec.p, (const double*)c->w64.p, (uint32_t)n, d.sh, Hq, keys, keys + (n + 1),
+                          idx, idx + (n + 1), (uint32_t*)c->pv_head.p, (uint32_t*)c->pv_slot.p,
+                          (uint32_t*)c->pv_bsum.p, c->pv_tmp.p, sort_bytes, (uint4*)c->pv_rec.p,
+                          (double*)c->pv_w64.p, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(&G, (uint32_t*)c->pv_slot.p + n, 4, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return TPCF_OK;
 }
@@ -777,8 +786,8 @@ int compute(tpcf_ctx* c, int64_t p_begin, int64_t p_end, double* zeta, int memsp
   const bool rebuild = !grid_current(c);
   const bool pivots = c->pivot_h != 0.0;
   if (pivots) {
-    if (use_graph || c->cats.size() != 1 || c->cats[0].sphere)
-      return fail(c, TPCF_E_UNSUPPORTED, "shared pivots need a single 3D catalogue set by tpcf_set_catalog");
+    if (use_graph || c->cats.size() != 1)
+      return fail(c, TPCF_E_UNSUPPORTED, "shared pivots need a single catalogue (tpcf_set_catalog or tpcf_set_sphere_catalog)");
     if (p_begin != 0 || p_end != c->ntot)
       return fail(c, TPCF_E_UNSUPPORTED, "shared pivots cover the whole catalogue: no primary ranges");
   }
@@ -903,8 +912,8 @@ void tpcf_destroy(tpcf_ctx* c) {
                      &c->idx_a, &c->idx_b, &c->bsum, &c->errflag, &c->cell_start, &c->rec, &c->w64, &c->perm,
                      &c->scratch, &c->tile, &c->zeta_d, &c->queue, &c->stats_d, &c->tasks, &c->counts32,
                      &c->alm_dbg, &c->conv_idx, &c->conv32, &c->conv64, &c->regions, &c->bin_pairs, &c->bin_dd,
-                     &c->edge_tab, &c->edge_io, &c->pv_count, &c->pv_sum, &c->pv_w, &c->pv_flag,
-                     &c->pv_slot, &c->pv_bsum, &c->pv_rec, &c->pv_w64};
+                     &c->edge_tab, &c->edge_io, &c->pv_keys, &c->pv_idx, &c->pv_head, &c->pv_slot,
+                     &c->pv_bsum, &c->pv_tmp, &c->pv_rec, &c->pv_w64};
     for (DevBuf* b : all) release(*b);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     for (auto& e : c->ev)

@@ -113,18 +113,9 @@ def pair_sums(x, y, z, w, box, periodic, nbins, rmin, rmax):
 
 # ---------------------------------------------------------------- projected fields on the sphere
 
-def zeta_sphere_triangles(x, y, z, w, nbins, theta_min, theta_max, mmax, primaries=None):
-    """zeta_m on the sphere in the basis-free triangle form
-
-        zeta_m(b1, b2) = sum_p w_p sum_{j in b1} sum_{k in b2} w_j w_k cos(m (phi_j - phi_k)),
-
-    where phi_j - phi_k is the angle between the projections of d_j and d_k on the tangent
-    plane at the primary, so no tangent basis is needed; cos(m x) = T_m(cos x). Also returns
-    the per-primary counts and sums S_p(b) = sum_{j in b} w_j."""
-    from scipy.special import eval_chebyt
+def sphere_lattice(x, y, z, nbins, theta_min, theta_max):
+    """(q [n, 3], scale, T) of unit vectors on the sphere's lattice, from the stated definition."""
     X = np.stack([np.asarray(a, dtype=np.float64) for a in (x, y, z)], 1) + 2.0
-    n = len(X)
-    w = np.ones(n) if w is None else np.asarray(w, dtype=np.float64)
     cmax = 2.0 * math.sin(0.5 * theta_max)
     K = lattice_bits(4.0, cmax, False)
     q = np.stack([snap(X[:, a], 4.0, K, False) for a in range(3)], 1)
@@ -135,38 +126,60 @@ def zeta_sphere_triangles(x, y, z, w, nbins, theta_min, theta_max, mmax, primari
         th = theta_max if k == nbins else theta_min + k * dth
         v = 2.0 * math.sin(0.5 * th) * sc
         T.append(int(math.ceil(v * v)))
+    return q, sc, T
+
+
+def sphere_triangles_at(qp, wp, skip, q, w, sc, T, nbins, mmax, zeta, counts, sums, row):
+    """Adds one pivot (lattice point qp, weight wp; point `skip` excluded) to zeta in the basis-free
+    triangle form; fills counts[row] and sums[row]."""
+    from scipy.special import eval_chebyt
+    npv = np.asarray(qp, dtype=np.float64) / sc - 2.0
+    npv = npv / np.linalg.norm(npv)
+    js, bs, P = [], [], []
+    for j in range(len(q)):
+        if j == skip:
+            continue
+        d = [int(a) - int(b) for a, b in zip(q[j], qp)]
+        R2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2]
+        if R2 == 0 or R2 < T[0] or R2 >= T[-1]:
+            continue
+        b = max(k for k in range(nbins) if T[k] <= R2)
+        dv = np.array(d, dtype=np.float64)
+        perp = dv - (dv @ npv) * npv
+        js.append(j)
+        bs.append(b)
+        P.append(perp / np.linalg.norm(perp))
+        if counts is not None:
+            counts[row, b] += 1
+            sums[row, b] += w[j]
+    if not js:
+        return
+    js, bs, P = np.array(js), np.array(bs), np.array(P)
+    cosd = np.clip(P @ P.T, -1.0, 1.0)
+    ww = np.outer(w[js], w[js])
+    for m in range(mmax + 1):
+        acc = np.zeros((nbins, nbins))
+        np.add.at(acc, (bs[:, None].repeat(len(js), 1), bs[None, :].repeat(len(js), 0)),
+                  eval_chebyt(m, cosd) * ww)
+        zeta[m] += wp * acc
+
+
+def zeta_sphere_triangles(x, y, z, w, nbins, theta_min, theta_max, mmax, primaries=None):
+    """zeta_m on the sphere in the basis-free triangle form
+
+        zeta_m(b1, b2) = sum_p w_p sum_{j in b1} sum_{k in b2} w_j w_k cos(m (phi_j - phi_k)),
+
+    where phi_j - phi_k is the angle between the projections of d_j and d_k on the tangent
+    plane at the primary, so no tangent basis is needed; cos(m x) = T_m(cos x). Also returns
+    the per-primary counts and sums S_p(b) = sum_{j in b} w_j."""
+    q, sc, T = sphere_lattice(x, y, z, nbins, theta_min, theta_max)
+    n = len(q)
+    w = np.ones(n) if w is None else np.asarray(w, dtype=np.float64)
     zeta = np.zeros((mmax + 1, nbins, nbins))
     counts = np.zeros((n, nbins), dtype=np.int64)
     sums = np.zeros((n, nbins))
     for p in (range(n) if primaries is None else primaries):
-        npv = q[p] / sc - 2.0
-        npv = npv / np.linalg.norm(npv)
-        js, bs, P = [], [], []
-        for j in range(n):
-            if j == p:
-                continue
-            d = [int(a) - int(b) for a, b in zip(q[j], q[p])]
-            R2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2]
-            if R2 == 0 or R2 < T[0] or R2 >= T[-1]:
-                continue
-            b = max(k for k in range(nbins) if T[k] <= R2)
-            dv = np.array(d, dtype=np.float64)
-            perp = dv - (dv @ npv) * npv
-            js.append(j)
-            bs.append(b)
-            P.append(perp / np.linalg.norm(perp))
-            counts[p, b] += 1
-            sums[p, b] += w[j]
-        if not js:
-            continue
-        js, bs, P = np.array(js), np.array(bs), np.array(P)
-        cosd = np.clip(P @ P.T, -1.0, 1.0)
-        ww = np.outer(w[js], w[js])
-        for m in range(mmax + 1):
-            acc = np.zeros((nbins, nbins))
-            np.add.at(acc, (bs[:, None].repeat(len(js), 1), bs[None, :].repeat(len(js), 0)),
-                      eval_chebyt(m, cosd) * ww)
-            zeta[m] += w[p] * acc
+        sphere_triangles_at(q[p], w[p], p, q, w, sc, T, nbins, mmax, zeta, counts, sums, p)
     return zeta, counts, sums
 
 
@@ -218,3 +231,25 @@ def zeta_triangles_lattice(qp, wp, qs, ws, K, periodic, T, nbins, lmax):
                       eval_legendre(l, cosg) * ww)
             zeta[l] += wp[p] * (2 * l + 1) / (4 * math.pi) * acc
     return zeta
+
+
+def zeta_sphere_pivots_triangles(x, y, z, w, nbins, theta_min, theta_max, mmax, h):
+    """Shared pivots on the sphere: numpy grouping of the sphere's lattice points by pivot cells of
+    Hq = max(1, floor(h scale)), pivots at the round-half-up mean, then the triangle form."""
+    q, sc, T = sphere_lattice(x, y, z, nbins, theta_min, theta_max)
+    w = np.ones(len(q)) if w is None else np.asarray(w, dtype=np.float64)
+    Hq = max(1, int(math.floor(h * sc)))
+    keys, inv = np.unique((q // Hq)[:, ::-1], axis=0, return_inverse=True)
+    inv = inv.ravel()
+    G = len(keys)
+    cnt = np.bincount(inv, minlength=G).astype(np.int64)
+    sums = np.zeros((G, 3), dtype=np.int64)
+    np.add.at(sums, inv, q)
+    W = np.zeros(G)
+    np.add.at(W, inv, w)
+    X = (2 * sums + cnt[:, None]) // (2 * cnt[:, None])
+    zeta = np.zeros((mmax + 1, nbins, nbins))
+    for g in range(G):
+        sphere_triangles_at(X[g], W[g], -1, q, w, sc, T, nbins, mmax, zeta, None, None, g)
+    return zeta, G
+

@@ -71,8 +71,8 @@ def test_one_point_per_cell_is_exact(tpcf):
 
 
 def test_mean_separation_default_and_errors(tpcf):
-    """side < 0 uses the mean separation L / n^(1/3); ranges, batches, sphere catalogues and
-    too many pivot cells are refused."""
+    """side < 0 uses the mean separation L / n^(1/3); ranges, batches and more than 2^21 pivot
+    cells per axis are refused."""
     cat = catalogs.lognormal(4000, 120.0, 6, grid=64)
     ctx, z = run(tpcf, cat, None, 6, 4.0, 24.0, 3, "fp64", -1.0)
     h = 120.0 / np.cbrt(4000.0)
@@ -90,19 +90,31 @@ def test_mean_separation_default_and_errors(tpcf):
     with pytest.raises(tpcf.TpcfError) as e:
         ctx.set_pivot_cell(float("nan"))
     assert e.value.code == 1
-    ctx.set_pivot_cell(1e-4)  # 120 / 1e-4 cells per axis
+    ctx.set_pivot_cell(1e-5)  # 1.2e7 cells per axis, above 2^21
     ctx.set_catalog(cat.x, cat.y, cat.z, None, box=120.0, periodic=True)
     with pytest.raises(tpcf.TpcfError) as e:
         ctx.compute_zeta()
     assert e.value.code == 1
-    m = catalogs.sphere_cluster(500, 1)
-    sp = tpcf.Context(0)
-    sp.set_bins(4, 0.0, 0.2, 2)
-    sp.set_pivot_cell(0.05)
-    sp.set_sphere_catalog(m.x, m.y, m.z, m.w)
-    with pytest.raises(tpcf.TpcfError) as e:
-        sp.compute_zeta()
-    assert e.value.code == 5
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_sphere_pivots_match_oracle(tpcf, prec):
+    """Shared pivots on a HEALPix nside-32 map (12,288 pixels, mean separation 0.032): cells of
+    0.06, 10 bins in [0.02, 0.3) rad, m_max = 8; and the sphere's mean-separation default."""
+    m = catalogs.sphere_map(32, 5, grid=64)
+    for side, h in ((0.06, 0.06), (-1.0, np.sqrt(4 * np.pi / m.n))):
+        ctx = tpcf.Context(0)
+        ctx.set_bins(10, 0.02, 0.3, 8)
+        ctx.set_precision(prec)
+        ctx.set_pivot_cell(side)
+        ctx.set_sphere_catalog(m.x, m.y, m.z, m.w)
+        z = ctx.compute_zeta()
+        ref = oracle.zeta_sphere_pivots(m.x, m.y, m.z, m.w, 10, 0.02, 0.3, 8, h)
+        st = ctx.stats()
+        say(f"sphere pivots side={side} prec={prec}: {st['n_primaries']} pivots, rel err",
+            rel_err_per_l(z, ref.zeta).max())
+        assert st["n_primaries"] == ref.ngroups and st["n_pairs"] == ref.npairs
+        assert rel_err_per_l(z, ref.zeta).max() <= TOL[prec]
 
 
 def test_full_size_pivots(tpcf):

@@ -45,8 +45,8 @@ MUTANTS = {
     "sphere: second tangent vector": ("np_[0] * e1[1] - np_[1] * e1[0]};",
                                       "np_[0] * e1[1] + np_[1] * e1[0]};"),
     "sphere: no basis at the pole": ("if (l1 < 1e-6) { /* x x n */", "if (l1 < 0.0) { /* x x n */"),
-    "sphere: primary weight dropped": ("w[p] * creal(am[b1 * M1 + m] * conj(am[b2 * M1 + m]));",
-                                       "creal(am[b1 * M1 + m] * conj(am[b2 * M1 + m]));"),
+    "sphere: primary weight dropped": ("+= wp * creal(am[b1 * M1 + m] * conj(am[b2 * M1 + m]));",
+                                       "+= creal(am[b1 * M1 + m] * conj(am[b2 * M1 + m]));"),
     "pivots: mean rounded down": ("pq[ax * n + G] = (2 * sum[ax] + cnt) / (2 * cnt);",
                                   "pq[ax * n + G] = sum[ax] / cnt;"),
     "pivots: group weight is the mean": ("pw[G] = W;", "pw[G] = W / (double)cnt;"),

@@ -522,3 +522,19 @@ def test_pivots_invalid():
         oracle.zeta_pivots(one, one, one, None, 10.0, True, 2, 0.0, 2.0, 1, 0.0)
     r = oracle.zeta_pivots(np.zeros(0), np.zeros(0), np.zeros(0), None, 10.0, True, 2, 0.0, 2.0, 1, 1.0)
     assert r.ngroups == 0 and not r.zeta.any()
+
+
+def test_sphere_pivots_against_brute_force_and_exact_limit():
+    """Shared pivots on the sphere: against the numpy grouping and triangle form on clustered
+    points; with one pixel per pivot cell (HEALPix nside 16, cells of 0.01) the exact estimator."""
+    m = catalogs.sphere_cluster(300, 4, ncentre=3, spread=0.05)
+    r = oracle.zeta_sphere_pivots(m.x, m.y, m.z, m.w, 5, 0.005, 0.2, 6, 0.02)
+    ref, G = brute.zeta_sphere_pivots_triangles(m.x, m.y, m.z, m.w, 5, 0.005, 0.2, 6, 0.02)
+    assert r.ngroups == G < 300
+    assert _rel(r.zeta, ref) < 1e-12
+    x, y, z = catalogs.healpix_centres(16)
+    w = np.random.default_rng(1).normal(1.0, 0.5, len(x))
+    rp = oracle.zeta_sphere_pivots(x, y, z, w, 4, 0.0, 0.3, 4, 0.01)
+    ex = oracle.zeta_sphere(x, y, z, w, 4, 0.0, 0.3, 4)
+    assert rp.ngroups == len(x) and rp.npairs == ex.npairs
+    assert _rel(rp.zeta, ex.zeta) < 1e-12
