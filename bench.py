@@ -407,6 +407,99 @@ def run_pivots(args):
     print(json.dumps(out), flush=True)
 
 
+def run_sphere_large(args):
+    """The sphere workload at a larger map (--nside, e.g. 4096: 201,326,592 pixels), same bins and
+    m_max as the nside-1024 form, mixed only: the exact sweep over --chunks primary ranges (their
+    zeta add up to the whole; each range reports its progress), shared pivots at the pivot cells of
+    --pivot-cells (in mean pixel separations), and sampled primary ranges against the oracle."""
+    import catalogs
+    import oracle
+
+    nside, nb, mmax = args.nside, 20, 8
+    arcmin = math.pi / (180.0 * 60.0)
+    tmin, tmax = 10 * arcmin, 200 * arcmin
+    t0 = time.time()
+    x, y, z = catalogs.healpix_centres(nside)
+    n = len(x)
+    log(f"[bench] HEALPix nside {nside}: {n} pixel centres in {time.time() - t0:.1f}s")
+    field = catalogs.sphere_field_sampler(2604)
+    w = np.empty(n)
+    step = 1 << 24
+    for a in range(0, n, step):
+        b = min(n, a + step)
+        w[a:b] = field(x[a:b], y[a:b], z[a:b])
+        log(f"[bench] map values {b}/{n} ({time.time() - t0:.1f}s)")
+
+    import torch
+
+    import paper_2604_08855_amd as tpcf
+
+    dev = [torch.from_numpy(a).cuda() for a in (x, y, z, w)]
+    torch.cuda.synchronize()
+    ctx = tpcf.Context(0, torch.cuda.current_stream())
+    ctx.set_bins(nb, tmin, tmax, mmax)
+    ctx.set_precision("mixed")
+    ppc, wpc = (float(v) for v in (args.tuning or "16,12").split(","))
+    ctx.set_tuning(ppc, int(wpc))
+    t1 = time.perf_counter()
+    ctx.set_sphere_catalog(*dev)
+    torch.cuda.synchronize()
+    t_stage = time.perf_counter() - t1
+    zsum = np.zeros((mmax + 1, nb, nb))
+    pairs, cands, t_sweep = 0, 0, 0.0
+    C = args.chunks
+    for k in range(C):
+        a, b = n * k // C, n * (k + 1) // C
+        t1 = time.perf_counter()
+        zsum += ctx.compute_zeta_range(a, b)
+        t_sweep += time.perf_counter() - t1
+        st = ctx.stats()
+        pairs += st["n_pairs"]
+        cands += st["n_candidates"]
+        log(f"[bench] exact range {k + 1}/{C}: {st['n_pairs']} pairs, {(time.perf_counter() - t1):.1f}s")
+    value = pairs / (t_stage + t_sweep)
+    log(f"[bench] exact: {pairs} pairs in {t_stage + t_sweep:.1f}s, {value:.3e} pairs/s")
+    errs = []
+    for a in (0, n // 2, n - 8):
+        zg = ctx.compute_zeta_range(a, a + 8)
+        ref = oracle.zeta_sphere(x, y, z, w, nb, tmin, tmax, mmax, a, a + 8).zeta
+        scale = np.abs(ref).reshape(mmax + 1, -1).max(axis=1)
+        errs.append(float((np.abs(zg - ref).reshape(mmax + 1, -1).max(axis=1) / scale).max()))
+        log(f"[bench] oracle check [{a}, {a + 8}): {errs[-1]:.2e}")
+    ctx.close()
+    sep = math.sqrt(4.0 * math.pi / n)
+    piv = []
+    for f in (float(v) for v in args.pivot_cells.split(",") if v):
+        ctx = tpcf.Context(0, torch.cuda.current_stream())
+        ctx.set_bins(nb, tmin, tmax, mmax)
+        ctx.set_precision("mixed")
+        ctx.set_tuning(ppc, int(wpc))
+        ctx.set_pivot_cell(f * sep)
+        t1 = time.perf_counter()
+        ctx.set_sphere_catalog(*dev)
+        zp = ctx.compute_zeta()
+        el = time.perf_counter() - t1
+        st = ctx.stats()
+        e = float(max(np.abs(zp[k] - zsum[k]).max() / np.abs(zsum[k]).max() for k in range(mmax + 1)))
+        piv.append({"pivot_cell": f * sep, "pivots": st["n_primaries"], "seconds": el,
+                    "speedup_vs_exact": (t_stage + t_sweep) / el, "max_rel_err_vs_exact_mixed": e})
+        log(f"[bench] shared pivots {piv[-1]}")
+        ctx.close()
+    out = {
+        "metric": f"primary-secondary pairs/sec (m_max=8, 20 angular bins), mixed, full-sky map nside {nside}",
+        "value": value, "unit": "pairs/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": (t_stage + t_sweep) * 1000.0, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"HEALPix nside {nside} full sky ({n} pixels), log-normal map values, 20 bins "
+                               f"[10,200) arcmin, m_max=8, mixed, {C} primary ranges", "n_points": n,
+                   "pairs_per_step": pairs, "candidates_per_step": cands,
+                   "tuning": {"points_per_cell": ppc, "waves_per_cu": int(wpc)}},
+        "max_rel_err_vs_oracle_on_sampled_ranges": max(errs),
+        "shared_pivots": piv,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def calibration_copy(torch, mib):
     """A plain device copy of `mib` MiB: its FETCH_SIZE / WRITE_SIZE calibrate the HBM counters."""
     if mib <= 0:
@@ -569,6 +662,10 @@ def main():
                          "nside 1024 map with angular bins; pivots: shared pivots (approximate) "
                          "on the main catalogue")
     ap.add_argument("--mocks", type=int, default=256, help="batch form: number of mocks")
+    ap.add_argument("--nside", type=int, default=1024, help="sphere form: HEALPix resolution of the map")
+    ap.add_argument("--chunks", type=int, default=16, help="sphere form above nside 1024: primary ranges")
+    ap.add_argument("--pivot-cells", default="2,4", help="sphere form above nside 1024: shared-pivot cells "
+                                                         "in mean pixel separations")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -581,7 +678,10 @@ def main():
         run_dmr(args)
         return
     if args.workload == "sphere":
-        run_sphere(args)
+        if args.nside != 1024:
+            run_sphere_large(args)
+        else:
+            run_sphere(args)
         return
     if args.workload == "pivots":
         run_pivots(args)

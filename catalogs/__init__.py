@@ -43,6 +43,7 @@ __all__ = [
     "radec_to_unit",
     "healpix_centres",
     "sphere_field",
+    "sphere_field_sampler",
     "sphere_map",
     "sphere_cluster",
     "SphereMap",
@@ -226,11 +227,22 @@ def healpix_centres(nside: int):
     return (np.ascontiguousarray(x / r), np.ascontiguousarray(y / r), np.ascontiguousarray(z / r))
 
 
+def sphere_field_sampler(seed: int, grid: int = 256, slope: float = -1.5, sigma: float = 0.5):
+    """The sampling function behind ``sphere_field``: builds the 3D field once and returns
+    f(x, y, z) -> rho - 1 at those unit vectors (for maps generated in slices)."""
+    side = 2.5
+    rho = lognormal_field(grid, side, seed, slope, sigma)
+    return lambda x, y, z: _trilinear(rho, side, x, y, z)
+
+
 def sphere_field(x, y, z, seed: int, grid: int = 256, slope: float = -1.5, sigma: float = 0.5) -> np.ndarray:
     """rho - 1 of a log-normal field (``lognormal_field`` on a periodic grid^3 mesh of side 2.5
     centred on the origin) at the unit vectors (x, y, z), trilinear interpolation."""
-    side = 2.5
-    rho = lognormal_field(grid, side, seed, slope, sigma)
+    return sphere_field_sampler(seed, grid, slope, sigma)(x, y, z)
+
+
+def _trilinear(rho, side, x, y, z):
+    grid = rho.shape[0]
     h = side / grid
     out = np.empty(len(x))
     step = 1 << 22
