@@ -281,9 +281,11 @@ int tpcf_edge_correct(tpcf_ctx* ctx, int ncat, const double* N, const double* R,
  * benchmark measure it against the exact estimator); stats report the pivot count as
  * n_primaries. Applies to tpcf_compute_zeta on a catalogue set by tpcf_set_catalog or
  * tpcf_set_sphere_catalog.
+ * The compute call synchronises the context's stream once (to learn the pivot count). The
+ * autotuner times the exact sweep, not the shared pivots.
  * Errors: TPCF_E_INVALID_ARG (side not finite). A compute call fails with TPCF_E_UNSUPPORTED for
  * ranges and batches, and with TPCF_E_INVALID_ARG when the pivot cells number more than 2^21 per
- * axis (cells of at least 2^-21 of the cube's side).
+ * axis (cells of at least 2^-21 of the cube's side) or, on the sphere, are larger than 0.25.
  * Debug output (per-point counts, a_lm) is not kept.
  */
 int tpcf_set_pivot_cell(tpcf_ctx* ctx, double side);

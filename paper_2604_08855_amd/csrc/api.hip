@@ -746,6 +746,9 @@ int prepare_pivots(tpcf_ctx* c, uint32_t& G) {
     if (h.n == 0) side = h.box;
     else side = h.sphere ? sqrt(4.0 * kPi / (double)h.n) : h.box / cbrt((double)h.n);
   }
+  // On the sphere a cell must stay well below the radius: a pivot is its members' mean position,
+  // which must keep a direction.
+  if (h.sphere && side > 0.25) return fail(c, TPCF_E_INVALID_ARG, "pivot cell on the sphere must be at most 0.25");
   const uint64_t span = (uint64_t)1 << d.K;
   double hq = floor(side * d.scale);
   if (!(hq >= 1.0)) hq = 1.0;

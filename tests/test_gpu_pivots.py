@@ -115,6 +115,10 @@ def test_sphere_pivots_match_oracle(tpcf, prec):
             rel_err_per_l(z, ref.zeta).max())
         assert st["n_primaries"] == ref.ngroups and st["n_pairs"] == ref.npairs
         assert rel_err_per_l(z, ref.zeta).max() <= TOL[prec]
+    ctx.set_pivot_cell(0.3)  # cells comparable with the radius: refused
+    with pytest.raises(tpcf.TpcfError) as e:
+        ctx.compute_zeta()
+    assert e.value.code == 1
 
 
 def test_full_size_pivots(tpcf):
