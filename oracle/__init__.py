@@ -58,6 +58,8 @@ def _load():
         lib.oracle_zeta_pivots.restype = i
         lib.oracle_zeta_sphere_pivots.argtypes = [i64, p, p, p, p, i, d, d, i, d, p, p, p, i]
         lib.oracle_zeta_sphere_pivots.restype = i
+        lib.oracle_edge_correct_sphere.argtypes = [i, i, i, p, p, p]
+        lib.oracle_edge_correct_sphere.restype = i
         _lib = lib
     return _lib
 
@@ -234,6 +236,21 @@ def zeta_sphere_pivots(x, y, z, w, nbins: int, theta_min: float, theta_max: floa
     if rc:
         raise ValueError("oracle_zeta_sphere_pivots: invalid arguments")
     return PivotResult(zt, int(ng.value), int(npairs.value), None, None)
+
+
+def edge_correct_sphere(N, R):
+    """Edge-corrected cosine multipoles c_m of N(phi) / R(phi) on the sphere (oracle_edge_correct_sphere).
+    N, R: [(mmax+1), nb, nb] or [ncat, (mmax+1), nb, nb]."""
+    N = np.ascontiguousarray(N, dtype=np.float64)
+    R = np.ascontiguousarray(R, dtype=np.float64)
+    squeeze = N.ndim == 3
+    if squeeze:
+        N, R = N[None], R[None]
+    out = np.zeros_like(N)
+    rc = _load().oracle_edge_correct_sphere(N.shape[0], N.shape[1] - 1, N.shape[2], _ptr(N), _ptr(R), _ptr(out))
+    if rc:
+        raise ValueError("oracle_edge_correct_sphere: invalid arguments")
+    return out[0] if squeeze else out
 
 
 def zeta_catalog(cat, nbins, rmin, rmax, lmax, **kw) -> Result:

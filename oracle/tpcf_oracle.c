@@ -487,6 +487,76 @@ int oracle_edge_correct(int ncat, int lmax, int nbins, const double *N, const do
     return 0;
 }
 
+/*
+ * Edge correction on the sphere (masked maps). The paper lists edge corrections for regions that
+ * are not the full sky (Features section, citing Slepian & Eisenstein 2015 for the construction);
+ * its 2D counterpart for the multipoles of the position angle, a reading since the paper gives no
+ * formula: per bin pair the triangle-angle densities of the masked field, N(phi), and of the mask,
+ * R(phi), have cosine moments N_m = int N(phi) cos(m phi) dphi (the raw zeta_m) and R_m; writing
+ * zeta(phi) = N(phi) / R(phi) = c_0 + 2 sum_{m>=1} c_m cos(m phi),
+ *     N_m = sum_{m'} eps_m' c_m' int cos(m phi) cos(m' phi) R(phi) dphi,   eps_0 = 1, eps_m' = 2,
+ * truncated at m_max (R_k = 0 above it), solved for c per bin pair; c = N / R_0 when R is
+ * isotropic. The coupling integrals are taken here by the trapezoid rule on 64 equispaced angles
+ * over R(phi) / R_0 = (1 + 2 sum_k R_k / R_0 cos(k phi)) / (2 pi), exact for these trigonometric
+ * polynomials. Arrays [ncat][(mmax+1)][nbins][nbins]; R_0 = 0 gives 0. Returns 0, or 1.
+ */
+int oracle_edge_correct_sphere(int ncat, int mmax, int nbins, const double *N, const double *R, double *zeta)
+{
+    if (ncat < 1 || mmax < 0 || mmax > ORACLE_LMAX_CAP || nbins < 1) return 1;
+    enum { NQ = 64 };
+    const double twopi = 6.283185307179586476925286766559;
+    const int M1 = mmax + 1, nb = nbins;
+    double A[ORACLE_LMAX_CAP + 1][ORACLE_LMAX_CAP + 2], cq[NQ][ORACLE_LMAX_CAP + 1];
+    for (int i = 0; i < NQ; i++)
+        for (int m = 0; m < M1; m++) cq[i][m] = cos(m * (twopi * i / NQ));
+    for (int c = 0; c < ncat; c++)
+        for (int b1 = 0; b1 < nb; b1++)
+            for (int b2 = 0; b2 < nb; b2++) {
+                const size_t base = (size_t)c * M1 * nb * nb + (size_t)b1 * nb + b2;
+#define AT(arr, m) arr[base + (size_t)(m) * nb * nb]
+                const double R0 = AT(R, 0);
+                if (R0 == 0.0) {
+                    for (int m = 0; m < M1; m++) AT(zeta, m) = 0.0;
+                    continue;
+                }
+                double g[NQ];
+                for (int i = 0; i < NQ; i++) {
+                    double t = 1.0;
+                    for (int k = 1; k < M1; k++) t += 2.0 * AT(R, k) / R0 * cq[i][k];
+                    g[i] = t / twopi;
+                }
+                for (int m = 0; m < M1; m++) {
+                    for (int mp = 0; mp < M1; mp++) {
+                        double t = 0.0;
+                        for (int i = 0; i < NQ; i++) t += cq[i][m] * cq[i][mp] * g[i];
+                        A[m][mp] = (mp == 0 ? 1.0 : 2.0) * t * (twopi / NQ);
+                    }
+                    A[m][M1] = AT(N, m) / R0;
+                }
+                for (int k = 0; k < M1; k++) {
+                    int piv = k;
+                    for (int r = k + 1; r < M1; r++)
+                        if (fabs(A[r][k]) > fabs(A[piv][k])) piv = r;
+                    for (int j = 0; j <= M1; j++) {
+                        double t = A[k][j];
+                        A[k][j] = A[piv][j];
+                        A[piv][j] = t;
+                    }
+                    for (int r = k + 1; r < M1; r++) {
+                        double f = A[r][k] / A[k][k];
+                        for (int j = k; j <= M1; j++) A[r][j] -= f * A[k][j];
+                    }
+                }
+                for (int k = M1 - 1; k >= 0; k--) {
+                    double t = A[k][M1];
+                    for (int j = k + 1; j < M1; j++) t -= A[k][j] * AT(zeta, j);
+                    AT(zeta, k) = t / A[k][k];
+                }
+#undef AT
+            }
+    return 0;
+}
+
 /* ---------------------------------------------------------------- projected fields on the sphere */
 
 /*

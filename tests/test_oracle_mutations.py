@@ -51,6 +51,8 @@ MUTANTS = {
                                   "pq[ax * n + G] = sum[ax] / cnt;"),
     "pivots: group weight is the mean": ("pw[G] = W;", "pw[G] = W / (double)cnt;"),
     "pivots: group key ignores y": ("keys[i].gy = q[n + i] / Hq;", "keys[i].gy = 0;"),
+    "sphere edge correction: weight of m' = 0": ("A[m][mp] = (mp == 0 ? 1.0 : 2.0) * t * (twopi / NQ);",
+                                                 "A[m][mp] = 2.0 * t * (twopi / NQ);"),
 }
 
 
@@ -131,6 +133,16 @@ def _pins():
     ref, _, _ = brute.zeta_sphere_triangles(*u, ws, 4, 0.01, 0.3, 5)
     if not np.all(np.isfinite(zs)) or np.max(np.abs(zs - ref)) > 1e-12 * np.max(np.abs(ref)):
         failed.append("sphere triangles")
+    # sphere edge correction: N built from the closed-form coupling is solved back
+    Rs = np.zeros((3, 1, 1))
+    Rs[:, 0, 0] = [1.0, 0.25, -0.1]
+    cs = np.array([0.6, -0.3, 0.2])
+    Ns = np.zeros((3, 1, 1))
+    Rk = lambda k: Rs[k, 0, 0] if k <= 2 else 0.0
+    for m in range(3):
+        Ns[m, 0, 0] = sum((1.0 if mp == 0 else 2.0) * 0.5 * (Rk(m + mp) + Rk(abs(m - mp))) * cs[mp] for mp in range(3))
+    if np.abs(oracle.edge_correct_sphere(Ns, Rs)[:, 0, 0] - cs).max() > 1e-12:
+        failed.append("sphere edge correction")
     # shared pivots: group pivots and zeta against the numpy grouping and Legendre form
     cP = (rng.random((4, 3))[rng.integers(0, 4, 150)] * 40.0 + rng.normal(0, 2.0, (150, 3))) % 40.0
     cw = rng.normal(1.0, 0.4, 150)

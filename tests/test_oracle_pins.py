@@ -538,3 +538,36 @@ def test_sphere_pivots_against_brute_force_and_exact_limit():
     ex = oracle.zeta_sphere(x, y, z, w, 4, 0.0, 0.3, 4)
     assert rp.ngroups == len(x) and rp.npairs == ex.npairs
     assert _rel(rp.zeta, ex.zeta) < 1e-12
+
+
+def test_sphere_edge_correction_closed_forms():
+    """Edge correction of the 2D multipoles: (1) N built from a known c with the closed-form
+    coupling eps_m' (R_{m+m'} + R_{|m-m'|}) / 2 (R_k = 0 above m_max) is solved back; (2) R/R gives
+    (1, 0, ...); (3) isotropic R gives N / R_0; (4) densities R(phi) = 1 + 0.4 cos(phi) and
+    zeta(phi) = 1 + 0.3 cos(2 phi), integrated on a fine grid, give c_0 = 1, c_2 = 0.15."""
+    rng = np.random.default_rng(8)
+    M, nb = 5, 3
+    R = np.zeros((M + 1, nb, nb))
+    R[0] = 1.0 + rng.random((nb, nb))
+    R[1:] = 0.3 * rng.normal(size=(M, nb, nb)) * R[0]
+    c = rng.normal(size=(M + 1, nb, nb))
+    N = np.zeros_like(c)
+    Rk = lambda k: R[k] if k <= M else 0.0
+    for m in range(M + 1):
+        for mp in range(M + 1):
+            N[m] += (1.0 if mp == 0 else 2.0) * 0.5 * (Rk(m + mp) + Rk(abs(m - mp))) * c[mp]
+    out = oracle.edge_correct_sphere(N, R)
+    assert np.abs(out - c).max() < 1e-11 * np.abs(c).max()
+    rr = oracle.edge_correct_sphere(R, R)
+    unit = np.zeros_like(rr)
+    unit[0] = 1.0
+    assert np.abs(rr - unit).max() < 1e-13
+    Ri = np.zeros_like(R)
+    Ri[0] = R[0]
+    np.testing.assert_allclose(oracle.edge_correct_sphere(N, Ri), N / R[0], rtol=1e-13, atol=0)
+    phi = np.linspace(0.0, 2 * np.pi, 4096, endpoint=False)
+    dens_R = 1.0 + 0.4 * np.cos(phi)
+    dens_N = (1.0 + 0.3 * np.cos(2 * phi)) * dens_R
+    mom = lambda f: np.array([np.sum(f * np.cos(m * phi)) * (2 * np.pi / len(phi)) for m in range(5)])
+    c2 = oracle.edge_correct_sphere(mom(dens_N)[:, None, None], mom(dens_R)[:, None, None])[:, 0, 0]
+    np.testing.assert_allclose(c2, [1.0, 0.0, 0.15, 0.0, 0.0], rtol=0, atol=1e-12)
