@@ -173,8 +173,9 @@ int tpcf_set_catalog(tpcf_ctx* ctx, int64_t n, const double* x, const double* y,
  * T_k = ceil(fl(fl(2 sin(theta_k / 2) 2^K / 4)^2)), so pair counts are exact; phi is measured
  * from a tangent basis at the primary's lattice position, which zeta_m does not depend on.
  * Debug a_m (tpcf_debug_alm) has 2 m_max + 1 components per bin: Re a_0, then Re a_m, Im a_m
- * (index 2m - 1, 2m). tpcf_pair_sums reports the angular bins; tpcf_edge_correct (3D coupling)
- * is refused. The call synchronises the context's stream.
+ * (index 2m - 1, 2m). tpcf_pair_sums reports the angular bins; masked maps are corrected with
+ * tpcf_edge_correct_sphere (tpcf_edge_correct, the 3D coupling, is refused). The call
+ * synchronises the context's stream.
  * Errors: TPCF_E_INVALID_ARG (n < 0, n >= 2^31, NULL arrays with n > 0, a non-finite value, a
  * vector that is not a unit vector, rmax > pi when bins are already set), TPCF_E_OUT_OF_MEMORY,
  * TPCF_E_DEVICE.
@@ -259,11 +260,27 @@ int tpcf_pair_sums(tpcf_ctx* ctx, int64_t capacity, int64_t* npairs, double* dd)
  * or R. Device arrays are processed in order on the context's stream; host arrays are copied
  * through the device and the call returns when zeta is written.
  * Errors: TPCF_E_INVALID_ARG (ncat < 1, NULL arrays, unknown memory space), TPCF_E_STATE (bins
- * not set), TPCF_E_UNSUPPORTED (the context holds a catalogue on the sphere),
- * TPCF_E_OUT_OF_MEMORY, TPCF_E_DEVICE.
+ * not set), TPCF_E_UNSUPPORTED (the context holds a catalogue on the sphere: see
+ * tpcf_edge_correct_sphere), TPCF_E_OUT_OF_MEMORY, TPCF_E_DEVICE.
  */
 int tpcf_edge_correct(tpcf_ctx* ctx, int ncat, const double* N, const double* R, double* zeta,
                       int memspace);
+
+/*
+ * Edge correction on the sphere, for maps that do not cover the full sky (the paper's Features
+ * section lists edge corrections for such regions). The same construction as tpcf_edge_correct
+ * applied to the 2D multipoles of the position angle: N holds zeta_m of the masked map values and
+ * R those of the mask (unit weights on the observed pixels), both [ncat][(m_max+1)][nbins][nbins]
+ * with the current bins and m_max. Per bin pair, zeta receives the cosine coefficients c_m of
+ * N(phi) / R(phi) = c_0 + 2 sum_{m>=1} c_m cos(m phi), truncated at m_max: the solution of
+ *     N_m / R_0 = sum_{m'} eps_m' (R_{m+m'} + R_{|m-m'|}) / (2 R_0) c_m',  eps_0 = 1, eps_m' = 2,
+ * with R_k = 0 above m_max; for a full-sky (isotropic) mask c = N / R_0. Bin pairs with R_0 = 0
+ * give 0. Memory spaces, aliasing and synchronisation as for tpcf_edge_correct.
+ * Errors: TPCF_E_INVALID_ARG (ncat < 1, NULL arrays, unknown memory space), TPCF_E_STATE (bins
+ * not set), TPCF_E_OUT_OF_MEMORY, TPCF_E_DEVICE.
+ */
+int tpcf_edge_correct_sphere(tpcf_ctx* ctx, int ncat, const double* N, const double* R, double* zeta,
+                             int memspace);
 
 /*
  * Shared pivots, an approximation with a speed knob (the paper's Implementation section: spatially

@@ -32,7 +32,7 @@ EXPORTS = [
     "tpcf_set_tuning", "tpcf_set_catalog", "tpcf_compute_zeta", "tpcf_compute_zeta_range",
     "tpcf_compute_batch", "tpcf_debug_pair_counts", "tpcf_debug_alm", "tpcf_set_debug",
     "tpcf_get_stats", "tpcf_last_error", "tpcf_autotune", "tpcf_pair_sums", "tpcf_edge_correct",
-    "tpcf_set_sphere_catalog", "tpcf_set_pivot_cell",
+    "tpcf_set_sphere_catalog", "tpcf_set_pivot_cell", "tpcf_edge_correct_sphere",
 ]
 
 
@@ -106,6 +106,7 @@ def _load() -> ctypes.CDLL:
         "tpcf_edge_correct": ([vp, i, vp, vp, vp, i], i),
         "tpcf_set_sphere_catalog": ([vp, i64, vp, vp, vp, vp, i], i),
         "tpcf_set_pivot_cell": ([vp, d], i),
+        "tpcf_edge_correct_sphere": ([vp, i, vp, vp, vp, i], i),
     }
     missing = [name for name in sig if not hasattr(lib, name)]
     if missing:
@@ -299,9 +300,11 @@ class Context:
         return npairs, dd
 
     def edge_correct(self, N, R):
-        """Edge-corrected multipoles N(mu)/R(mu) per bin pair (see tpcf_edge_correct). N, R:
+        """Edge-corrected multipoles N(mu)/R(mu) per bin pair (see tpcf_edge_correct; on the
+        sphere tpcf_edge_correct_sphere, the cosine coefficients of N(phi)/R(phi)). N, R:
         [(lmax+1), nbins, nbins] or [ncat, (lmax+1), nbins, nbins], numpy (host) or torch
         CUDA tensors (device); the result has the same shape and kind."""
+        fn = _lib.tpcf_edge_correct_sphere if self.sphere else _lib.tpcf_edge_correct
         if _is_torch(N):
             import torch
             Nt = N.contiguous().to(torch.float64)
@@ -310,16 +313,15 @@ class Context:
                 raise ValueError("N and R must have the same shape")
             out = torch.empty_like(Nt)
             ncat = 1 if Nt.dim() == 3 else Nt.shape[0]
-            self._check(_lib.tpcf_edge_correct(self._h, ncat, ctypes.c_void_p(Nt.data_ptr()),
-                                               ctypes.c_void_p(Rt.data_ptr()),
-                                               ctypes.c_void_p(out.data_ptr()), MEM_DEVICE))
+            self._check(fn(self._h, ncat, ctypes.c_void_p(Nt.data_ptr()), ctypes.c_void_p(Rt.data_ptr()),
+                           ctypes.c_void_p(out.data_ptr()), MEM_DEVICE))
             return out
         Na, Ra = _host_f64(N), _host_f64(R)
         if Na.shape != Ra.shape:
             raise ValueError("N and R must have the same shape")
         out = np.zeros_like(Na)
         ncat = 1 if Na.ndim == 3 else Na.shape[0]
-        self._check(_lib.tpcf_edge_correct(self._h, ncat, _ptr_np(Na), _ptr_np(Ra), _ptr_np(out), MEM_HOST))
+        self._check(fn(self._h, ncat, _ptr_np(Na), _ptr_np(Ra), _ptr_np(out), MEM_HOST))
         return out
 
     # -- debug and statistics

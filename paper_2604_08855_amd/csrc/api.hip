@@ -31,6 +31,8 @@ size_t sweep_tile_bytes_per_wave(int lmax, int nb, bool f64, bool sphere);
 std::vector<double> threej_squared_table(int lmax);
 hipError_t launch_edge_correct(int ncat, int lmax, int nb, const double* N, const double* R, const double* t3,
                                double* out, hipStream_t s);
+hipError_t launch_edge_correct_sphere(int ncat, int mmax, int nb, const double* N, const double* R, double* out,
+                                      hipStream_t s);
 size_t pivot_sort_bytes(uint32_t n);
 hipError_t build_pivots(const uint4* rec, const double* w64, uint32_t n, int sh, uint64_t Hq,
                         unsigned long long* key_a, unsigned long long* key_b, uint32_t* idx_a, uint32_t* idx_b,
@@ -1082,29 +1084,43 @@ int tpcf_pair_sums(tpcf_ctx* c, int64_t capacity, int64_t* npairs, double* dd) {
   return TPCF_OK;
 }
 
-int tpcf_edge_correct(tpcf_ctx* c, int ncat, const double* N, const double* R, double* zeta, int memspace) {
+}  // extern "C"
+
+namespace {
+
+// Shared body of the two edge corrections: argument checks, host staging, the launch.
+int edge_correct_impl(tpcf_ctx* c, int ncat, const double* N, const double* R, double* zeta, int memspace,
+                      bool sphere) {
   if (!c) return TPCF_E_INVALID_ARG;
   if (ncat < 1) return fail(c, TPCF_E_INVALID_ARG, "ncat must be >= 1");
   if (!N || !R || !zeta) return fail(c, TPCF_E_INVALID_ARG, "NULL array");
   if (memspace != TPCF_MEM_HOST && memspace != TPCF_MEM_DEVICE)
     return fail(c, TPCF_E_INVALID_ARG, "unknown memory space");
   if (!c->bins_set) return fail(c, TPCF_E_STATE, "set_bins has not been called");
-  if (is_sphere(c))
-    return fail(c, TPCF_E_UNSUPPORTED, "the edge correction couples 3D multipoles; the context holds a sphere catalogue");
+  if (!sphere && is_sphere(c))
+    return fail(c, TPCF_E_UNSUPPORTED,
+                "the 3D edge correction couples spherical-harmonic multipoles; use tpcf_edge_correct_sphere");
   int rc;
   if ((rc = ensure_device(c))) return rc;
   const int L = c->lmax, nb = c->nbins;
   const size_t cnt = (size_t)ncat * (L + 1) * nb * nb;
-  if (c->edge_lmax != L) {
-    const std::vector<double> t = threej_squared_table(L);
-    if ((rc = ensure(c, c->edge_tab, t.size() * 8, "3j table"))) return rc;
-    HIP_TRY(c, hipMemcpyAsync(c->edge_tab.p, t.data(), t.size() * 8, hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
-    c->edge_lmax = L;
+  const double* t3 = nullptr;
+  if (!sphere) {
+    if (c->edge_lmax != L) {
+      const std::vector<double> t = threej_squared_table(L);
+      if ((rc = ensure(c, c->edge_tab, t.size() * 8, "3j table"))) return rc;
+      HIP_TRY(c, hipMemcpyAsync(c->edge_tab.p, t.data(), t.size() * 8, hipMemcpyHostToDevice, c->stream));
+      HIP_TRY(c, hipStreamSynchronize(c->stream));
+      c->edge_lmax = L;
+    }
+    t3 = (const double*)c->edge_tab.p;
   }
-  const double* t3 = (const double*)c->edge_tab.p;
+  auto launch = [&](const double* n, const double* r, double* z) {
+    return sphere ? launch_edge_correct_sphere(ncat, L, nb, n, r, z, c->stream)
+                  : launch_edge_correct(ncat, L, nb, n, r, t3, z, c->stream);
+  };
   if (memspace == TPCF_MEM_DEVICE) {
-    HIP_TRY(c, launch_edge_correct(ncat, L, nb, N, R, t3, zeta, c->stream));
+    HIP_TRY(c, launch(N, R, zeta));
   } else {
     if ((rc = ensure(c, c->edge_io, cnt * 3 * 8, "edge correction staging"))) return rc;
     double* dN = (double*)c->edge_io.p;
@@ -1112,12 +1128,24 @@ int tpcf_edge_correct(tpcf_ctx* c, int ncat, const double* N, const double* R, d
     double* dZ = dR + cnt;
     HIP_TRY(c, hipMemcpyAsync(dN, N, cnt * 8, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(dR, R, cnt * 8, hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(c, launch_edge_correct(ncat, L, nb, dN, dR, t3, dZ, c->stream));
+    HIP_TRY(c, launch(dN, dR, dZ));
     HIP_TRY(c, hipMemcpyAsync(zeta, dZ, cnt * 8, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
   }
   c->err.clear();
   return TPCF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tpcf_edge_correct(tpcf_ctx* c, int ncat, const double* N, const double* R, double* zeta, int memspace) {
+  return edge_correct_impl(c, ncat, N, R, zeta, memspace, false);
+}
+
+int tpcf_edge_correct_sphere(tpcf_ctx* c, int ncat, const double* N, const double* R, double* zeta, int memspace) {
+  return edge_correct_impl(c, ncat, N, R, zeta, memspace, true);
 }
 
 int tpcf_set_pivot_cell(tpcf_ctx* c, double side) {
