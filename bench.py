@@ -35,7 +35,10 @@ NB, RMIN, RMAX, LMAX, BOX, N = 20, 10.0, 200.0, 10, 1000.0, 1_000_000
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "sweep_kernel_lognormal1e6_hbm_traffic.md")
 SPHERE_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "sweep_kernel_sphere_nside1024_hbm_traffic.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2604_08855_amd", "csrc", f) for f in ("sweep.hip", "tpcf_internal.h")]
-PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32, published
+PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32, published (counts packed FP32 instructions)
+# The same chip without packed FP32 (which the library's build leaves off): 256 CUs x 4 SIMDs x
+# 16 lanes x 2 flops per FMA x 2.4 GHz.
+PEAK_FP32_UNPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 F_PAIR = 4 * (LMAX + 1) ** 2  # algorithmic flops per in-range pair (2 to generate + 2 to add)
 F_PRIM = 2 * NB * NB * (LMAX + 1) ** 2  # algorithmic flops per primary for the contraction
 
@@ -248,6 +251,8 @@ def run_batch(args):
             "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS,
+            "peak_without_packed_fp32": PEAK_FP32_UNPACKED_TFLOPS,
+            "frac_without_packed_fp32": achieved / PEAK_FP32_UNPACKED_TFLOPS,
             "traffic": None,
             "flops_per_launch": flops,
         },
@@ -343,6 +348,8 @@ def run_dmr(args):
                                                     for k, v in res.items()},
         "roofline": {"bound": "alu", "kernel": "sweep_kernel<10,false,false>", "achieved": achieved,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
+                     "peak_without_packed_fp32": PEAK_FP32_UNPACKED_TFLOPS,
+                     "frac_without_packed_fp32": achieved / PEAK_FP32_UNPACKED_TFLOPS,
                      "traffic": None, "flops_per_launch": flops},
     }
     print(json.dumps(out), flush=True)
@@ -655,6 +662,8 @@ def run_sphere(args):
         "masked_map_edge_correction": masked,
         "roofline": {"bound": "alu", "kernel": "sweep_kernel<8,false,true>", "achieved": achieved,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
+                     "peak_without_packed_fp32": PEAK_FP32_UNPACKED_TFLOPS,
+                     "frac_without_packed_fp32": achieved / PEAK_FP32_UNPACKED_TFLOPS,
                      "traffic": traffic["bytes"] if traffic else None, "traffic_detail": traffic,
                      "flops_per_launch": flops, "flops_per_pair": f_pair, "flops_per_primary": f_prim,
                      "sweep_ms": mx["sweep_ms"]},
@@ -779,6 +788,8 @@ def main():
             "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS,
+            "peak_without_packed_fp32": PEAK_FP32_UNPACKED_TFLOPS,
+            "frac_without_packed_fp32": achieved / PEAK_FP32_UNPACKED_TFLOPS,
             "traffic": traffic["bytes"] if traffic else None,
             "traffic_detail": traffic,
             "flops_per_launch": flops,
