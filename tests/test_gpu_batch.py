@@ -126,3 +126,39 @@ def test_batch_equals_single_runs(tpcf):
             assert not zs.any() and not zb[k].any()
         else:
             assert rel_err_per_l(zb[k], zs).max() < 1e-12
+
+
+def test_batch_at_full_mock_sizes(tpcf):
+    """The batch recipe at full size for its first 6 mocks (seeds 0..5, sizes from the C4 size
+    stream: log-uniform in [2e5, 2e6]), L = 1000, 20 bins [10, 200), l_max = 10, mixed, in the
+    bench's configuration (graph on a stream): each batch slice against a single run of the same
+    mock (the single path is checked against the oracle at this size elsewhere), and the batch's
+    pair total against the single runs' totals."""
+    import torch
+
+    sizes = catalogs.mock_sizes(256, 2e5, 2e6, 1000)[:6]
+    cats = [catalogs.lognormal(int(n), 1000.0, i, grid=256) for i, n in enumerate(sizes)]
+    say(f"mock sizes {list(map(int, sizes))}")
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    cat_all = [np.concatenate([getattr(c, a) for c in cats]) for a in ("x", "y", "z")]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        ctx = tpcf.Context(0, stream)
+        ctx.set_bins(20, 10.0, 200.0, 10)
+        ctx.set_precision("mixed")
+        dev = [torch.from_numpy(a).cuda() for a in cat_all]
+        zb = ctx.compute_batch(off, *dev, None, 1000.0, True).cpu().numpy()
+        pairs_b = ctx.stats()["n_pairs"]
+    torch.cuda.synchronize()
+    total = 0
+    for k, c in enumerate(cats):
+        s = tpcf.Context(0)
+        s.set_bins(20, 10.0, 200.0, 10)
+        s.set_precision("mixed")
+        s.set_catalog(c.x, c.y, c.z, None, box=1000.0, periodic=True)
+        zs = s.compute_zeta()
+        total += s.stats()["n_pairs"]
+        err = rel_err_per_l(zb[k], zs).max()
+        say(f"mock {k}: n={c.n} batch vs single {err:.2e}")
+        assert err < 1e-6
+    assert pairs_b == total
