@@ -184,6 +184,21 @@ int tpcf_set_sphere_catalog(tpcf_ctx* ctx, int64_t n, const double* x, const dou
                             const double* z, const double* w, int memspace);
 
 /*
+ * ncat independent maps on the sphere in one persistent launch (the batch form of
+ * tpcf_set_sphere_catalog + tpcf_compute_zeta, for many simulated maps): map c holds the unit
+ * vectors [offsets[c], offsets[c+1]) of the concatenated FP64 arrays x, y, z and values w (w may
+ * be NULL); offsets is a host array; zeta receives [ncat][(m_max+1)][nbins][nbins] doubles in
+ * `memspace`. Maps never interact. The batch replaces the context's catalogue; graph capture and
+ * replay as for tpcf_compute_batch.
+ * Errors: TPCF_E_INVALID_ARG (ncat < 1, offsets not non-decreasing from 0, total points >= 2^31,
+ * NULL arrays, a vector that is not a unit vector, rmax > pi), TPCF_E_STATE (bins not set),
+ * TPCF_E_UNSUPPORTED (shared pivots set), TPCF_E_OUT_OF_MEMORY, TPCF_E_DEVICE.
+ */
+int tpcf_compute_sphere_batch(tpcf_ctx* ctx, int ncat, const int64_t* offsets, const double* x,
+                              const double* y, const double* z, const double* w, double* zeta,
+                              int memspace);
+
+/*
  * zeta for the catalogue set by tpcf_set_catalog: every point is a primary and a secondary.
  * zeta has (lmax+1)*nbins*nbins doubles in memory space `memspace`.
  * Errors: TPCF_E_STATE (bins or catalogue missing), TPCF_E_INVALID_ARG (periodic with

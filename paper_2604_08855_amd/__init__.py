@@ -32,7 +32,7 @@ EXPORTS = [
     "tpcf_set_tuning", "tpcf_set_catalog", "tpcf_compute_zeta", "tpcf_compute_zeta_range",
     "tpcf_compute_batch", "tpcf_debug_pair_counts", "tpcf_debug_alm", "tpcf_set_debug",
     "tpcf_get_stats", "tpcf_last_error", "tpcf_autotune", "tpcf_pair_sums", "tpcf_edge_correct",
-    "tpcf_set_sphere_catalog", "tpcf_set_pivot_cell", "tpcf_edge_correct_sphere",
+    "tpcf_set_sphere_catalog", "tpcf_set_pivot_cell", "tpcf_edge_correct_sphere", "tpcf_compute_sphere_batch",
 ]
 
 
@@ -107,6 +107,7 @@ def _load() -> ctypes.CDLL:
         "tpcf_set_sphere_catalog": ([vp, i64, vp, vp, vp, vp, i], i),
         "tpcf_set_pivot_cell": ([vp, d], i),
         "tpcf_edge_correct_sphere": ([vp, i, vp, vp, vp, i], i),
+        "tpcf_compute_sphere_batch": ([vp, i, vp, vp, vp, vp, vp, vp, i], i),
     }
     missing = [name for name in sig if not hasattr(lib, name)]
     if missing:
@@ -288,6 +289,19 @@ class Context:
         self._check(_lib.tpcf_compute_batch(self._h, ncat, _ptr_np(offsets), *ptrs, _ptr_np(box),
                                             _ptr_np(per), p, mem))
         self.n, self.ncat, self.sphere = int(offsets[-1]), ncat, False
+        return out
+
+    def compute_sphere_batch(self, offsets, x, y, z, w=None, device_output: bool = False):
+        """ncat independent maps on the sphere in one launch (see tpcf_compute_sphere_batch):
+        zeta [ncat, (m_max+1), nbins, nbins]."""
+        offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+        ncat = len(offsets) - 1
+        ptrs, mem, keep = self._arrays(x, y, z, w)
+        out, p, omem = self._out(device_output or mem == MEM_DEVICE, (ncat, self.lmax + 1, self.nbins, self.nbins))
+        if omem != mem:
+            raise ValueError("batch inputs and output must be in the same memory space")
+        self._check(_lib.tpcf_compute_sphere_batch(self._h, ncat, _ptr_np(offsets), *ptrs, p, mem))
+        self.n, self.ncat, self.sphere = int(offsets[-1]), ncat, True
         return out
 
     def pair_sums(self):

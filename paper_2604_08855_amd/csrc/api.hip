@@ -1254,6 +1254,34 @@ int tpcf_compute_batch(tpcf_ctx* c, int ncat, const int64_t* offsets, const doub
   return rc;
 }
 
+int tpcf_compute_sphere_batch(tpcf_ctx* c, int ncat, const int64_t* offsets, const double* x, const double* y,
+                              const double* z, const double* w, double* zeta, int memspace) {
+  if (!c) return TPCF_E_INVALID_ARG;
+  if (ncat < 1 || !offsets) return fail(c, TPCF_E_INVALID_ARG, "invalid batch description");
+  if (!c->bins_set) return fail(c, TPCF_E_STATE, "set_bins has not been called");
+  if (!(c->rmax <= kPi)) return fail(c, TPCF_E_INVALID_ARG, "angular bins on the sphere need theta_max <= pi");
+  if (c->pivot_h != 0.0) return fail(c, TPCF_E_UNSUPPORTED, "shared pivots are not available for batches");
+  if (offsets[0] != 0) return fail(c, TPCF_E_INVALID_ARG, "offsets[0] must be 0");
+  std::vector<HostCat> cats(ncat);
+  for (int k = 0; k < ncat; ++k) {
+    if (offsets[k + 1] < offsets[k]) return fail(c, TPCF_E_INVALID_ARG, "offsets must be non-decreasing");
+    cats[k].first = offsets[k];
+    cats[k].n = offsets[k + 1] - offsets[k];
+    cats[k].box = 4.0;
+    cats[k].periodic = 0;
+    cats[k].sphere = 1;
+  }
+  const int64_t ntot = offsets[ncat];
+  if (ntot >= kMaxPoints) return fail(c, TPCF_E_INVALID_ARG, "total points must be < 2^31");
+  if (ntot > 0 && (!x || !y || !z)) return fail(c, TPCF_E_INVALID_ARG, "NULL position array");
+  if (!zeta) return fail(c, TPCF_E_INVALID_ARG, "zeta is NULL");
+  int rc = stage(c, cats, ntot, x, y, z, w, memspace);
+  if (rc) return rc;
+  rc = compute(c, 0, c->ntot, zeta, memspace, true);
+  if (!rc) c->err.clear();
+  return rc;
+}
+
 int tpcf_debug_pair_counts(tpcf_ctx* c, int64_t* counts) {
   if (!c || !counts) return TPCF_E_INVALID_ARG;
   if (!c->dbg_valid) return fail(c, TPCF_E_STATE, "no compute call with debug output enabled");
