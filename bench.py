@@ -159,6 +159,90 @@ def _mock(args):
     return c.x, c.y, c.z
 
 
+def _map_values(args):
+    """Values of one batch map (worker process, before the parent touches the GPU)."""
+    import catalogs
+
+    seed, nside = args
+    x, y, z = catalogs.healpix_centres(nside)
+    return catalogs.sphere_field(x, y, z, seed)
+
+
+def run_sphere_batch(args):
+    """Batch of maps: --mocks full-sky HEALPix nside-512 maps (3,145,728 pixels each) with map
+    values from seeds 0..M-1, 20 bins [10, 200) arcmin, m_max = 8, mixed, one persistent launch
+    per call, captured as a HIP graph on a non-default stream and replayed."""
+    import multiprocessing as mp
+
+    import catalogs
+
+    nside, nb, mmax = 512, 20, 8
+    arcmin = math.pi / (180.0 * 60.0)
+    tmin, tmax = 10 * arcmin, 200 * arcmin
+    M = args.mocks
+    t0 = time.time()
+    x, y, z = catalogs.healpix_centres(nside)
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    with mp.get_context("fork").Pool(workers) as pool:
+        vals = pool.map(_map_values, [(i, nside) for i in range(M)], chunksize=1)
+    n = len(x)
+    log(f"[bench] {M} maps of {n} pixels generated in {time.time() - t0:.1f}s on {workers} processes")
+    off = np.arange(M + 1, dtype=np.int64) * n
+
+    import torch
+
+    import paper_2604_08855_amd as tpcf
+
+    dev = [torch.from_numpy(np.tile(a, M)).cuda() for a in (x, y, z)] + \
+          [torch.from_numpy(np.concatenate(vals)).cuda()]
+    torch.cuda.synchronize()
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        ctx = tpcf.Context(0, stream)
+        ctx.set_bins(nb, tmin, tmax, mmax)
+        ctx.set_precision("mixed")
+        ctx.set_sphere_catalog(*[t[:n] for t in dev])
+        tuning = None if args.no_autotune else ctx.autotune()
+        log(f"[bench] sphere batch autotune on map 0: {tuning}")
+        for i in range(args.warmup):
+            ctx.compute_sphere_batch(off, *dev, device_output=True)
+            stream.synchronize()
+        times = []
+        for i in range(args.steps):
+            t1 = time.perf_counter()
+            zb = ctx.compute_sphere_batch(off, *dev, device_output=True)
+            stream.synchronize()
+            times.append(time.perf_counter() - t1)
+            log(f"[bench] sphere batch step {i + 1}/{args.steps}: {times[-1]:.2f}s")
+        st = ctx.stats()
+        zb = zb.cpu().numpy()
+        # the first and last map, each run alone, against their batch slices
+        check = {}
+        for k in (0, M - 1):
+            ctx.set_sphere_catalog(*[t[off[k]:off[k + 1]] for t in dev])
+            z1 = ctx.compute_zeta(device_output=True).cpu().numpy()
+            check[f"map{k}"] = float(np.abs(z1 - zb[k]).max() / np.abs(z1).max())
+        ctx.close()
+    ms = float(np.mean(times)) * 1000.0
+    pairs = st["n_pairs"]
+    f_pair, f_prim = 4 * (2 * mmax + 1), 2 * nb * nb * (2 * mmax + 1)
+    achieved = (pairs * f_pair + M * n * f_prim) / (ms / 1000.0) / 1e12
+    out = {
+        "metric": "primary-secondary pairs/sec (m_max=8, 20 angular bins), mixed, batch of full-sky maps",
+        "value": pairs / (ms / 1000.0), "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{M} HEALPix nside {nside} maps (seeds 0..{M - 1}), log-normal map values, "
+                               "20 bins [10,200) arcmin, m_max=8, mixed, one graph-replayed launch",
+                   "maps": M, "n_points": M * n, "pairs_per_step": pairs, "tuning": tuning},
+        "batch_slice_vs_single_run_rel_err": check,
+        "roofline": {"bound": "alu", "kernel": "sweep_kernel<8,false,true>", "achieved": achieved,
+                     "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
+                     "traffic": None},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def run_batch(args):
     """Batch form: independent log-normal mocks (seeds 0..M-1, sizes log-uniform in [2e5, 2e6]
     from seed 1000), L = 1000 periodic, unit weights, 20 bins [10, 200), l_max = 10, mixed, one
@@ -695,11 +779,12 @@ def main():
                                                  "instead of the autotuner (profiling runs)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (HBM counter calibration)")
-    ap.add_argument("--workload", choices=["single", "batch", "dmr", "sphere", "pivots"], default="single",
+    ap.add_argument("--workload", choices=["single", "batch", "dmr", "sphere", "sphere-batch", "pivots"],
+                    default="single",
                     help="single: the 1e6-point catalogue (default); batch: the mock batch form; "
                          "dmr: 4e6 data + 1.6e7 randoms, non-periodic; sphere: a full-sky HEALPix "
-                         "nside 1024 map with angular bins; pivots: shared pivots (approximate) "
-                         "on the main catalogue")
+                         "nside 1024 map with angular bins; sphere-batch: --mocks nside-512 maps in "
+                         "one launch; pivots: shared pivots (approximate) on the main catalogue")
     ap.add_argument("--mocks", type=int, default=256, help="batch form: number of mocks")
     ap.add_argument("--nside", type=int, default=1024, help="sphere form: HEALPix resolution of the map")
     ap.add_argument("--chunks", type=int, default=16, help="sphere form above nside 1024: primary ranges")
@@ -724,6 +809,9 @@ def main():
         return
     if args.workload == "pivots":
         run_pivots(args)
+        return
+    if args.workload == "sphere-batch":
+        run_sphere_batch(args)
         return
 
     import torch

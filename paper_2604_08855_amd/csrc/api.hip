@@ -286,7 +286,7 @@ typedef unsigned __int128 u128;
 // T_k = ceil(fl(fl(2 sin(theta_k / 2) 2^K / 4)^2)). The grid side follows the surface density
 // (a plane through a cubic grid cuts 1.5 / cs^2 cells per unit area on average, so cells on the
 // sphere hold about n cs^2 / (6 pi) points).
-void configure_sphere(const tpcf_ctx* c, const HostCat& h, CatDesc& d) {
+void configure_sphere(const tpcf_ctx* c, const HostCat& h, CatDesc& d, int max_nc) {
   const int nb = c->nbins;
   const double dth = (c->rmax - c->rmin) / nb;
   const double cmax = 2.0 * sin(0.5 * c->rmax);
@@ -303,7 +303,7 @@ void configure_sphere(const tpcf_ctx* c, const HostCat& h, CatDesc& d) {
   }
   int ncx = 1;
   if (h.n > 0) ncx = (int)floor(4.0 / sqrt(6.0 * kPi * c->ppc / (double)h.n));
-  ncx = std::max(1, std::min(ncx, 512));
+  ncx = std::max(1, std::min(ncx, max_nc));
   d.nc = ncx;
   const double span = ldexp(1.0, d.K);
   const double margin = ldexp(1.0, d.K - 14);
@@ -354,7 +354,10 @@ int configure_grid(tpcf_ctx* c) {
     d.periodic = h.periodic;
     d.box = h.box;
     if (h.sphere) {
-      configure_sphere(c, h, d);
+      // the dense cell table of a sphere's cube grows as nc^3: at most 512 per axis, and at most
+      // 2^30 cells over all the maps of a batch
+      const int max_nc = std::max(16, std::min(512, (int)floor(cbrt(1073741824.0 / (double)c->cats.size()))));
+      configure_sphere(c, h, d, max_nc);
       d.cell_base = (uint32_t)cells;
       cells += (uint64_t)d.nc * d.nc * d.nc;
       if (cells >= ((uint64_t)1 << 31)) return fail(c, TPCF_E_UNSUPPORTED, "too many grid cells");
