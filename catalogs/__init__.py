@@ -202,7 +202,10 @@ def healpix_centres(nside: int):
     4 nside pixels at phi = (pi / (2 nside)) (j - s/2), s = (i - nside + 1) mod 2, j = 1..4 nside.
     """
     ns = int(nside)
-    zs, phis = [], []
+    npix = 12 * ns * ns
+    out = [np.empty(npix) for _ in range(3)]
+    at = 0
+    # ring by ring into preallocated outputs: the peak memory stays at the three outputs
     for i in range(1, 4 * ns):
         if i < ns or i > 3 * ns:
             k = i if i < ns else 4 * ns - i
@@ -216,15 +219,18 @@ def healpix_centres(nside: int):
             sft = (i - ns + 1) % 2
             j = np.arange(1, 4 * ns + 1, dtype=np.float64)
             phi = (np.pi / (2.0 * ns)) * (j - 0.5 * sft)
-        zs.append(np.full(phi.shape, z))
-        phis.append(phi)
-    z = np.concatenate(zs)
-    phi = np.concatenate(phis)
-    st = np.sqrt(np.maximum(0.0, (1.0 - z) * (1.0 + z)))
-    x, y = st * np.cos(phi), st * np.sin(phi)
-    # unit length to rounding: renormalise so |v|^2 = 1 within a few ulp
-    r = np.sqrt(x * x + y * y + z * z)
-    return (np.ascontiguousarray(x / r), np.ascontiguousarray(y / r), np.ascontiguousarray(z / r))
+        zr = np.full(phi.shape, z)
+        st = np.sqrt(np.maximum(0.0, (1.0 - zr) * (1.0 + zr)))
+        x, y = st * np.cos(phi), st * np.sin(phi)
+        # unit length to rounding: renormalise so |v|^2 = 1 within a few ulp
+        r = np.sqrt(x * x + y * y + zr * zr)
+        m = len(phi)
+        out[0][at:at + m] = x / r
+        out[1][at:at + m] = y / r
+        out[2][at:at + m] = zr / r
+        at += m
+    assert at == npix
+    return tuple(out)
 
 
 def sphere_field_sampler(seed: int, grid: int = 256, slope: float = -1.5, sigma: float = 0.5):

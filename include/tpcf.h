@@ -123,6 +123,16 @@ int tpcf_set_precision(tpcf_ctx* ctx, int precision);
 int tpcf_set_tuning(tpcf_ctx* ctx, double points_per_cell, int waves_per_cu, int scratch_blocks);
 
 /*
+ * Optional: phase-aligned stencil sweeps (a performance setting; results agree up to the rounding
+ * of a different summation order, pair counts are identical). Each wave takes the stencil rows of
+ * its primary in a rotated order that starts where the waves in flight currently are, so that they
+ * read the same records at about the same time and share them through L2. mode -1 (default):
+ * on when the expected neighbourhood of one primary exceeds 1 MiB of records; 0: off; 1: on.
+ * Takes effect at the next compute call. Errors: TPCF_E_INVALID_ARG for another mode.
+ */
+int tpcf_set_phase_aligned(tpcf_ctx* ctx, int mode);
+
+/*
  * Autotuner for the persistent sweep. On the catalogue(s) staged by the last tpcf_set_catalog,
  * tpcf_set_sphere_catalog or tpcf_compute_batch call, with the current bins and precision, it times
  * the sweep over a sample of primaries (a fraction sample_fraction of all, taken as up to 16 evenly

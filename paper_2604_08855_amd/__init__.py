@@ -33,6 +33,7 @@ EXPORTS = [
     "tpcf_compute_batch", "tpcf_debug_pair_counts", "tpcf_debug_alm", "tpcf_set_debug",
     "tpcf_get_stats", "tpcf_last_error", "tpcf_autotune", "tpcf_pair_sums", "tpcf_edge_correct",
     "tpcf_set_sphere_catalog", "tpcf_set_pivot_cell", "tpcf_edge_correct_sphere", "tpcf_compute_sphere_batch",
+    "tpcf_set_phase_aligned",
 ]
 
 
@@ -92,6 +93,7 @@ def _load() -> ctypes.CDLL:
         "tpcf_set_bins": ([vp, i, d, d, i], i),
         "tpcf_set_precision": ([vp, i], i),
         "tpcf_set_tuning": ([vp, d, i, i], i),
+        "tpcf_set_phase_aligned": ([vp, i], i),
         "tpcf_set_catalog": ([vp, i64, vp, vp, vp, vp, d, i, i], i),
         "tpcf_compute_zeta": ([vp, vp, i], i),
         "tpcf_compute_zeta_range": ([vp, i64, i64, vp, i], i),
@@ -202,6 +204,11 @@ class Context:
     def set_tuning(self, points_per_cell: float = 0.0, waves_per_cu: int = 0, scratch_blocks: int = 0):
         self._check(_lib.tpcf_set_tuning(self._h, float(points_per_cell), int(waves_per_cu),
                                          int(scratch_blocks)))
+
+    def set_phase_aligned(self, mode: int = -1):
+        """Phase-aligned stencil sweeps: -1 by neighbourhood size (default), 0 off, 1 on
+        (see tpcf_set_phase_aligned)."""
+        self._check(_lib.tpcf_set_phase_aligned(self._h, int(mode)))
 
     def autotune(self, sample_fraction: float = 0.0) -> dict:
         """Times the sweep on a sample of primaries of the staged catalogue(s) for several grid

@@ -79,6 +79,7 @@ struct tpcf_ctx {
   double ppc = 8.0;
   int waves_per_cu = 8;
   int scratch_blocks = 1024;
+  int phase_mode = -1;  // phase-aligned stencil sweeps: -1 by neighbourhood size, 0 off, 1 on
   bool debug = false;
 
   // staged input (device FP64 copies, concatenated catalogues)
@@ -591,6 +592,29 @@ void mark_grid(tpcf_ctx* c) {
   c->grid_nb = c->nbins;
 }
 
+// Phase-aligned stencil sweeps. A wave reads every record within reach of its primary; the waves
+// in flight hold nearby primaries (tasks are taken in cell order) and so read nearly the same
+// records, but each from its own starting point, so together they touch the whole neighbourhood
+// at once. Once that exceeds an XCD's 4 MiB L2 the records come from the Infinity Cache or HBM.
+// Aligned, each wave starts at the point of its stencil that matches its ticket's phase among the
+// waves in flight, which keeps them all at about the same rows at the same time. On by default
+// when the expected neighbourhood of one primary (records of 16 bytes) exceeds 1 MiB.
+int phase_aligned(const tpcf_ctx* c) {
+  if (c->phase_mode >= 0) return c->phase_mode;
+  double most = 0.0;
+  for (const HostCat& h : c->cats) {
+    double nbr;
+    if (h.sphere) {
+      nbr = (double)h.n * 0.5 * (1.0 - cos(std::min(c->rmax, kPi)));
+    } else {
+      const double r = c->rmax;
+      nbr = (double)h.n * (4.0 / 3.0) * kPi * r * r * r / (h.box * h.box * h.box);
+    }
+    most = std::max(most, std::min(nbr, (double)h.n));
+  }
+  return most * 16.0 > 1048576.0 ? 1 : 0;
+}
+
 // Host part of the sweep: buffers, normalisation constants and the kernel arguments.
 int prepare_sweep(tpcf_ctx* c, const uint32_t* tasks_d, uint32_t ntask, SweepArgs& a, int& waves) {
   const bool f64 = c->precision == TPCF_PREC_FP64;
@@ -662,6 +686,7 @@ int prepare_sweep(tpcf_ctx* c, const uint32_t* tasks_d, uint32_t ntask, SweepArg
   a.conv_idx = (const int16_t*)c->conv_idx.p;
   a.conv_coef32 = (const float*)c->conv32.p;
   a.conv_coef64 = (const double*)c->conv64.p;
+  a.phase_rows = phase_aligned(c);
   return TPCF_OK;
 }
 
@@ -970,6 +995,14 @@ int tpcf_set_tuning(tpcf_ctx* c, double points_per_cell, int waves_per_cu, int s
   if (points_per_cell > 0.0) c->ppc = points_per_cell;
   if (waves_per_cu > 0) c->waves_per_cu = waves_per_cu;
   if (scratch_blocks > 0) c->scratch_blocks = scratch_blocks;
+  c->err.clear();
+  return TPCF_OK;
+}
+
+int tpcf_set_phase_aligned(tpcf_ctx* c, int mode) {
+  if (!c) return TPCF_E_INVALID_ARG;
+  if (mode < -1 || mode > 1) return fail(c, TPCF_E_INVALID_ARG, "mode must be -1, 0 or 1");
+  c->phase_mode = mode;
   c->err.clear();
   return TPCF_OK;
 }

@@ -9,7 +9,10 @@
 //
 // The cells are found by sorting, so only occupied cells cost anything (points on the sphere fill
 // a thin shell of the cube):
-//   k_pivot_keys : per point (cell-sorted records): 63-bit key (gz, gy, gx), 21 bits per axis.
+//   k_pivot_keys : per point (cell-sorted records): the 63-bit Morton code of its pivot cell
+//                  (gx, gy, gz), 21 bits per axis. Any one-to-one key groups the same cells; the
+//                  Z order also makes the pivots, which the sweep takes in key order, come in
+//                  compact patches, so the waves in flight have overlapping neighbourhoods.
 //   radix sort   : rocPRIM, stable, so a cell's members stay in sorted-record order.
 //   k_pivot_heads: 1 where a cell starts; an exclusive scan numbers the cells.
 //   k_pivot_emit : one thread per cell start walks its members: pivot record (X << sh, FP32
@@ -25,13 +28,24 @@ namespace tpcf {
 
 constexpr int kPivotAxisBits = 21;
 
+// The 21 low bits of v moved to bits 0, 3, 6, ..., 60 (masked shift-or spreading).
+__device__ __forceinline__ uint64_t spread3(uint64_t v) {
+  v &= 0x1fffffull;
+  v = (v | (v << 32)) & 0x1f00000000ffffull;
+  v = (v | (v << 16)) & 0x1f0000ff0000ffull;
+  v = (v | (v << 8)) & 0x100f00f00f00f00full;
+  v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+  v = (v | (v << 2)) & 0x1249249249249249ull;
+  return v;
+}
+
 __global__ void k_pivot_keys(const uint4* __restrict__ rec, uint32_t n, int sh, uint64_t Hq,
                              unsigned long long* __restrict__ key, uint32_t* __restrict__ idx) {
   const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
   const uint4 r = rec[s];
   const uint64_t gx = (uint64_t)(r.x >> sh) / Hq, gy = (uint64_t)(r.y >> sh) / Hq, gz = (uint64_t)(r.z >> sh) / Hq;
-  key[s] = (gz << (2 * kPivotAxisBits)) | (gy << kPivotAxisBits) | gx;
+  key[s] = spread3(gx) | (spread3(gy) << 1) | (spread3(gz) << 2);
   idx[s] = s;
 }
 

@@ -15,7 +15,8 @@
 //   stencil : the primary's own stencil: every (y, z) row of cells whose slab comes within
 //             r_max of the primary, clipped in x to the chord of the r_max sphere (cell
 //             granularity). Rows are built 64 at a time, one per lane; the rows' cell ranges are
-//             contiguous runs of the cell-sorted records.
+//             contiguous runs of the cell-sorted records. For large neighbourhoods the rows are
+//             taken in a rotated order, phase-aligned across the waves in flight (L2 sharing).
 //   pass    : rounds of 64 consecutive candidates, packed across runs. Each candidate's bin is
 //             decided in FP32 when its fractional bin position is farther than a proven error
 //             bound from a bin edge, and otherwise exactly (FP64 squared lattice separation
@@ -701,6 +702,18 @@ __device__ __forceinline__ Row make_row(const uint32_t* __restrict__ cell_start,
 // workgroup: the hardware executes a wavefront's LDS instructions in order.
 __device__ __forceinline__ void lds_order() { __atomic_signal_fence(__ATOMIC_SEQ_CST); }
 
+// Inclusive prefix sum over the 64 lanes of the wavefront.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t u = __shfl_up(v, (unsigned)d);
+    if (lane >= d) v += u;
+  }
+  return v;
+}
+
+__device__ __forceinline__ uint32_t row_len(const Row& r) { return (r.e0 - r.b0) + (r.e1 - r.b1); }
+
 __device__ __forceinline__ int lanes_below(uint64_t m) {
   return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
@@ -872,8 +885,42 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sw
     uint32_t delta_c = 0;  // sorted minus candidate position for the run holding position o - 1
     uint32_t pre_v = kInvalid, dl_v = 0;
 
+    // Phase alignment: start at the row holding candidate floor(total * phase), phase = (ticket mod
+    // waves) / waves, and wrap around. Tickets are handed out at a steady rate, so a wave's phase
+    // is where the waves in flight are in their own stencils when it starts, and all of them keep
+    // reading about the same rows (shared through L2) instead of the whole neighbourhood. Rows are
+    // counted in chunks of 64 (at most 64 chunks: lane k keeps chunk k's candidates).
+    int rot = 0;
+    if (a.phase_rows && nrows <= 64 * 64) {
+      const int nchunk = (nrows + 63) >> 6;
+      uint32_t ctot = 0, total = 0;
+      for (int k = 0; k < nchunk; ++k) {
+        const Row rw = make_row(a.cell_start, cu, k * 64 + lane, cx, cy, cz, qxf, qyf, qzf);
+        const uint32_t sk = uniform(__builtin_amdgcn_readlane(wave_incl_scan(row_len(rw), lane), 63));
+        if (lane == k) ctot = sk;
+        total += sk;
+      }
+      const uint32_t W = gridDim.x;
+      const uint32_t target = (uint32_t)((uint64_t)total * (t % W) / W);  // < total when total > 0
+      const uint32_t incl = wave_incl_scan(ctot, lane);
+      // chunk holding the target: lanes at or past nchunk have incl == total > target
+      const int k = __popcll(__ballot(incl <= target));
+      if (k < nchunk) {
+        const uint32_t before = uniform(__builtin_amdgcn_readlane(incl - ctot, k));
+        const Row rw = make_row(a.cell_start, cu, k * 64 + lane, cx, cy, cz, qxf, qyf, qzf);
+        const uint32_t li = wave_incl_scan(row_len(rw), lane);
+        const int r = k * 64 + __popcll(__ballot(before + li <= target));
+        rot = r < nrows ? r : 0;
+      }
+    }
+
     auto build_rows = [&]() {
-      const Row rw = make_row(a.cell_start, cu, row_base + lane, cx, cy, cz, qxf, qyf, qzf);
+      int tr = row_base + lane;  // rows past nrows stay past it (empty)
+      if (tr < nrows) {
+        tr += rot;
+        if (tr >= nrows) tr -= nrows;
+      }
+      const Row rw = make_row(a.cell_start, cu, tr, cx, cy, cz, qxf, qyf, qzf);
       const bool h0 = rw.e0 > rw.b0, h1 = rw.e1 > rw.b1;
       const uint64_t m0 = __ballot(h0), m1 = __ballot(h1);
       const int below = lanes_below(m0) + lanes_below(m1);

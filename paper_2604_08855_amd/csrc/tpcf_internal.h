@@ -63,6 +63,7 @@ struct SweepArgs {
   const uint4* prim_rec;        // optional: task t is the pivot prim_rec[t] (shared pivots), not a point
   const double* prim_w64;       // FP64 weights of those pivots
   uint32_t ntask;
+  int32_t phase_rows;           // 1: each wave starts its stencil at the row matching its ticket's phase
   uint32_t* queue;              // [0] task ticket counter
   uint32_t* scratch;            // per wave: scratch_blocks + kScratchTail blocks of 64 sorted positions
   int32_t scratch_blocks;       // blocks per wave in bin regions
