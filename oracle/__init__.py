@@ -57,6 +57,10 @@ def _load():
         lib.oracle_zeta_pivots.argtypes = [i64, p, p, p, p, d, i, i, d, d, i, d, p, p, p, p, p, i]
         lib.oracle_zeta_pivots.restype = i
         lib.oracle_zeta_sphere_pivots.argtypes = [i64, p, p, p, p, i, d, d, i, d, p, p, p, i]
+        lib.oracle_degenerate.argtypes = [i64, p, p, p, p, d, i, i, d, d, i, i64, i64, p, i]
+        lib.oracle_degenerate.restype = i
+        lib.oracle_degenerate_sphere.argtypes = [i64, p, p, p, p, i, d, d, i, i64, i64, p, i]
+        lib.oracle_degenerate_sphere.restype = i
         lib.oracle_zeta_sphere_pivots.restype = i
         lib.oracle_edge_correct_sphere.argtypes = [i, i, i, p, p, p]
         lib.oracle_edge_correct_sphere.restype = i
@@ -192,6 +196,42 @@ def zeta_sphere(x, y, z, w, nbins: int, theta_min: float, theta_max: float, mmax
     if rc:
         raise ValueError("oracle_zeta_sphere: invalid arguments")
     return Result(zt, counts, None, int(npairs.value))
+
+
+def degenerate(x, y, z, w, box: float, periodic: bool, nbins: int, rmin: float, rmax: float, lmax: int,
+               p_begin: int = 0, p_end: int | None = None, threads: int = 0) -> np.ndarray:
+    """D_l(b) = (2l+1)/(4 pi) sum_p w_p sum_{j in b(p)} w_j^2, the j = k part of zeta_l(b, b)
+    (oracle_degenerate); [(lmax+1), nbins]."""
+    x, y, z = (np.ascontiguousarray(a, dtype=np.float64) for a in (x, y, z))
+    n = x.shape[0]
+    w = np.ones(n) if w is None else np.ascontiguousarray(w, dtype=np.float64)
+    if p_end is None:
+        p_end = n
+    D = np.zeros((lmax + 1, nbins))
+    rc = _load().oracle_degenerate(n, _ptr(x), _ptr(y), _ptr(z), _ptr(w), float(box), int(bool(periodic)),
+                                   int(nbins), float(rmin), float(rmax), int(lmax), int(p_begin), int(p_end),
+                                   _ptr(D), int(threads))
+    if rc:
+        raise ValueError("oracle_degenerate: invalid arguments")
+    return D
+
+
+def degenerate_sphere(x, y, z, w, nbins: int, theta_min: float, theta_max: float, mmax: int,
+                      p_begin: int = 0, p_end: int | None = None, threads: int = 0) -> np.ndarray:
+    """D_m(b) = sum_p w_p sum_{j in b(p)} w_j^2 for every m, the j = k part of zeta_m(b, b) on the
+    sphere (oracle_degenerate_sphere); [(mmax+1), nbins]."""
+    x, y, z = (np.ascontiguousarray(a, dtype=np.float64) for a in (x, y, z))
+    n = x.shape[0]
+    w = np.ones(n) if w is None else np.ascontiguousarray(w, dtype=np.float64)
+    if p_end is None:
+        p_end = n
+    D = np.zeros((mmax + 1, nbins))
+    rc = _load().oracle_degenerate_sphere(n, _ptr(x), _ptr(y), _ptr(z), _ptr(w), int(nbins), float(theta_min),
+                                          float(theta_max), int(mmax), int(p_begin), int(p_end), _ptr(D),
+                                          int(threads))
+    if rc:
+        raise ValueError("oracle_degenerate_sphere: invalid arguments")
+    return D
 
 
 class PivotResult:

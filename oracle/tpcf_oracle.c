@@ -383,6 +383,74 @@ int oracle_pair_sums(int64_t n, const double *x, const double *y, const double *
     return 0;
 }
 
+/*
+ * The degenerate (j = k) part of the estimator: triangles whose two legs end on the same
+ * secondary. In zeta_l(b, b) = sum_p w_p sum_m |a_lm(p, b)|^2 every secondary j of bin b meets
+ * itself once, and by the addition theorem sum_m |Y_lm(u)|^2 = (2l + 1) / (4 pi) for any unit u,
+ * so that part is
+ *     D_l(b) = (2l + 1) / (4 pi) * sum_p w_p sum_{j in b(p)} w_j^2,
+ * to be subtracted from the diagonal by callers who want triangles of distinct points only.
+ * Same lattice binning as oracle_zeta. Output D[(lmax+1)][nbins]. Returns 0, or 1 on invalid
+ * arguments.
+ */
+static void degenerate_sums(const problem *P, int64_t p_begin, int64_t p_end, double *S, int nthreads)
+{
+    const int nb = P->nbins;
+    const int64_t np = p_end - p_begin;
+    for (int b = 0; b < nb; b++) S[b] = 0.0;
+    if (np <= 0) return;
+    const int64_t nchunk = np < ORACLE_CHUNKS ? np : ORACLE_CHUNKS;
+    double *part = (double *)calloc((size_t)nchunk * nb, sizeof(double));
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t c = 0; c < nchunk; c++) {
+        int64_t lo = p_begin + np * c / nchunk, hi = p_begin + np * (c + 1) / nchunk;
+        for (int64_t p = lo; p < hi; p++)
+            for (int64_t j = 0; j < P->n; j++) {
+                if (j == p) continue;
+                int64_t d[3];
+                int b = pair_bin(P, p, j, d);
+                if (b < 0) continue;
+                part[c * nb + b] += P->w[p] * P->w[j] * P->w[j];
+            }
+    }
+    for (int64_t c = 0; c < nchunk; c++)
+        for (int b = 0; b < nb; b++) S[b] += part[c * nb + b];
+    free(part);
+}
+
+int oracle_degenerate(int64_t n, const double *x, const double *y, const double *z, const double *w, double box,
+                      int periodic, int nbins, double rmin, double rmax, int lmax, int64_t p_begin, int64_t p_end,
+                      double *D, int nthreads)
+{
+    if (n < 0 || nbins < 1 || lmax < 0 || !(rmin >= 0.0) || !(rmax > rmin) || !(box > 0.0) || p_begin < 0 ||
+        p_end > n || p_begin > p_end || !w)
+        return 1;
+    const int nb = nbins;
+    for (int i = 0; i < (lmax + 1) * nb; i++) D[i] = 0.0;
+    if (n == 0 || p_begin == p_end) return 0;
+    int K = oracle_lattice_bits(box, rmax, periodic);
+    int64_t *q = (int64_t *)malloc(sizeof(int64_t) * 3 * (size_t)n);
+    uint64_t *T = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(nb + 1));
+    double *S = (double *)malloc(sizeof(double) * (size_t)nb);
+    oracle_snap(n, x, box, K, periodic, q);
+    oracle_snap(n, y, box, K, periodic, q + n);
+    oracle_snap(n, z, box, K, periodic, q + 2 * n);
+    oracle_thresholds(nb, rmin, rmax, box, K, T);
+    problem P = {n, q, q + n, q + 2 * n, w, K, periodic, nb, lmax, T};
+    degenerate_sums(&P, p_begin, p_end, S, nthreads);
+    for (int l = 0; l <= lmax; l++)
+        for (int b = 0; b < nb; b++) D[l * nb + b] = (2.0 * l + 1.0) / (4.0 * 3.14159265358979323846) * S[b];
+    free(S);
+    free(q);
+    free(T);
+    return 0;
+}
+
 /* Legendre polynomials P_0..P_lmax at x (Bonnet recurrence). */
 static void legendre_all(int lmax, double x, double *P)
 {
@@ -910,3 +978,32 @@ int oracle_zeta_sphere_pivots(int64_t n, const double *x, const double *y, const
     return 0;
 }
 
+/*
+ * The degenerate (j = k) part of zeta_m on the sphere: |exp(-i m phi)|^2 = 1, so for every m
+ *     D_m(b) = sum_p w_p sum_{j in b(p)} w_j^2,
+ * the part of zeta_m(b, b) from one secondary on both legs. Same lattice and chord thresholds
+ * as oracle_zeta_sphere. Output D[(mmax+1)][nbins]. Returns 0, or 1 on invalid arguments.
+ */
+int oracle_degenerate_sphere(int64_t n, const double *x, const double *y, const double *z, const double *w,
+                             int nbins, double theta_min, double theta_max, int mmax, int64_t p_begin,
+                             int64_t p_end, double *D, int nthreads)
+{
+    if (n < 0 || nbins < 1 || mmax < 0 || !(theta_min >= 0.0) || !(theta_max > theta_min) ||
+        !(theta_max <= 3.14159265358979323846) || p_begin < 0 || p_end > n || p_begin > p_end || !w)
+        return 1;
+    const int nb = nbins;
+    for (int i = 0; i < (mmax + 1) * nb; i++) D[i] = 0.0;
+    if (n == 0 || p_begin == p_end) return 0;
+    int64_t *q = (int64_t *)malloc(sizeof(int64_t) * 3 * (size_t)n);
+    uint64_t *T = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(nb + 1));
+    double *S = (double *)malloc(sizeof(double) * (size_t)nb);
+    const int K = sphere_setup(n, x, y, z, nb, theta_min, theta_max, q, T);
+    problem P = {n, q, q + n, q + 2 * n, w, K, 0, nb, mmax, T};
+    degenerate_sums(&P, p_begin, p_end, S, nthreads);
+    for (int m = 0; m <= mmax; m++)
+        for (int b = 0; b < nb; b++) D[m * nb + b] = S[b];
+    free(S);
+    free(q);
+    free(T);
+    return 0;
+}

@@ -68,7 +68,9 @@ def pair_table(x, y, z, box, periodic, nbins, rmin, rmax, primaries=None):
     return out
 
 
-def zeta_triangles(x, y, z, w, box, periodic, nbins, rmin, rmax, lmax, primaries=None):
+def zeta_triangles(x, y, z, w, box, periodic, nbins, rmin, rmax, lmax, primaries=None, drop_jk=False):
+    """Legendre form (2l+1)/(4 pi) sum_p w_p sum_{j,k} w_j w_k P_l(u_j . u_k) from the pair table;
+    drop_jk leaves out the terms with j = k (one secondary on both legs)."""
     n = len(x)
     w = np.ones(n) if w is None else np.asarray(w, dtype=np.float64)
     pairs = pair_table(x, y, z, box, periodic, nbins, rmin, rmax, primaries)
@@ -82,6 +84,8 @@ def zeta_triangles(x, y, z, w, box, periodic, nbins, rmin, rmax, lmax, primaries
         U = np.array([t[2] for t in lst])
         cosg = np.clip(U @ U.T, -1.0, 1.0)
         ww = np.outer(w[js], w[js])
+        if drop_jk:
+            np.fill_diagonal(ww, 0.0)
         for l in range(lmax + 1):
             Pl = eval_legendre(l, cosg) * ww
             # accumulate sum over (j,k) into (b_j, b_k)
@@ -129,7 +133,7 @@ def sphere_lattice(x, y, z, nbins, theta_min, theta_max):
     return q, sc, T
 
 
-def sphere_triangles_at(qp, wp, skip, q, w, sc, T, nbins, mmax, zeta, counts, sums, row):
+def sphere_triangles_at(qp, wp, skip, q, w, sc, T, nbins, mmax, zeta, counts, sums, row, drop_jk=False):
     """Adds one pivot (lattice point qp, weight wp; point `skip` excluded) to zeta in the basis-free
     triangle form; fills counts[row] and sums[row]."""
     from scipy.special import eval_chebyt
@@ -157,6 +161,8 @@ def sphere_triangles_at(qp, wp, skip, q, w, sc, T, nbins, mmax, zeta, counts, su
     js, bs, P = np.array(js), np.array(bs), np.array(P)
     cosd = np.clip(P @ P.T, -1.0, 1.0)
     ww = np.outer(w[js], w[js])
+    if drop_jk:
+        np.fill_diagonal(ww, 0.0)
     for m in range(mmax + 1):
         acc = np.zeros((nbins, nbins))
         np.add.at(acc, (bs[:, None].repeat(len(js), 1), bs[None, :].repeat(len(js), 0)),
@@ -164,7 +170,7 @@ def sphere_triangles_at(qp, wp, skip, q, w, sc, T, nbins, mmax, zeta, counts, su
         zeta[m] += wp * acc
 
 
-def zeta_sphere_triangles(x, y, z, w, nbins, theta_min, theta_max, mmax, primaries=None):
+def zeta_sphere_triangles(x, y, z, w, nbins, theta_min, theta_max, mmax, primaries=None, drop_jk=False):
     """zeta_m on the sphere in the basis-free triangle form
 
         zeta_m(b1, b2) = sum_p w_p sum_{j in b1} sum_{k in b2} w_j w_k cos(m (phi_j - phi_k)),
@@ -179,7 +185,7 @@ def zeta_sphere_triangles(x, y, z, w, nbins, theta_min, theta_max, mmax, primari
     counts = np.zeros((n, nbins), dtype=np.int64)
     sums = np.zeros((n, nbins))
     for p in (range(n) if primaries is None else primaries):
-        sphere_triangles_at(q[p], w[p], p, q, w, sc, T, nbins, mmax, zeta, counts, sums, p)
+        sphere_triangles_at(q[p], w[p], p, q, w, sc, T, nbins, mmax, zeta, counts, sums, p, drop_jk)
     return zeta, counts, sums
 
 

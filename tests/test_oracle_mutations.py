@@ -51,6 +51,12 @@ MUTANTS = {
                                   "pq[ax * n + G] = sum[ax] / cnt;"),
     "pivots: group weight is the mean": ("pw[G] = W;", "pw[G] = W / (double)cnt;"),
     "pivots: group key ignores y": ("keys[i].gy = q[n + i] / Hq;", "keys[i].gy = 0;"),
+    "degenerate: w_j in place of w_j^2": ("part[c * nb + b] += P->w[p] * P->w[j] * P->w[j];",
+                                          "part[c * nb + b] += P->w[p] * P->w[j];"),
+    "degenerate: factor 2l - 1": ("D[l * nb + b] = (2.0 * l + 1.0) / (4.0 * 3.14159265358979323846) * S[b];",
+                                  "D[l * nb + b] = (2.0 * l - 1.0) / (4.0 * 3.14159265358979323846) * S[b];"),
+    "degenerate sphere: 3D factor": ("for (int b = 0; b < nb; b++) D[m * nb + b] = S[b];",
+                                     "for (int b = 0; b < nb; b++) D[m * nb + b] = (2.0 * m + 1.0) * S[b];"),
     "sphere edge correction: weight of m' = 0": ("A[m][mp] = (mp == 0 ? 1.0 : 2.0) * t * (twopi / NQ);",
                                                  "A[m][mp] = 2.0 * t * (twopi / NQ);"),
 }
@@ -79,6 +85,13 @@ def _pins():
         if np.max(np.abs(z - ref)) > 1e-12 * np.max(np.abs(ref)):
             failed.append("brute-force triangles")
             break
+    # degenerate (j = k) term: the brute-force j = k part, 3D and sphere
+    D = oracle.degenerate(P[:, 0], P[:, 1], P[:, 2], w, 50.0, True, 4, 2.0, 20.0, 5)
+    part = brute.zeta_triangles(P[:, 0], P[:, 1], P[:, 2], w, 50.0, True, 4, 2.0, 20.0, 5, drop_jk=True)
+    full = brute.zeta_triangles(P[:, 0], P[:, 1], P[:, 2], w, 50.0, True, 4, 2.0, 20.0, 5)
+    dd = np.array([np.diag(full[l] - part[l]) for l in range(6)])
+    if np.max(np.abs(D - dd)) > 1e-12 * np.max(np.abs(dd)):
+        failed.append("degenerate term")
     # Y_lm against scipy
     v = rng.normal(size=(50, 3))
     v /= np.linalg.norm(v, axis=1)[:, None]
@@ -133,6 +146,12 @@ def _pins():
     ref, _, _ = brute.zeta_sphere_triangles(*u, ws, 4, 0.01, 0.3, 5)
     if not np.all(np.isfinite(zs)) or np.max(np.abs(zs - ref)) > 1e-12 * np.max(np.abs(ref)):
         failed.append("sphere triangles")
+    Ds = oracle.degenerate_sphere(*u, ws - 1.0, 4, 0.01, 0.3, 5)
+    fs, _, _ = brute.zeta_sphere_triangles(*u, ws - 1.0, 4, 0.01, 0.3, 5)
+    ps, _, _ = brute.zeta_sphere_triangles(*u, ws - 1.0, 4, 0.01, 0.3, 5, drop_jk=True)
+    dds = np.array([np.diag(fs[m] - ps[m]) for m in range(6)])
+    if np.max(np.abs(Ds - dds)) > 1e-12 * np.max(np.abs(dds)):
+        failed.append("sphere degenerate term")
     # sphere edge correction: N built from the closed-form coupling is solved back
     Rs = np.zeros((3, 1, 1))
     Rs[:, 0, 0] = [1.0, 0.25, -0.1]

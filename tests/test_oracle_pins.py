@@ -91,6 +91,61 @@ def test_bruteforce_triangles_subset_at_larger_n():
         assert _rel(tot[l], ref[l]) < 1e-12
 
 
+# ---------------------------------------------------------------- the degenerate (j = k) term
+
+def test_degenerate_worked_triangle():
+    """The three-point example: bin 1 holds A and B for O, and O for A and for B (4 secondaries,
+    unit weights); bin 2 holds B for A and A for B (2). D_l = (2l+1)/(4 pi) x those counts, and
+    on bin 2, where no primary has two secondaries, D_l(2) is all of zeta_l(2, 2)."""
+    x, y, z = np.array([125.0, 135.0, 125.0]), np.array([125.0, 125.0, 135.0]), np.full(3, 125.0)
+    D = oracle.degenerate(x, y, z, None, 250.0, True, 10, 5.0, 50.0, 4)
+    c = np.array([(2 * l + 1) / (4 * math.pi) for l in range(5)])
+    expect = np.zeros((5, 10))
+    expect[:, 1] = 4 * c
+    expect[:, 2] = 2 * c
+    np.testing.assert_allclose(D, expect, rtol=1e-15, atol=0)
+    zt = oracle.zeta(x, y, z, None, 250.0, True, 10, 5.0, 50.0, 4).zeta
+    np.testing.assert_allclose(D[:, 2], zt[:, 2, 2], rtol=1e-14)
+
+
+@pytest.mark.parametrize("periodic", [True, False])
+def test_degenerate_is_the_jk_part_of_brute_force(periodic):
+    """zeta with every (j, k) minus zeta without j = k (both from the brute-force triangle form)
+    is D_l(b) on the diagonal and zero off it; signed weights, so w_j^2 against w_j matters."""
+    rng = np.random.default_rng(17)
+    n, box = 140, 100.0
+    P = rng.random((n, 3)) * box
+    w = rng.normal(0.2, 1.0, n)
+    nb, rmin, rmax, lmax = 6, 4.0, 40.0, 5
+    full = brute.zeta_triangles(P[:, 0], P[:, 1], P[:, 2], w, box, periodic, nb, rmin, rmax, lmax)
+    part = brute.zeta_triangles(P[:, 0], P[:, 1], P[:, 2], w, box, periodic, nb, rmin, rmax, lmax, drop_jk=True)
+    D = oracle.degenerate(P[:, 0], P[:, 1], P[:, 2], w, box, periodic, nb, rmin, rmax, lmax)
+    diff = full - part
+    for l in range(lmax + 1):
+        np.testing.assert_allclose(np.diag(diff[l]), D[l], rtol=1e-11, atol=1e-12 * np.abs(D[l]).max())
+        assert np.abs(diff[l] - np.diag(np.diag(diff[l]))).max() <= 1e-12 * np.abs(D[l]).max()
+    # weight homogeneity: w -> a w scales D by a^3; primary ranges add up
+    D2 = oracle.degenerate(P[:, 0], P[:, 1], P[:, 2], -2.0 * w, box, periodic, nb, rmin, rmax, lmax)
+    np.testing.assert_allclose(D2, -8.0 * D, rtol=1e-14)
+    Da = oracle.degenerate(P[:, 0], P[:, 1], P[:, 2], w, box, periodic, nb, rmin, rmax, lmax, 0, 50)
+    Db = oracle.degenerate(P[:, 0], P[:, 1], P[:, 2], w, box, periodic, nb, rmin, rmax, lmax, 50, n)
+    np.testing.assert_allclose(Da + Db, D, rtol=1e-13, atol=1e-14 * np.abs(D).max())
+
+
+def test_degenerate_sphere_is_the_jk_part_of_brute_force():
+    """On the sphere |exp(-i m phi)|^2 = 1: D_m(b) does not depend on m and equals the diagonal
+    of the brute-force zeta_m minus its j != k part."""
+    x, y, z, w = _sphere_points(150, 4)
+    w = w - 1.0
+    full, _, _ = brute.zeta_sphere_triangles(x, y, z, w, 5, 0.01, 0.3, 6)
+    part, _, _ = brute.zeta_sphere_triangles(x, y, z, w, 5, 0.01, 0.3, 6, drop_jk=True)
+    D = oracle.degenerate_sphere(x, y, z, w, 5, 0.01, 0.3, 6)
+    assert np.abs(D).max() > 0
+    for m in range(7):
+        np.testing.assert_allclose(np.diag(full[m] - part[m]), D[m], rtol=1e-11, atol=1e-12 * np.abs(D).max())
+        np.testing.assert_array_equal(D[m], D[0])
+
+
 # ---------------------------------------------------------------- l = 0 and pair counts
 
 def test_l0_is_product_of_pair_counts():
