@@ -259,6 +259,24 @@ int tpcf_debug_pair_counts(tpcf_ctx* ctx, int64_t* counts);
 int tpcf_debug_alm(tpcf_ctx* ctx, double* alm);
 
 /*
+ * The degenerate (j = k) part of the estimator, for the catalogue(s) staged by the last
+ * tpcf_set_catalog, tpcf_set_sphere_catalog or batch call, with the current bins: the triangles
+ * whose two legs end on the same secondary, which zeta includes on its diagonal b1 = b2 (the
+ * paper's estimator leaves their treatment open; they are part of sum_m |a_lm|^2). In 3D
+ *     D_l(b) = (2l + 1) / (4 pi) * sum_p w_p sum_{j in b(p)} w_j^2
+ * (the addition theorem: sum_m |Y_lm(u)|^2 = (2l + 1) / (4 pi)); on the sphere
+ *     D_m(b) = sum_p w_p sum_{j in b(p)} w_j^2 for every m.
+ * zeta_l(b, b) - D_l(b) is then the sum over triangles of three distinct points. Always the exact
+ * estimator (every point a primary, also when shared pivots are set), in FP64: one extra sweep at
+ * l_max = 0 with squared secondary weights. The outputs of the last compute call (zeta, pair
+ * sums, debug rows, statistics) are left as they are.
+ * D: [ncat][(lmax+1)][nbins] row-major, FP64, caller-owned, in `memspace`.
+ * Errors: TPCF_E_STATE before tpcf_set_bins or without a catalogue; TPCF_E_INVALID_ARG for a NULL
+ * D or an unknown memspace or the periodic range check of tpcf_compute_zeta; TPCF_E_OUT_OF_MEMORY.
+ */
+int tpcf_degenerate(tpcf_ctx* ctx, double* D, int memspace);
+
+/*
  * Two-point by-product of the last compute call (tpcf_compute_zeta, _range or _batch), per
  * catalogue c and radial bin b, over that call's primaries and all secondaries:
  *     npairs[c][b] = ordered (primary, secondary) pairs in bin b, exact;

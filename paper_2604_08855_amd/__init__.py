@@ -33,7 +33,7 @@ EXPORTS = [
     "tpcf_compute_batch", "tpcf_debug_pair_counts", "tpcf_debug_alm", "tpcf_set_debug",
     "tpcf_get_stats", "tpcf_last_error", "tpcf_autotune", "tpcf_pair_sums", "tpcf_edge_correct",
     "tpcf_set_sphere_catalog", "tpcf_set_pivot_cell", "tpcf_edge_correct_sphere", "tpcf_compute_sphere_batch",
-    "tpcf_set_phase_aligned",
+    "tpcf_set_phase_aligned", "tpcf_degenerate",
 ]
 
 
@@ -94,6 +94,7 @@ def _load() -> ctypes.CDLL:
         "tpcf_set_precision": ([vp, i], i),
         "tpcf_set_tuning": ([vp, d, i, i], i),
         "tpcf_set_phase_aligned": ([vp, i], i),
+        "tpcf_degenerate": ([vp, vp, i], i),
         "tpcf_set_catalog": ([vp, i64, vp, vp, vp, vp, d, i, i], i),
         "tpcf_compute_zeta": ([vp, vp, i], i),
         "tpcf_compute_zeta_range": ([vp, i64, i64, vp, i], i),
@@ -310,6 +311,14 @@ class Context:
         self._check(_lib.tpcf_compute_sphere_batch(self._h, ncat, _ptr_np(offsets), *ptrs, p, mem))
         self.n, self.ncat, self.sphere = int(offsets[-1]), ncat, True
         return out
+
+    def degenerate(self):
+        """The j = k part of zeta's diagonal for the staged catalogue(s) (see tpcf_degenerate):
+        float64 [ncat, (lmax+1), nbins]; zeta_l(b, b) - D_l(b) counts triangles of distinct points."""
+        L, nb = (self.lmax or 0), (self.nbins or 1)
+        D = np.zeros((max(self.ncat, 1), L + 1, nb))
+        self._check(_lib.tpcf_degenerate(self._h, _ptr_np(D), MEM_HOST))
+        return D
 
     def pair_sums(self):
         """Two-point by-product of the last compute call: (npairs int64 [ncat, nbins] ordered

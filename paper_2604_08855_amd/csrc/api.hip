@@ -23,6 +23,7 @@ void validate_inputs(const double* x, const double* y, const double* z, const do
 size_t scan_block_count(uint32_t ncell);
 void fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s);
 void fill_f64(double* p, double v, size_t n, hipStream_t s);
+hipError_t square_weights(const uint4* rec, const double* w64, uint32_t n, uint4* out, double* w2, hipStream_t s);
 void unsort_counts(const int32_t* in, const uint32_t* perm, int64_t* out, uint32_t n, int nb, hipStream_t s);
 void unsort_alm(const void* in, bool f64, const uint32_t* perm, double* out, uint32_t n, int row, hipStream_t s);
 hipError_t launch_sweep(int lmax, bool f64, bool sphere, const SweepArgs& args, int waves, hipStream_t stream);
@@ -101,6 +102,8 @@ struct tpcf_ctx {
   DevBuf scratch, tile, zeta_d, queue, stats_d, tasks, counts32, alm_dbg, conv_idx, conv32, conv64, regions;
   DevBuf bin_pairs, bin_dd;  // two-point by-product of the last compute call, [ncat][nbins]
   DevBuf edge_tab, edge_io;  // squared 3j table (for edge_lmax) and host-call staging
+  // degenerate-term sweep: records with squared weights, and its own outputs
+  DevBuf dg_rec, dg_w64, dg_zeta, dg_stats, dg_pairs, dg_dd;
   // shared pivots: pivot cell side (0 = exact, < 0 = the mean separation), cell tables, pivots
   double pivot_h = 0.0;
   DevBuf pv_keys, pv_idx, pv_head, pv_slot, pv_bsum, pv_tmp, pv_rec, pv_w64;
@@ -699,11 +702,11 @@ int record_sweep(tpcf_ctx* c, const SweepArgs& a, int waves) {
     fill_u32((uint32_t*)c->counts32.p, 0u, (size_t)c->ntot * nb, c->stream);
     fill_u32((uint32_t*)c->alm_dbg.p, 0u, (size_t)c->ntot * nb * NC * (f64 ? 2 : 1), c->stream);
   }
-  fill_f64((double*)c->zeta_d.p, 0.0, (size_t)a.ncat * (L + 1) * nb * nb, c->stream);
-  fill_u32((uint32_t*)c->queue.p, 0u, 4, c->stream);
-  fill_u32((uint32_t*)c->stats_d.p, 0u, 4, c->stream);
-  fill_u32((uint32_t*)c->bin_pairs.p, 0u, (size_t)a.ncat * nb * 2, c->stream);
-  fill_f64((double*)c->bin_dd.p, 0.0, (size_t)a.ncat * nb, c->stream);
+  fill_f64(a.zeta, 0.0, (size_t)a.ncat * (L + 1) * nb * nb, c->stream);
+  fill_u32(a.queue, 0u, 4, c->stream);
+  fill_u32(reinterpret_cast<uint32_t*>(a.stats), 0u, 4, c->stream);
+  fill_u32(reinterpret_cast<uint32_t*>(a.bin_pairs), 0u, (size_t)a.ncat * nb * 2, c->stream);
+  fill_f64(a.bin_dd, 0.0, (size_t)a.ncat * nb, c->stream);
   if (a.ntask > 0) HIP_TRY(c, launch_sweep(L, f64, sph, a, waves, c->stream));
   return TPCF_OK;
 }
@@ -946,7 +949,8 @@ void tpcf_destroy(tpcf_ctx* c) {
                      &c->scratch, &c->tile, &c->zeta_d, &c->queue, &c->stats_d, &c->tasks, &c->counts32,
                      &c->alm_dbg, &c->conv_idx, &c->conv32, &c->conv64, &c->regions, &c->bin_pairs, &c->bin_dd,
                      &c->edge_tab, &c->edge_io, &c->pv_keys, &c->pv_idx, &c->pv_head, &c->pv_slot,
-                     &c->pv_bsum, &c->pv_tmp, &c->pv_rec, &c->pv_w64};
+                     &c->pv_bsum, &c->pv_tmp, &c->pv_rec, &c->pv_w64, &c->dg_rec, &c->dg_w64,
+                     &c->dg_zeta, &c->dg_stats, &c->dg_pairs, &c->dg_dd};
     for (DevBuf* b : all) release(*b);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     for (auto& e : c->ev)
@@ -1103,6 +1107,75 @@ int tpcf_autotune(tpcf_ctx* c, double sample_fraction, tpcf_tuning* out) {
     out->candidates = tried;
     out->ms_best = best_ms;
     out->ms_default = ms_default;
+  }
+  c->err.clear();
+  return TPCF_OK;
+}
+
+int tpcf_degenerate(tpcf_ctx* c, double* D, int memspace) {
+  if (!c) return TPCF_E_INVALID_ARG;
+  if (!c->bins_set) return fail(c, TPCF_E_STATE, "set_bins has not been called");
+  if (!c->cat_set) return fail(c, TPCF_E_STATE, "no catalogue set");
+  if (!D) return fail(c, TPCF_E_INVALID_ARG, "D is NULL");
+  if (memspace != TPCF_MEM_HOST && memspace != TPCF_MEM_DEVICE)
+    return fail(c, TPCF_E_INVALID_ARG, "unknown memory space");
+  int rc;
+  if ((rc = check_periodic_range(c))) return rc;
+  if ((rc = ensure_device(c))) return rc;
+  if (!grid_current(c)) {
+    if ((rc = prepare_grid(c)) || (rc = record_grid(c))) return rc;
+    mark_grid(c);
+  }
+  const size_t n = (size_t)c->ntot;
+  const int ncat = (int)c->cd.size(), nb = c->nbins, L = c->lmax;
+  if ((rc = ensure(c, c->dg_rec, (n + 1) * sizeof(uint4), "degenerate term")) ||
+      (rc = ensure(c, c->dg_w64, (n + 1) * 8, "degenerate term")) ||
+      (rc = ensure(c, c->dg_zeta, (size_t)ncat * nb * nb * 8, "degenerate term")) ||
+      (rc = ensure(c, c->dg_stats, 16, "degenerate term")) ||
+      (rc = ensure(c, c->dg_pairs, (size_t)ncat * nb * 8, "degenerate term")) ||
+      (rc = ensure(c, c->dg_dd, (size_t)ncat * nb * 8, "degenerate term")))
+    return rc;
+  HIP_TRY(c, square_weights((const uint4*)c->rec.p, (const double*)c->w64.p, (uint32_t)(n + 1), (uint4*)c->dg_rec.p,
+                            (double*)c->dg_w64.p, c->stream));
+  // The sweep at l_max = 0 in FP64 over every point as a primary (its own record and weight),
+  // with the squared weights on the secondaries: its two-point by-product is then
+  // sum_p w_p sum_{j in b} w_j^2 per bin. The last compute call's outputs stay untouched.
+  const int saved_L = c->lmax, saved_prec = c->precision;
+  const bool saved_debug = c->debug;
+  c->lmax = 0;
+  c->precision = TPCF_PREC_FP64;
+  c->debug = false;
+  SweepArgs a;
+  int waves = 0;
+  rc = prepare_sweep(c, nullptr, (uint32_t)n, a, waves);
+  if (!rc) {
+    a.rec = (const uint4*)c->dg_rec.p;
+    a.w64 = (const double*)c->dg_w64.p;
+    a.prim_rec = (const uint4*)c->rec.p;
+    a.prim_w64 = (const double*)c->w64.p;
+    a.zeta = (double*)c->dg_zeta.p;
+    a.stats = (unsigned long long*)c->dg_stats.p;
+    a.bin_pairs = (unsigned long long*)c->dg_pairs.p;
+    a.bin_dd = (double*)c->dg_dd.p;
+    rc = record_sweep(c, a, waves);
+  }
+  c->lmax = saved_L;
+  c->precision = saved_prec;
+  c->debug = saved_debug;
+  if (rc) return rc;
+  std::vector<double> dd((size_t)ncat * nb), out((size_t)ncat * (L + 1) * nb);
+  HIP_TRY(c, hipMemcpyAsync(dd.data(), c->dg_dd.p, dd.size() * 8, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  const bool sph = is_sphere(c);
+  for (int k = 0; k < ncat; ++k)
+    for (int l = 0; l <= L; ++l)
+      for (int b = 0; b < nb; ++b)
+        out[((size_t)k * (L + 1) + l) * nb + b] = (sph ? 1.0 : (2.0 * l + 1.0) / (4.0 * kPi)) * dd[(size_t)k * nb + b];
+  if (memspace == TPCF_MEM_HOST) {
+    memcpy(D, out.data(), out.size() * 8);
+  } else {
+    HIP_TRY(c, hipMemcpyAsync(D, out.data(), out.size() * 8, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
   }
   c->err.clear();
   return TPCF_OK;

@@ -231,6 +231,19 @@ __global__ void k_validate(const double* __restrict__ x, const double* __restric
   if (bad) atomicOr(err, bad);
 }
 
+// Records and FP64 weights with each weight squared (the secondaries of the degenerate-term
+// sweep); the FP32 weight bits hold the rounded FP64 square.
+__global__ void k_square_weights(const uint4* __restrict__ rec, const double* __restrict__ w64, uint32_t n,
+                                 uint4* __restrict__ out, double* __restrict__ w2) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double v = w64[i] * w64[i];
+  uint4 r = rec[i];
+  r.w = __float_as_uint((float)v);
+  out[i] = r;
+  w2[i] = v;
+}
+
 __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t v, size_t n) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -255,6 +268,11 @@ void fill_f64(double* p, double v, size_t n, hipStream_t s) {
 void validate_inputs(const double* x, const double* y, const double* z, const double* w, uint32_t n,
                      const CatDesc* cats, int ncat, int* err, hipStream_t s) {
   if (n) hipLaunchKernelGGL(k_validate, dim3(blocks_for(n, 256)), dim3(256), 0, s, x, y, z, w, n, cats, ncat, err);
+}
+
+hipError_t square_weights(const uint4* rec, const double* w64, uint32_t n, uint4* out, double* w2, hipStream_t s) {
+  if (n) hipLaunchKernelGGL(k_square_weights, dim3(blocks_for(n, 256)), dim3(256), 0, s, rec, w64, n, out, w2);
+  return hipGetLastError();
 }
 
 size_t scan_block_count(uint32_t ncell) { return (ncell + kScanTile - 1) / kScanTile; }

@@ -67,6 +67,7 @@ def test_precision_and_tuning_validation():
     assert _code(c.set_tuning, 0.0, -2, 0) == 1
     assert _code(c.set_tuning, 0.0, 0, 100) == 1  # not a multiple of 64
     c.set_tuning(20.0, 4, 256)
+    assert _code(c.degenerate) == 2  # no bins, no catalogue
     assert _code(c.set_phase_aligned, 2) == 1
     assert _code(c.set_phase_aligned, -2) == 1
     for mode in (-1, 0, 1):
