@@ -90,7 +90,9 @@ const char* tpcf_version(void);
  * Creates a context on HIP device `device` using stream `hip_stream` (a hipStream_t; NULL means
  * the null stream). Every device operation of the context is ordered on that stream. The device
  * is first touched by the first call that needs it, so a context can be created and configured
- * on a machine without a GPU.
+ * on a machine without a GPU. If the environment variable TPCF_MAX_DEVICE_BYTES holds a byte
+ * count, a context never holds more device memory than that: a call that would need more fails
+ * with TPCF_E_OUT_OF_MEMORY.
  * Errors: TPCF_E_INVALID_ARG if out is NULL or device < 0; TPCF_E_OUT_OF_MEMORY.
  */
 int tpcf_create(tpcf_ctx** out, int device, void* hip_stream);
@@ -121,6 +123,23 @@ int tpcf_set_precision(tpcf_ctx* ctx, int precision);
  * compute call with scratch_blocks below 5 x nbins fails with TPCF_E_INVALID_ARG.
  */
 int tpcf_set_tuning(tpcf_ctx* ctx, double points_per_cell, int waves_per_cu, int scratch_blocks);
+
+/*
+ * Optional device allocator (for example torch's caching allocator). From this call on, every
+ * device buffer the context allocates (catalogue staging, grid, sweep scratch, outputs, debug
+ * staging) comes from alloc(bytes, user) and goes back through free_(ptr, user); buffers that
+ * exist already keep the allocator that made them and are freed by it. alloc must return device
+ * memory of the context's device, aligned to at least 256 bytes, or NULL on failure (the call that
+ * needed it then fails with TPCF_E_OUT_OF_MEMORY). The library frees a buffer while work that used
+ * it may still be queued on the context's stream, so the allocator must follow that stream's order
+ * (as a caching allocator bound to the stream does); with plain hipMalloc semantics nothing is
+ * needed. The TPCF_MAX_DEVICE_BYTES cap applies as well. alloc = free_ = NULL restores hipMalloc /
+ * hipFree for later buffers.
+ * Errors: TPCF_E_INVALID_ARG if exactly one of alloc and free_ is NULL.
+ */
+typedef void* (*tpcf_alloc_fn)(size_t bytes, void* user);
+typedef void (*tpcf_free_fn)(void* ptr, void* user);
+int tpcf_set_allocator(tpcf_ctx* ctx, tpcf_alloc_fn alloc, tpcf_free_fn free_, void* user);
 
 /*
  * Optional: phase-aligned stencil sweeps (a performance setting; results agree up to the rounding

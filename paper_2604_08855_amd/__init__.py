@@ -33,7 +33,7 @@ EXPORTS = [
     "tpcf_compute_batch", "tpcf_debug_pair_counts", "tpcf_debug_alm", "tpcf_set_debug",
     "tpcf_get_stats", "tpcf_last_error", "tpcf_autotune", "tpcf_pair_sums", "tpcf_edge_correct",
     "tpcf_set_sphere_catalog", "tpcf_set_pivot_cell", "tpcf_edge_correct_sphere", "tpcf_compute_sphere_batch",
-    "tpcf_set_phase_aligned", "tpcf_degenerate",
+    "tpcf_set_phase_aligned", "tpcf_degenerate", "tpcf_set_allocator",
 ]
 
 
@@ -95,6 +95,7 @@ def _load() -> ctypes.CDLL:
         "tpcf_set_tuning": ([vp, d, i, i], i),
         "tpcf_set_phase_aligned": ([vp, i], i),
         "tpcf_degenerate": ([vp, vp, i], i),
+        "tpcf_set_allocator": ([vp, vp, vp, vp], i),
         "tpcf_set_catalog": ([vp, i64, vp, vp, vp, vp, d, i, i], i),
         "tpcf_compute_zeta": ([vp, vp, i], i),
         "tpcf_compute_zeta_range": ([vp, i64, i64, vp, i], i),
@@ -147,6 +148,11 @@ def _ptr_np(a) -> ctypes.c_void_p:
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
+# tpcf_alloc_fn / tpcf_free_fn
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
 class Context:
     """One library context (one device, one stream). Not thread-safe."""
 
@@ -164,6 +170,7 @@ class Context:
             sh = getattr(stream, "cuda_stream", stream)
         self._check(_lib.tpcf_create(ctypes.byref(self._h), int(device),
                                      ctypes.c_void_p(sh) if sh else None))
+        self._stream_ptr = int(sh) if sh else 0
         self.nbins = self.lmax = None
         self.n = 0
         self.ncat = 0
@@ -205,6 +212,29 @@ class Context:
     def set_tuning(self, points_per_cell: float = 0.0, waves_per_cu: int = 0, scratch_blocks: int = 0):
         self._check(_lib.tpcf_set_tuning(self._h, float(points_per_cell), int(waves_per_cu),
                                          int(scratch_blocks)))
+
+    def use_torch_allocator(self):
+        """Routes the context's device buffers through torch's caching allocator on the context's
+        stream (tpcf_set_allocator), so that they show in torch's memory statistics and reuse its
+        pool. The callbacks stay referenced by the context."""
+        import torch
+
+        dev, stream = self.device, self._stream_ptr
+
+        @_ALLOC_FN
+        def _alloc(nbytes, user):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(nbytes), dev, stream)
+            except Exception:  # out of memory or a bad size: the library reports the failure
+                return None
+
+        @_FREE_FN
+        def _free(ptr, user):
+            torch.cuda.caching_allocator_delete(ptr)
+
+        self._alloc_cbs = (_alloc, _free)
+        self._check(_lib.tpcf_set_allocator(self._h, ctypes.cast(_alloc, ctypes.c_void_p),
+                                            ctypes.cast(_free, ctypes.c_void_p), None))
 
     def set_phase_aligned(self, mode: int = -1):
         """Phase-aligned stencil sweeps: -1 by neighbourhood size (default), 0 off, 1 on

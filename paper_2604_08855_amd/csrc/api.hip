@@ -50,6 +50,8 @@ constexpr int64_t kMaxPoints = (int64_t)1 << 31;
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  tpcf_free_fn free_fn = nullptr;  // the caller's free function if the caller's allocator made it
+  void* user = nullptr;
 };
 
 // Per-catalogue host description.
@@ -81,6 +83,10 @@ struct tpcf_ctx {
   int waves_per_cu = 8;
   int scratch_blocks = 1024;
   int phase_mode = -1;  // phase-aligned stencil sweeps: -1 by neighbourhood size, 0 off, 1 on
+  // optional caller-supplied device allocator (both set or both NULL)
+  tpcf_alloc_fn alloc_fn = nullptr;
+  tpcf_free_fn free_fn = nullptr;
+  void* alloc_user = nullptr;
   bool debug = false;
 
   // staged input (device FP64 copies, concatenated catalogues)
@@ -151,16 +157,33 @@ size_t device_cap() {
   return (size_t)strtoull(s, nullptr, 10);
 }
 
+// Every device buffer the context owns.
+std::vector<DevBuf*> all_bufs(tpcf_ctx* c) {
+  return {&c->sx, &c->sy, &c->sz, &c->sw, &c->cats_d, &c->qtmp, &c->cellid, &c->hist,
+          &c->idx_a, &c->idx_b, &c->bsum, &c->errflag, &c->cell_start, &c->rec, &c->w64, &c->perm,
+          &c->scratch, &c->tile, &c->zeta_d, &c->queue, &c->stats_d, &c->tasks, &c->counts32,
+          &c->alm_dbg, &c->conv_idx, &c->conv32, &c->conv64, &c->regions, &c->bin_pairs, &c->bin_dd,
+          &c->edge_tab, &c->edge_io, &c->pv_keys, &c->pv_idx, &c->pv_head, &c->pv_slot,
+          &c->pv_bsum, &c->pv_tmp, &c->pv_rec, &c->pv_w64, &c->dg_rec, &c->dg_w64,
+          &c->dg_zeta, &c->dg_stats, &c->dg_pairs, &c->dg_dd};
+}
+
 size_t total_bytes(tpcf_ctx* c) {
-  DevBuf* all[] = {&c->sx, &c->sy, &c->sz, &c->sw, &c->cats_d, &c->qtmp, &c->cellid, &c->hist,
-                   &c->idx_a, &c->idx_b, &c->bsum, &c->errflag, &c->cell_start, &c->rec, &c->w64, &c->perm,
-                   &c->scratch, &c->tile, &c->zeta_d, &c->queue, &c->stats_d, &c->tasks, &c->counts32,
-                   &c->alm_dbg, &c->conv_idx, &c->conv32, &c->conv64, &c->regions, &c->bin_pairs, &c->bin_dd,
-                   &c->edge_tab, &c->edge_io, &c->pv_keys, &c->pv_idx, &c->pv_head, &c->pv_slot,
-                   &c->pv_bsum, &c->pv_tmp, &c->pv_rec, &c->pv_w64};
   size_t t = 0;
-  for (DevBuf* b : all) t += b->bytes;
+  for (DevBuf* b : all_bufs(c)) t += b->bytes;
   return t;
+}
+
+// Frees a buffer with whatever allocated it (the caller's free function or hipFree).
+void release(DevBuf& b) {
+  if (b.p) {
+    if (b.free_fn) b.free_fn(b.p, b.user);
+    else (void)hipFree(b.p);
+  }
+  b.p = nullptr;
+  b.bytes = 0;
+  b.free_fn = nullptr;
+  b.user = nullptr;
 }
 
 int ensure(tpcf_ctx* c, DevBuf& b, size_t bytes, const char* what) {
@@ -169,24 +192,22 @@ int ensure(tpcf_ctx* c, DevBuf& b, size_t bytes, const char* what) {
   const size_t cap = device_cap();
   if (total_bytes(c) - b.bytes + bytes > cap)
     return fail(c, TPCF_E_OUT_OF_MEMORY, std::string("device byte cap (TPCF_MAX_DEVICE_BYTES) exceeded by ") + what);
-  if (b.p) {
-    (void)hipFree(b.p);
-    b.p = nullptr;
-    b.bytes = 0;
-  }
-  hipError_t e = hipMalloc(&b.p, bytes);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    return fail(c, TPCF_E_OUT_OF_MEMORY, std::string("hipMalloc failed for ") + what);
+  release(b);
+  if (c->alloc_fn) {
+    b.p = c->alloc_fn(bytes, c->alloc_user);
+    if (!b.p) return fail(c, TPCF_E_OUT_OF_MEMORY, std::string("the caller's allocator failed for ") + what);
+    b.free_fn = c->free_fn;
+    b.user = c->alloc_user;
+  } else {
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      b.p = nullptr;
+      return fail(c, TPCF_E_OUT_OF_MEMORY, std::string("hipMalloc failed for ") + what);
+    }
   }
   b.bytes = bytes;
   return TPCF_OK;
-}
-
-void release(DevBuf& b) {
-  if (b.p) (void)hipFree(b.p);
-  b.p = nullptr;
-  b.bytes = 0;
 }
 
 int ensure_device(tpcf_ctx* c) {
@@ -944,14 +965,7 @@ void tpcf_destroy(tpcf_ctx* c) {
   if (c->dev_ready) {
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
-    DevBuf* all[] = {&c->sx, &c->sy, &c->sz, &c->sw, &c->cats_d, &c->qtmp, &c->cellid, &c->hist,
-                     &c->idx_a, &c->idx_b, &c->bsum, &c->errflag, &c->cell_start, &c->rec, &c->w64, &c->perm,
-                     &c->scratch, &c->tile, &c->zeta_d, &c->queue, &c->stats_d, &c->tasks, &c->counts32,
-                     &c->alm_dbg, &c->conv_idx, &c->conv32, &c->conv64, &c->regions, &c->bin_pairs, &c->bin_dd,
-                     &c->edge_tab, &c->edge_io, &c->pv_keys, &c->pv_idx, &c->pv_head, &c->pv_slot,
-                     &c->pv_bsum, &c->pv_tmp, &c->pv_rec, &c->pv_w64, &c->dg_rec, &c->dg_w64,
-                     &c->dg_zeta, &c->dg_stats, &c->dg_pairs, &c->dg_dd};
-    for (DevBuf* b : all) release(*b);
+    for (DevBuf* b : all_bufs(c)) release(*b);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     for (auto& e : c->ev)
       if (e) (void)hipEventDestroy(e);
@@ -999,6 +1013,17 @@ int tpcf_set_tuning(tpcf_ctx* c, double points_per_cell, int waves_per_cu, int s
   if (points_per_cell > 0.0) c->ppc = points_per_cell;
   if (waves_per_cu > 0) c->waves_per_cu = waves_per_cu;
   if (scratch_blocks > 0) c->scratch_blocks = scratch_blocks;
+  c->err.clear();
+  return TPCF_OK;
+}
+
+int tpcf_set_allocator(tpcf_ctx* c, tpcf_alloc_fn alloc, tpcf_free_fn free_, void* user) {
+  if (!c) return TPCF_E_INVALID_ARG;
+  if ((alloc == nullptr) != (free_ == nullptr))
+    return fail(c, TPCF_E_INVALID_ARG, "alloc and free must both be set or both be NULL");
+  c->alloc_fn = alloc;
+  c->free_fn = free_;
+  c->alloc_user = alloc ? user : nullptr;
   c->err.clear();
   return TPCF_OK;
 }
@@ -1397,13 +1422,13 @@ int tpcf_debug_pair_counts(tpcf_ctx* c, int64_t* counts) {
   int rc;
   DevBuf tmp;
   const size_t tot = (size_t)c->ntot * c->dbg_nb;
-  if ((rc = ensure_device(c))) return rc;
-  HIP_TRY(c, hipMalloc(&tmp.p, std::max<size_t>(8, tot * 8)));
+  if ((rc = ensure_device(c)) || (rc = ensure(c, tmp, std::max<size_t>(8, tot * 8), "debug staging"))) return rc;
   unsort_counts((const int32_t*)c->counts32.p, (const uint32_t*)c->perm.p, (int64_t*)tmp.p, (uint32_t)c->ntot,
                 c->dbg_nb, c->stream);
   hipError_t e = hipMemcpyAsync(counts, tmp.p, tot * 8, hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  (void)hipFree(tmp.p);
+  if (e != hipSuccess) (void)hipStreamSynchronize(c->stream);
+  release(tmp);
   if (e != hipSuccess) return hip_fail(c, e, "tpcf_debug_pair_counts");
   return TPCF_OK;
 }
@@ -1415,13 +1440,13 @@ int tpcf_debug_alm(tpcf_ctx* c, double* alm) {
   DevBuf tmp;
   const int row = c->dbg_nb * c->dbg_nc;
   const size_t tot = (size_t)c->ntot * row;
-  if ((rc = ensure_device(c))) return rc;
-  HIP_TRY(c, hipMalloc(&tmp.p, std::max<size_t>(8, tot * 8)));
+  if ((rc = ensure_device(c)) || (rc = ensure(c, tmp, std::max<size_t>(8, tot * 8), "debug staging"))) return rc;
   unsort_alm(c->alm_dbg.p, c->dbg_f64, (const uint32_t*)c->perm.p, (double*)tmp.p, (uint32_t)c->ntot, row,
              c->stream);
   hipError_t e = hipMemcpyAsync(alm, tmp.p, tot * 8, hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  (void)hipFree(tmp.p);
+  if (e != hipSuccess) (void)hipStreamSynchronize(c->stream);
+  release(tmp);
   if (e != hipSuccess) return hip_fail(c, e, "tpcf_debug_alm");
   return TPCF_OK;
 }

@@ -68,6 +68,11 @@ def test_precision_and_tuning_validation():
     assert _code(c.set_tuning, 0.0, 0, 100) == 1  # not a multiple of 64
     c.set_tuning(20.0, 4, 256)
     assert _code(c.degenerate) == 2  # no bins, no catalogue
+    lib = ctypes.CDLL(tpcf.library_path())
+    cb = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)(lambda p, u: None)
+    lib.tpcf_set_allocator.argtypes = [ctypes.c_void_p] * 4
+    assert lib.tpcf_set_allocator(c._h, None, ctypes.cast(cb, ctypes.c_void_p), None) == 1
+    assert lib.tpcf_set_allocator(c._h, None, None, None) == 0
     assert _code(c.set_phase_aligned, 2) == 1
     assert _code(c.set_phase_aligned, -2) == 1
     for mode in (-1, 0, 1):
