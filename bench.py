@@ -47,6 +47,16 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+PHASE_ALIGNED = -1  # --phase-aligned: -1 by neighbourhood size, 0 off, 1 on
+
+
+def make_ctx(tpcf, stream):
+    """A library context on device 0 and `stream`, with the run's phase-alignment setting."""
+    ctx = tpcf.Context(0, stream)
+    ctx.set_phase_aligned(PHASE_ALIGNED)
+    return ctx
+
+
 def make_catalog():
     import catalogs
 
@@ -60,7 +70,7 @@ def make_catalog():
 def time_path(tpcf, torch, dev, precision, steps, warmup, autotune=True):
     """Times `steps` hot-path steps; returns (ms_per_step, mean sweep ms, stats, zeta, tuning).
     The autotuner (if on) runs once before the warmup, outside the timed steps."""
-    ctx = tpcf.Context(0, torch.cuda.current_stream())
+    ctx = make_ctx(tpcf, torch.cuda.current_stream())
     ctx.set_bins(NB, RMIN, RMAX, LMAX)
     ctx.set_precision(precision)
 
@@ -198,7 +208,7 @@ def run_sphere_batch(args):
     torch.cuda.synchronize()
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        ctx = tpcf.Context(0, stream)
+        ctx = make_ctx(tpcf, stream)
         ctx.set_bins(nb, tmin, tmax, mmax)
         ctx.set_precision("mixed")
         ctx.set_sphere_catalog(*[t[:n] for t in dev])
@@ -268,7 +278,7 @@ def run_batch(args):
     torch.cuda.synchronize()
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        ctx = tpcf.Context(0, stream)
+        ctx = make_ctx(tpcf, stream)
         ctx.set_bins(NB, RMIN, RMAX, LMAX)
         ctx.set_precision("mixed")
         tuning = None
@@ -364,7 +374,7 @@ def run_dmr(args):
     res = {}
     ranges = [(0, 24), (4_000_000, 4_000_024)]  # 24 data primaries, 24 random primaries
     for prec, steps in (("mixed", args.steps), ("fp64", 1)):
-        ctx = tpcf.Context(0, torch.cuda.current_stream())
+        ctx = make_ctx(tpcf, torch.cuda.current_stream())
         ctx.set_bins(NB, RMIN, RMAX, LMAX)
         ctx.set_precision(prec)
         ctx.set_catalog(*dev, box=cat.box, periodic=False)
@@ -452,7 +462,7 @@ def run_pivots(args):
     torch.cuda.synchronize()
 
     def timed(prec, side):
-        ctx = tpcf.Context(0, torch.cuda.current_stream())
+        ctx = make_ctx(tpcf, torch.cuda.current_stream())
         ctx.set_bins(NB, RMIN, RMAX, LMAX)
         ctx.set_precision(prec)
         ctx.set_tuning(16.0, 8)
@@ -527,12 +537,11 @@ def run_sphere_large(args):
 
     dev = [torch.from_numpy(a).cuda() for a in (x, y, z, w)]
     torch.cuda.synchronize()
-    ctx = tpcf.Context(0, torch.cuda.current_stream())
+    ctx = make_ctx(tpcf, torch.cuda.current_stream())
     ctx.set_bins(nb, tmin, tmax, mmax)
     ctx.set_precision("mixed")
     ppc, wpc = (float(v) for v in (args.tuning or "16,12").split(","))
     ctx.set_tuning(ppc, int(wpc))
-    ctx.set_phase_aligned(args.phase_aligned)
     t1 = time.perf_counter()
     ctx.set_sphere_catalog(*dev)
     torch.cuda.synchronize()
@@ -569,11 +578,10 @@ def run_sphere_large(args):
     sep = math.sqrt(4.0 * math.pi / n)
     piv = []
     for f in (float(v) for v in args.pivot_cells.split(",") if v):
-        ctx = tpcf.Context(0, torch.cuda.current_stream())
+        ctx = make_ctx(tpcf, torch.cuda.current_stream())
         ctx.set_bins(nb, tmin, tmax, mmax)
         ctx.set_precision("mixed")
         ctx.set_tuning(ppc, int(wpc))
-        ctx.set_phase_aligned(args.phase_aligned)
         ctx.set_pivot_cell(f * sep)
         t1 = time.perf_counter()
         ctx.set_sphere_catalog(*dev)
@@ -641,7 +649,7 @@ def run_sphere(args):
     res, zfull, tunings = {}, {}, {}
     ranges = [(0, 24), (m.n // 2, m.n // 2 + 24), (m.n - 24, m.n)]
     for prec, steps in (("mixed", args.steps), ("fp64", max(1, min(args.steps, 2)))):
-        ctx = tpcf.Context(0, torch.cuda.current_stream())
+        ctx = make_ctx(tpcf, torch.cuda.current_stream())
         ctx.set_bins(nb, tmin, tmax, mmax)
         ctx.set_precision(prec)
         ctx.set_sphere_catalog(*dev)
@@ -686,7 +694,7 @@ def run_sphere(args):
     z64 = zfull["fp64"]
     piv = []
     for f in (1.0, 2.0, 4.0):
-        ctx = tpcf.Context(0, torch.cuda.current_stream())
+        ctx = make_ctx(tpcf, torch.cuda.current_stream())
         ctx.set_bins(nb, tmin, tmax, mmax)
         ctx.set_precision("mixed")
         t = tunings["mixed"] or {}
@@ -712,7 +720,7 @@ def run_sphere(args):
     # N from the masked values, R from the mask; corrected against the full sky's own correction
     dec = np.arcsin(np.clip(m.z, -1.0, 1.0))
     keep = torch.from_numpy((np.abs(dec) > np.radians(10.0)) & (dec < np.radians(60.0))).cuda()
-    ctx = tpcf.Context(0, torch.cuda.current_stream())
+    ctx = make_ctx(tpcf, torch.cuda.current_stream())
     ctx.set_bins(nb, tmin, tmax, mmax)
     ctx.set_precision("mixed")
     t = tunings["mixed"] or {}
@@ -805,8 +813,7 @@ def main():
     ap.add_argument("--pivot-cells", default="2,4", help="sphere form above nside 1024: shared-pivot cells "
                                                          "in mean pixel separations")
     ap.add_argument("--phase-aligned", type=int, default=-1, choices=(-1, 0, 1),
-                    help="sphere form above nside 1024: phase-aligned stencil sweeps (-1 by neighbourhood "
-                         "size, 0 off, 1 on)")
+                    help="phase-aligned stencil sweeps (-1 by neighbourhood size, 0 off, 1 on)")
     ap.add_argument("--exact-chunks", type=int, default=0, help="sphere form above nside 1024: time the exact "
                                                                 "sum on this many of the --chunks ranges (0: all)")
     args = ap.parse_args()
@@ -814,6 +821,8 @@ def main():
         print("bench.py measures one GPU only: the library has no multi-GPU path "
               f"(asked for --gpus {args.gpus}).", file=sys.stderr)
         sys.exit(2)
+    global PHASE_ALIGNED
+    PHASE_ALIGNED = args.phase_aligned
     if args.workload == "batch":
         run_batch(args)
         return

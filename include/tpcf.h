@@ -146,7 +146,7 @@ int tpcf_set_allocator(tpcf_ctx* ctx, tpcf_alloc_fn alloc, tpcf_free_fn free_, v
  * of a different summation order, pair counts are identical). Each wave takes the stencil rows of
  * its primary in a rotated order that starts where the waves in flight currently are, so that they
  * read the same records at about the same time and share them through L2. mode -1 (default):
- * on when the expected neighbourhood of one primary exceeds 1 MiB of records; 0: off; 1: on.
+ * on when the expected neighbourhood of one primary exceeds 2 MiB of records; 0: off; 1: on.
  * Takes effect at the next compute call. Errors: TPCF_E_INVALID_ARG for another mode.
  */
 int tpcf_set_phase_aligned(tpcf_ctx* ctx, int mode);
