@@ -420,10 +420,12 @@ class Context:
         return {k: getattr(s, k) for k, _ in Stats._fields_}
 
 
-def zeta_sphere(x, y, z, w=None, *, theta_min: float, theta_max: float, nbins: int, mmax: int,
+def zeta_sphere(x, y=None, z=None, w=None, *, theta_min: float, theta_max: float, nbins: int, mmax: int,
                 precision="fp64", device: int = 0, stream=None):
-    """zeta_m(b1, b2) of a field on the unit sphere (unit vectors x, y, z; angles in radians),
-    float64 [(mmax+1), nbins, nbins]."""
+    """zeta_m(b1, b2) of a field on the unit sphere (unit vectors x, y, z or one [N, 3] array x;
+    angles in radians), float64 [(mmax+1), nbins, nbins]."""
+    if y is None and z is None:
+        x, y, z = _columns(x)
     with Context(device, stream) as ctx:
         ctx.set_bins(nbins, theta_min, theta_max, mmax)
         ctx.set_precision(precision)
@@ -431,9 +433,69 @@ def zeta_sphere(x, y, z, w=None, *, theta_min: float, theta_max: float, nbins: i
         return ctx.compute_zeta(device_output=_is_torch(x) and x.is_cuda)
 
 
-def zeta(x, y, z, w=None, *, box: float, periodic: bool = True, rmin: float, rmax: float,
+def _columns(pos):
+    """(x, y, z) of an [N, 3] position array (numpy or torch), each contiguous."""
+    if _is_torch(pos):
+        return tuple(pos[:, k].contiguous() for k in range(3))
+    pos = np.asarray(pos, dtype=np.float64)
+    if pos.ndim != 2 or pos.shape[1] != 3:
+        raise ValueError("positions must be an [N, 3] array or three arrays x, y, z")
+    return tuple(np.ascontiguousarray(pos[:, k]) for k in range(3))
+
+
+def _concat(cats):
+    """offsets and concatenated x, y, z, w (w None if no catalogue has weights) of a sequence of
+    catalogues, each (x, y, z), (x, y, z, w) or ([N, 3] positions, w)."""
+    parts = []
+    for c in cats:
+        c = tuple(c)
+        if len(c) == 2:
+            parts.append((*_columns(c[0]), c[1]))
+        elif len(c) in (3, 4):
+            parts.append((c[0], c[1], c[2], c[3] if len(c) == 4 else None))
+        else:
+            raise ValueError("a catalogue is (x, y, z), (x, y, z, w) or (positions, w)")
+    host = [tuple(None if a is None else (a.detach().cpu().numpy() if _is_torch(a) else np.asarray(a, dtype=np.float64))
+                  for a in p) for p in parts]
+    n = [len(p[0]) for p in host]
+    offsets = np.concatenate([[0], np.cumsum(n)]).astype(np.int64)
+    xyz = [np.concatenate([p[k] for p in host]) if host else np.zeros(0) for k in range(3)]
+    w = None
+    if any(p[3] is not None for p in host):
+        w = np.concatenate([p[3] if p[3] is not None else np.ones(len(p[0])) for p in host])
+    return offsets, xyz[0], xyz[1], xyz[2], w
+
+
+def zeta_batch(catalogues, *, box, periodic=True, rmin: float, rmax: float, nbins: int, lmax: int,
+               precision="mixed", device: int = 0, stream=None):
+    """zeta_l of many independent catalogues in one persistent launch (tpcf_compute_batch):
+    catalogues is a sequence of (x, y, z), (x, y, z, w) or ([N, 3] positions, w); box and periodic
+    are one value or one per catalogue. float64 [ncat, (lmax+1), nbins, nbins]."""
+    offsets, x, y, z, w = _concat(catalogues)
+    with Context(device, stream) as ctx:
+        ctx.set_bins(nbins, rmin, rmax, lmax)
+        ctx.set_precision(precision)
+        return ctx.compute_batch(offsets, x, y, z, w, box, periodic)
+
+
+def zeta_sphere_batch(maps, *, theta_min: float, theta_max: float, nbins: int, mmax: int, precision="mixed",
+                      device: int = 0, stream=None):
+    """zeta_m of many independent maps on the unit sphere in one launch (tpcf_compute_sphere_batch):
+    maps is a sequence of (x, y, z), (x, y, z, w) or ([N, 3] unit vectors, w).
+    float64 [nmaps, (mmax+1), nbins, nbins]."""
+    offsets, x, y, z, w = _concat(maps)
+    with Context(device, stream) as ctx:
+        ctx.set_bins(nbins, theta_min, theta_max, mmax)
+        ctx.set_precision(precision)
+        return ctx.compute_sphere_batch(offsets, x, y, z, w)
+
+
+def zeta(x, y=None, z=None, w=None, *, box: float, periodic: bool = True, rmin: float, rmax: float,
          nbins: int, lmax: int, precision="fp64", device: int = 0, stream=None):
-    """zeta_l(b1, b2) of one catalogue, float64 [(lmax+1), nbins, nbins]."""
+    """zeta_l(b1, b2) of one catalogue, float64 [(lmax+1), nbins, nbins]. Positions are x, y, z or
+    one [N, 3] array x (numpy or torch) with y = z = None."""
+    if y is None and z is None:
+        x, y, z = _columns(x)
     with Context(device, stream) as ctx:
         ctx.set_bins(nbins, rmin, rmax, lmax)
         ctx.set_precision(precision)

@@ -190,3 +190,23 @@ def test_pivot_cell_validation_on_host():
     c.set_pivot_cell(-1.0)
     c.set_pivot_cell(0.0)
     assert tpcf._lib.tpcf_set_pivot_cell(None, 1.0) == 1
+
+
+def test_one_call_forms_marshal_catalogues():
+    """Host-side marshalling of the one-call batch forms: offsets, concatenation, unit weights for a
+    catalogue given without them, [N, 3] positions split into columns."""
+    rng = np.random.default_rng(1)
+    a = rng.random((5, 3))
+    b = [rng.random(3) for _ in range(3)]
+    wb = rng.random(3)
+    off, x, y, z, w = tpcf._concat([(a, None), (b[0], b[1], b[2], wb), (b[0], b[1], b[2])])
+    np.testing.assert_array_equal(off, [0, 5, 8, 11])
+    np.testing.assert_array_equal(x, np.concatenate([a[:, 0], b[0], b[0]]))
+    np.testing.assert_array_equal(z, np.concatenate([a[:, 2], b[2], b[2]]))
+    np.testing.assert_array_equal(w, np.concatenate([np.ones(5), wb, np.ones(3)]))
+    off, x, y, z, w = tpcf._concat([(b[0], b[1], b[2])])
+    assert w is None and list(off) == [0, 3]
+    with pytest.raises(ValueError):
+        tpcf._columns(rng.random((4, 2)))
+    with pytest.raises(ValueError):
+        tpcf._concat([(b[0],)])

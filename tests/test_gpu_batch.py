@@ -162,3 +162,31 @@ def test_batch_at_full_mock_sizes(tpcf):
         say(f"mock {k}: n={c.n} batch vs single {err:.2e}")
         assert err < 1e-6
     assert pairs_b == total
+
+
+def test_one_call_forms(tpcf):
+    """tpcf.zeta with [N, 3] positions, tpcf.zeta_batch over catalogues given in the three accepted
+    forms, and tpcf.zeta_sphere_batch over two maps, each against the oracle."""
+    a = catalogs.uniform(2000, 150.0, 301)
+    b = catalogs.uniform(1500, 150.0, 302)
+    c = catalogs.uniform(2500, 150.0, 303)
+    wb = catalogs.gaussian_weights(b.n, 304, 1.0, 0.3)
+    say("one-call forms")
+    pos = np.stack([a.x, a.y, a.z], 1)
+    z1 = tpcf.zeta(pos, box=150.0, periodic=True, rmin=4.0, rmax=30.0, nbins=6, lmax=3)
+    r1 = oracle.zeta(a.x, a.y, a.z, None, 150.0, True, 6, 4.0, 30.0, 3)
+    assert rel_err_per_l(z1, r1.zeta).max() <= 1e-10
+    zb = tpcf.zeta_batch([(pos, None), (b.x, b.y, b.z, wb), (c.x, c.y, c.z)], box=150.0, periodic=[True, False, True],
+                         rmin=4.0, rmax=30.0, nbins=6, lmax=3)
+    assert zb.shape == (3, 4, 6, 6)
+    refs = [r1.zeta, oracle.zeta(b.x, b.y, b.z, wb, 150.0, False, 6, 4.0, 30.0, 3).zeta,
+            oracle.zeta(c.x, c.y, c.z, None, 150.0, True, 6, 4.0, 30.0, 3).zeta]
+    for k in range(3):
+        assert rel_err_per_l(zb[k], refs[k]).max() <= 1e-5
+    maps = [catalogs.sphere_map(16, 7 + k, grid=32) for k in range(2)]
+    zs = tpcf.zeta_sphere_batch([(m.x, m.y, m.z, m.w) for m in maps], theta_min=0.05, theta_max=0.4, nbins=5,
+                                mmax=4)
+    for k, m in enumerate(maps):
+        ref = oracle.zeta_sphere(m.x, m.y, m.z, m.w, 5, 0.05, 0.4, 4).zeta
+        assert rel_err_per_l(zs[k], ref).max() <= 1e-5
+
