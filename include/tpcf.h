@@ -147,6 +147,8 @@ int tpcf_set_allocator(tpcf_ctx* ctx, tpcf_alloc_fn alloc, tpcf_free_fn free_, v
  * its primary in a rotated order that starts where the waves in flight currently are, so that they
  * read the same records at about the same time and share them through L2. mode -1 (default):
  * on when the expected neighbourhood of one primary exceeds 2 MiB of records; 0: off; 1: on.
+ * Stencils of more than 4096 rows (grids far finer than the search radius) keep their natural
+ * order either way.
  * Takes effect at the next compute call. Errors: TPCF_E_INVALID_ARG for another mode.
  */
 int tpcf_set_phase_aligned(tpcf_ctx* ctx, int mode);

@@ -128,3 +128,13 @@ def test_degenerate_batch_and_pivots(tpcf):
     ctx.compute_zeta()
     ref = oracle.degenerate(c.x, c.y, c.z, wc, c.box, True, 8, 5.0, 40.0, 4)
     assert _rel(ctx.degenerate()[0], ref) <= TOL
+
+
+def test_degenerate_empty_catalogue(tpcf):
+    ctx = tpcf.Context(0)
+    ctx.set_bins(5, 1.0, 10.0, 2)
+    ctx.set_catalog(np.zeros(0), np.zeros(0), np.zeros(0), None, box=50.0, periodic=True)
+    assert np.abs(ctx.compute_zeta()).max() == 0.0
+    D = ctx.degenerate()
+    assert D.shape == (1, 3, 5) and np.abs(D).max() == 0.0
+

@@ -115,3 +115,19 @@ def test_phase_aligned_range_and_batch(tpcf):
             assert np.abs(zb[k]).max() == 0.0
         else:
             assert rel_err_per_l(zb[k], ref.zeta).max() <= TOL["mixed"]
+
+
+def test_phase_aligned_beyond_64_row_chunks(tpcf):
+    """A stencil of more than 64 row chunks (0.005 points per cell: 158 cells per axis, 67 x 67 =
+    4,489 rows) keeps its natural row order, as documented; results as usual."""
+    cat = catalogs.uniform(20000, 250.0, 45)
+    say("phase: stencil beyond 4096 rows")
+
+    def setup(ctx):
+        ctx.set_catalog(cat.x, cat.y, cat.z, None, box=cat.box, periodic=True)
+
+    on, zon = run(tpcf, setup, 1, "fp64", 6, 4.0, 50.0, 3, 0.005)
+    ref = oracle.zeta(cat.x, cat.y, cat.z, None, cat.box, True, 6, 4.0, 50.0, 3, want_counts=True)
+    assert rel_err_per_l(zon, ref.zeta).max() <= TOL["fp64"]
+    np.testing.assert_array_equal(on.pair_counts(), ref.counts)
+
