@@ -11,7 +11,11 @@
  * This is the harmonic decomposition of the triangle angle that the paper's Implementation
  * section builds its fast estimator on (per pivot: find all neighbours in range, fill the
  * multipole bins), written for 3D positions with spherical harmonics as in the works the paper
- * cites (Szapudi 2004; Slepian & Eisenstein 2015).
+ * cites (Szapudi 2004; Slepian & Eisenstein 2015). Fields on the unit sphere, the paper's own
+ * workload, use the 2D multipoles of the position angle instead (tpcf_set_sphere_catalog).
+ * Beside zeta: the two-point by-product (tpcf_pair_sums), the degenerate j = k term
+ * (tpcf_degenerate), edge corrections (tpcf_edge_correct, tpcf_edge_correct_sphere), batches of
+ * catalogues in one launch, and an opt-in shared-pivot approximation (tpcf_set_pivot_cell).
  *
  * Conventions fixed by the library (the paper gives no formula):
  *   - Positions are snapped to a lattice of spacing L / 2^K, K = 25 + floor(log2(L / r_max)),
@@ -20,7 +24,7 @@
  *   - Bins are linear and half-open: [r_min + k D, r_min + (k+1) D), D = (r_max - r_min)/nbins.
  *   - Periodic boxes use the minimum image and need r_max < L/2.
  *   - Y_lm is orthonormal with the Condon-Shortley phase; the j = k (same secondary on both
- *     legs) term is included; pairs at zero separation are skipped.
+ *     legs) term is included (tpcf_degenerate returns it); pairs at zero separation are skipped.
  *   - zeta is written as double [(lmax+1)][nbins][nbins], row-major.
  *
  * Every function returns a status code (TPCF_OK = 0). No C++ exception crosses this boundary.
