@@ -362,15 +362,18 @@ int tpcf_edge_correct_sphere(tpcf_ctx* ctx, int ncat, const double* N, const dou
  * sqrt(4 pi / n) on the sphere; side = 0 (default) is the exact estimator. On the sphere the
  * cells are those of the unit-vector cube (side in its units, about radians at small angles), a
  * pivot sits at its members' rounded mean lattice position (just inside the sphere) and its
- * position angles are measured in the tangent plane at that point's direction. The error falls with the cell side (the tests and the
- * benchmark measure it against the exact estimator); stats report the pivot count as
- * n_primaries. Applies to tpcf_compute_zeta on a catalogue set by tpcf_set_catalog or
- * tpcf_set_sphere_catalog.
+ * position angles are measured in the tangent plane at that point's direction. The error falls
+ * with the cell side (the tests and the benchmark measure it against the exact estimator); stats
+ * report the pivot count as n_primaries. Applies to tpcf_compute_zeta and to the batch calls
+ * (tpcf_compute_batch, tpcf_compute_sphere_batch), where every catalogue gets its own pivots, with
+ * side in its own units (side < 0: its own mean separation); batches with pivots launch eagerly,
+ * not from a graph.
  * The compute call synchronises the context's stream once (to learn the pivot count). The
  * autotuner times the exact sweep, not the shared pivots.
  * Errors: TPCF_E_INVALID_ARG (side not finite). A compute call fails with TPCF_E_UNSUPPORTED for
- * ranges and batches, and with TPCF_E_INVALID_ARG when the pivot cells number more than 2^21 per
- * axis (cells of at least 2^-21 of the cube's side) or, on the sphere, are larger than 0.25.
+ * primary ranges, and with TPCF_E_INVALID_ARG when the pivot cells number more than 2^B per axis
+ * (B = 21 for one catalogue, floor((63 - ceil(log2 ncat)) / 3) for a batch of ncat) or, on the
+ * sphere, are larger than 0.25.
  * Debug output (per-point counts, a_lm) is not kept.
  */
 int tpcf_set_pivot_cell(tpcf_ctx* ctx, double side);

@@ -35,10 +35,12 @@ hipError_t launch_edge_correct(int ncat, int lmax, int nb, const double* N, cons
 hipError_t launch_edge_correct_sphere(int ncat, int mmax, int nb, const double* N, const double* R, double* out,
                                       hipStream_t s);
 size_t pivot_sort_bytes(uint32_t n);
-hipError_t build_pivots(const uint4* rec, const double* w64, uint32_t n, int sh, uint64_t Hq,
-                        unsigned long long* key_a, unsigned long long* key_b, uint32_t* idx_a, uint32_t* idx_b,
-                        uint32_t* head, uint32_t* slot, uint32_t* block_sum, void* sort_tmp, size_t sort_bytes,
-                        uint4* prim_rec, double* prim_w, hipStream_t s);
+int pivot_axis_bits(int ncat);
+hipError_t build_pivots(const uint4* rec, const double* w64, uint32_t n, const CatDesc* cats, int ncat,
+                        const unsigned long long* hq, unsigned long long* key_a, unsigned long long* key_b,
+                        uint32_t* idx_a, uint32_t* idx_b, uint32_t* head, uint32_t* slot, uint32_t* block_sum,
+                        void* sort_tmp, size_t sort_bytes, uint4* prim_rec, double* prim_w, uint32_t* start,
+                        hipStream_t s);
 }  // namespace tpcf
 
 using namespace tpcf;
@@ -112,7 +114,7 @@ struct tpcf_ctx {
   DevBuf dg_rec, dg_w64, dg_zeta, dg_stats, dg_pairs, dg_dd;
   // shared pivots: pivot cell side (0 = exact, < 0 = the mean separation), cell tables, pivots
   double pivot_h = 0.0;
-  DevBuf pv_keys, pv_idx, pv_head, pv_slot, pv_bsum, pv_tmp, pv_rec, pv_w64;
+  DevBuf pv_keys, pv_idx, pv_head, pv_slot, pv_bsum, pv_tmp, pv_rec, pv_w64, pv_hq, pv_start;
   int edge_lmax = -1;
   bool sums_valid = false;
   int sums_ncat = 0, sums_nb = 0;
@@ -164,7 +166,7 @@ std::vector<DevBuf*> all_bufs(tpcf_ctx* c) {
           &c->scratch, &c->tile, &c->zeta_d, &c->queue, &c->stats_d, &c->tasks, &c->counts32,
           &c->alm_dbg, &c->conv_idx, &c->conv32, &c->conv64, &c->regions, &c->bin_pairs, &c->bin_dd,
           &c->edge_tab, &c->edge_io, &c->pv_keys, &c->pv_idx, &c->pv_head, &c->pv_slot,
-          &c->pv_bsum, &c->pv_tmp, &c->pv_rec, &c->pv_w64, &c->dg_rec, &c->dg_w64,
+          &c->pv_bsum, &c->pv_tmp, &c->pv_rec, &c->pv_w64, &c->pv_hq, &c->pv_start, &c->dg_rec, &c->dg_w64,
           &c->dg_zeta, &c->dg_stats, &c->dg_pairs, &c->dg_dd};
 }
 
@@ -795,23 +797,30 @@ bool graphs_enabled() {
 // sqrt(4 pi / n) on the sphere. Builds the pivots on the stream and returns their number G
 // (synchronises).
 int prepare_pivots(tpcf_ctx* c, uint32_t& G) {
-  const CatDesc& d = c->cd[0];
-  const HostCat& h = c->cats[0];
-  double side = c->pivot_h;
-  if (side < 0.0) {
-    if (h.n == 0) side = h.box;
-    else side = h.sphere ? sqrt(4.0 * kPi / (double)h.n) : h.box / cbrt((double)h.n);
+  const int ncat = (int)c->cats.size();
+  const int B = pivot_axis_bits(ncat);
+  std::vector<unsigned long long> hq(ncat);
+  for (int k = 0; k < ncat; ++k) {
+    const CatDesc& d = c->cd[k];
+    const HostCat& h = c->cats[k];
+    double side = c->pivot_h;
+    if (side < 0.0) {
+      if (h.n == 0) side = h.box;
+      else side = h.sphere ? sqrt(4.0 * kPi / (double)h.n) : h.box / cbrt((double)h.n);
+    }
+    // On the sphere a cell must stay well below the radius: a pivot is its members' mean position,
+    // which must keep a direction.
+    if (h.sphere && side > 0.25) return fail(c, TPCF_E_INVALID_ARG, "pivot cell on the sphere must be at most 0.25");
+    const uint64_t span = (uint64_t)1 << d.K;
+    double q = floor(side * d.scale);
+    if (!(q >= 1.0)) q = 1.0;
+    if (q > (double)span) q = (double)span;
+    hq[k] = (unsigned long long)q;
+    if ((span + hq[k] - 1) / hq[k] > ((uint64_t)1 << B))
+      return fail(c, TPCF_E_INVALID_ARG,
+                  "pivot cell too small: more than 2^" + std::to_string(B) + " pivot cells per axis" +
+                      (ncat > 1 ? " in a batch of " + std::to_string(ncat) + " catalogues" : std::string()));
   }
-  // On the sphere a cell must stay well below the radius: a pivot is its members' mean position,
-  // which must keep a direction.
-  if (h.sphere && side > 0.25) return fail(c, TPCF_E_INVALID_ARG, "pivot cell on the sphere must be at most 0.25");
-  const uint64_t span = (uint64_t)1 << d.K;
-  double hq = floor(side * d.scale);
-  if (!(hq >= 1.0)) hq = 1.0;
-  if (hq > (double)span) hq = (double)span;
-  const uint64_t Hq = (uint64_t)hq;
-  if ((span + Hq - 1) / Hq > ((uint64_t)1 << 21))
-    return fail(c, TPCF_E_INVALID_ARG, "pivot cell too small: more than 2^21 pivot cells per axis");
   const size_t n = (size_t)c->ntot;
   const size_t sort_bytes = pivot_sort_bytes((uint32_t)n);
   int rc;
@@ -819,14 +828,18 @@ int prepare_pivots(tpcf_ctx* c, uint32_t& G) {
       (rc = ensure(c, c->pv_head, (n + 1) * 4, "pivot keys")) || (rc = ensure(c, c->pv_slot, (n + 1) * 4, "pivot keys")) ||
       (rc = ensure(c, c->pv_bsum, scan_block_count((uint32_t)n) * 4 + 4, "pivot keys")) ||
       (rc = ensure(c, c->pv_tmp, sort_bytes, "pivot sort")) ||
-      (rc = ensure(c, c->pv_rec, (n + 1) * 16, "pivots")) || (rc = ensure(c, c->pv_w64, (n + 1) * 8, "pivots")))
+      (rc = ensure(c, c->pv_rec, (n + 1) * 16, "pivots")) || (rc = ensure(c, c->pv_w64, (n + 1) * 8, "pivots")) ||
+      (rc = ensure(c, c->pv_hq, (size_t)ncat * 8, "pivot cells")) ||
+      (rc = ensure(c, c->pv_start, ((size_t)ncat + 1) * 4, "pivot ranges")))
     return rc;
+  HIP_TRY(c, hipMemcpyAsync(c->pv_hq.p, hq.data(), hq.size() * 8, hipMemcpyHostToDevice, c->stream));
   unsigned long long* keys = (unsigned long long*)c->pv_keys.p;
   uint32_t* idx = (uint32_t*)c->pv_idx.p;
-  HIP_TRY(c, build_pivots((const uint4*)c->rec.p, (const double*)c->w64.p, (uint32_t)n, d.sh, Hq, keys, keys + (n + 1),
-                          idx, idx + (n + 1), (uint32_t*)c->pv_head.p, (uint32_t*)c->pv_slot.p,
-                          (uint32_t*)c->pv_bsum.p, c->pv_tmp.p, sort_bytes, (uint4*)c->pv_rec.p,
-                          (double*)c->pv_w64.p, c->stream));
+  HIP_TRY(c, build_pivots((const uint4*)c->rec.p, (const double*)c->w64.p, (uint32_t)n, (const CatDesc*)c->cats_d.p,
+                          ncat, (const unsigned long long*)c->pv_hq.p, keys, keys + (n + 1), idx, idx + (n + 1),
+                          (uint32_t*)c->pv_head.p, (uint32_t*)c->pv_slot.p, (uint32_t*)c->pv_bsum.p, c->pv_tmp.p,
+                          sort_bytes, (uint4*)c->pv_rec.p, (double*)c->pv_w64.p, (uint32_t*)c->pv_start.p,
+                          c->stream));
   HIP_TRY(c, hipMemcpyAsync(&G, (uint32_t*)c->pv_slot.p + n, 4, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return TPCF_OK;
@@ -844,12 +857,8 @@ int compute(tpcf_ctx* c, int64_t p_begin, int64_t p_end, double* zeta, int memsp
   if ((rc = ensure_device(c))) return rc;
   const bool rebuild = !grid_current(c);
   const bool pivots = c->pivot_h != 0.0;
-  if (pivots) {
-    if (use_graph || c->cats.size() != 1)
-      return fail(c, TPCF_E_UNSUPPORTED, "shared pivots need a single catalogue (tpcf_set_catalog or tpcf_set_sphere_catalog)");
-    if (p_begin != 0 || p_end != c->ntot)
-      return fail(c, TPCF_E_UNSUPPORTED, "shared pivots cover the whole catalogue: no primary ranges");
-  }
+  if (pivots && (p_begin != 0 || p_end != c->ntot))
+    return fail(c, TPCF_E_UNSUPPORTED, "shared pivots cover the whole catalogue: no primary ranges");
   if (rebuild && (rc = prepare_grid(c))) return rc;
   const uint32_t* tasks = nullptr;
   uint32_t ntask = (uint32_t)c->ntot;
@@ -886,12 +895,14 @@ int compute(tpcf_ctx* c, int64_t p_begin, int64_t p_end, double* zeta, int memsp
   if (pivots) {
     a.prim_rec = (const uint4*)c->pv_rec.p;
     a.prim_w64 = (const double*)c->pv_w64.p;
+    a.prim_cat_start = (const uint32_t*)c->pv_start.p;
     a.counts = nullptr;  // per-point debug rows do not apply to pivots
     a.alm_debug = nullptr;
   }
   c->stats.waves = waves;
-  // The null stream cannot be captured: batches on it launch eagerly.
-  const bool graph = use_graph && graphs_enabled() && c->stream != nullptr;
+  // The null stream cannot be captured: batches on it launch eagerly. So do batches with shared
+  // pivots, whose pivot count is read back on the host before the sweep.
+  const bool graph = use_graph && !pivots && graphs_enabled() && c->stream != nullptr;
   if (graph) {
     // The whole device sequence (grid build + clears + persistent sweep) as one HIP graph,
     // captured once per batch shape and replayed afterwards.
@@ -1364,7 +1375,6 @@ int tpcf_compute_batch(tpcf_ctx* c, int ncat, const int64_t* offsets, const doub
   if (!c) return TPCF_E_INVALID_ARG;
   if (ncat < 1 || !offsets || !box_side || !periodic) return fail(c, TPCF_E_INVALID_ARG, "invalid batch description");
   if (!c->bins_set) return fail(c, TPCF_E_STATE, "set_bins has not been called");
-  if (c->pivot_h != 0.0) return fail(c, TPCF_E_UNSUPPORTED, "shared pivots are not available for batches");
   if (offsets[0] != 0) return fail(c, TPCF_E_INVALID_ARG, "offsets[0] must be 0");
   std::vector<HostCat> cats(ncat);
   for (int k = 0; k < ncat; ++k) {
@@ -1396,7 +1406,6 @@ int tpcf_compute_sphere_batch(tpcf_ctx* c, int ncat, const int64_t* offsets, con
   if (ncat < 1 || !offsets) return fail(c, TPCF_E_INVALID_ARG, "invalid batch description");
   if (!c->bins_set) return fail(c, TPCF_E_STATE, "set_bins has not been called");
   if (!(c->rmax <= kPi)) return fail(c, TPCF_E_INVALID_ARG, "angular bins on the sphere need theta_max <= pi");
-  if (c->pivot_h != 0.0) return fail(c, TPCF_E_UNSUPPORTED, "shared pivots are not available for batches");
   if (offsets[0] != 0) return fail(c, TPCF_E_INVALID_ARG, "offsets[0] must be 0");
   std::vector<HostCat> cats(ncat);
   for (int k = 0; k < ncat; ++k) {

@@ -22,16 +22,6 @@ namespace tpcf {
 
 constexpr int kCellSortMax = 4096;
 
-__device__ __forceinline__ int cat_of_point(const CatDesc* cats, int ncat, uint32_t i) {
-  int lo = 0, hi = ncat - 1;
-  while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if (cats[mid].point_base <= i) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
-
 // Points on the sphere must be unit vectors to within 1e-6 in |v|^2 (flag bit 8).
 __device__ __forceinline__ int unit_norm_flag(double px, double py, double pz) {
   const double r2 = px * px + py * py + pz * pz;
@@ -57,7 +47,7 @@ __global__ void k_snap(const double* __restrict__ x, const double* __restrict__ 
                        uint32_t* __restrict__ cell, uint32_t* __restrict__ hist, int* __restrict__ err) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const int c = cat_of_point(cats, ncat, i);
+  const int c = catalogue_of(cats, ncat, i);
   const CatDesc& cd = cats[c];
   double px = x[i], py = y[i], pz = z[i];
   const double pw = w ? w[i] : 1.0;
@@ -216,7 +206,7 @@ __global__ void k_validate(const double* __restrict__ x, const double* __restric
                            const CatDesc* __restrict__ cats, int ncat, int* __restrict__ err) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const CatDesc& cd = cats[cat_of_point(cats, ncat, i)];
+  const CatDesc& cd = cats[catalogue_of(cats, ncat, i)];
   const double px = x[i], py = y[i], pz = z[i], pw = w ? w[i] : 1.0;
   int bad = 0;
   if (!isfinite(px) || !isfinite(py) || !isfinite(pz) || !isfinite(pw)) bad |= 1;

@@ -589,15 +589,6 @@ __device__ __noinline__ void contract_tile(const double* __restrict__ tile, cons
 // ------------------------------------------------------------------------------------------
 // The persistent sweep kernel.
 // ------------------------------------------------------------------------------------------
-__device__ __forceinline__ int find_cat(const CatDesc* cats, int ncat, uint32_t p) {
-  int lo = 0, hi = ncat - 1;
-  while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if (cats[mid].point_base <= p) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
 
 template <class T>
 __device__ __forceinline__ T uniform(T v) {
@@ -807,7 +798,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sw
     t = uniform(t);
     if (t >= a.ntask) break;
     const uint32_t p = uniform(a.task_list ? a.task_list[t] : t);
-    const int cat = uniform(find_cat(a.cats, a.ncat, p));
+    const int cat = uniform(a.prim_cat_start ? range_of([&](int k) { return a.prim_cat_start[k]; }, a.ncat, p)
+                                             : catalogue_of(a.cats, a.ncat, p));
     if (cat != tile_cat) {
       do_contract();
       tile_cat = cat;

@@ -62,6 +62,7 @@ struct SweepArgs {
   const uint32_t* task_list;    // NULL: task t is sorted position t
   const uint4* prim_rec;        // optional: task t is the pivot prim_rec[t] (shared pivots), not a point
   const double* prim_w64;       // FP64 weights of those pivots
+  const uint32_t* prim_cat_start;  // with pivots: catalogue k owns pivots [start[k], start[k+1])
   uint32_t ntask;
   int32_t phase_rows;           // 1: each wave starts its stencil at the row matching its ticket's phase
   uint32_t* queue;              // [0] task ticket counter
@@ -82,6 +83,24 @@ struct SweepArgs {
 };
 
 constexpr int kConvTerms = 6;
+
+// Index k of the range [start(k), start(k+1)) holding i, for non-decreasing starts with start(0) = 0
+// (binary search; empty ranges are skipped).
+template <class Start>
+__host__ __device__ __forceinline__ int range_of(Start start, int n, uint32_t i) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start(mid) <= i) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Catalogue of sorted point i.
+__device__ __forceinline__ int catalogue_of(const CatDesc* cats, int ncat, uint32_t i) {
+  return range_of([&](int k) { return cats[k].point_base; }, ncat, i);
+}
 
 // Components per primary and bin: (lmax+1)^2 real numbers in 3D; on the sphere 2 m_max + 1
 // (Re a_0, then Re and Im of a_m for m = 1..m_max).

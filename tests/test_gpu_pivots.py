@@ -71,8 +71,8 @@ def test_one_point_per_cell_is_exact(tpcf):
 
 
 def test_mean_separation_default_and_errors(tpcf):
-    """side < 0 uses the mean separation L / n^(1/3); ranges, batches and more than 2^21 pivot
-    cells per axis are refused."""
+    """side < 0 uses the mean separation L / n^(1/3); ranges and more than 2^21 pivot cells per
+    axis are refused."""
     cat = catalogs.lognormal(4000, 120.0, 6, grid=64)
     ctx, z = run(tpcf, cat, None, 6, 4.0, 24.0, 3, "fp64", -1.0)
     h = 120.0 / np.cbrt(4000.0)
@@ -81,11 +81,6 @@ def test_mean_separation_default_and_errors(tpcf):
     assert rel_err_per_l(z, ref.zeta).max() <= TOL["fp64"]
     with pytest.raises(tpcf.TpcfError) as e:
         ctx.compute_zeta_range(0, 10)
-    assert e.value.code == 5
-    x = np.concatenate([cat.x, cat.x])
-    with pytest.raises(tpcf.TpcfError) as e:
-        ctx.compute_batch([0, cat.n, 2 * cat.n], x, np.concatenate([cat.y, cat.y]), np.concatenate([cat.z, cat.z]),
-                          None, 120.0, True)
     assert e.value.code == 5
     with pytest.raises(tpcf.TpcfError) as e:
         ctx.set_pivot_cell(float("nan"))
@@ -119,6 +114,58 @@ def test_sphere_pivots_match_oracle(tpcf, prec):
     with pytest.raises(tpcf.TpcfError) as e:
         ctx.compute_zeta()
     assert e.value.code == 1
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batch_pivots_match_oracle(tpcf, prec):
+    """Shared pivots over a batch: four catalogues (clustered and periodic, one point, none,
+    uniform and non-periodic with another box), pivot cells of 3 and the per-catalogue
+    mean-separation default. Every catalogue's pivots stay its own (cells never merge across
+    catalogues, even where the boxes overlap); each zeta against oracle_zeta_pivots."""
+    cats = [catalogs.lognormal(4000, 120.0, 21, grid=64), catalogs.uniform(1, 120.0, 22),
+            catalogs.uniform(0, 120.0, 23), catalogs.uniform(2500, 150.0, 24)]
+    per = [True, True, True, False]
+    ws = [catalogs.gaussian_weights(c.n, 30 + k, 0.4, 1.0) for k, c in enumerate(cats)]
+    off = np.cumsum([0] + [c.n for c in cats]).astype(np.int64)
+    x, y, z = (np.concatenate([getattr(c, a) for c in cats]) for a in "xyz")
+    w = np.concatenate(ws)
+    for side in (3.0, -1.0):
+        say(f"batch pivots side={side} prec={prec}")
+        ctx = tpcf.Context(0)
+        ctx.set_bins(8, 3.0, 24.0, 4)
+        ctx.set_precision(prec)
+        ctx.set_pivot_cell(side)
+        zb = ctx.compute_batch(off, x, y, z, w, [c.box for c in cats], per)
+        groups = pairs = 0
+        for k, c in enumerate(cats):
+            h = side if side > 0 else (c.box / np.cbrt(c.n) if c.n else c.box)
+            ref = oracle.zeta_pivots(c.x, c.y, c.z, ws[k], c.box, per[k], 8, 3.0, 24.0, 4, h)
+            groups += ref.ngroups
+            pairs += ref.npairs
+            if np.abs(ref.zeta).max() == 0.0:
+                assert np.abs(zb[k]).max() == 0.0
+            else:
+                assert rel_err_per_l(zb[k], ref.zeta).max() <= TOL[prec], k
+        st = ctx.stats()
+        assert st["n_primaries"] == groups and st["n_pairs"] == pairs
+        npairs, _ = ctx.pair_sums()
+        assert npairs.sum() == pairs
+
+
+def test_sphere_batch_pivots_match_oracle(tpcf):
+    """Shared pivots over a batch of two HEALPix nside-16 maps (cells of 0.08), per map against
+    oracle_zeta_sphere_pivots."""
+    maps = [catalogs.sphere_map(16, 40 + k, grid=32) for k in range(2)]
+    off = np.cumsum([0] + [m.n for m in maps]).astype(np.int64)
+    x, y, z, w = (np.concatenate([getattr(m, a) for m in maps]) for a in ("x", "y", "z", "w"))
+    ctx = tpcf.Context(0)
+    ctx.set_bins(6, 0.05, 0.4, 6)
+    ctx.set_precision("mixed")
+    ctx.set_pivot_cell(0.08)
+    zb = ctx.compute_sphere_batch(off, x, y, z, w)
+    for k, m in enumerate(maps):
+        ref = oracle.zeta_sphere_pivots(m.x, m.y, m.z, m.w, 6, 0.05, 0.4, 6, 0.08)
+        assert rel_err_per_l(zb[k], ref.zeta).max() <= TOL["mixed"]
 
 
 def test_full_size_pivots(tpcf):
