@@ -89,3 +89,51 @@ def test_random_sphere(tpcf, seed):
     z = ctx.compute_zeta()
     ref = oracle.zeta_sphere(m.x, m.y, m.z, m.w, nb, tmin, tmax, mmax, want_counts=True)
     _check(ctx, z, ref, prec, what)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_batch(tpcf, seed):
+    """1 to 5 catalogues with their own boxes, periodicity, sizes (0 included) and weights; exact
+    or with shared pivots (a random cell side, or each catalogue's mean separation); zeta and the
+    degenerate term of every catalogue against the oracle."""
+    rng = np.random.default_rng(3000 + seed)
+    ncat = int(rng.integers(1, 6))
+    rmax = float(rng.uniform(5.0, 30.0))
+    rmin = float(rng.uniform(0.0, 0.5) * rmax)
+    nb = int(rng.integers(1, 21))
+    lmax = int(rng.integers(0, 9))
+    prec = str(rng.choice(["fp64", "mixed"]))
+    side = float(rng.choice([0.0, 0.0, -1.0, rng.uniform(1.0, 6.0)]))
+    cats = []
+    for k in range(ncat):
+        n = 0 if rng.random() < 0.1 else int(rng.integers(1, 1500))
+        box = float(rng.uniform(2.2 * rmax, 8.0 * rmax))
+        per = bool(rng.integers(0, 2))
+        pos = np.minimum(rng.random((n, 3)) * box, np.nextafter(box, 0.0))
+        w = rng.normal(0.3, 1.0, n)
+        cats.append((pos, w, box, per))
+    what = f"seed={seed} ncat={ncat} r=[{rmin:.2f},{rmax:.2f}) nb={nb} lmax={lmax} {prec} pivot side={side:.2f}"
+    say(what)
+    off = np.cumsum([0] + [len(c[0]) for c in cats]).astype(np.int64)
+    allpos = np.concatenate([c[0] for c in cats]) if off[-1] else np.zeros((0, 3))
+    w = np.concatenate([c[1] for c in cats])
+    ctx = tpcf.Context(0)
+    ctx.set_bins(nb, rmin, rmax, lmax)
+    ctx.set_precision(prec)
+    ctx.set_pivot_cell(side)
+    zb = ctx.compute_batch(off, allpos[:, 0].copy(), allpos[:, 1].copy(), allpos[:, 2].copy(), w,
+                           [c[2] for c in cats], [c[3] for c in cats])
+    D = ctx.degenerate()
+    for k, (pos, wk, box, per) in enumerate(cats):
+        x, y, z = pos[:, 0], pos[:, 1], pos[:, 2]
+        if side != 0.0:
+            h = side if side > 0 else (box / np.cbrt(len(pos)) if len(pos) else box)
+            ref = oracle.zeta_pivots(x, y, z, wk, box, per, nb, rmin, rmax, lmax, h).zeta
+        else:
+            ref = oracle.zeta(x, y, z, wk, box, per, nb, rmin, rmax, lmax).zeta
+        if np.abs(ref).max() == 0.0:
+            assert np.abs(zb[k]).max() == 0.0, (what, k)
+        else:
+            assert rel_err_per_l(zb[k], ref).max() <= TOL[prec], (what, k)
+        Dref = oracle.degenerate(x, y, z, wk, box, per, nb, rmin, rmax, lmax)
+        assert np.abs(D[k] - Dref).max() <= 1e-10 * max(np.abs(Dref).max(), 1e-300), (what, k)
