@@ -660,7 +660,7 @@ int prepare_sweep(tpcf_ctx* c, const uint32_t* tasks_d, uint32_t ntask, SweepArg
   if ((rc = ensure(c, c->scratch, (size_t)waves * (S + kScratchTail) * kBlock * 4, "scratch")) ||
       (rc = ensure(c, c->tile, (size_t)waves * sweep_tile_bytes_per_wave(L, nb, f64, sph), "tiles")) ||
       (rc = ensure(c, c->zeta_d, (size_t)ncat * (L + 1) * nb * nb * 8, "zeta")) ||
-      (rc = ensure(c, c->queue, 16, "queue")) || (rc = ensure(c, c->stats_d, 16, "stats")) ||
+      (rc = ensure(c, c->queue, kQueueSegments * 4, "queue")) || (rc = ensure(c, c->stats_d, 16, "stats")) ||
       (rc = ensure(c, c->bin_pairs, (size_t)ncat * nb * 8, "pair sums")) ||
       (rc = ensure(c, c->bin_dd, (size_t)ncat * nb * 8, "pair sums")))
     return rc;
@@ -728,7 +728,7 @@ int record_sweep(tpcf_ctx* c, const SweepArgs& a, int waves) {
     fill_u32((uint32_t*)c->alm_dbg.p, 0u, (size_t)c->ntot * nb * NC * (f64 ? 2 : 1), c->stream);
   }
   fill_f64(a.zeta, 0.0, (size_t)a.ncat * (L + 1) * nb * nb, c->stream);
-  fill_u32(a.queue, 0u, 4, c->stream);
+  fill_u32(a.queue, 0u, kQueueSegments, c->stream);
   fill_u32(reinterpret_cast<uint32_t*>(a.stats), 0u, 4, c->stream);
   fill_u32(reinterpret_cast<uint32_t*>(a.bin_pairs), 0u, (size_t)a.ncat * nb * 2, c->stream);
   fill_f64(a.bin_dd, 0.0, (size_t)a.ncat * nb, c->stream);

@@ -792,11 +792,25 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sw
     tile_n = 0;
   };
 
+  // XCD-aware tickets: the task list is cut into kQueueSegments contiguous segments, one counter
+  // each. Workgroups are dispatched round-robin over the 8 XCDs, so wave w starts on segment
+  // w mod 8, the one of its own XCD: each XCD's L2 then serves a compact run of primaries rather
+  // than every eighth one. A wave moves on to the next segment when its own is exhausted and
+  // leaves after it has found all of them exhausted.
+  int seg = (int)(blockIdx.x % (uint32_t)kQueueSegments), seg_left = kQueueSegments;
+  const uint32_t seg_waves = max(1u, gridDim.x / (uint32_t)kQueueSegments);  // waves in flight per segment
   for (;;) {
-    uint32_t t = 0;
-    if (lane == 0) t = atomicAdd(a.queue, 1u);
-    t = uniform(t);
-    if (t >= a.ntask) break;
+    const uint32_t lo = (uint32_t)((uint64_t)a.ntask * (uint32_t)seg / kQueueSegments);
+    const uint32_t hi = (uint32_t)((uint64_t)a.ntask * (uint32_t)(seg + 1) / kQueueSegments);
+    uint32_t j = 0;  // ticket within the segment
+    if (lane == 0) j = atomicAdd(a.queue + seg, 1u);
+    j = uniform(j);
+    if (j >= hi - lo) {
+      if (--seg_left == 0) break;
+      seg = (seg + 1) % kQueueSegments;
+      continue;
+    }
+    const uint32_t t = lo + j;
     const uint32_t p = uniform(a.task_list ? a.task_list[t] : t);
     const int cat = uniform(a.prim_cat_start ? range_of([&](int k) { return a.prim_cat_start[k]; }, a.ncat, p)
                                              : catalogue_of(a.cats, a.ncat, p));
@@ -877,11 +891,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sw
     uint32_t delta_c = 0;  // sorted minus candidate position for the run holding position o - 1
     uint32_t pre_v = kInvalid, dl_v = 0;
 
-    // Phase alignment: start at the row holding candidate floor(total * phase), phase = (ticket mod
-    // waves) / waves, and wrap around. Tickets are handed out at a steady rate, so a wave's phase
-    // is where the waves in flight are in their own stencils when it starts, and all of them keep
-    // reading about the same rows (shared through L2) instead of the whole neighbourhood. Rows are
-    // counted in chunks of 64 (at most 64 chunks: lane k keeps chunk k's candidates).
+    // Phase alignment: start at the row holding candidate floor(total * phase), phase = (ticket
+    // within the segment mod the segment's waves) / those waves, and wrap around. Tickets are
+    // handed out at a steady rate, so a wave's phase is where the waves in flight on its segment
+    // are in their own stencils when it starts, and all of them keep reading about the same rows
+    // (shared through L2) instead of the whole neighbourhood. Rows are counted in chunks of 64 (at
+    // most 64 chunks: lane k keeps chunk k's candidates).
     int rot = 0;
     if (a.phase_rows && nrows <= 64 * 64) {
       const int nchunk = (nrows + 63) >> 6;
@@ -892,8 +907,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sw
         if (lane == k) ctot = sk;
         total += sk;
       }
-      const uint32_t W = gridDim.x;
-      const uint32_t target = (uint32_t)((uint64_t)total * (t % W) / W);  // < total when total > 0
+      const uint32_t target = (uint32_t)((uint64_t)total * (j % seg_waves) / seg_waves);  // < total if total > 0
       const uint32_t incl = wave_incl_scan(ctot, lane);
       // chunk holding the target: lanes at or past nchunk have incl == total > target
       const int k = __popcll(__ballot(incl <= target));

@@ -17,6 +17,7 @@ constexpr int kMinRegionBlocks = kBatch + 1;
 // Blocks after a wave's regions: one takes rejected lanes' stores, and the shell replay may
 // read (and discard) up to four blocks past a region's last block.
 constexpr int kScratchTail = 5;
+constexpr int kQueueSegments = 8;  // task-queue segments, one per XCD
 constexpr int kTileF32 = 32;     // primaries per contraction tile, mixed precision
 constexpr int kTileF64 = 16;     // primaries per contraction tile, FP64
 
@@ -65,7 +66,7 @@ struct SweepArgs {
   const uint32_t* prim_cat_start;  // with pivots: catalogue k owns pivots [start[k], start[k+1])
   uint32_t ntask;
   int32_t phase_rows;           // 1: each wave starts its stencil at the row matching its ticket's phase
-  uint32_t* queue;              // [0] task ticket counter
+  uint32_t* queue;              // [kQueueSegments] ticket counters, one per segment of the task list
   uint32_t* scratch;            // per wave: scratch_blocks + kScratchTail blocks of 64 sorted positions
   int32_t scratch_blocks;       // blocks per wave in bin regions
   const uint32_t* regions;      // [nb + 1]: bin b owns scratch blocks [regions[b], regions[b+1])
