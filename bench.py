@@ -67,19 +67,22 @@ def make_catalog():
     return cat, w
 
 
-def time_path(tpcf, torch, dev, precision, steps, warmup, autotune=True):
+def time_path(tpcf, torch, dev, precision, steps, warmup, autotune=True, fixed=None):
     """Times `steps` hot-path steps; returns (ms_per_step, mean sweep ms, stats, zeta, tuning).
-    The autotuner (if on) runs once before the warmup, outside the timed steps."""
+    The autotuner (if on) runs once before the warmup, outside the timed steps; `fixed` =
+    (points per cell, waves per CU) sets the tuning instead."""
     ctx = make_ctx(tpcf, torch.cuda.current_stream())
     ctx.set_bins(NB, RMIN, RMAX, LMAX)
     ctx.set_precision(precision)
+    if fixed:
+        ctx.set_tuning(fixed[0], int(fixed[1]))
 
     def step():
         ctx.set_catalog(*dev[:3], dev[3], box=BOX, periodic=True)
         return ctx.compute_zeta(device_output=True)
 
-    tuning = None
-    if autotune:
+    tuning = {"points_per_cell": fixed[0], "waves_per_cu": int(fixed[1]), "source": "--tuning"} if fixed else None
+    if autotune and not fixed:
         ctx.set_catalog(*dev[:3], dev[3], box=BOX, periodic=True)
         t0 = time.perf_counter()
         tuning = ctx.autotune()
@@ -797,7 +800,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--fp64-steps", type=int, default=None)
     ap.add_argument("--no-autotune", action="store_true", help="keep the library's default tuning")
-    ap.add_argument("--tuning", default="", help="sphere form: 'PPC,WPC' points per cell and waves per CU "
+    ap.add_argument("--tuning", default="", help="'PPC,WPC' points per cell and waves per CU "
                                                  "instead of the autotuner (profiling runs)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (HBM counter calibration)")
@@ -852,13 +855,14 @@ def main():
     calibration_copy(torch, args.copy_calibration_mib)
 
     tune = not args.no_autotune
-    ms, sweep_ms, st, zmix, tmix = time_path(tpcf, torch, dev, "mixed", args.steps, args.warmup, tune)
+    fixed = tuple(float(v) for v in args.tuning.split(",")) if args.tuning else None
+    ms, sweep_ms, st, zmix, tmix = time_path(tpcf, torch, dev, "mixed", args.steps, args.warmup, tune, fixed)
     pairs = st["n_pairs"]
     value = pairs / (ms / 1000.0)
     log(f"[bench] mixed: {ms:.1f} ms/step, sweep {sweep_ms:.1f} ms, {pairs} pairs, {value:.3e} pairs/s")
 
     f64_steps = args.fp64_steps if args.fp64_steps is not None else max(1, min(args.steps, 3))
-    ms64, sweep64, st64, z64, t64 = time_path(tpcf, torch, dev, "fp64", f64_steps, 1, tune)
+    ms64, sweep64, st64, z64, t64 = time_path(tpcf, torch, dev, "fp64", f64_steps, 1, tune, fixed)
     value64 = st64["n_pairs"] / (ms64 / 1000.0)
     log(f"[bench] fp64: {ms64:.1f} ms/step, sweep {sweep64:.1f} ms, {value64:.3e} pairs/s")
     err = []
