@@ -163,6 +163,19 @@ def cpu_baseline_parallel(cat, w, seconds):
     return r.npairs, k, el, threads
 
 
+def cpu_baseline_one_thread(cat, w, nprim=8):
+    """The same oracle on one thread: nprim random primaries (seed 54321) against all secondaries."""
+    import oracle
+
+    rng = np.random.default_rng(54321)
+    sample = np.sort(rng.choice(cat.n, size=nprim, replace=False))
+    perm = np.concatenate([sample, np.setdiff1d(np.arange(cat.n), sample)])
+    x, y, z, ww = cat.x[perm], cat.y[perm], cat.z[perm], w[perm]
+    t0 = time.perf_counter()
+    r = oracle.zeta(x, y, z, ww, BOX, True, NB, RMIN, RMAX, LMAX, 0, nprim, threads=1)
+    return r.npairs, time.perf_counter() - t0
+
+
 def _mock(args):
     """One batch mock (runs in a worker process, before the parent touches the GPU)."""
     import catalogs
@@ -927,6 +940,11 @@ def main():
                       f"all secondaries, FP64, {cp} pairs in {el:.1f}s",
         }
         log(f"[bench] cpu oracle: {cp / el:.3e} pairs/s on {threads} threads")
+        c1, el1 = cpu_baseline_one_thread(cat, w)
+        out["cpu_baseline"]["value_one_thread"] = c1 / el1
+        out["cpu_baseline"]["sample_one_thread"] = (f"8 random primaries (seed 54321), one thread, {c1} pairs "
+                                                    f"in {el1:.1f}s")
+        log(f"[bench] cpu oracle, one thread: {c1 / el1:.3e} pairs/s")
     print(json.dumps(out), flush=True)
 
 
