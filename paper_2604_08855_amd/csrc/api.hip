@@ -23,6 +23,8 @@ void validate_inputs(const double* x, const double* y, const double* z, const do
 size_t scan_block_count(uint32_t ncell);
 void fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s);
 void fill_f64(double* p, double v, size_t n, hipStream_t s);
+hipError_t range_tasks(const uint32_t* perm, uint32_t n, uint32_t lo, uint32_t hi, uint32_t* flag, uint32_t* pos,
+                       uint32_t* block_sum, uint32_t* list, hipStream_t s);
 hipError_t square_weights(const uint4* rec, const double* w64, uint32_t n, uint4* out, double* w2, hipStream_t s);
 void unsort_counts(const int32_t* in, const uint32_t* perm, int64_t* out, uint32_t n, int nb, hipStream_t s);
 void unsort_alm(const void* in, bool f64, const uint32_t* perm, double* out, uint32_t n, int row, hipStream_t s);
@@ -112,6 +114,7 @@ struct tpcf_ctx {
   DevBuf edge_tab, edge_io;  // squared 3j table (for edge_lmax) and host-call staging
   // degenerate-term sweep: records with squared weights, and its own outputs
   DevBuf dg_rec, dg_w64, dg_zeta, dg_stats, dg_pairs, dg_dd;
+  DevBuf rg_flag, rg_pos, rg_bsum;  // primary-range task lists
   // shared pivots: pivot cell side (0 = exact, < 0 = the mean separation), cell tables, pivots
   double pivot_h = 0.0;
   DevBuf pv_keys, pv_idx, pv_head, pv_slot, pv_bsum, pv_tmp, pv_rec, pv_w64, pv_hq, pv_start;
@@ -167,7 +170,7 @@ std::vector<DevBuf*> all_bufs(tpcf_ctx* c) {
           &c->alm_dbg, &c->conv_idx, &c->conv32, &c->conv64, &c->regions, &c->bin_pairs, &c->bin_dd,
           &c->edge_tab, &c->edge_io, &c->pv_keys, &c->pv_idx, &c->pv_head, &c->pv_slot,
           &c->pv_bsum, &c->pv_tmp, &c->pv_rec, &c->pv_w64, &c->pv_hq, &c->pv_start, &c->dg_rec, &c->dg_w64,
-          &c->dg_zeta, &c->dg_stats, &c->dg_pairs, &c->dg_dd};
+          &c->dg_zeta, &c->dg_stats, &c->dg_pairs, &c->dg_dd, &c->rg_flag, &c->rg_pos, &c->rg_bsum};
 }
 
 size_t total_bytes(tpcf_ctx* c) {
@@ -874,17 +877,17 @@ int compute(tpcf_ctx* c, int64_t p_begin, int64_t p_end, double* zeta, int memsp
       if ((rc = record_grid(c))) return rc;
       mark_grid(c);
     }
-    std::vector<uint32_t> perm((size_t)c->ntot);
-    if (c->ntot)
-      HIP_TRY(c, hipMemcpyAsync(perm.data(), c->perm.p, (size_t)c->ntot * 4, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
-    std::vector<uint32_t> list;
-    for (uint32_t s = 0; s < (uint32_t)c->ntot; ++s)
-      if ((int64_t)perm[s] >= p_begin && (int64_t)perm[s] < p_end) list.push_back(s);
-    ntask = (uint32_t)list.size();
-    if ((rc = ensure(c, c->tasks, std::max<size_t>(1, list.size()) * 4, "task list"))) return rc;
-    if (ntask)
-      HIP_TRY(c, hipMemcpyAsync(c->tasks.p, list.data(), list.size() * 4, hipMemcpyHostToDevice, c->stream));
+    // sorted positions of the range's primaries, in sorted order, built on the device
+    const size_t n = (size_t)c->ntot;
+    if ((rc = ensure(c, c->rg_flag, std::max<size_t>(1, n) * 4, "range tasks")) ||
+        (rc = ensure(c, c->rg_pos, (n + 1) * 4, "range tasks")) ||
+        (rc = ensure(c, c->rg_bsum, scan_block_count((uint32_t)n) * 4 + 4, "range tasks")) ||
+        (rc = ensure(c, c->tasks, std::max<size_t>(1, n) * 4, "task list")))
+      return rc;
+    HIP_TRY(c, range_tasks((const uint32_t*)c->perm.p, (uint32_t)n, (uint32_t)p_begin, (uint32_t)p_end,
+                           (uint32_t*)c->rg_flag.p, (uint32_t*)c->rg_pos.p, (uint32_t*)c->rg_bsum.p,
+                           (uint32_t*)c->tasks.p, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(&ntask, (uint32_t*)c->rg_pos.p + n, 4, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     tasks = (const uint32_t*)c->tasks.p;
   }

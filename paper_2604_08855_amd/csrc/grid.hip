@@ -310,6 +310,31 @@ hipError_t build_grid(const double* x, const double* y, const double* z, const d
   return hipGetLastError();
 }
 
+// Primary ranges: the sorted positions s whose input index perm[s] lies in [lo, hi), in sorted
+// order (flags, an exclusive scan, a compacting scatter), so that a range sweep keeps the cell
+// order of its primaries.
+__global__ void k_range_flags(const uint32_t* __restrict__ perm, uint32_t n, uint32_t lo, uint32_t hi,
+                              uint32_t* __restrict__ flag) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < n) flag[s] = (perm[s] - lo < hi - lo) ? 1u : 0u;  // lo <= perm[s] < hi
+}
+__global__ void k_range_emit(const uint32_t* __restrict__ flag, const uint32_t* __restrict__ pos, uint32_t n,
+                             uint32_t* __restrict__ list) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < n && flag[s]) list[pos[s]] = s;
+}
+
+// Task list of the primaries with input index in [lo, hi) into list (n entries); pos[n] receives
+// their count. Buffers: flag (n), pos (n + 1), block_sum (scan_block_count(n)).
+hipError_t range_tasks(const uint32_t* perm, uint32_t n, uint32_t lo, uint32_t hi, uint32_t* flag, uint32_t* pos,
+                       uint32_t* block_sum, uint32_t* list, hipStream_t s) {
+  if (n) hipLaunchKernelGGL(k_range_flags, dim3(blocks_for(n, 256)), dim3(256), 0, s, perm, n, lo, hi, flag);
+  hipError_t e = exclusive_scan_u32(flag, pos, n, block_sum, s);
+  if (e != hipSuccess) return e;
+  if (n) hipLaunchKernelGGL(k_range_emit, dim3(blocks_for(n, 256)), dim3(256), 0, s, flag, pos, n, list);
+  return hipGetLastError();
+}
+
 // Copies per-primary debug rows from sorted to input order and widens them to int64 / FP64.
 __global__ void k_unsort_counts(const int32_t* __restrict__ in, const uint32_t* __restrict__ perm,
                                 int64_t* __restrict__ out, uint32_t n, int nb) {
