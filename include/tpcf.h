@@ -191,6 +191,15 @@ int tpcf_set_catalog(tpcf_ctx* ctx, int64_t n, const double* x, const double* y,
                      const double* w, double box, int periodic, int memspace);
 
 /*
+ * tpcf_set_catalog with FP32 arrays (same meaning, layout, ownership and errors). Each value is
+ * widened to FP64 exactly before anything else happens, so the result is that of
+ * tpcf_set_catalog on the widened values. Host arrays are widened on the host, device arrays by a
+ * kernel on the context's stream.
+ */
+int tpcf_set_catalog_f32(tpcf_ctx* ctx, int64_t n, const float* x, const float* y, const float* z,
+                         const float* w, double box, int periodic, int memspace);
+
+/*
  * One projected scalar field on the unit sphere (the paper's own geometry: pixels or galaxies of
  * a map; Statement of need, Features and Performance sections): n unit vectors x, y, z (FP64,
  * |v|^2 within 1e-6 of 1) with field values w (NULL = unit weights), in `memspace`. Replaces the
@@ -217,6 +226,14 @@ int tpcf_set_catalog(tpcf_ctx* ctx, int64_t n, const double* x, const double* y,
  */
 int tpcf_set_sphere_catalog(tpcf_ctx* ctx, int64_t n, const double* x, const double* y,
                             const double* z, const double* w, int memspace);
+
+/*
+ * tpcf_set_sphere_catalog with FP32 arrays (same meaning, layout, ownership and errors), widened
+ * to FP64 exactly first. FP32 unit vectors are unit to about 1e-7 in |v|^2, well within the 1e-6
+ * the check allows.
+ */
+int tpcf_set_sphere_catalog_f32(tpcf_ctx* ctx, int64_t n, const float* x, const float* y, const float* z,
+                                const float* w, int memspace);
 
 /*
  * ncat independent maps on the sphere in one persistent launch (the batch form of

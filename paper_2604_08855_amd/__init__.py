@@ -33,7 +33,8 @@ EXPORTS = [
     "tpcf_compute_batch", "tpcf_debug_pair_counts", "tpcf_debug_alm", "tpcf_set_debug",
     "tpcf_get_stats", "tpcf_last_error", "tpcf_autotune", "tpcf_pair_sums", "tpcf_edge_correct",
     "tpcf_set_sphere_catalog", "tpcf_set_pivot_cell", "tpcf_edge_correct_sphere", "tpcf_compute_sphere_batch",
-    "tpcf_set_phase_aligned", "tpcf_degenerate", "tpcf_set_allocator",
+    "tpcf_set_phase_aligned", "tpcf_degenerate", "tpcf_set_allocator", "tpcf_set_catalog_f32",
+    "tpcf_set_sphere_catalog_f32",
 ]
 
 
@@ -96,6 +97,8 @@ def _load() -> ctypes.CDLL:
         "tpcf_set_phase_aligned": ([vp, i], i),
         "tpcf_degenerate": ([vp, vp, i], i),
         "tpcf_set_allocator": ([vp, vp, vp, vp], i),
+        "tpcf_set_catalog_f32": ([vp, i64, vp, vp, vp, vp, d, i, i], i),
+        "tpcf_set_sphere_catalog_f32": ([vp, i64, vp, vp, vp, vp, i], i),
         "tpcf_set_catalog": ([vp, i64, vp, vp, vp, vp, d, i, i], i),
         "tpcf_compute_zeta": ([vp, vp, i], i),
         "tpcf_compute_zeta_range": ([vp, i64, i64, vp, i], i),
@@ -276,10 +279,33 @@ class Context:
         ptrs = [_ptr_np(a) for a in arrs] + [_ptr_np(wa) if wa is not None else None]
         return ptrs, MEM_HOST, arrs + ([wa] if wa is not None else [])
 
+    def _f32_arrays(self, x, y, z, w):
+        """(pointers, memspace, keep-alive list) when every array is FP32 (numpy, or torch on the
+        device), else None: FP32 inputs go to the _f32 entry points, which widen them exactly."""
+        arrs = [a for a in (x, y, z, w) if a is not None]
+        if all(_is_torch(a) and a.is_cuda and a.dtype == __import__("torch").float32 for a in arrs):
+            ts = [a.contiguous() for a in (x, y, z)]
+            wt = None if w is None else w.contiguous()
+            ptrs = [ctypes.c_void_p(t.data_ptr()) for t in ts]
+            ptrs.append(ctypes.c_void_p(wt.data_ptr()) if wt is not None else None)
+            return ptrs, MEM_DEVICE, ts + ([wt] if wt is not None else [])
+        if all(isinstance(a, np.ndarray) and a.dtype == np.float32 for a in arrs):
+            hs = [np.ascontiguousarray(a) for a in (x, y, z)]
+            wh = None if w is None else np.ascontiguousarray(w)
+            ptrs = [_ptr_np(a) for a in hs] + [_ptr_np(wh) if wh is not None else None]
+            return ptrs, MEM_HOST, hs + ([wh] if wh is not None else [])
+        return None
+
     def set_catalog(self, x, y, z, w=None, *, box: float, periodic: bool = True):
         n = len(x)
         if len(y) != n or len(z) != n or (w is not None and len(w) != n):
             raise ValueError("x, y, z, w must have the same length")
+        f32 = self._f32_arrays(x, y, z, w)
+        if f32 is not None:
+            ptrs, mem, keep = f32
+            self._check(_lib.tpcf_set_catalog_f32(self._h, int(n), *ptrs, float(box), int(bool(periodic)), mem))
+            self.n, self.ncat, self.sphere = n, 1, False
+            return
         ptrs, mem, keep = self._arrays(x, y, z, w)
         self._check(_lib.tpcf_set_catalog(self._h, int(n), *ptrs, float(box), int(bool(periodic)), mem))
         self.n, self.ncat, self.sphere = n, 1, False
@@ -291,8 +317,13 @@ class Context:
         n = len(x)
         if len(y) != n or len(z) != n or (w is not None and len(w) != n):
             raise ValueError("x, y, z, w must have the same length")
-        ptrs, mem, keep = self._arrays(x, y, z, w)
-        self._check(_lib.tpcf_set_sphere_catalog(self._h, int(n), *ptrs, mem))
+        f32 = self._f32_arrays(x, y, z, w)
+        if f32 is not None:
+            ptrs, mem, keep = f32
+            self._check(_lib.tpcf_set_sphere_catalog_f32(self._h, int(n), *ptrs, mem))
+        else:
+            ptrs, mem, keep = self._arrays(x, y, z, w)
+            self._check(_lib.tpcf_set_sphere_catalog(self._h, int(n), *ptrs, mem))
         self.n, self.ncat, self.sphere = n, 1, True
 
     # -- compute

@@ -23,6 +23,7 @@ void validate_inputs(const double* x, const double* y, const double* z, const do
 size_t scan_block_count(uint32_t ncell);
 void fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s);
 void fill_f64(double* p, double v, size_t n, hipStream_t s);
+void widen_f32(const float* in, double* out, size_t n, hipStream_t s);
 hipError_t range_tasks(const uint32_t* perm, uint32_t n, uint32_t lo, uint32_t hi, uint32_t* flag, uint32_t* pos,
                        uint32_t* block_sum, uint32_t* list, hipStream_t s);
 hipError_t square_weights(const uint4* rec, const double* w64, uint32_t n, uint4* out, double* w2, hipStream_t s);
@@ -512,8 +513,28 @@ int validate_host(tpcf_ctx* c, const double* x, const double* y, const double* z
 }
 
 // Copies (and validates) the concatenated catalogues into the staging buffers.
-int stage(tpcf_ctx* c, const std::vector<HostCat>& cats, int64_t ntot, const double* x, const double* y,
-          const double* z, const double* w, int memspace) {
+int stage(tpcf_ctx* c, const std::vector<HostCat>& cats, int64_t ntot, const void* xv, const void* yv,
+          const void* zv, const void* wv, int memspace, bool f32 = false) {
+  // FP32 host inputs are widened on the host (exact) and then staged as FP64 host inputs; FP32
+  // device inputs are widened on the device into the FP64 staging arrays.
+  std::vector<double> hx, hy, hz, hw;
+  if (f32 && memspace == TPCF_MEM_HOST) {
+    auto widen = [&](const void* p, std::vector<double>& v) -> const void* {
+      if (!p) return nullptr;
+      const float* f = static_cast<const float*>(p);
+      v.assign(f, f + ntot);
+      return v.data();
+    };
+    xv = widen(xv, hx);
+    yv = widen(yv, hy);
+    zv = widen(zv, hz);
+    wv = widen(wv, hw);
+    f32 = false;
+  }
+  const double* x = static_cast<const double*>(xv);
+  const double* y = static_cast<const double*>(yv);
+  const double* z = static_cast<const double*>(zv);
+  const double* w = static_cast<const double*>(wv);
   if (memspace == TPCF_MEM_HOST) {
     for (const HostCat& h : cats) {
       int rc = validate_host(c, x + h.first, y + h.first, z + h.first, w ? w + h.first : nullptr, h.n, h.box,
@@ -529,7 +550,13 @@ int stage(tpcf_ctx* c, const std::vector<HostCat>& cats, int64_t ntot, const dou
     return rc;
   if (w && (rc = ensure(c, c->sw, bytes, "weights"))) return rc;
   const hipMemcpyKind kind = memspace == TPCF_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
-  if (ntot) {
+  if (ntot && f32) {
+    widen_f32(static_cast<const float*>(xv), (double*)c->sx.p, (size_t)ntot, c->stream);
+    widen_f32(static_cast<const float*>(yv), (double*)c->sy.p, (size_t)ntot, c->stream);
+    widen_f32(static_cast<const float*>(zv), (double*)c->sz.p, (size_t)ntot, c->stream);
+    if (w) widen_f32(static_cast<const float*>(wv), (double*)c->sw.p, (size_t)ntot, c->stream);
+    HIP_TRY(c, hipGetLastError());
+  } else if (ntot) {
     HIP_TRY(c, hipMemcpyAsync(c->sx.p, x, bytes, kind, c->stream));
     HIP_TRY(c, hipMemcpyAsync(c->sy.p, y, bytes, kind, c->stream));
     HIP_TRY(c, hipMemcpyAsync(c->sz.p, z, bytes, kind, c->stream));
@@ -957,6 +984,49 @@ int compute(tpcf_ctx* c, int64_t p_begin, int64_t p_end, double* zeta, int memsp
   return rc;
 }
 
+// Shared body of tpcf_set_catalog and tpcf_set_catalog_f32 (arrays of double or float).
+int set_catalog_impl(tpcf_ctx* c, int64_t n, const void* x, const void* y, const void* z, const void* w, double box,
+                     int periodic, int memspace, bool f32) {
+  if (!c) return TPCF_E_INVALID_ARG;
+  if (n < 0 || n >= kMaxPoints) return fail(c, TPCF_E_INVALID_ARG, "n must be in [0, 2^31)");
+  if (!is_finite(box) || !(box > 0.0)) return fail(c, TPCF_E_INVALID_ARG, "box must be finite and > 0");
+  if (n > 0 && (!x || !y || !z)) return fail(c, TPCF_E_INVALID_ARG, "NULL position array");
+  if (memspace != TPCF_MEM_HOST && memspace != TPCF_MEM_DEVICE)
+    return fail(c, TPCF_E_INVALID_ARG, "unknown memory space");
+  if (c->bins_set && periodic && !(c->rmax < 0.5 * box))
+    return fail(c, TPCF_E_INVALID_ARG, "periodic catalogue needs rmax < box/2");
+  std::vector<HostCat> cats(1);
+  cats[0].first = 0;
+  cats[0].n = n;
+  cats[0].box = box;
+  cats[0].periodic = periodic ? 1 : 0;
+  cats[0].sphere = 0;
+  int rc = stage(c, cats, n, x, y, z, w, memspace, f32);
+  if (!rc) c->err.clear();
+  return rc;
+}
+
+// Shared body of tpcf_set_sphere_catalog and tpcf_set_sphere_catalog_f32.
+int set_sphere_impl(tpcf_ctx* c, int64_t n, const void* x, const void* y, const void* z, const void* w,
+                    int memspace, bool f32) {
+  if (!c) return TPCF_E_INVALID_ARG;
+  if (n < 0 || n >= kMaxPoints) return fail(c, TPCF_E_INVALID_ARG, "n must be in [0, 2^31)");
+  if (n > 0 && (!x || !y || !z)) return fail(c, TPCF_E_INVALID_ARG, "NULL position array");
+  if (memspace != TPCF_MEM_HOST && memspace != TPCF_MEM_DEVICE)
+    return fail(c, TPCF_E_INVALID_ARG, "unknown memory space");
+  if (c->bins_set && !(c->rmax <= kPi))
+    return fail(c, TPCF_E_INVALID_ARG, "angular bins on the sphere need theta_max <= pi");
+  std::vector<HostCat> cats(1);
+  cats[0].first = 0;
+  cats[0].n = n;
+  cats[0].box = 4.0;
+  cats[0].periodic = 0;
+  cats[0].sphere = 1;
+  int rc = stage(c, cats, n, x, y, z, w, memspace, f32);
+  if (!rc) c->err.clear();
+  return rc;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------------------------------
@@ -1314,43 +1384,22 @@ int tpcf_set_debug(tpcf_ctx* c, int enable) {
 
 int tpcf_set_catalog(tpcf_ctx* c, int64_t n, const double* x, const double* y, const double* z, const double* w,
                      double box, int periodic, int memspace) {
-  if (!c) return TPCF_E_INVALID_ARG;
-  if (n < 0 || n >= kMaxPoints) return fail(c, TPCF_E_INVALID_ARG, "n must be in [0, 2^31)");
-  if (!is_finite(box) || !(box > 0.0)) return fail(c, TPCF_E_INVALID_ARG, "box must be finite and > 0");
-  if (n > 0 && (!x || !y || !z)) return fail(c, TPCF_E_INVALID_ARG, "NULL position array");
-  if (memspace != TPCF_MEM_HOST && memspace != TPCF_MEM_DEVICE)
-    return fail(c, TPCF_E_INVALID_ARG, "unknown memory space");
-  if (c->bins_set && periodic && !(c->rmax < 0.5 * box))
-    return fail(c, TPCF_E_INVALID_ARG, "periodic catalogue needs rmax < box/2");
-  std::vector<HostCat> cats(1);
-  cats[0].first = 0;
-  cats[0].n = n;
-  cats[0].box = box;
-  cats[0].periodic = periodic ? 1 : 0;
-  cats[0].sphere = 0;
-  int rc = stage(c, cats, n, x, y, z, w, memspace);
-  if (!rc) c->err.clear();
-  return rc;
+  return set_catalog_impl(c, n, x, y, z, w, box, periodic, memspace, false);
+}
+
+int tpcf_set_catalog_f32(tpcf_ctx* c, int64_t n, const float* x, const float* y, const float* z, const float* w,
+                         double box, int periodic, int memspace) {
+  return set_catalog_impl(c, n, x, y, z, w, box, periodic, memspace, true);
 }
 
 int tpcf_set_sphere_catalog(tpcf_ctx* c, int64_t n, const double* x, const double* y, const double* z,
                             const double* w, int memspace) {
-  if (!c) return TPCF_E_INVALID_ARG;
-  if (n < 0 || n >= kMaxPoints) return fail(c, TPCF_E_INVALID_ARG, "n must be in [0, 2^31)");
-  if (n > 0 && (!x || !y || !z)) return fail(c, TPCF_E_INVALID_ARG, "NULL position array");
-  if (memspace != TPCF_MEM_HOST && memspace != TPCF_MEM_DEVICE)
-    return fail(c, TPCF_E_INVALID_ARG, "unknown memory space");
-  if (c->bins_set && !(c->rmax <= kPi))
-    return fail(c, TPCF_E_INVALID_ARG, "angular bins on the sphere need theta_max <= pi");
-  std::vector<HostCat> cats(1);
-  cats[0].first = 0;
-  cats[0].n = n;
-  cats[0].box = 4.0;
-  cats[0].periodic = 0;
-  cats[0].sphere = 1;
-  int rc = stage(c, cats, n, x, y, z, w, memspace);
-  if (!rc) c->err.clear();
-  return rc;
+  return set_sphere_impl(c, n, x, y, z, w, memspace, false);
+}
+
+int tpcf_set_sphere_catalog_f32(tpcf_ctx* c, int64_t n, const float* x, const float* y, const float* z,
+                                const float* w, int memspace) {
+  return set_sphere_impl(c, n, x, y, z, w, memspace, true);
 }
 
 int tpcf_compute_zeta(tpcf_ctx* c, double* zeta, int memspace) {

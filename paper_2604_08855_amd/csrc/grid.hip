@@ -234,6 +234,12 @@ __global__ void k_square_weights(const uint4* __restrict__ rec, const double* __
   w2[i] = v;
 }
 
+// FP32 inputs widened to the FP64 staging arrays (exact).
+__global__ void k_widen_f32(const float* __restrict__ in, double* __restrict__ out, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (double)in[i];
+}
+
 __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t v, size_t n) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -250,6 +256,9 @@ static inline unsigned blocks_for(size_t n, unsigned t) { return (unsigned)((n +
 
 void fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s) {
   if (n) hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, v, n);
+}
+void widen_f32(const float* in, double* out, size_t n, hipStream_t s) {
+  if (n) hipLaunchKernelGGL(k_widen_f32, dim3(blocks_for(n, 256)), dim3(256), 0, s, in, out, n);
 }
 void fill_f64(double* p, double v, size_t n, hipStream_t s) {
   if (n) hipLaunchKernelGGL(k_fill_f64, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, v, n);

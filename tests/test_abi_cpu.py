@@ -18,7 +18,7 @@ HEADER = os.path.join(ROOT, "include", "tpcf.h")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(tpcf_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(tpcf_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_header_and_binding_agree():

@@ -316,3 +316,39 @@ def test_device_tensors_in_and_out(tpcf):
     with pytest.raises(tpcf.TpcfError) as e:
         tpcf.zeta(bad, t[1], t[2], box=cat.box, periodic=True, rmin=2.0, rmax=25.0, nbins=6, lmax=5)
     assert e.value.code == 1
+
+
+@pytest.mark.parametrize("where", ["host", "device"])
+def test_fp32_inputs(tpcf, where):
+    """tpcf_set_catalog_f32 / tpcf_set_sphere_catalog_f32 (numpy float32 on the host, torch float32
+    on the device): the same result as the oracle on the values widened to FP64."""
+    import torch
+
+    cat = catalogs.uniform(4000, 150.0, 71)
+    w = catalogs.gaussian_weights(cat.n, 72, 0.5, 1.0)
+    f = [np.minimum(a.astype(np.float32), np.nextafter(np.float32(150.0), np.float32(0))) for a in (cat.x, cat.y, cat.z)]
+    wf = w.astype(np.float32)
+    say(f"fp32 inputs on the {where}")
+    args = [torch.from_numpy(a).cuda() for a in (*f, wf)] if where == "device" else [*f, wf]
+    ctx = tpcf.Context(0)
+    ctx.set_bins(8, 4.0, 30.0, 4)
+    ctx.set_precision("fp64")
+    ctx.set_debug(True)
+    ctx.set_catalog(*args, box=150.0, periodic=True)
+    z = ctx.compute_zeta()
+    x64, y64, z64, w64 = (a.astype(np.float64) for a in (*f, wf))
+    ref = oracle.zeta(x64, y64, z64, w64, 150.0, True, 8, 4.0, 30.0, 4, want_counts=True)
+    assert rel_err_per_l(z, ref.zeta).max() <= TOL["fp64"]
+    np.testing.assert_array_equal(ctx.pair_counts(), ref.counts)
+
+    m = catalogs.sphere_map(16, 73, grid=32)
+    u = [a.astype(np.float32) for a in (m.x, m.y, m.z, m.w)]
+    args = [torch.from_numpy(a).cuda() for a in u] if where == "device" else u
+    ctx = tpcf.Context(0)
+    ctx.set_bins(6, 0.05, 0.5, 5)
+    ctx.set_precision("fp64")
+    ctx.set_sphere_catalog(*args)
+    zs = ctx.compute_zeta()
+    u64 = [a.astype(np.float64) for a in u]
+    ref = oracle.zeta_sphere(*u64, 6, 0.05, 0.5, 5)
+    assert rel_err_per_l(zs, ref.zeta).max() <= TOL["fp64"]
