@@ -283,7 +283,11 @@ class Context:
         """(pointers, memspace, keep-alive list) when every array is FP32 (numpy, or torch on the
         device), else None: FP32 inputs go to the _f32 entry points, which widen them exactly."""
         arrs = [a for a in (x, y, z, w) if a is not None]
-        if all(_is_torch(a) and a.is_cuda and a.dtype == __import__("torch").float32 for a in arrs):
+        if all(_is_torch(a) for a in arrs):
+            import torch
+
+            if not all(a.is_cuda and a.dtype == torch.float32 for a in arrs):
+                return None
             ts = [a.contiguous() for a in (x, y, z)]
             wt = None if w is None else w.contiguous()
             ptrs = [ctypes.c_void_p(t.data_ptr()) for t in ts]
