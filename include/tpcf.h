@@ -81,7 +81,7 @@ typedef struct tpcf_stats {
 typedef struct tpcf_tuning {
     double points_per_cell; /* grid density */
     int waves_per_cu;       /* persistent waves per compute unit */
-    int scratch_blocks;     /* scratch blocks of 64 secondaries per wave (unchanged by the tuner) */
+    int scratch_blocks;     /* scratch blocks of 64 secondaries per wave in use (not tuned) */
     int candidates;         /* configurations timed */
     double ms_best;         /* sweep time of the sample with the chosen configuration */
     double ms_default;      /* sweep time of the sample with the configuration in force before */
@@ -122,7 +122,8 @@ int tpcf_set_precision(tpcf_ctx* ctx, int precision);
 /*
  * Optional tuning: target mean points per grid cell (default 8; the grid side follows from it
  * and the catalogue density), persistent waves per compute unit (default 8), and scratch blocks
- * of 64 secondaries per wave (default 1024). A value of 0 keeps the default.
+ * of 64 secondaries per wave (default 1024 in 3D and 512 on the sphere). A value of 0 keeps the
+ * current setting.
  * Errors: TPCF_E_INVALID_ARG for negative values or scratch_blocks not a multiple of 64; a
  * compute call with scratch_blocks below 5 x nbins fails with TPCF_E_INVALID_ARG.
  */
