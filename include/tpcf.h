@@ -105,7 +105,8 @@ int tpcf_create(tpcf_ctx** out, int device, void* hip_stream);
 void tpcf_destroy(tpcf_ctx* ctx);
 
 /*
- * Radial bins and multipole order. nbins in [1, TPCF_MAX_NBINS], 0 <= rmin < rmax (finite),
+ * Radial bins and multipole order: the multipole bins a pivot's neighbours fill (paper,
+ * Implementation section). nbins in [1, TPCF_MAX_NBINS], 0 <= rmin < rmax (finite),
  * lmax in [0, TPCF_MAX_LMAX]. With a catalogue on the sphere (tpcf_set_sphere_catalog) rmin and
  * rmax are angles in radians (rmax <= pi) and lmax is m_max. Errors: TPCF_E_INVALID_ARG.
  */
@@ -178,7 +179,9 @@ int tpcf_set_phase_aligned(tpcf_ctx* ctx, int mode);
 int tpcf_autotune(tpcf_ctx* ctx, double sample_fraction, tpcf_tuning* out);
 
 /*
- * One catalogue of n points: positions x, y, z and weights w (w = NULL means unit weights), all
+ * One catalogue of n points, the pivots and neighbours of the estimator (paper, Implementation
+ * section: every point is a pivot whose neighbours in range fill the bins): positions x, y, z and
+ * weights w (w = NULL means unit weights), all
  * FP64 arrays of length n in memory space `memspace`. box is the cube side; periodic != 0 wraps
  * positions into [0, box) and uses minimum images; otherwise every coordinate must lie in
  * [0, box). The positions are copied into library-owned, cell-sorted device buffers (lattice
@@ -252,7 +255,9 @@ int tpcf_compute_sphere_batch(tpcf_ctx* ctx, int ncat, const int64_t* offsets, c
                               int memspace);
 
 /*
- * zeta for the catalogue set by tpcf_set_catalog: every point is a primary and a secondary.
+ * zeta for the catalogue set by tpcf_set_catalog: every point is a primary and a secondary; the
+ * multipoles of each pivot's neighbours, contracted over m and summed over pivots (paper,
+ * Implementation section).
  * zeta has (lmax+1)*nbins*nbins doubles in memory space `memspace`.
  * Errors: TPCF_E_STATE (bins or catalogue missing), TPCF_E_INVALID_ARG (periodic with
  * rmax >= box/2, NULL zeta), TPCF_E_OUT_OF_MEMORY, TPCF_E_DEVICE.
@@ -268,7 +273,9 @@ int tpcf_compute_zeta_range(tpcf_ctx* ctx, int64_t p_begin, int64_t p_end, doubl
                             int memspace);
 
 /*
- * ncat independent catalogues in one persistent launch. Catalogue c holds the points
+ * ncat independent catalogues in one persistent launch, each measured as tpcf_compute_zeta does
+ * (paper, Implementation section; the paper's engine runs its pivots in parallel over threads,
+ * Features section). Catalogue c holds the points
  * [offsets[c], offsets[c+1]) of the concatenated FP64 arrays x, y, z, w (w may be NULL); its box
  * side is box_side[c] and periodic flag periodic[c]. offsets, box_side and periodic are host
  * arrays; x, y, z, w live in `memspace`; zeta receives [ncat][(lmax+1)][nbins][nbins] doubles in

@@ -57,6 +57,10 @@ MUTANTS = {
                                   "D[l * nb + b] = (2.0 * l - 1.0) / (4.0 * 3.14159265358979323846) * S[b];"),
     "degenerate sphere: 3D factor": ("for (int b = 0; b < nb; b++) D[m * nb + b] = S[b];",
                                      "for (int b = 0; b < nb; b++) D[m * nb + b] = (2.0 * m + 1.0) * S[b];"),
+    "edge correction: 8-node quadrature": ("enum { NQ = 32 };", "enum { NQ = 8 };"),
+    "edge correction: 16-node quadrature": ("enum { NQ = 32 };", "enum { NQ = 16 };"),
+    "sphere edge correction: 16-point trapezoid": ("enum { NQ = 64 };", "enum { NQ = 16 };"),
+    "sphere edge correction: 32-point trapezoid": ("enum { NQ = 64 };", "enum { NQ = 32 };"),
     "sphere edge correction: weight of m' = 0": ("A[m][mp] = (mp == 0 ? 1.0 : 2.0) * t * (twopi / NQ);",
                                                  "A[m][mp] = 2.0 * t * (twopi / NQ);"),
 }
@@ -162,6 +166,31 @@ def _pins():
         Ns[m, 0, 0] = sum((1.0 if mp == 0 else 2.0) * 0.5 * (Rk(m + mp) + Rk(abs(m - mp))) * cs[mp] for mp in range(3))
     if np.abs(oracle.edge_correct_sphere(Ns, Rs)[:, 0, 0] - cs).max() > 1e-12:
         failed.append("sphere edge correction")
+    # edge corrections at the oracle's highest order (16), against closed forms that use neither
+    # quadrature nor 3j symbols: Legendre-series and cosine-series products
+    from tests.test_oracle_pins import _tridiagonal_3d, _tridiagonal_sphere
+    Lh = 16
+    Rh = np.zeros((Lh + 1, 1, 1))
+    Rh[:, 0, 0] = 0.2 * rng.normal(size=Lh + 1) / np.arange(1, Lh + 2)
+    Rh[0, 0, 0] = 1.5
+    zh = rng.normal(size=Lh + 1)
+    Nh = np.polynomial.legendre.legmul(zh, Rh[:, 0, 0])[: Lh + 1][:, None, None]
+    if np.abs(oracle.edge_correct(Nh, Rh)[:, 0, 0] - zh).max() > 1e-10:
+        failed.append("edge correction, order 16")
+    Nt = (1.5 * _tridiagonal_3d(10, 0.4) @ zh[:11])[:, None, None]
+    Rt = np.zeros((11, 1, 1))
+    Rt[0, 0, 0], Rt[1, 0, 0] = 1.5, 0.6
+    if np.abs(oracle.edge_correct(Nt, Rt)[:, 0, 0] - zh[:11]).max() > 1e-10:
+        failed.append("edge correction, order 10")
+    two = lambda v: np.concatenate([v[:0:-1], v])
+    Nsh = np.convolve(two(zh), two(Rh[:, 0, 0]))[2 * Lh: 3 * Lh + 1][:, None, None]
+    if np.abs(oracle.edge_correct_sphere(Nsh, Rh)[:, 0, 0] - zh).max() > 1e-10:
+        failed.append("sphere edge correction, order 16")
+    Nst = (1.5 * _tridiagonal_sphere(10, 0.3) @ zh[:11])[:, None, None]
+    Rst = np.zeros((11, 1, 1))
+    Rst[0, 0, 0], Rst[1, 0, 0] = 1.5, 0.45
+    if np.abs(oracle.edge_correct_sphere(Nst, Rst)[:, 0, 0] - zh[:11]).max() > 1e-10:
+        failed.append("sphere edge correction, order 10")
     # shared pivots: group pivots and zeta against the numpy grouping and Legendre form
     cP = (rng.random((4, 3))[rng.integers(0, 4, 150)] * 40.0 + rng.normal(0, 2.0, (150, 3))) % 40.0
     cw = rng.normal(1.0, 0.4, 150)

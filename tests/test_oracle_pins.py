@@ -227,6 +227,47 @@ def test_edge_correction_closed_forms():
     assert not oracle.edge_correct(N, R0)[:, 0, 1].any()
 
 
+def _tridiagonal_3d(lmax, a):
+    """Coupling matrix for R(mu) = R_0 (1 + a P_1(mu)), from mu P_l = ((l+1) P_{l+1} + l P_{l-1}) / (2l+1):
+    the Legendre coefficient L of P_l(mu) (1 + a mu) is delta_{lL} + a (l+1)/(2l+1) delta_{L,l+1}
+    + a l/(2l+1) delta_{L,l-1}."""
+    M = np.eye(lmax + 1)
+    for l in range(lmax + 1):
+        if l + 1 <= lmax:
+            M[l + 1, l] += a * (l + 1) / (2 * l + 1)
+        if l >= 1:
+            M[l - 1, l] += a * l / (2 * l + 1)
+    return M
+
+
+@pytest.mark.parametrize("lmax", [10, 16])
+def test_edge_correction_high_order(lmax):
+    """Edge correction at the orders the library runs (l_max = 10) and at the oracle's cap (16),
+    pinned without 3j symbols or quadrature: (1) with R(mu) = R_0 (1 + a P_1(mu)) the coupling
+    matrix is I plus the tridiagonal of the three-term recurrence of mu P_l; N = R_0 M zeta is
+    solved back; (2) for random Legendre series zeta(mu) and R(mu), N(mu) = zeta(mu) R(mu) is
+    their product taken with numpy's Legendre-series multiplication (exact, degree 2 l_max)
+    truncated at l_max, and zeta is recovered."""
+    rng = np.random.default_rng(100 + lmax)
+    R0, a = 2.5, 0.45
+    zt = rng.normal(size=lmax + 1)
+    R = np.zeros((lmax + 1, 1, 1))
+    R[0, 0, 0], R[1, 0, 0] = R0, a * R0
+    N = (R0 * _tridiagonal_3d(lmax, a) @ zt)[:, None, None]
+    assert np.abs(oracle.edge_correct(N, R)[:, 0, 0] - zt).max() < 1e-12 * np.abs(zt).max()
+    # random series, several bin pairs at once
+    nb = 3
+    Rr = np.zeros((lmax + 1, nb, nb))
+    Rr[0] = rng.uniform(1.0, 2.0, (nb, nb))
+    Rr[1:] = 0.25 * rng.normal(size=(lmax, nb, nb)) * Rr[0] / np.arange(1, lmax + 1)[:, None, None]
+    zr = rng.normal(size=(lmax + 1, nb, nb))
+    Nr = np.zeros_like(zr)
+    for i in range(nb):
+        for j in range(nb):
+            Nr[:, i, j] = np.polynomial.legendre.legmul(zr[:, i, j], Rr[:, i, j])[: lmax + 1]
+    assert np.abs(oracle.edge_correct(Nr, Rr) - zr).max() < 1e-11 * np.abs(zr).max()
+
+
 def test_bin_edges_are_half_open():
     # box 256 and bins [8, 64) of width 8: with K = 27 every edge is a whole number of lattice
     # steps, so separations can sit exactly on an edge. A separation of exactly 16 belongs to
@@ -626,3 +667,43 @@ def test_sphere_edge_correction_closed_forms():
     mom = lambda f: np.array([np.sum(f * np.cos(m * phi)) * (2 * np.pi / len(phi)) for m in range(5)])
     c2 = oracle.edge_correct_sphere(mom(dens_N)[:, None, None], mom(dens_R)[:, None, None])[:, 0, 0]
     np.testing.assert_allclose(c2, [1.0, 0.0, 0.15, 0.0, 0.0], rtol=0, atol=1e-12)
+
+
+def _tridiagonal_sphere(mmax, a):
+    """Coupling of the 2D edge correction for R(phi) = R_0 (1 + 2 a cos phi) / (2 pi): by
+    2 cos(phi) cos(m' phi) = cos((m'+1) phi) + cos((m'-1) phi), A = I + a (sub- and super-diagonal)
+    except A[0, 1] = 2 a (the m' = 1 term counts +1 and -1)."""
+    A = np.eye(mmax + 1)
+    for m in range(mmax):
+        A[m, m + 1] += a
+        A[m + 1, m] += a
+    A[0, 1] = 2 * a
+    return A
+
+
+@pytest.mark.parametrize("mmax", [10, 16])
+def test_sphere_edge_correction_high_order(mmax):
+    """2D edge correction at m_max = 10 and at the oracle's cap (16), pinned without the
+    coupling formula the oracle integrates: (1) R(phi) = R_0 (1 + 2 a cos phi) / (2 pi) gives the
+    tridiagonal coupling of the cosine product rule, and N = R_0 A c is solved back; (2) for random
+    cosine series, N(phi) = zeta(phi) R(phi) is their product taken as a discrete convolution of
+    the two-sided Fourier coefficients (numpy.convolve), R_k = 0 above m_max, and c is recovered."""
+    rng = np.random.default_rng(200 + mmax)
+    R0, a = 1.7, 0.35
+    c = rng.normal(size=mmax + 1)
+    R = np.zeros((mmax + 1, 1, 1))
+    R[0, 0, 0], R[1, 0, 0] = R0, a * R0
+    N = (R0 * _tridiagonal_sphere(mmax, a) @ c)[:, None, None]
+    assert np.abs(oracle.edge_correct_sphere(N, R)[:, 0, 0] - c).max() < 1e-12 * np.abs(c).max()
+    nb = 2
+    Rr = np.zeros((mmax + 1, nb, nb))
+    Rr[0] = rng.uniform(1.0, 2.0, (nb, nb))
+    Rr[1:] = 0.3 * rng.normal(size=(mmax, nb, nb)) * Rr[0] / np.arange(1, mmax + 1)[:, None, None]
+    cr = rng.normal(size=(mmax + 1, nb, nb))
+    Nr = np.zeros_like(cr)
+    for i in range(nb):
+        for j in range(nb):
+            two = lambda v: np.concatenate([v[:0:-1], v])  # coefficients of exp(i k phi), k = -M..M
+            full = np.convolve(two(cr[:, i, j]), two(Rr[:, i, j]))  # k = -2M..2M
+            Nr[:, i, j] = full[2 * mmax: 3 * mmax + 1]
+    assert np.abs(oracle.edge_correct_sphere(Nr, Rr) - cr).max() < 1e-11 * np.abs(cr).max()
