@@ -30,7 +30,7 @@ hipError_t square_weights(const uint4* rec, const double* w64, uint32_t n, uint4
 void unsort_counts(const int32_t* in, const uint32_t* perm, int64_t* out, uint32_t n, int nb, hipStream_t s);
 void unsort_alm(const void* in, bool f64, const uint32_t* perm, double* out, uint32_t n, int row, hipStream_t s);
 hipError_t launch_sweep(int lmax, bool f64, bool sphere, const SweepArgs& args, int waves, hipStream_t stream);
-size_t sweep_lds_bytes(int scratch_blocks, int nb);
+size_t sweep_lds_bytes(int nb, bool f64);
 size_t sweep_tile_bytes_per_wave(int lmax, int nb, bool f64, bool sphere);
 std::vector<double> threej_squared_table(int lmax);
 hipError_t launch_edge_correct(int ncat, int lmax, int nb, const double* N, const double* R, const double* t3,
@@ -85,7 +85,7 @@ struct tpcf_ctx {
   int lmax = 0;
   int precision = TPCF_PREC_FP64;
   double ppc = 8.0;
-  int waves_per_cu = 8;
+  int waves_per_cu = 0;    // 0: the default for the kernel (waves_per_cu_for)
   int scratch_blocks = 0;  // 0: the default for the geometry (scratch_blocks_for)
   int phase_mode = -1;  // phase-aligned stencil sweeps: -1 by neighbourhood size, 0 off, 1 on
   // optional caller-supplied device allocator (both set or both NULL)
@@ -367,6 +367,7 @@ void configure_sphere(const tpcf_ctx* c, const HostCat& h, CatDesc& d, int max_n
   double eps = 4.0 * ((c->rmax / dth + 1.0) * (4.5 * kappa + 24.0) * ldexp(1.0, -24) + edge);
   if (!(eps <= 0.2)) eps = 2.0;  // every candidate takes the exact path
   d.eps = (float)eps;
+  d.one_minus_eps = 1.0f - d.eps;
 }
 
 // Grid side, lattice, thresholds, stencil geometry and FP32 bin-decision bound of every
@@ -447,6 +448,7 @@ int configure_grid(tpcf_ctx* c) {
     double eps = 52.0 * ldexp(1.0, -24) * (c->rmax / delta + 1.0);
     if (eps > 0.2) eps = 2.0;  // no FP32 decisions at all: every candidate takes the exact path
     d.eps = (float)eps;
+  d.one_minus_eps = 1.0f - d.eps;
     c->cd.push_back(d);
   }
   c->ncell = (uint32_t)cells;
@@ -682,18 +684,27 @@ int scratch_blocks_for(const tpcf_ctx* c) {
   return is_sphere(c) ? 512 : 1024;
 }
 
+// Persistent waves per compute unit, unless set by tpcf_set_tuning: 12 (three per SIMD, as the
+// register allocation of the FP32 sweeps allows) for the mixed and sphere kernels, 8 for FP64.
+int waves_per_cu_for(const tpcf_ctx* c) {
+  if (c->waves_per_cu > 0) return c->waves_per_cu;
+  return c->precision == TPCF_PREC_FP64 ? 8 : 12;
+}
+
 // Host part of the sweep: buffers, normalisation constants and the kernel arguments.
 int prepare_sweep(tpcf_ctx* c, const uint32_t* tasks_d, uint32_t ntask, SweepArgs& a, int& waves) {
   const bool f64 = c->precision == TPCF_PREC_FP64;
   const bool sph = is_sphere(c);
   const int nb = c->nbins, L = c->lmax, NC = ncomp(L, sph);
   const int ncat = (int)c->cd.size();
-  waves = std::max(1, c->ncu * c->waves_per_cu);
-  if ((uint32_t)waves > ntask) waves = (int)std::max<uint32_t>(1, ntask);
   const int S = scratch_blocks_for(c);
   int rc;
-  const size_t lds = sweep_lds_bytes(S, nb);
+  const size_t lds = sweep_lds_bytes(nb, f64);
   if (lds > 160 * 1024) return fail(c, TPCF_E_UNSUPPORTED, "LDS layout too large");
+  // no more waves per CU than its 160 KiB of LDS holds (allocated in 512-byte granules)
+  const int lds_waves = (int)((160 * 1024) / ((lds + 511) & ~(size_t)511));
+  waves = std::max(1, c->ncu * std::min(waves_per_cu_for(c), lds_waves));
+  if ((uint32_t)waves > ntask) waves = (int)std::max<uint32_t>(1, ntask);
   if (S < kMinRegionBlocks * nb)
     return fail(c, TPCF_E_INVALID_ARG, "scratch_blocks must be at least 5 x nbins");
   if ((rc = ensure(c, c->scratch, (size_t)waves * (S + kScratchTail) * kBlock * 4, "scratch")) ||
@@ -1144,7 +1155,8 @@ int tpcf_autotune(tpcf_ctx* c, double sample_fraction, tpcf_tuning* out) {
   const tpcf_stats saved_stats = c->stats;
   const bool saved_debug = c->debug;
   const double ppc0 = c->ppc;
-  const int wpc0 = c->waves_per_cu;
+  const int wpc_set = c->waves_per_cu;
+  const int wpc0 = waves_per_cu_for(c);
   c->debug = false;
 
   // Up to 16 evenly spaced runs of consecutive cell-sorted points, sample_fraction of all: the
@@ -1196,8 +1208,8 @@ int tpcf_autotune(tpcf_ctx* c, double sample_fraction, tpcf_tuning* out) {
   double best_ms = ms_default, best_ppc = ppc0;
   int best_wpc = wpc0, tried = 1;
   const double ppcs[] = {3.0, 4.0, 6.0, 8.0, 12.0, 16.0, 24.0};
-  // The sphere's kernels hold fewer registers (three waves fit on a SIMD): 12 waves per CU too.
-  const int wpcs[] = {8, is_sphere(c) ? 12 : 6};
+  // The FP32 kernels are built for three waves per SIMD (12 per CU), FP64 for two (8 per CU).
+  const int wpcs[] = {wpc0, c->precision == TPCF_PREC_FP64 ? 6 : 8};
   for (int wi = 0; wi < 2 && rc == TPCF_OK; ++wi)
     for (int pi = 0; pi < 7 && rc == TPCF_OK; ++pi) {
       if (ppcs[pi] == ppc0 && wpcs[wi] == wpc0) continue;
@@ -1215,7 +1227,7 @@ int tpcf_autotune(tpcf_ctx* c, double sample_fraction, tpcf_tuning* out) {
   c->dbg_valid = false;  // debug output is kept by sorted position, and the grid was rebuilt
   if (rc) {
     c->ppc = ppc0;
-    c->waves_per_cu = wpc0;
+    c->waves_per_cu = wpc_set;
     return rc;
   }
   c->ppc = best_ppc;

@@ -141,7 +141,10 @@ __device__ __forceinline__ void add_moments(real (&acc)[S], real x, real y, real
   real pr = w, pi = real(0);  // w (x - i y)^m
   static_for<0, LMAX + 1>([&](auto M) {
     constexpr int m = M;
-    if constexpr (m > 0) {
+    if constexpr (m == 1) {  // pi is still 0
+      pi = -(pr * y);
+      pr = pr * x;
+    } else if constexpr (m > 1) {
       real nr = pr * x + pi * y;
       real ni = pi * x - pr * y;
       pr = nr;
@@ -335,6 +338,10 @@ template <class real>
 struct Tangent {
   real e1x, e1y, e1z, e2x, e2y, e2z;
 };
+
+__device__ __forceinline__ float uniform_f(float v) {
+  return __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(v)));
+}
 
 __device__ __forceinline__ double uniform_d(double v) {
   const uint64_t u = __double_as_longlong(v);
@@ -604,8 +611,9 @@ struct Lds {
   static constexpr int REG = BBLK + 128;         // uint32[33] scratch region start per bin (blocks)
   static constexpr int MOM = REG + 144;          // real[128] moments of one bin
   static constexpr int RUNS = MOM + 1024;        // uint2[128] non-empty runs of one row chunk
-  static constexpr int CUR = RUNS + 1024;        // uint64[kMaxBins + 64]: bin cursors, lane dummies
-  static constexpr int END = CUR + 8 * (kMaxBins + 64);
+  static constexpr int CUR = RUNS + 1024;        // uint64[kMaxBins]: bin cursors
+  static constexpr int PARK = CUR + 8 * kMaxBins;  // uint4[kBatch][64] records, uint32[kBatch][64] ids
+  static constexpr int END = PARK + kBatch * 64 * 20;
   static __host__ __device__ int bytes(int) { return END; }
 };
 
@@ -618,7 +626,7 @@ struct Row {
 struct CatU {
   int sh, K, nc, periodic, row_lo, row_w;
   uint32_t cell_base;
-  float cs, inv_cs, span, inv_span, reach, margin, inv_dl, u0, eps, inv_w, hinv;
+  float cs, inv_cs, span, inv_span, reach, margin, inv_dl, u0, eps, one_me, inv_w, hinv;
   int asin_small;
 };
 
@@ -709,8 +717,13 @@ __device__ __forceinline__ int lanes_below(uint64_t m) {
   return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
+// Waves per SIMD the register allocation targets: three for the FP32 sweeps (the mixed 3D shells
+// fit in 168 VGPRs while the pass state is parked in LDS during the replay), two for FP64.
+template <bool F64>
+constexpr int kSweepWaves = F64 ? 2 : 3;
+
 template <int LMAX, bool F64, bool SPH>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sweep_kernel(SweepArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSweepWaves<F64>))) void sweep_kernel(SweepArgs a) {
   using real = std::conditional_t<F64, double, float>;
   using P = std::conditional_t<SPH, PlanSph<LMAX>, Plan<LMAX, F64>>;
   constexpr int NC = P::NC;
@@ -827,17 +840,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sw
       cu.row_lo = uniform(cd.row_lo);
       cu.row_w = uniform(cd.row_w);
       cu.cell_base = uniform(cd.cell_base);
-      cu.cs = cd.cs;
-      cu.inv_cs = cd.inv_cs;
-      cu.span = cd.span;
-      cu.inv_span = 1.0f / cd.span;
-      cu.reach = cd.reach;
-      cu.margin = cd.margin;
-      cu.inv_dl = cd.inv_delta_l;
-      cu.u0 = cd.u0;
-      cu.eps = cd.eps;
-      cu.inv_w = 1.0f / (float)cu.row_w;
-      cu.hinv = cd.half_inv_scale;
+      // wave-uniform values live in scalar registers
+      cu.cs = uniform_f(cd.cs);
+      cu.inv_cs = uniform_f(cd.inv_cs);
+      cu.span = uniform_f(cd.span);
+      cu.inv_span = uniform_f(1.0f / cd.span);
+      cu.reach = uniform_f(cd.reach);
+      cu.margin = uniform_f(cd.margin);
+      cu.inv_dl = uniform_f(cd.inv_delta_l);
+      cu.u0 = uniform_f(cd.u0);
+      cu.eps = uniform_f(cd.eps);
+      cu.one_me = uniform_f(cd.one_minus_eps);
+      cu.inv_w = uniform_f(1.0f / (float)cu.row_w);
+      cu.hinv = uniform_f(cd.half_inv_scale);
       cu.asin_small = uniform(cd.asin_small);
       if (lane <= nb) sT[lane] = cd.T[lane];
       cur_cat = cat;
@@ -956,11 +971,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sw
       o = 0;
       lds_order();
     };
-    // Next round: lane k gets the sorted position of candidate o + k (kInvalid past the end).
+    // Next round: lane k gets the sorted position of candidate o + k (past the end: the index of
+    // the sentinel record, which is never a candidate, so every lane loads a valid record).
     auto gen_round = [&]() -> uint32_t {
       while (o >= sub_T) {
         if (run_next >= nrun) {
-          if (row_base >= nrows) return kInvalid;
+          if (row_base >= nrows) return a.sentinel;
           build_rows();
         } else {
           load_sub();
@@ -978,14 +994,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sw
         delta_c = ds;
       }
       my_cand += (unsigned long long)min(sub_T - o, (uint32_t)kBlock);
-      const uint32_t idx = g < sub_T ? g + delta : kInvalid;
+      const uint32_t idx = g < sub_T ? g + delta : a.sentinel;
       o += kBlock;
       return idx;
     };
     // Next batch of rounds (shifted through registers so gen_round is expanded once).
     auto gen_batch = [&](uint32_t(&id)[kBatch]) -> bool {
 #pragma unroll
-      for (int u = 0; u < kBatch; ++u) id[u] = kInvalid;
+      for (int u = 0; u < kBatch; ++u) id[u] = a.sentinel;
 #pragma unroll 1
       for (int u = 0; u < kBatch; ++u) {
         const uint32_t v = gen_round();
@@ -993,11 +1009,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sw
         for (int k = 0; k + 1 < kBatch; ++k) id[k] = id[k + 1];
         id[kBatch - 1] = v;
       }
-      return __ballot(id[0] != kInvalid) != 0;
+      return __ballot(id[0] != a.sentinel) != 0;
     };
     auto load_batch = [&](const uint32_t(&id)[kBatch], uint4(&rc)[kBatch]) {
 #pragma unroll
-      for (int u = 0; u < kBatch; ++u) rc[u] = a.rec[id[u] != kInvalid ? id[u] : p];
+      for (int u = 0; u < kBatch; ++u) rc[u] = a.rec[id[u]];
     };
 
     // ---- shells: replay every bin's blocks (one copy of this code)
@@ -1179,12 +1195,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sw
 
     // Evaluates one batch of rounds. Bin decision in FP32 when the fractional bin position is
     // farther than the proven error bound from an edge; every accepted lane takes the next entry
-    // of its bin's region from one LDS cursor increment and stores its sorted position there.
-    // Rejected lanes use their own dummy cursor and store slot, so the fast path has no
-    // divergent branch. Lanes near a bin edge are decided exactly afterwards (FP64 squared
-    // lattice separation against the integer thresholds). Returns true when a region passed
-    // its soft limit.
-    const uint32_t dummy_pos = (uint32_t)S * kBlock + lane;
+    // of its bin's region from one LDS cursor increment and stores its sorted position there
+    // (rejected lanes sit out both). Lanes near a bin edge are decided exactly afterwards (FP64
+    // squared lattice separation against the integer thresholds). Returns true when a region
+    // passed its soft limit.
     auto process_batch = [&](const uint32_t(&id)[kBatch], const uint4(&rc)[kBatch]) -> bool {
       bool soft = false;
       bool slowv[kBatch], accv[kBatch];
@@ -1209,20 +1223,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sw
         const float fl = floorf(uu);
         const float fr = uu - fl;
         const int bb = (int)fl;
-        const bool ok = id[u] != kInvalid;
-        const bool fast = fr >= cu.eps && fr <= 1.0f - cu.eps;
+        const bool ok = id[u] != a.sentinel;
+        const bool fast = fr >= cu.eps && fr <= cu.one_me;
         const bool acc = ok && fast && (uint32_t)bb < (uint32_t)nb;
         slowv[u] = ok && !fast;
         bbv[u] = bb;
         anyslow |= __ballot(slowv[u]);
         accv[u] = acc;
-        cwv[u] = atomicAdd(&cur[acc ? bb : kMaxBins + lane], 1ull);
+        cwv[u] = acc ? atomicAdd(&cur[bb], 1ull) : 0ull;
       }
 #pragma unroll
       for (int u = 0; u < kBatch; ++u) {
         const unsigned long long cw = cwv[u];
-        soft |= accv[u] && (uint32_t)cw >= (uint32_t)(cw >> 32);
-        scratch[accv[u] ? (uint32_t)cw : dummy_pos] = id[u];
+        if (accv[u]) {
+          soft |= (uint32_t)cw >= (uint32_t)(cw >> 32);
+          scratch[(uint32_t)cw] = id[u];
+        }
       }
       if (anyslow) {
 #pragma unroll
@@ -1267,7 +1283,29 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sw
           rA[u] = rB[u];
         }
       }
-      if (flush) flush_shells();
+      if (flush) {
+        // The batch in flight waits in LDS while the shells are replayed, so that the replay has
+        // the register file to itself (three waves per SIMD without spilling in the replay).
+        uint4* prec = reinterpret_cast<uint4*>(smem + Lds::PARK);
+        uint32_t* pid = reinterpret_cast<uint32_t*>(smem + Lds::PARK + kBatch * 64 * 16);
+        if (!last) {
+#pragma unroll
+          for (int u = 0; u < kBatch; ++u) {
+            prec[u * 64 + lane] = rA[u];
+            pid[u * 64 + lane] = idA[u];
+          }
+        }
+        asm volatile("" ::: "memory");
+        flush_shells();
+        asm volatile("" ::: "memory");
+        if (!last) {
+#pragma unroll
+          for (int u = 0; u < kBatch; ++u) {
+            rA[u] = prec[u * 64 + lane];
+            idA[u] = pid[u * 64 + lane];
+          }
+        }
+      }
       if (last) break;
     }
 
@@ -1317,8 +1355,8 @@ static hipError_t launch_one(SweepArgs args, int waves, size_t lds, hipStream_t 
   return hipSuccess;
 }
 
-size_t sweep_lds_bytes(int scratch_blocks, int nb) {
-  (void)scratch_blocks;
+size_t sweep_lds_bytes(int nb, bool f64) {
+  (void)f64;
   return (size_t)Lds::bytes(nb);
 }
 
@@ -1337,7 +1375,7 @@ static hipError_t launch_l(bool f64, bool sphere, const SweepArgs& args, int wav
 }
 
 hipError_t launch_sweep(int lmax, bool f64, bool sphere, const SweepArgs& args, int waves, hipStream_t stream) {
-  const size_t lds = sweep_lds_bytes(args.scratch_blocks, args.nb);
+  const size_t lds = sweep_lds_bytes(args.nb, f64);
   hipError_t err = hipErrorInvalidValue;
   switch (lmax) {
     case 0: err = launch_l<0>(f64, sphere, args, waves, lds, stream); break;

@@ -14,9 +14,9 @@ constexpr int kBatch = 4;        // pass rounds evaluated together (one batch of
 // crosses that soft limit still fits, then the shells are replayed and the region emptied.
 constexpr int kSoftReserve = kBatch * kBlock;
 constexpr int kMinRegionBlocks = kBatch + 1;
-// Blocks after a wave's regions: one takes rejected lanes' stores, and the shell replay may
-// read (and discard) up to four blocks past a region's last block.
-constexpr int kScratchTail = 5;
+// Blocks after a wave's regions: the shell replay may read (and discard) up to four blocks past
+// a region's last block.
+constexpr int kScratchTail = 4;
 constexpr int kQueueSegments = 8;  // task-queue segments, one per XCD
 constexpr int kTileF32 = 32;     // primaries per contraction tile, mixed precision
 constexpr int kTileF64 = 16;     // primaries per contraction tile, FP64
@@ -47,6 +47,7 @@ struct CatDesc {
   float inv_delta_l;     // 2^-sh / bin width: bin position per unit of stored coordinate difference
   float u0;              // -r_min / bin width
   float eps;             // fast bin decisions need a fractional bin position in [eps, 1 - eps]
+  float one_minus_eps;   // 1 - eps in FP32
   float half_inv_scale;  // sphere: 0.5 / scale, so that sqrt(R^2) * half_inv_scale = sin(theta / 2)
   int32_t asin_small;    // sphere: sin(theta_max / 2) <= 0.06, the three-term arcsine suffices
 };
