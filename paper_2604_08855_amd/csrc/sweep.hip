@@ -971,45 +971,47 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSweepWaves<
       o = 0;
       lds_order();
     };
-    // Next round: lane k gets the sorted position of candidate o + k (past the end: the index of
-    // the sentinel record, which is never a candidate, so every lane loads a valid record).
-    auto gen_round = [&]() -> uint32_t {
+    // Next batch: up to kBatch rounds from the current sub-chunk. Lane k of round u gets the sorted
+    // position of candidate o + 64 u + k, or past the sub-chunk's end the index of the sentinel
+    // record (never a candidate, so every lane loads a valid record). A batch never spans two
+    // sub-chunks, so the run offsets of all its rounds come from one window of run starts (the
+    // last batch of a sub-chunk may hold empty rounds). Returns false once the stencil is done.
+    auto gen_batch = [&](uint32_t(&id)[kBatch]) -> bool {
       while (o >= sub_T) {
         if (run_next >= nrun) {
-          if (row_base >= nrows) return a.sentinel;
+          if (row_base >= nrows) {
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) id[u] = a.sentinel;
+            return false;
+          }
           build_rows();
         } else {
           load_sub();
         }
       }
-      const uint32_t g = o + (uint32_t)lane;
-      uint64_t starts = __ballot(pre_v >= o && pre_v < o + (uint32_t)kBlock);
-      uint32_t delta = delta_c;
+      constexpr uint32_t span = kBatch * kBlock;
+      uint32_t g[kBatch], delta[kBatch];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        g[u] = o + (uint32_t)(u * kBlock + lane);
+        delta[u] = delta_c;
+      }
+      uint64_t starts = __ballot(pre_v >= o && pre_v < o + span);
       while (starts) {
         const int r = __ffsll((unsigned long long)starts) - 1;
         starts &= starts - 1;
         const uint32_t ps = uniform(__builtin_amdgcn_readlane(pre_v, r));
         const uint32_t ds = uniform(__builtin_amdgcn_readlane(dl_v, r));
-        if (g >= ps) delta = ds;
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u)
+          if (g[u] >= ps) delta[u] = ds;
         delta_c = ds;
       }
-      my_cand += (unsigned long long)min(sub_T - o, (uint32_t)kBlock);
-      const uint32_t idx = g < sub_T ? g + delta : a.sentinel;
-      o += kBlock;
-      return idx;
-    };
-    // Next batch of rounds (shifted through registers so gen_round is expanded once).
-    auto gen_batch = [&](uint32_t(&id)[kBatch]) -> bool {
+      my_cand += (unsigned long long)min(sub_T - o, span);
 #pragma unroll
-      for (int u = 0; u < kBatch; ++u) id[u] = a.sentinel;
-#pragma unroll 1
-      for (int u = 0; u < kBatch; ++u) {
-        const uint32_t v = gen_round();
-#pragma unroll
-        for (int k = 0; k + 1 < kBatch; ++k) id[k] = id[k + 1];
-        id[kBatch - 1] = v;
-      }
-      return __ballot(id[0] != a.sentinel) != 0;
+      for (int u = 0; u < kBatch; ++u) id[u] = g[u] < sub_T ? g[u] + delta[u] : a.sentinel;
+      o += span;
+      return true;
     };
     auto load_batch = [&](const uint32_t(&id)[kBatch], uint4(&rc)[kBatch]) {
 #pragma unroll
@@ -1199,56 +1201,60 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSweepWaves<
     // (rejected lanes sit out both). Lanes near a bin edge are decided exactly afterwards (FP64
     // squared lattice separation against the integer thresholds). Returns true when a region
     // passed its soft limit.
+    // FP32 bin position of a candidate: 3D linear in the separation, sphere linear in
+    // theta = 2 asin(chord / 2). fast: far enough from a bin edge for the FP32 decision.
+    auto bin_pos = [&](const uint4& r, int& bb, bool& fast) {
+      const float fx = (float)sdiff(r.x, P0.qx), fy = (float)sdiff(r.y, P0.qy), fz = (float)sdiff(r.z, P0.qz);
+      const float r2 = fx * fx + fy * fy + fz * fz;
+      float uu;
+      if constexpr (SPH) {
+        const float x = __builtin_amdgcn_sqrtf(r2) * cu.hinv;
+        uu = (cu.asin_small ? asin_small(x) : asin01(x)) * cu.inv_dl + cu.u0;
+      } else {
+        uu = __builtin_amdgcn_sqrtf(r2) * cu.inv_dl + cu.u0;
+      }
+      const float fl = floorf(uu);
+      const float fr = uu - fl;
+      bb = (int)fl;
+      fast = fr >= cu.eps && fr <= cu.one_me;
+    };
     auto process_batch = [&](const uint32_t(&id)[kBatch], const uint4(&rc)[kBatch]) -> bool {
       bool soft = false;
-      bool slowv[kBatch], accv[kBatch];
-      int bbv[kBatch];
-      unsigned long long cwv[kBatch];
-      uint64_t anyslow = 0;
+      bool accv[kBatch];
+      unsigned long long cwv[kBatch];  // set (and read) on accepted lanes only
+      bool slow = false;  // this lane has a candidate near a bin edge
       // all cursor increments of the batch are issued before the first result is used, so their
       // LDS round trips overlap
 #pragma unroll
       for (int u = 0; u < kBatch; ++u) {
-        const float fx = (float)sdiff(rc[u].x, P0.qx), fy = (float)sdiff(rc[u].y, P0.qy),
-                    fz = (float)sdiff(rc[u].z, P0.qz);
-        const float r2 = fx * fx + fy * fy + fz * fz;
-        // 3D: linear in the separation; sphere: linear in theta = 2 asin(chord / 2)
-        float uu;
-        if constexpr (SPH) {
-          const float x = __builtin_amdgcn_sqrtf(r2) * cu.hinv;
-          uu = (cu.asin_small ? asin_small(x) : asin01(x)) * cu.inv_dl + cu.u0;
-        } else {
-          uu = __builtin_amdgcn_sqrtf(r2) * cu.inv_dl + cu.u0;
-        }
-        const float fl = floorf(uu);
-        const float fr = uu - fl;
-        const int bb = (int)fl;
+        int bb;
+        bool fast;
+        bin_pos(rc[u], bb, fast);
         const bool ok = id[u] != a.sentinel;
-        const bool fast = fr >= cu.eps && fr <= cu.one_me;
         const bool acc = ok && fast && (uint32_t)bb < (uint32_t)nb;
-        slowv[u] = ok && !fast;
-        bbv[u] = bb;
-        anyslow |= __ballot(slowv[u]);
+        slow |= ok && !fast;
         accv[u] = acc;
-        cwv[u] = acc ? atomicAdd(&cur[bb], 1ull) : 0ull;
+        if (acc) cwv[u] = atomicAdd(&cur[bb], 1ull);
       }
 #pragma unroll
       for (int u = 0; u < kBatch; ++u) {
-        const unsigned long long cw = cwv[u];
         if (accv[u]) {
+          const unsigned long long cw = cwv[u];
           soft |= (uint32_t)cw >= (uint32_t)(cw >> 32);
           scratch[(uint32_t)cw] = id[u];
         }
       }
-      if (anyslow) {
+      if (__builtin_amdgcn_ballot_w64(slow)) {  // rare: the FP32 position is recomputed rather than kept
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
-          if (slowv[u]) {
+          int bb;
+          bool fast;
+          bin_pos(rc[u], bb, fast);
+          if (id[u] != a.sentinel && !fast) {
             const double ddx = sdiff(rc[u].x, P0.qx) >> cu.sh, ddy = sdiff(rc[u].y, P0.qy) >> cu.sh,
                          ddz = sdiff(rc[u].z, P0.qz) >> cu.sh;
             const double R2 = fma(ddx, ddx, fma(ddy, ddy, ddz * ddz));
             if (R2 > 0.0 && R2 >= T0 && R2 < Tn) {
-              int bb = bbv[u];
               bb = bb < 0 ? 0 : (bb >= nb ? nb - 1 : bb);
               while (R2 < sT[bb]) --bb;
               while (bb + 1 < nb && R2 >= sT[bb + 1]) ++bb;
