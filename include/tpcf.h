@@ -121,8 +121,9 @@ int tpcf_set_bins(tpcf_ctx* ctx, int nbins, double rmin, double rmax, int lmax);
 int tpcf_set_precision(tpcf_ctx* ctx, int precision);
 
 /*
- * Optional tuning: target mean points per grid cell (default 8; the grid side follows from it
- * and the catalogue density), persistent waves per compute unit (default 12 for the mixed and
+ * Optional tuning: target mean points per grid cell (default 8; the grid side in y and z follows
+ * from it and the catalogue density, and each such cell is split into up to 4 thinner cells along
+ * x), persistent waves per compute unit (default 12 for the mixed and
  * sphere sweeps, 8 for FP64; capped by what the compute unit's LDS holds), and scratch blocks
  * of 64 secondaries per wave (default 1024 in 3D and 512 on the sphere). A value of 0 keeps the
  * current setting.

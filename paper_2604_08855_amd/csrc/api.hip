@@ -317,7 +317,19 @@ typedef unsigned __int128 u128;
 // T_k = ceil(fl(fl(2 sin(theta_k / 2) 2^K / 4)^2)). The grid side follows the surface density
 // (a plane through a cubic grid cuts 1.5 / cs^2 cells per unit area on average, so cells on the
 // sphere hold about n cs^2 / (6 pi) points).
-void configure_sphere(const tpcf_ctx* c, const HostCat& h, CatDesc& d, int max_nc) {
+// Cells along x per cell along y and z. A stencil row (fixed y, z) is one contiguous run of
+// cell-sorted records however many x cells it spans, so thinner x cells clip each row closer to
+// the chord of the r_max sphere at no cost in the sweep: 4 thinner cells take the candidates per
+// in-range pair from about 1.31 to 1.23 at 16 points per cell. Capped so that a grid keeps at most
+// `budget` cells.
+int x_split(int nc, double budget) {
+  const double cube = (double)nc * nc * nc;
+  int f = 4;
+  while (f > 1 && cube * f > budget) f >>= 1;
+  return f;
+}
+
+void configure_sphere(const tpcf_ctx* c, const HostCat& h, CatDesc& d, int max_nc, double cell_budget) {
   const int nb = c->nbins;
   const double dth = (c->rmax - c->rmin) / nb;
   const double cmax = 2.0 * sin(0.5 * c->rmax);
@@ -336,6 +348,7 @@ void configure_sphere(const tpcf_ctx* c, const HostCat& h, CatDesc& d, int max_n
   if (h.n > 0) ncx = (int)floor(4.0 / sqrt(6.0 * kPi * c->ppc / (double)h.n));
   ncx = std::max(1, std::min(ncx, max_nc));
   d.nc = ncx;
+  d.nx = ncx * x_split(ncx, cell_budget);
   const double span = ldexp(1.0, d.K);
   const double margin = ldexp(1.0, d.K - 14);
   const double reach = cmax * d.scale + margin;
@@ -345,6 +358,7 @@ void configure_sphere(const tpcf_ctx* c, const HostCat& h, CatDesc& d, int max_n
   d.row_w = 2 * R + 1;
   d.cs = (float)(span / ncx);
   d.inv_cs = (float)(ncx / span);
+  d.inv_csx = (float)(d.nx / span);
   d.span = (float)span;
   d.reach = (float)reach;
   d.margin = (float)margin;
@@ -389,9 +403,9 @@ int configure_grid(tpcf_ctx* c) {
       // the dense cell table of a sphere's cube grows as nc^3: at most 512 per axis, and at most
       // 2^30 cells over all the maps of a batch
       const int max_nc = std::max(16, std::min(512, (int)floor(cbrt(1073741824.0 / (double)c->cats.size()))));
-      configure_sphere(c, h, d, max_nc);
+      configure_sphere(c, h, d, max_nc, std::min(67108864.0, 1073741824.0 / (double)c->cats.size()));
       d.cell_base = (uint32_t)cells;
-      cells += (uint64_t)d.nc * d.nc * d.nc;
+      cells += (uint64_t)d.nx * d.nc * d.nc;
       if (cells >= ((uint64_t)1 << 31)) return fail(c, TPCF_E_UNSUPPORTED, "too many grid cells");
       c->cd.push_back(d);
       continue;
@@ -413,8 +427,9 @@ int configure_grid(tpcf_ctx* c) {
     }
     ncx = std::max(1, std::min(ncx, 512));
     d.nc = ncx;
+    d.nx = ncx * x_split(ncx, 67108864.0);
     d.cell_base = (uint32_t)cells;
-    cells += (uint64_t)ncx * ncx * ncx;
+    cells += (uint64_t)d.nx * ncx * ncx;
     if (cells >= ((uint64_t)1 << 31)) return fail(c, TPCF_E_UNSUPPORTED, "too many grid cells");
     // per-primary stencil: rows within reach = r_max + margin (lattice units) of the primary
     const double span = ldexp(1.0, d.K);
@@ -437,6 +452,7 @@ int configure_grid(tpcf_ctx* c) {
     }
     d.cs = (float)(span / ncx);
     d.inv_cs = (float)(ncx / span);
+    d.inv_csx = (float)(d.nx / span);
     d.span = (float)span;
     d.reach = (float)reach;
     d.margin = (float)margin;

@@ -72,11 +72,11 @@ __global__ void k_snap(const double* __restrict__ x, const double* __restrict__ 
   const uint32_t qx = snap_coord(px, cd.scale, cd.K, cd.periodic);
   const uint32_t qy = snap_coord(py, cd.scale, cd.K, cd.periodic);
   const uint32_t qz = snap_coord(pz, cd.scale, cd.K, cd.periodic);
-  const uint64_t nc = (uint64_t)cd.nc;
-  const uint32_t cx = (uint32_t)(((uint64_t)qx * nc) >> cd.K);
+  const uint64_t nc = (uint64_t)cd.nc, nx = (uint64_t)cd.nx;
+  const uint32_t cx = (uint32_t)(((uint64_t)qx * nx) >> cd.K);
   const uint32_t cy = (uint32_t)(((uint64_t)qy * nc) >> cd.K);
   const uint32_t cz = (uint32_t)(((uint64_t)qz * nc) >> cd.K);
-  const uint32_t id = cd.cell_base + (cz * (uint32_t)nc + cy) * (uint32_t)nc + cx;
+  const uint32_t id = cd.cell_base + (cz * (uint32_t)nc + cy) * (uint32_t)nx + cx;
   cell[i] = id;
   qtmp[i] = make_uint4(qx << cd.sh, qy << cd.sh, qz << cd.sh, __float_as_uint((float)pw));
   atomicAdd(&hist[id], 1u);

@@ -624,14 +624,15 @@ struct Row {
 
 // Wave-uniform catalogue parameters.
 struct CatU {
-  int sh, K, nc, periodic, row_lo, row_w;
+  int sh, K, nc, nx, periodic, row_lo, row_w;
   uint32_t cell_base;
-  float cs, inv_cs, span, inv_span, reach, margin, inv_dl, u0, eps, one_me, inv_w, hinv;
+  float cs, inv_cs, inv_csx, span, inv_span, reach, margin, inv_dl, u0, eps, one_me, inv_w, hinv;
   int asin_small;
 };
 
 // Builds row t of the primary's stencil (rows are offsets (dy, dz) from the primary's cell):
-// the x cells whose slab intersects the chord of the r_max sphere through that row.
+// the x cells (nx per row, thinner than the y-z cells) whose slab intersects the chord of the
+// r_max sphere through that row.
 __device__ __forceinline__ Row make_row(const uint32_t* __restrict__ cell_start, const CatU& c, int t, int cx,
                                         int cy, int cz, float qx, float qy, float qz) {
   Row r = {0u, 0u, 0u, 0u};
@@ -663,29 +664,30 @@ __device__ __forceinline__ Row make_row(const uint32_t* __restrict__ cell_start,
   const float d2 = dyf * dyf + dzf * dzf;
   if (d2 >= rr) return r;
   const float h = __builtin_amdgcn_sqrtf(rr - d2) + c.margin;
-  const int xa = (int)floorf((qx - h) * c.inv_cs);
-  const int xb = (int)floorf((qx + h) * c.inv_cs);
-  const uint32_t rowbase = c.cell_base + (uint32_t)((zw * nc + yw) * nc);
+  const int nx = c.nx;
+  const int xa = (int)floorf((qx - h) * c.inv_csx);
+  const int xb = (int)floorf((qx + h) * c.inv_csx);
+  const uint32_t rowbase = c.cell_base + (uint32_t)((zw * nc + yw) * nx);
   int a0, b0, a1 = 0, b1 = -1;
   if (c.periodic) {
-    if (xb - xa + 1 >= nc) {
+    if (xb - xa + 1 >= nx) {
       a0 = 0;
-      b0 = nc - 1;
+      b0 = nx - 1;
     } else {
-      int aw = xa % nc;
-      aw += aw < 0 ? nc : 0;
+      int aw = xa % nx;
+      aw += aw < 0 ? nx : 0;
       const int bw = aw + (xb - xa);
       a0 = aw;
-      if (bw < nc) {
+      if (bw < nx) {
         b0 = bw;
       } else {
-        b0 = nc - 1;
-        b1 = bw - nc;
+        b0 = nx - 1;
+        b1 = bw - nx;
       }
     }
   } else {
     a0 = xa < 0 ? 0 : xa;
-    b0 = xb > nc - 1 ? nc - 1 : xb;
+    b0 = xb > nx - 1 ? nx - 1 : xb;
     if (a0 > b0) return r;
   }
   r.b0 = cell_start[rowbase + a0];
@@ -836,6 +838,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSweepWaves<
       cu.sh = uniform(cd.sh);
       cu.K = uniform(cd.K);
       cu.nc = uniform(cd.nc);
+      cu.nx = uniform(cd.nx);
       cu.periodic = uniform(cd.periodic);
       cu.row_lo = uniform(cd.row_lo);
       cu.row_w = uniform(cd.row_w);
@@ -843,6 +846,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSweepWaves<
       // wave-uniform values live in scalar registers
       cu.cs = uniform_f(cd.cs);
       cu.inv_cs = uniform_f(cd.inv_cs);
+      cu.inv_csx = uniform_f(cd.inv_csx);
       cu.span = uniform_f(cd.span);
       cu.inv_span = uniform_f(1.0f / cd.span);
       cu.reach = uniform_f(cd.reach);

@@ -28,7 +28,9 @@ struct CatDesc {
   uint32_t point_base;
   uint32_t npoints;
   uint32_t cell_base;    // index of this catalogue's first cell_start entry
-  int32_t nc;            // cells per axis
+  int32_t nc;            // cells per axis in y and z
+  int32_t nx;            // cells along x: a multiple of nc (thinner slabs clip stencil rows closer
+                         // to the r_max sphere at no cost, a row being one contiguous run)
   int32_t K;             // lattice bits: coordinates are integers in [0, 2^K)
   int32_t sh;            // stored coordinate = q << sh (32-K when periodic, else 0)
   int32_t periodic;
@@ -41,6 +43,7 @@ struct CatDesc {
   // FP32 quantities of the per-primary stencil and of the fast bin decision (lattice units)
   float cs;              // cell side 2^K / nc
   float inv_cs;
+  float inv_csx;         // nx / 2^K
   float span;            // 2^K
   float reach;           // r_max + margin
   float margin;
