@@ -162,6 +162,25 @@ int tpcf_set_allocator(tpcf_ctx* ctx, tpcf_alloc_fn alloc, tpcf_free_fn free_, v
 int tpcf_set_phase_aligned(tpcf_ctx* ctx, int mode);
 
 /*
+ * Optional: deterministic mode, for bit-for-bit reproducible results (the same inputs, settings
+ * and library give the same bits on every run). Every primary's shells are already fixed by its
+ * stencil order; what scheduling changes is how primaries are grouped into contraction tiles and
+ * the order in which partial sums meet (the reduction over primaries of the paper's
+ * Implementation section is a plain sum, so any order is correct up to rounding). With enable = 1
+ * the sweep hands out fixed tiles of consecutive primaries (32 mixed, 16 FP64; a tile never spans
+ * two catalogues), writes each tile's zeta contribution and 2PCF weight sums to a slot of its own
+ * (device memory: (lmax+1) nbins^2 + nbins doubles per tile, about 1.1 GB for 10^6 points at
+ * 20 bins and lmax 10 in mixed precision) and adds the slots in tile order in a second kernel
+ * (chunks of 64 tiles, then the chunks of each catalogue), in place of atomic additions;
+ * phase-aligned sweeps are off. Applies to tpcf_compute_zeta, tpcf_compute_zeta_range,
+ * tpcf_compute_batch, tpcf_compute_sphere_batch and tpcf_degenerate. enable = 0 (default)
+ * restores the faster atomic reduction.
+ * Takes effect at the next compute call. Errors: TPCF_E_INVALID_ARG for another value; a compute
+ * call whose slots do not fit fails with TPCF_E_OUT_OF_MEMORY.
+ */
+int tpcf_set_deterministic(tpcf_ctx* ctx, int enable);
+
+/*
  * Autotuner for the persistent sweep. On the catalogue(s) staged by the last tpcf_set_catalog,
  * tpcf_set_sphere_catalog or tpcf_compute_batch call, with the current bins and precision, it times
  * the sweep over a sample of primaries (a fraction sample_fraction of all, taken as up to 16 evenly

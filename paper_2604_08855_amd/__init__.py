@@ -33,7 +33,7 @@ EXPORTS = [
     "tpcf_compute_batch", "tpcf_debug_pair_counts", "tpcf_debug_alm", "tpcf_set_debug",
     "tpcf_get_stats", "tpcf_last_error", "tpcf_autotune", "tpcf_pair_sums", "tpcf_edge_correct",
     "tpcf_set_sphere_catalog", "tpcf_set_pivot_cell", "tpcf_edge_correct_sphere", "tpcf_compute_sphere_batch",
-    "tpcf_set_phase_aligned", "tpcf_degenerate", "tpcf_set_allocator", "tpcf_set_catalog_f32",
+    "tpcf_set_phase_aligned", "tpcf_set_deterministic", "tpcf_degenerate", "tpcf_set_allocator", "tpcf_set_catalog_f32",
     "tpcf_set_sphere_catalog_f32",
 ]
 
@@ -95,6 +95,7 @@ def _load() -> ctypes.CDLL:
         "tpcf_set_precision": ([vp, i], i),
         "tpcf_set_tuning": ([vp, d, i, i], i),
         "tpcf_set_phase_aligned": ([vp, i], i),
+        "tpcf_set_deterministic": ([vp, i], i),
         "tpcf_degenerate": ([vp, vp, i], i),
         "tpcf_set_allocator": ([vp, vp, vp, vp], i),
         "tpcf_set_catalog_f32": ([vp, i64, vp, vp, vp, vp, d, i, i], i),
@@ -238,6 +239,11 @@ class Context:
         self._alloc_cbs = (_alloc, _free)
         self._check(_lib.tpcf_set_allocator(self._h, ctypes.cast(_alloc, ctypes.c_void_p),
                                             ctypes.cast(_free, ctypes.c_void_p), None))
+
+    def set_deterministic(self, enable: bool = True):
+        """Bit-for-bit reproducible results: fixed tiles and a fixed-order reduction
+        (see tpcf_set_deterministic)."""
+        self._check(_lib.tpcf_set_deterministic(self._h, 1 if enable else 0))
 
     def set_phase_aligned(self, mode: int = -1):
         """Phase-aligned stencil sweeps: -1 by neighbourhood size (default), 0 off, 1 on

@@ -30,6 +30,9 @@ hipError_t square_weights(const uint4* rec, const double* w64, uint32_t n, uint4
 void unsort_counts(const int32_t* in, const uint32_t* perm, int64_t* out, uint32_t n, int nb, hipStream_t s);
 void unsort_alm(const void* in, bool f64, const uint32_t* perm, double* out, uint32_t n, int row, hipStream_t s);
 hipError_t launch_sweep(int lmax, bool f64, bool sphere, const SweepArgs& args, int waves, hipStream_t stream);
+hipError_t launch_det_reduce(const double* det_out, uint32_t stride, const uint2* chunks, uint32_t nchunk,
+                             const uint32_t* cat_chunk, int ncat, uint32_t Z, int nb, double* part1, double* zeta,
+                             double* dd, hipStream_t s);
 size_t sweep_lds_bytes(int nb, bool f64);
 size_t sweep_tile_bytes_per_wave(int lmax, int nb, bool f64, bool sphere);
 std::vector<double> threej_squared_table(int lmax);
@@ -93,6 +96,7 @@ struct tpcf_ctx {
   tpcf_free_fn free_fn = nullptr;
   void* alloc_user = nullptr;
   bool debug = false;
+  bool deterministic = false;  // fixed tiles and a fixed-order reduction (tpcf_set_deterministic)
 
   // staged input (device FP64 copies, concatenated catalogues)
   bool cat_set = false;
@@ -116,6 +120,8 @@ struct tpcf_ctx {
   // degenerate-term sweep: records with squared weights, and its own outputs
   DevBuf dg_rec, dg_w64, dg_zeta, dg_stats, dg_pairs, dg_dd;
   DevBuf rg_flag, rg_pos, rg_bsum;  // primary-range task lists
+  DevBuf det_tiles, det_out, det_chunks, det_catchunk, det_part1;  // deterministic form
+  uint32_t det_nchunk = 0;
   // shared pivots: pivot cell side (0 = exact, < 0 = the mean separation), cell tables, pivots
   double pivot_h = 0.0;
   DevBuf pv_keys, pv_idx, pv_head, pv_slot, pv_bsum, pv_tmp, pv_rec, pv_w64, pv_hq, pv_start;
@@ -171,7 +177,8 @@ std::vector<DevBuf*> all_bufs(tpcf_ctx* c) {
           &c->alm_dbg, &c->conv_idx, &c->conv32, &c->conv64, &c->regions, &c->bin_pairs, &c->bin_dd,
           &c->edge_tab, &c->edge_io, &c->pv_keys, &c->pv_idx, &c->pv_head, &c->pv_slot,
           &c->pv_bsum, &c->pv_tmp, &c->pv_rec, &c->pv_w64, &c->pv_hq, &c->pv_start, &c->dg_rec, &c->dg_w64,
-          &c->dg_zeta, &c->dg_stats, &c->dg_pairs, &c->dg_dd, &c->rg_flag, &c->rg_pos, &c->rg_bsum};
+          &c->dg_zeta, &c->dg_stats, &c->dg_pairs, &c->dg_dd, &c->rg_flag, &c->rg_pos, &c->rg_bsum,
+          &c->det_tiles, &c->det_out, &c->det_chunks, &c->det_catchunk, &c->det_part1};
 }
 
 size_t total_bytes(tpcf_ctx* c) {
@@ -784,6 +791,54 @@ int prepare_sweep(tpcf_ctx* c, const uint32_t* tasks_d, uint32_t ntask, SweepArg
   return TPCF_OK;
 }
 
+// Deterministic form: tiles of the contraction size over each catalogue's tasks (starts[k] = first
+// task of catalogue k, ncat + 1 entries), one result slot per tile, and the tables of the
+// fixed-order reduction (chunks of kDetChunk consecutive tiles, then the chunks of a catalogue).
+constexpr uint32_t kDetChunk = 64;
+int setup_det(tpcf_ctx* c, const std::vector<uint32_t>& starts, SweepArgs& a) {
+  const int ncat = (int)starts.size() - 1;
+  const uint32_t TP = c->precision == TPCF_PREC_FP64 ? kTileF64 : kTileF32;
+  std::vector<uint2> tiles, chunks;
+  std::vector<uint32_t> cat_chunk(ncat + 1, 0);
+  for (int k = 0; k < ncat; ++k) {
+    const size_t tile0 = tiles.size();
+    for (uint32_t t = starts[k]; t < starts[k + 1]; t += TP)
+      tiles.push_back(make_uint2(t, std::min(t + TP, starts[k + 1])));
+    cat_chunk[k] = (uint32_t)chunks.size();
+    for (size_t q = tile0; q < tiles.size(); q += kDetChunk)
+      chunks.push_back(make_uint2((uint32_t)q, (uint32_t)std::min(q + kDetChunk, tiles.size())));
+  }
+  cat_chunk[ncat] = (uint32_t)chunks.size();
+  const size_t stride = (size_t)(c->lmax + 1) * c->nbins * c->nbins + c->nbins;
+  int rc;
+  if ((rc = ensure(c, c->det_tiles, std::max<size_t>(1, tiles.size()) * sizeof(uint2), "deterministic tiles")) ||
+      (rc = ensure(c, c->det_out, std::max<size_t>(1, tiles.size()) * stride * 8, "deterministic tiles")) ||
+      (rc = ensure(c, c->det_chunks, std::max<size_t>(1, chunks.size()) * sizeof(uint2), "deterministic tiles")) ||
+      (rc = ensure(c, c->det_catchunk, cat_chunk.size() * 4, "deterministic tiles")) ||
+      (rc = ensure(c, c->det_part1, std::max<size_t>(1, chunks.size()) * stride * 8, "deterministic tiles")))
+    return rc;
+  if (!tiles.empty()) {
+    HIP_TRY(c, hipMemcpyAsync(c->det_tiles.p, tiles.data(), tiles.size() * sizeof(uint2), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->det_chunks.p, chunks.data(), chunks.size() * sizeof(uint2), hipMemcpyHostToDevice, c->stream));
+  }
+  HIP_TRY(c, hipMemcpyAsync(c->det_catchunk.p, cat_chunk.data(), cat_chunk.size() * 4, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));  // the host tables go out of scope
+  a.det_tiles = (const uint2*)c->det_tiles.p;
+  a.ndet = (uint32_t)tiles.size();
+  a.det_out = (double*)c->det_out.p;
+  a.phase_rows = 0;
+  c->det_nchunk = (uint32_t)chunks.size();
+  return TPCF_OK;
+}
+
+// First task of every catalogue when every point is a primary.
+std::vector<uint32_t> point_starts(const tpcf_ctx* c) {
+  std::vector<uint32_t> st;
+  for (const CatDesc& d : c->cd) st.push_back(d.point_base);
+  st.push_back((uint32_t)c->ntot);
+  return st;
+}
+
 // Device part of the sweep: clears (fill kernels, never memset nodes) and the persistent launch.
 int record_sweep(tpcf_ctx* c, const SweepArgs& a, int waves) {
   const bool f64 = c->precision == TPCF_PREC_FP64;
@@ -799,6 +854,12 @@ int record_sweep(tpcf_ctx* c, const SweepArgs& a, int waves) {
   fill_u32(reinterpret_cast<uint32_t*>(a.bin_pairs), 0u, (size_t)a.ncat * nb * 2, c->stream);
   fill_f64(a.bin_dd, 0.0, (size_t)a.ncat * nb, c->stream);
   if (a.ntask > 0) HIP_TRY(c, launch_sweep(L, f64, sph, a, waves, c->stream));
+  if (a.det_tiles && a.ntask > 0) {
+    const uint32_t Z = (uint32_t)((L + 1) * nb * nb);
+    HIP_TRY(c, launch_det_reduce(a.det_out, Z + (uint32_t)nb, (const uint2*)c->det_chunks.p, c->det_nchunk,
+                                 (const uint32_t*)c->det_catchunk.p, a.ncat, Z, nb, (double*)c->det_part1.p,
+                                 a.zeta, a.bin_dd, c->stream));
+  }
   return TPCF_OK;
 }
 
@@ -964,6 +1025,23 @@ int compute(tpcf_ctx* c, int64_t p_begin, int64_t p_end, double* zeta, int memsp
     a.prim_cat_start = (const uint32_t*)c->pv_start.p;
     a.counts = nullptr;  // per-point debug rows do not apply to pivots
     a.alm_debug = nullptr;
+  }
+  if (c->deterministic) {
+    std::vector<uint32_t> starts;
+    if (pivots) {
+      starts.resize(c->cd.size() + 1);
+      HIP_TRY(c, hipMemcpyAsync(starts.data(), c->pv_start.p, starts.size() * 4, hipMemcpyDeviceToHost, c->stream));
+      HIP_TRY(c, hipStreamSynchronize(c->stream));
+    } else if (tasks) {  // a primary range: its tasks are grouped by catalogue
+      starts.push_back(0);
+      for (const HostCat& h : c->cats) {
+        const int64_t lo = std::max<int64_t>(p_begin, h.first), hi = std::min<int64_t>(p_end, h.first + h.n);
+        starts.push_back(starts.back() + (uint32_t)std::max<int64_t>(0, hi - lo));
+      }
+    } else {
+      starts = point_starts(c);
+    }
+    if ((rc = setup_det(c, starts, a))) return rc;
   }
   c->stats.waves = waves;
   // The null stream cannot be captured: batches on it launch eagerly. So do batches with shared
@@ -1150,6 +1228,14 @@ int tpcf_set_allocator(tpcf_ctx* c, tpcf_alloc_fn alloc, tpcf_free_fn free_, voi
   return TPCF_OK;
 }
 
+int tpcf_set_deterministic(tpcf_ctx* c, int enable) {
+  if (!c) return TPCF_E_INVALID_ARG;
+  if (enable != 0 && enable != 1) return fail(c, TPCF_E_INVALID_ARG, "enable must be 0 or 1");
+  c->deterministic = enable == 1;
+  c->err.clear();
+  return TPCF_OK;
+}
+
 int tpcf_set_phase_aligned(tpcf_ctx* c, int mode) {
   if (!c) return TPCF_E_INVALID_ARG;
   if (mode < -1 || mode > 1) return fail(c, TPCF_E_INVALID_ARG, "mode must be -1, 0 or 1");
@@ -1305,7 +1391,8 @@ int tpcf_degenerate(tpcf_ctx* c, double* D, int memspace) {
     a.stats = (unsigned long long*)c->dg_stats.p;
     a.bin_pairs = (unsigned long long*)c->dg_pairs.p;
     a.bin_dd = (double*)c->dg_dd.p;
-    rc = record_sweep(c, a, waves);
+    if (c->deterministic) rc = setup_det(c, point_starts(c), a);
+    if (!rc) rc = record_sweep(c, a, waves);
   }
   c->lmax = saved_L;
   c->precision = saved_prec;

@@ -724,7 +724,11 @@ __device__ __forceinline__ int lanes_below(uint64_t m) {
 template <bool F64>
 constexpr int kSweepWaves = F64 ? 2 : 3;
 
-template <int LMAX, bool F64, bool SPH>
+// DET: deterministic form. Tickets hand out whole tiles of consecutive tasks (a tile never spans
+// two catalogues), each tile's contraction and 2PCF weight sums go to the tile's own slot of
+// a.det_out, and a second kernel adds the slots in tile order; with every primary's shells fixed
+// by its stencil order, the result no longer depends on scheduling.
+template <int LMAX, bool F64, bool SPH, bool DET>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSweepWaves<F64>))) void sweep_kernel(SweepArgs a) {
   using real = std::conditional_t<F64, double, float>;
   using P = std::conditional_t<SPH, PlanSph<LMAX>, Plan<LMAX, F64>>;
@@ -748,6 +752,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSweepWaves<
   uint32_t* scratch = a.scratch + (size_t)wave * (S + kScratchTail) * kBlock;
   real* tile = reinterpret_cast<real*>(a.tile) + (size_t)wave * (TP * nb * NC + (LMAX + 1) * nb * nb * (F64 ? 1 : 2));
   double* part = reinterpret_cast<double*>(tile + TP * nb * NC);
+  // DET: slot of the current tile, [(LMAX+1) nb nb] zeta then [nb] weight sums
+  const size_t det_stride = (size_t)(LMAX + 1) * nb * nb + nb;
 
   // Scratch regions: bin b owns blocks [reg[b], reg[b+1]).
   if (lane <= nb) reg[lane] = a.regions[lane];
@@ -778,7 +784,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSweepWaves<
   auto flush_bins = [&]() {
     if (bins_cat >= 0 && lane < nb) {
       if (bins_np) atomicAdd(&a.bin_pairs[(size_t)bins_cat * nb + lane], bins_np);
-      if (bins_dd != 0.0) atomicAdd(&a.bin_dd[(size_t)bins_cat * nb + lane], bins_dd);
+      if (!DET && bins_dd != 0.0) atomicAdd(&a.bin_dd[(size_t)bins_cat * nb + lane], bins_dd);
     }
     bins_np = 0;
     bins_dd = 0.0;
@@ -786,7 +792,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSweepWaves<
   CatU cu = {};
 
   auto flush_part = [&]() {
-    if (part_cat >= 0) {
+    if (!DET && part_cat >= 0) {
       double* zt = a.zeta + (size_t)part_cat * (LMAX + 1) * nb * nb;
       for (int i = lane; i < (LMAX + 1) * nb * nb; i += 64) {
         const double v = part[i];
@@ -814,18 +820,47 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSweepWaves<
   // leaves after it has found all of them exhausted.
   int seg = (int)(blockIdx.x % (uint32_t)kQueueSegments), seg_left = kQueueSegments;
   const uint32_t seg_waves = max(1u, gridDim.x / (uint32_t)kQueueSegments);  // waves in flight per segment
-  for (;;) {
-    const uint32_t lo = (uint32_t)((uint64_t)a.ntask * (uint32_t)seg / kQueueSegments);
-    const uint32_t hi = (uint32_t)((uint64_t)a.ntask * (uint32_t)(seg + 1) / kQueueSegments);
-    uint32_t j = 0;  // ticket within the segment
-    if (lane == 0) j = atomicAdd(a.queue + seg, 1u);
-    j = uniform(j);
-    if (j >= hi - lo) {
-      if (--seg_left == 0) break;
+  uint32_t j = 0;  // ticket within its segment
+  // Next ticket of [0, n): segment base + j; false once every segment is exhausted.
+  auto next_ticket = [&](uint32_t n, uint32_t& ticket) -> bool {
+    for (;;) {
+      const uint32_t lo = (uint32_t)((uint64_t)n * (uint32_t)seg / kQueueSegments);
+      const uint32_t hi = (uint32_t)((uint64_t)n * (uint32_t)(seg + 1) / kQueueSegments);
+      uint32_t jj = 0;
+      if (lane == 0) jj = atomicAdd(a.queue + seg, 1u);
+      j = uniform(jj);
+      if (j < hi - lo) {
+        ticket = lo + j;
+        return true;
+      }
+      if (--seg_left == 0) return false;
       seg = (seg + 1) % kQueueSegments;
-      continue;
     }
-    const uint32_t t = lo + j;
+  };
+  uint32_t det_t = 0, det_end = 0;
+  // DET: closes the current tile (contraction into its slot, weight sums) and opens the next.
+  auto det_next_tile = [&]() -> bool {
+    do_contract();
+    if (det_end > 0 && lane < nb) part[(size_t)(LMAX + 1) * nb * nb + lane] = bins_dd;
+    bins_dd = 0.0;
+    uint32_t tk;
+    if (!next_ticket(a.ndet, tk)) return false;
+    const uint2 tr = a.det_tiles[tk];
+    det_t = uniform(tr.x);
+    det_end = uniform(tr.y);
+    part = a.det_out + (size_t)tk * det_stride;
+    for (size_t i = lane; i < det_stride; i += 64) part[i] = 0.0;
+    __syncthreads();
+    return true;
+  };
+  for (;;) {
+    uint32_t t;
+    if constexpr (DET) {
+      if (det_t == det_end && !det_next_tile()) break;
+      t = det_t++;
+    } else {
+      if (!next_ticket(a.ntask, t)) break;
+    }
     const uint32_t p = uniform(a.task_list ? a.task_list[t] : t);
     const int cat = uniform(a.prim_cat_start ? range_of([&](int k) { return a.prim_cat_start[k]; }, a.ncat, p)
                                              : catalogue_of(a.cats, a.ncat, p));
@@ -917,7 +952,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSweepWaves<
     // (shared through L2) instead of the whole neighbourhood. Rows are counted in chunks of 64 (at
     // most 64 chunks: lane k keeps chunk k's candidates).
     int rot = 0;
-    if (a.phase_rows && nrows <= 64 * 64) {
+    if (!DET && a.phase_rows && nrows <= 64 * 64) {
       const int nchunk = (nrows + 63) >> 6;
       uint32_t ctot = 0, total = 0;
       for (int k = 0; k < nchunk; ++k) {
@@ -1344,8 +1379,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSweepWaves<
     ++tile_n;
     if (tile_n == TP) do_contract();
   }
-  do_contract();
-  flush_part();
+  if constexpr (!DET) {  // (DET closed its last tile before leaving the loop)
+    do_contract();
+    flush_part();
+  }
   flush_bins();
   if (lane == 0) {
     atomicAdd(&a.stats[0], my_pairs);
@@ -1356,13 +1393,52 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSweepWaves<
 // ------------------------------------------------------------------------------------------
 // Host-side launch table.
 // ------------------------------------------------------------------------------------------
-template <int LMAX, bool F64, bool SPH>
-static hipError_t launch_one(SweepArgs args, int waves, size_t lds, hipStream_t stream) {
-  const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&sweep_kernel<LMAX, F64, SPH>),
+template <int LMAX, bool F64, bool SPH, bool DET>
+static hipError_t launch_det(SweepArgs args, int waves, size_t lds, hipStream_t stream) {
+  const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&sweep_kernel<LMAX, F64, SPH, DET>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((sweep_kernel<LMAX, F64, SPH>), dim3(waves), dim3(64), lds, stream, args);
+  hipLaunchKernelGGL((sweep_kernel<LMAX, F64, SPH, DET>), dim3(waves), dim3(64), lds, stream, args);
   return hipSuccess;
+}
+template <int LMAX, bool F64, bool SPH>
+static hipError_t launch_one(SweepArgs args, int waves, size_t lds, hipStream_t stream) {
+  return args.det_tiles ? launch_det<LMAX, F64, SPH, true>(args, waves, lds, stream)
+                        : launch_det<LMAX, F64, SPH, false>(args, waves, lds, stream);
+}
+
+// Deterministic form, second step: the tile slots are added in tile order, in two fixed levels
+// (chunks of consecutive tiles, then the chunks of each catalogue).
+__global__ void k_det_chunks(const double* __restrict__ det_out, uint32_t stride, const uint2* __restrict__ chunks,
+                             uint32_t nchunk, double* __restrict__ part1) {
+  const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= (size_t)nchunk * stride) return;
+  const uint32_t q = (uint32_t)(g / stride), i = (uint32_t)(g % stride);
+  const uint2 c = chunks[q];
+  double s = 0.0;
+  for (uint32_t t = c.x; t < c.y; ++t) s += det_out[(size_t)t * stride + i];
+  part1[g] = s;
+}
+__global__ void k_det_cats(const double* __restrict__ part1, uint32_t stride, const uint32_t* __restrict__ cat_chunk,
+                           int ncat, uint32_t Z, int nb, double* __restrict__ zeta, double* __restrict__ dd) {
+  const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= (size_t)ncat * stride) return;
+  const uint32_t k = (uint32_t)(g / stride), i = (uint32_t)(g % stride);
+  double s = 0.0;
+  for (uint32_t q = cat_chunk[k]; q < cat_chunk[k + 1]; ++q) s += part1[(size_t)q * stride + i];
+  if (i < Z) zeta[(size_t)k * Z + i] = s;
+  else dd[(size_t)k * nb + (i - Z)] = s;
+}
+
+hipError_t launch_det_reduce(const double* det_out, uint32_t stride, const uint2* chunks, uint32_t nchunk,
+                             const uint32_t* cat_chunk, int ncat, uint32_t Z, int nb, double* part1, double* zeta,
+                             double* dd, hipStream_t s) {
+  const size_t n1 = (size_t)nchunk * stride, n2 = (size_t)ncat * stride;
+  if (n1) hipLaunchKernelGGL(k_det_chunks, dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, s, det_out, stride, chunks,
+                             nchunk, part1);
+  if (n2) hipLaunchKernelGGL(k_det_cats, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s, part1, stride, cat_chunk,
+                             ncat, Z, nb, zeta, dd);
+  return hipGetLastError();
 }
 
 size_t sweep_lds_bytes(int nb, bool f64) {

@@ -85,6 +85,11 @@ struct SweepArgs {
   const int16_t* conv_idx;
   const float* conv_coef32;
   const double* conv_coef64;
+  // deterministic form (NULL det_tiles: off): tile k covers tasks [det_tiles[k].x, det_tiles[k].y)
+  // of one catalogue; its zeta contraction and weight sums go to det_out + k * det_stride
+  const uint2* det_tiles;
+  uint32_t ndet;
+  double* det_out;
 };
 
 constexpr int kConvTerms = 6;
