@@ -11,9 +11,10 @@
 //   k_scan_*    : exclusive scan of the histogram -> cell_start (three small kernels).
 //   k_scatter   : each point claims a slot of its cell (atomic, so the order inside a cell is
 //                 arbitrary at this point).
-//   k_cellsort  : restores input order inside every cell of up to kCellSortMax points, so the
-//                 sorted layout (catalogue, cell, input index) and hence every summation order is
-//                 reproducible.
+//   k_cellsort  : restores input order inside every cell, so the sorted layout (catalogue, cell,
+//                 input index) and hence every summation order is reproducible: cells of up to
+//                 64 points by a one-wave rank count, up to kCellSortMax by a bitonic sort in
+//                 LDS, larger ones by a rank count of the whole workgroup.
 //   k_gather    : writes the cell-sorted records (Qx, Qy, Qz, float w), FP64 weights and the
 //                 permutation back to input order, then one zero-weight sentinel record.
 #include "tpcf_internal.h"
@@ -158,10 +159,10 @@ __global__ void k_scatter(const uint32_t* __restrict__ cell, const uint32_t* __r
   slot_idx[cell_start[c] + k] = i;
 }
 
-// One wavefront per cell at a time (cells strided over the grid, which may be far smaller than
-// the cell count of a sparsely filled grid): rank every entry by its input index (cells of up to
-// kCellSortMax points; larger cells keep the scatter order).
+// Cells strided over the grid (which may be far smaller than the cell count of a sparsely filled
+// grid). Small cells: one wavefront per cell, each lane ranks its entry by input index.
 constexpr uint32_t kCellSortGrid = 65536;
+constexpr uint32_t kCellSortSmall = 64;
 
 __global__ __launch_bounds__(64) void k_cellsort(const uint32_t* __restrict__ cell_start,
                                                  const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
@@ -169,16 +170,58 @@ __global__ __launch_bounds__(64) void k_cellsort(const uint32_t* __restrict__ ce
   for (uint32_t c = blockIdx.x; c < ncell; c += gridDim.x) {
     const uint32_t beg = cell_start[c], end = cell_start[c + 1];
     const uint32_t n = end - beg;
-    if (n <= 1 || n > (uint32_t)kCellSortMax) {
-      for (uint32_t k = threadIdx.x; k < n; k += 64) out[beg + k] = in[beg + k];
-      continue;
-    }
-    for (uint32_t k = threadIdx.x; k < n; k += 64) {
-      const uint32_t v = in[beg + k];
+    if (n > kCellSortSmall) continue;  // k_cellsort_large
+    if (threadIdx.x < n) {
+      const uint32_t v = in[beg + threadIdx.x];
       uint32_t rank = 0;
       for (uint32_t m = 0; m < n; ++m) rank += in[beg + m] < v ? 1u : 0u;
       out[beg + rank] = v;
     }
+  }
+}
+
+// Larger cells, one workgroup of 256 per cell: a bitonic sort of the cell's input indices in LDS
+// (padded with 0xFFFFFFFF to a power of two) up to kCellSortMax entries, beyond that a rank count
+// over the cell.
+__global__ __launch_bounds__(256) void k_cellsort_large(const uint32_t* __restrict__ cell_start,
+                                                        const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
+                                                        uint32_t ncell) {
+  __shared__ uint32_t buf[kCellSortMax];
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t c = blockIdx.x; c < ncell; c += gridDim.x) {
+    const uint32_t beg = cell_start[c], end = cell_start[c + 1];
+    const uint32_t n = end - beg;
+    if (n <= kCellSortSmall) continue;
+    if (n > (uint32_t)kCellSortMax) {
+      for (uint32_t k = tid; k < n; k += 256) {
+        const uint32_t v = in[beg + k];
+        uint32_t rank = 0;
+        for (uint32_t m = 0; m < n; ++m) rank += in[beg + m] < v ? 1u : 0u;
+        out[beg + rank] = v;
+      }
+      continue;
+    }
+    uint32_t P = 1;
+    while (P < n) P <<= 1;
+    for (uint32_t k = tid; k < P; k += 256) buf[k] = k < n ? in[beg + k] : 0xFFFFFFFFu;
+    __syncthreads();
+    for (uint32_t size = 2; size <= P; size <<= 1) {
+      for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+        for (uint32_t t = tid; t < (P >> 1); t += 256) {
+          const uint32_t i = 2 * t - (t & (stride - 1));  // lower index of the pair
+          const uint32_t j = i + stride;
+          const uint32_t a = buf[i], b = buf[j];
+          const bool up = (i & size) == 0;
+          if ((a > b) == up) {
+            buf[i] = b;
+            buf[j] = a;
+          }
+        }
+        __syncthreads();
+      }
+    }
+    for (uint32_t k = tid; k < n; k += 256) out[beg + k] = buf[k];
+    __syncthreads();
   }
 }
 
@@ -312,8 +355,9 @@ hipError_t build_grid(const double* x, const double* y, const double* z, const d
                      ncell, n);
   if (n) {
     hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, s, cell, cell_start, hist, idx_a, n);
-    hipLaunchKernelGGL(k_cellsort, dim3(ncell < kCellSortGrid ? ncell : kCellSortGrid), dim3(64), 0, s,
-                       cell_start, idx_a, idx_b, ncell);
+    const uint32_t grid = ncell < kCellSortGrid ? ncell : kCellSortGrid;
+    hipLaunchKernelGGL(k_cellsort, dim3(grid), dim3(64), 0, s, cell_start, idx_a, idx_b, ncell);
+    hipLaunchKernelGGL(k_cellsort_large, dim3(grid), dim3(256), 0, s, cell_start, idx_a, idx_b, ncell);
   }
   hipLaunchKernelGGL(k_gather, dim3(blocks_for(n + 1, 256)), dim3(256), 0, s, idx_b, qtmp, w, rec, w64, perm, n);
   return hipGetLastError();

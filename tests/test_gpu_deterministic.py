@@ -98,3 +98,25 @@ def test_range_and_degenerate_bit_identical(tpcf):
     assert rel_err_per_l(zs[0], ref).max() <= TOL["mixed"]
     dref = oracle.degenerate(cat.x, cat.y, cat.z, w, cat.box, True, 10, 4.0, 50.0, 6)
     assert np.abs(ds[0] - dref).max() <= 1e-10 * np.abs(dref).max()
+
+
+@pytest.mark.parametrize("ppc", [400.0, 40000.0])
+def test_large_cells_sorted(tpcf, ppc):
+    """Cells far above the usual occupancy (about 100 points with 400 per cell, several thousand
+    with 40000: one cell across y and z, split four ways along x) go through the in-LDS bitonic
+    sort or the workgroup rank count; their in-cell order is the input order, so deterministic runs
+    still agree bit for bit, and counts and zeta match the oracle."""
+    cat = catalogs.uniform(20000, 100.0, 5)
+    w = catalogs.gaussian_weights(cat.n, 6)
+    zs = []
+    for waves in (12, 4):
+        ctx = det_ctx(tpcf, "fp64", 6, 2.0, 20.0, 3, waves)
+        ctx.set_tuning(ppc, waves)
+        ctx.set_debug(True)
+        ctx.set_catalog(cat.x, cat.y, cat.z, w, box=cat.box, periodic=True)
+        zs.append(ctx.compute_zeta())
+    say("cells per axis", ctx.stats()["cells_per_axis"])
+    assert np.array_equal(zs[0], zs[1])
+    ref = oracle.zeta(cat.x, cat.y, cat.z, w, cat.box, True, 6, 2.0, 20.0, 3, want_counts=True)
+    np.testing.assert_array_equal(ctx.pair_counts(), ref.counts)
+    assert rel_err_per_l(zs[0], ref.zeta).max() <= TOL["fp64"]
