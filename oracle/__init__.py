@@ -16,11 +16,16 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "tpcf_oracle.c")
 _LIB = os.path.join(_HERE, "libtpcf_oracle.so")
+# A prebuilt copy of this oracle (for example a sanitizer build made by the tests) replaces the
+# default library when TPCF_ORACLE_LIB names it; it is then loaded as it is, never rebuilt.
+_LIB_OVERRIDE = os.environ.get("TPCF_ORACLE_LIB", "")
 _lib = None
 
 
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc (-O2, no fast-math, OpenMP). Returns the library path."""
+    if _LIB_OVERRIDE:
+        return _LIB_OVERRIDE
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
@@ -32,8 +37,7 @@ def build(force: bool = False) -> str:
 def _load():
     global _lib
     if _lib is None:
-        build()
-        lib = ctypes.CDLL(_LIB)
+        lib = ctypes.CDLL(build())
         p = ctypes.c_void_p
         i64 = ctypes.c_int64
         d = ctypes.c_double

@@ -19,7 +19,9 @@ import numpy as np
 __all__ = ["Context", "zeta", "TpcfError", "library_path", "exported_symbols", "PREC_FP64", "PREC_MIXED"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "libtpcf.so")
+# TPCF_LIBRARY_PATH may name another build of the same library (for example one with host-side
+# sanitizers); by default the in-tree libtpcf.so is loaded.
+_LIB_PATH = os.environ.get("TPCF_LIBRARY_PATH") or os.path.join(_HERE, "libtpcf.so")
 
 TPCF_OK = 0
 ERRORS = {1: "INVALID_ARG", 2: "STATE", 3: "OUT_OF_MEMORY", 4: "DEVICE", 5: "UNSUPPORTED"}

@@ -40,6 +40,8 @@ static int validate(void)
     if ((e = expect(tpcf_set_bins(c, 4, 1.0, 2.0, 3), TPCF_OK, 9, c))) return e;
     if ((e = expect(tpcf_compute_zeta(c, zeta, TPCF_MEM_HOST), TPCF_E_STATE, 10, c))) return e;
     if ((e = expect(tpcf_set_phase_aligned(c, 3), TPCF_E_INVALID_ARG, 11, c))) return e;
+    if ((e = expect(tpcf_set_deterministic(c, 2), TPCF_E_INVALID_ARG, 12, c))) return e;
+    if ((e = expect(tpcf_set_deterministic(c, 1), TPCF_OK, 13, c))) return e;
     tpcf_destroy(c);
     tpcf_destroy(NULL);
     printf("validate: ok (%s)\n", tpcf_version());
