@@ -314,6 +314,30 @@ int tpcf_compute_batch(tpcf_ctx* ctx, int ncat, const int64_t* offsets, const do
                        const double* box_side, const int* periodic, double* zeta, int memspace);
 
 /*
+ * tpcf_compute_batch for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, hosts that forbid hipMalloc): same arguments, meaning, layout,
+ * ownership and results, but the call allocates nothing. Every device buffer it needs (staged
+ * positions, cell grid, per-wave pair lists and tiles, zeta and pair-sum partials, deterministic
+ * tiles) is a slice of one static device array of TPCF_NOALLOC_SCRATCH_BYTES bytes that the library
+ * holds on each GPU it runs on, from its first kernel launch there until the process ends; the
+ * caller's allocator and TPCF_MAX_DEVICE_BYTES do not apply. The sweep runs as many waves as that
+ * array holds beside the batch's other buffers (with 256 scratch blocks per wave unless
+ * tpcf_set_tuning sets them), so large batches run with fewer waves than tpcf_compute_batch. No HIP
+ * graph is captured. The call returns after the context's stream has drained. The context's own
+ * buffers, catalogue and grid are left as they were; afterwards tpcf_get_stats describes this call,
+ * while tpcf_pair_sums and the debug calls fail with TPCF_E_STATE until the next compute call.
+ * Every call on one GPU shares that GPU's array and overwrites it: calls that overlap in time on
+ * one GPU (several host threads, or contexts on different streams) race and must be serialised
+ * by the caller.
+ * Errors: as tpcf_compute_batch; TPCF_E_OUT_OF_MEMORY when the batch does not fit in the array
+ * (the message gives the bytes needed).
+ */
+#define TPCF_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+int tpcf_compute_batch_noalloc(tpcf_ctx* ctx, int ncat, const int64_t* offsets, const double* x,
+                               const double* y, const double* z, const double* w,
+                               const double* box_side, const int* periodic, double* zeta, int memspace);
+
+/*
  * Exact unit-weight pair counts of the last compute call: counts[i][b] (host, int64,
  * n x nbins, input order) is the number of secondaries of primary i in bin b (0 for points that
  * were not primaries). Enable with tpcf_set_debug(ctx, 1) before the compute call.

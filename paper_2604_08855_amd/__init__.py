@@ -36,7 +36,7 @@ EXPORTS = [
     "tpcf_get_stats", "tpcf_last_error", "tpcf_autotune", "tpcf_pair_sums", "tpcf_edge_correct",
     "tpcf_set_sphere_catalog", "tpcf_set_pivot_cell", "tpcf_edge_correct_sphere", "tpcf_compute_sphere_batch",
     "tpcf_set_phase_aligned", "tpcf_set_deterministic", "tpcf_degenerate", "tpcf_set_allocator", "tpcf_set_catalog_f32",
-    "tpcf_set_sphere_catalog_f32",
+    "tpcf_set_sphere_catalog_f32", "tpcf_compute_batch_noalloc",
 ]
 
 
@@ -106,6 +106,7 @@ def _load() -> ctypes.CDLL:
         "tpcf_compute_zeta": ([vp, vp, i], i),
         "tpcf_compute_zeta_range": ([vp, i64, i64, vp, i], i),
         "tpcf_compute_batch": ([vp, i, vp, vp, vp, vp, vp, vp, vp, vp, i], i),
+        "tpcf_compute_batch_noalloc": ([vp, i, vp, vp, vp, vp, vp, vp, vp, vp, i], i),
         "tpcf_debug_pair_counts": ([vp, vp], i),
         "tpcf_debug_alm": ([vp, vp], i),
         "tpcf_set_debug": ([vp, i], i),
@@ -358,17 +359,34 @@ class Context:
         return out
 
     def compute_batch(self, offsets, x, y, z, w, box, periodic, device_output: bool = False):
+        return self._batch(_lib.tpcf_compute_batch, offsets, x, y, z, w, box, periodic, device_output)
+
+    def compute_batch_noalloc(self, offsets, x, y, z, w, box, periodic, out=None):
+        """compute_batch through tpcf_compute_batch_noalloc: the library allocates no device memory
+        (its buffers are slices of a fixed static array per GPU). With torch CUDA inputs pass `out`,
+        a preallocated float64 CUDA tensor [ncat, (lmax+1), nbins, nbins], to keep the call free of
+        allocations on the Python side as well."""
+        return self._batch(_lib.tpcf_compute_batch_noalloc, offsets, x, y, z, w, box, periodic, False, out)
+
+    def _batch(self, fn, offsets, x, y, z, w, box, periodic, device_output, out=None):
         offsets = np.ascontiguousarray(offsets, dtype=np.int64)
         ncat = len(offsets) - 1
         box = np.ascontiguousarray(np.broadcast_to(np.asarray(box, dtype=np.float64), (ncat,)))
         per = np.ascontiguousarray(np.broadcast_to(np.asarray(periodic, dtype=np.int32), (ncat,)))
         ptrs, mem, keep = self._arrays(x, y, z, w)
-        out, p, omem = self._out(device_output or mem == MEM_DEVICE,
-                                 (ncat, self.lmax + 1, self.nbins, self.nbins))
+        shape = (ncat, self.lmax + 1, self.nbins, self.nbins)
+        if out is not None:
+            if not (_is_torch(out) and out.is_cuda and mem == MEM_DEVICE):
+                raise ValueError("out must be a CUDA tensor, with CUDA inputs")
+            import torch
+            if tuple(out.shape) != shape or out.dtype != torch.float64 or not out.is_contiguous():
+                raise ValueError(f"out must be a contiguous float64 tensor of shape {shape}")
+            p, omem = ctypes.c_void_p(out.data_ptr()), MEM_DEVICE
+        else:
+            out, p, omem = self._out(device_output or mem == MEM_DEVICE, shape)
         if omem != mem:
             raise ValueError("batch inputs and output must be in the same memory space")
-        self._check(_lib.tpcf_compute_batch(self._h, ncat, _ptr_np(offsets), *ptrs, _ptr_np(box),
-                                            _ptr_np(per), p, mem))
+        self._check(fn(self._h, ncat, _ptr_np(offsets), *ptrs, _ptr_np(box), _ptr_np(per), p, mem))
         self.n, self.ncat, self.sphere = int(offsets[-1]), ncat, False
         return out
 

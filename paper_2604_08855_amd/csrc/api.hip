@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -54,12 +55,22 @@ using namespace tpcf;
 namespace {
 
 constexpr int64_t kMaxPoints = (int64_t)1 << 31;
+constexpr uint32_t kDetChunk = 64;   // deterministic form: tiles per first-level reduction chunk
+constexpr int kStaticScratchBlocks = 256;  // default scratch blocks per wave from the static scratch
 
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
   tpcf_free_fn free_fn = nullptr;  // the caller's free function if the caller's allocator made it
   void* user = nullptr;
+  bool fixed = false;  // a slice of the static scratch: never freed
+};
+
+// Bump allocation from the static scratch during tpcf_compute_batch_noalloc.
+struct Arena {
+  bool on = false;
+  char* base = nullptr;
+  size_t cap = 0, used = 0;
 };
 
 // Per-catalogue host description.
@@ -143,6 +154,8 @@ struct tpcf_ctx {
   std::string gkey;
 
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+
+  Arena arena;  // on only inside tpcf_compute_batch_noalloc
 };
 
 namespace {
@@ -189,7 +202,7 @@ size_t total_bytes(tpcf_ctx* c) {
 
 // Frees a buffer with whatever allocated it (the caller's free function or hipFree).
 void release(DevBuf& b) {
-  if (b.p) {
+  if (b.p && !b.fixed) {
     if (b.free_fn) b.free_fn(b.p, b.user);
     else (void)hipFree(b.p);
   }
@@ -197,11 +210,35 @@ void release(DevBuf& b) {
   b.bytes = 0;
   b.free_fn = nullptr;
   b.user = nullptr;
+  b.fixed = false;
+}
+
+constexpr size_t kArenaAlign = 256;
+
+size_t arena_left(const tpcf_ctx* c) {
+  const size_t at = (c->arena.used + kArenaAlign - 1) & ~(kArenaAlign - 1);
+  return at >= c->arena.cap ? 0 : c->arena.cap - at;
 }
 
 int ensure(tpcf_ctx* c, DevBuf& b, size_t bytes, const char* what) {
   if (bytes == 0) bytes = 16;
   if (b.bytes >= bytes) return TPCF_OK;
+  if (c->arena.on) {
+    // a new slice; a smaller earlier slice of this buffer is simply left behind
+    if (bytes > arena_left(c))
+      return fail(c, TPCF_E_OUT_OF_MEMORY,
+                  std::string("the static scratch of tpcf_compute_batch_noalloc (") + std::to_string(c->arena.cap) +
+                      " bytes) cannot hold " + what + " (" + std::to_string(bytes) + " bytes with " +
+                      std::to_string(c->arena.cap - arena_left(c)) + " in use)");
+    const size_t at = c->arena.cap - arena_left(c);
+    b.p = c->arena.base + at;
+    b.bytes = bytes;
+    b.free_fn = nullptr;
+    b.user = nullptr;
+    b.fixed = true;
+    c->arena.used = at + bytes;
+    return TPCF_OK;
+  }
   const size_t cap = device_cap();
   if (total_bytes(c) - b.bytes + bytes > cap)
     return fail(c, TPCF_E_OUT_OF_MEMORY, std::string("device byte cap (TPCF_MAX_DEVICE_BYTES) exceeded by ") + what);
@@ -714,13 +751,36 @@ int waves_per_cu_for(const tpcf_ctx* c) {
   return c->precision == TPCF_PREC_FP64 ? 8 : 12;
 }
 
+// Device bytes that prepare_sweep and setup_det request after the per-wave scratch and tiles
+// (upper bounds, each rounded up to the arena alignment), for a sweep over ntask tasks.
+size_t later_sweep_bytes(const tpcf_ctx* c, uint32_t ntask) {
+  const bool f64 = c->precision == TPCF_PREC_FP64;
+  const bool sph = is_sphere(c);
+  const size_t nb = (size_t)c->nbins, L = (size_t)c->lmax, NC = (size_t)ncomp(c->lmax, sph);
+  const size_t ncat = c->cd.size(), n = (size_t)c->ntot;
+  auto up = [](size_t b) { return (std::max<size_t>(b, 16) + kArenaAlign - 1) & ~(kArenaAlign - 1); };
+  size_t t = up(ncat * (L + 1) * nb * nb * 8) + up(kQueueSegments * 4) + up(16) + 2 * up(ncat * nb * 8);
+  const size_t nconv = (L + 1) * (L + 1) * kConvTerms;
+  t += up(nconv * 2) + up(nconv * 8) + up(nconv * 4) + up((nb + 1) * 4);
+  if (c->debug) t += up(n * nb * 4) + up(n * nb * NC * (f64 ? 8 : 4));
+  if (c->deterministic) {
+    const size_t TP = f64 ? kTileF64 : kTileF32;
+    const size_t tiles = ntask / TP + ncat + 1, chunks = tiles / kDetChunk + ncat + 1;
+    const size_t stride = (L + 1) * nb * nb + nb;
+    t += up(tiles * 8) + up(tiles * stride * 8) + up(chunks * 8) + up((ncat + 1) * 4) + up(chunks * stride * 8);
+  }
+  return t;
+}
+
 // Host part of the sweep: buffers, normalisation constants and the kernel arguments.
 int prepare_sweep(tpcf_ctx* c, const uint32_t* tasks_d, uint32_t ntask, SweepArgs& a, int& waves) {
   const bool f64 = c->precision == TPCF_PREC_FP64;
   const bool sph = is_sphere(c);
   const int nb = c->nbins, L = c->lmax, NC = ncomp(L, sph);
   const int ncat = (int)c->cd.size();
-  const int S = scratch_blocks_for(c);
+  int S = scratch_blocks_for(c);
+  // From the static scratch, shorter pair lists by default (more waves fit in it).
+  if (c->arena.on && c->scratch_blocks <= 0) S = std::min(S, std::max(kMinRegionBlocks * nb, kStaticScratchBlocks));
   int rc;
   const size_t lds = sweep_lds_bytes(nb, f64);
   if (lds > 160 * 1024) return fail(c, TPCF_E_UNSUPPORTED, "LDS layout too large");
@@ -730,6 +790,19 @@ int prepare_sweep(tpcf_ctx* c, const uint32_t* tasks_d, uint32_t ntask, SweepArg
   if ((uint32_t)waves > ntask) waves = (int)std::max<uint32_t>(1, ntask);
   if (S < kMinRegionBlocks * nb)
     return fail(c, TPCF_E_INVALID_ARG, "scratch_blocks must be at least 5 x nbins");
+  if (c->arena.on) {
+    // As many waves as the static scratch holds beside the buffers still to come.
+    const size_t per_wave = (size_t)(S + kScratchTail) * kBlock * 4 + sweep_tile_bytes_per_wave(L, nb, f64, sph);
+    const size_t rest = later_sweep_bytes(c, ntask) + 2 * kArenaAlign;
+    const size_t left = arena_left(c);
+    if (left < rest + per_wave)
+      return fail(c, TPCF_E_OUT_OF_MEMORY,
+                  "the static scratch of tpcf_compute_batch_noalloc (" + std::to_string(c->arena.cap) +
+                      " bytes) cannot hold one sweep wave beside this batch's grid (" +
+                      std::to_string(c->arena.cap - left) + " bytes in use, " + std::to_string(rest + per_wave) +
+                      " more needed)");
+    waves = (int)std::min<size_t>((size_t)waves, (left - rest) / per_wave);
+  }
   if ((rc = ensure(c, c->scratch, (size_t)waves * (S + kScratchTail) * kBlock * 4, "scratch")) ||
       (rc = ensure(c, c->tile, (size_t)waves * sweep_tile_bytes_per_wave(L, nb, f64, sph), "tiles")) ||
       (rc = ensure(c, c->zeta_d, (size_t)ncat * (L + 1) * nb * nb * 8, "zeta")) ||
@@ -794,7 +867,6 @@ int prepare_sweep(tpcf_ctx* c, const uint32_t* tasks_d, uint32_t ntask, SweepArg
 // Deterministic form: tiles of the contraction size over each catalogue's tasks (starts[k] = first
 // task of catalogue k, ncat + 1 entries), one result slot per tile, and the tables of the
 // fixed-order reduction (chunks of kDetChunk consecutive tiles, then the chunks of a catalogue).
-constexpr uint32_t kDetChunk = 64;
 int setup_det(tpcf_ctx* c, const std::vector<uint32_t>& starts, SweepArgs& a) {
   const int ncat = (int)starts.size() - 1;
   const uint32_t TP = c->precision == TPCF_PREC_FP64 ? kTileF64 : kTileF32;
@@ -1545,14 +1617,18 @@ int tpcf_compute_zeta_range(tpcf_ctx* c, int64_t p_begin, int64_t p_end, double*
   return rc;
 }
 
-int tpcf_compute_batch(tpcf_ctx* c, int ncat, const int64_t* offsets, const double* x, const double* y,
-                       const double* z, const double* w, const double* box_side, const int* periodic,
-                       double* zeta, int memspace) {
-  if (!c) return TPCF_E_INVALID_ARG;
+}  // extern "C"
+
+namespace {
+
+// Validation shared by the batch entry points: the per-catalogue host description.
+int batch_cats(tpcf_ctx* c, int ncat, const int64_t* offsets, const double* x, const double* y,
+               const double* z, const double* box_side, const int* periodic, const double* zeta,
+               std::vector<HostCat>& cats) {
   if (ncat < 1 || !offsets || !box_side || !periodic) return fail(c, TPCF_E_INVALID_ARG, "invalid batch description");
   if (!c->bins_set) return fail(c, TPCF_E_STATE, "set_bins has not been called");
   if (offsets[0] != 0) return fail(c, TPCF_E_INVALID_ARG, "offsets[0] must be 0");
-  std::vector<HostCat> cats(ncat);
+  cats.assign(ncat, HostCat{});
   for (int k = 0; k < ncat; ++k) {
     if (offsets[k + 1] < offsets[k]) return fail(c, TPCF_E_INVALID_ARG, "offsets must be non-decreasing");
     if (!is_finite(box_side[k]) || !(box_side[k] > 0.0))
@@ -1569,10 +1645,83 @@ int tpcf_compute_batch(tpcf_ctx* c, int ncat, const int64_t* offsets, const doub
   if (ntot >= kMaxPoints) return fail(c, TPCF_E_INVALID_ARG, "total points must be < 2^31");
   if (ntot > 0 && (!x || !y || !z)) return fail(c, TPCF_E_INVALID_ARG, "NULL position array");
   if (!zeta) return fail(c, TPCF_E_INVALID_ARG, "zeta is NULL");
-  int rc = stage(c, cats, ntot, x, y, z, w, memspace);
+  return TPCF_OK;
+}
+
+// Device memory of tpcf_compute_batch_noalloc: a fixed array in the library's code object, one
+// copy per GPU, held from the first launch of the library's kernels on that GPU until the process
+// ends. Host code never uses the array's name as an address (on the host it stands for a host-side
+// shadow): the device address comes from hipGetSymbolAddress, once per device.
+constexpr size_t kNoallocScratchBytes = TPCF_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+std::mutex g_scratch_mu;
+std::vector<char*> g_scratch_at;  // [device]: device address of that device's copy of scratch
+
+// The device address of scratch on the context's device (current after ensure_device).
+int scratch_address(tpcf_ctx* c, char** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if ((size_t)c->device >= g_scratch_at.size()) g_scratch_at.resize((size_t)c->device + 1, nullptr);
+  if (!g_scratch_at[c->device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(c, e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(c, TPCF_E_DEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_at[c->device] = static_cast<char*>(p);
+  }
+  *out = g_scratch_at[c->device];
+  return TPCF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tpcf_compute_batch(tpcf_ctx* c, int ncat, const int64_t* offsets, const double* x, const double* y,
+                       const double* z, const double* w, const double* box_side, const int* periodic,
+                       double* zeta, int memspace) {
+  if (!c) return TPCF_E_INVALID_ARG;
+  std::vector<HostCat> cats;
+  int rc = batch_cats(c, ncat, offsets, x, y, z, box_side, periodic, zeta, cats);
+  if (rc) return rc;
+  rc = stage(c, cats, offsets[ncat], x, y, z, w, memspace);
   if (rc) return rc;
   rc = compute(c, 0, c->ntot, zeta, memspace, true);
   if (!rc) c->err.clear();
+  return rc;
+}
+
+int tpcf_compute_batch_noalloc(tpcf_ctx* c, int ncat, const int64_t* offsets, const double* x, const double* y,
+                               const double* z, const double* w, const double* box_side, const int* periodic,
+                               double* zeta, int memspace) {
+  if (!c) return TPCF_E_INVALID_ARG;
+  std::vector<HostCat> cats;
+  int rc = batch_cats(c, ncat, offsets, x, y, z, box_side, periodic, zeta, cats);
+  if (rc) return rc;
+  if ((rc = ensure_device(c))) return rc;
+  char* base = nullptr;
+  if ((rc = scratch_address(c, &base))) return rc;
+  // Every device buffer of this call is a slice of scratch; the context's own buffers, catalogue,
+  // grid and caches are put back afterwards, whatever happens.
+  const tpcf_ctx saved = *c;
+  for (DevBuf* b : all_bufs(c)) *b = DevBuf{};
+  c->grid_valid = false;
+  c->conv_lmax = -1;
+  c->regions_key = -1;
+  c->edge_lmax = -1;
+  c->arena.on = true;
+  c->arena.base = base;
+  c->arena.cap = kNoallocScratchBytes;
+  c->arena.used = 0;
+  rc = stage(c, cats, offsets[ncat], x, y, z, w, memspace);
+  if (!rc) rc = compute(c, 0, c->ntot, zeta, memspace, false);  // returns after the stream has drained
+  const tpcf_stats stats = c->stats;
+  const std::string err = rc ? c->err : std::string();
+  *c = saved;
+  c->stats = stats;
+  c->err = err;
+  c->sums_valid = false;  // the two-point sums and debug output of this call lived in scratch
+  c->dbg_valid = false;
   return rc;
 }
 
