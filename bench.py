@@ -102,9 +102,56 @@ def time_path(tpcf, torch, dev, precision, steps, warmup, autotune=True, fixed=N
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1000.0 / steps
     st = ctx.stats()
+    st["bin_pairs"] = ctx.pair_sums()[0][0]
     zc = z.cpu().numpy()
     ctx.close()
     return ms, float(np.mean(sweep_ms)), st, zc, tuning
+
+
+ORACLE_FIXTURE = os.path.join(ROOT, "tests", "golden", "lognormal1e6_oracle.txt")
+TOL = {"mixed": 1e-5, "fp64": 1e-10}
+
+
+def rel_errors(z, ref):
+    """Error per (l, r1, r2) relative to max |ref_l| over the bin pairs of l: the per-l maxima and
+    the worst (l, r1, r2)."""
+    L1 = ref.shape[0]
+    scale = np.abs(ref).reshape(L1, -1).max(axis=1)
+    scale = np.where(scale > 0, scale, 1.0)
+    e = np.abs(z - ref) / scale[:, None, None]
+    l, b1, b2 = np.unravel_index(int(np.argmax(e)), e.shape)
+    return ([float(v) for v in e.reshape(L1, -1).max(axis=1)],
+            {"l": int(l), "r1_bin": int(b1), "r2_bin": int(b2), "rel_err": float(e[l, b1, b2])})
+
+
+def oracle_check(cat, w, results):
+    """Compares full-catalogue results with the stored FP64 oracle zeta of the same catalogue
+    (tests/golden/lognormal1e6_oracle.txt, written by the oracle alone). results: precision ->
+    (zeta, stats with n_pairs and bin_pairs). None when the fixture is absent."""
+    if not os.path.exists(ORACLE_FIXTURE):
+        return None
+    import importlib.util
+
+    spec = importlib.util.spec_from_file_location(
+        "oracle_fixture", os.path.join(ROOT, "tests", "golden", "make_lognormal1e6_oracle.py"))
+    fx = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(fx)
+    gold = fx.read(ORACLE_FIXTURE)
+    out = {"fixture": os.path.relpath(ORACLE_FIXTURE, ROOT),
+           "catalogue_sha256_match": fx.catalogue_hash(cat, w) == gold["sha256"],
+           "tolerance": TOL, "per_l": {}, "worst": {}}
+    if not out["catalogue_sha256_match"]:
+        return out
+    ok = True
+    for prec, (z, st) in results.items():
+        per_l, worst = rel_errors(z, gold["zeta"])
+        out["per_l"][prec] = per_l
+        out["worst"][prec] = worst
+        out.setdefault("pairs_match", {})[prec] = int(st["n_pairs"]) == gold["npairs"]
+        out.setdefault("bin_pairs_match", {})[prec] = bool(np.array_equal(st["bin_pairs"], gold["bin_pairs"]))
+        ok = ok and worst["rel_err"] <= TOL[prec] and out["pairs_match"][prec] and out["bin_pairs_match"][prec]
+    out["within_tolerance"] = ok
+    return out
 
 
 def kernel_source_hash():
@@ -387,7 +434,7 @@ def run_dmr(args):
 
     dev = [torch.from_numpy(a).cuda() for a in (cat.x, cat.y, cat.z, cat.w)]
     torch.cuda.synchronize()
-    res = {}
+    res, zfull = {}, {}
     ranges = [(0, 24), (4_000_000, 4_000_024)]  # 24 data primaries, 24 random primaries
     for prec, steps in (("mixed", args.steps), ("fp64", 1)):
         ctx = make_ctx(tpcf, torch.cuda.current_stream())
@@ -408,6 +455,7 @@ def run_dmr(args):
             log(f"[bench] dmr {prec} step {i + 1}/{steps}: {times[-1]:.2f}s")
         st = ctx.stats()
         npairs, _ = ctx.pair_sums()
+        zfull[prec] = zN.cpu().numpy()
         extra = {"pair_sums_total_equals_pair_count": int(npairs.sum()) == st["n_pairs"]}
         if prec == "mixed":
             # randoms alone (weight +N_d/N_r) and the edge-corrected multipoles N / R
@@ -441,6 +489,8 @@ def run_dmr(args):
                      "tuning": tuning, "max_rel_err_vs_oracle_on_sampled_ranges": max(errs), **extra}
         log(f"[bench] dmr {prec}: {res[prec]}")
     m = res["mixed"]
+    err_vs_fp64, worst_vs_fp64 = rel_errors(zfull["mixed"], zfull["fp64"])
+    log(f"[bench] dmr mixed vs fp64 worst {worst_vs_fp64}")
     flops = m["pairs_per_step"] * F_PAIR + cat.n * F_PRIM
     achieved = flops / (m["sweep_ms"] / 1000.0) / 1e12
     out = {
@@ -456,6 +506,8 @@ def run_dmr(args):
         "mixed_over_fp64_speedup": m["value"] / res["fp64"]["value"],
         "max_rel_err_vs_oracle_on_sampled_ranges": {k: v["max_rel_err_vs_oracle_on_sampled_ranges"]
                                                     for k, v in res.items()},
+        "max_rel_err_mixed_vs_fp64_per_l": err_vs_fp64,
+        "worst_mixed_vs_fp64": worst_vs_fp64,
         "roofline": {"bound": "alu", "kernel": "sweep_kernel<10,false,false>", "achieved": achieved,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
                      "peak_without_packed_fp32": PEAK_FP32_UNPACKED_TFLOPS,
@@ -800,6 +852,8 @@ def run_sphere(args):
         r = oracle.zeta_sphere(m.x, m.y, m.z, m.w, nb, tmin, tmax, mmax, 0, k, threads=threads)
         el = time.perf_counter() - t1
         out["cpu_baseline"] = {"value": r.npairs / el, "unit": "pairs/s", "cores": threads, "kind": "oracle",
+                               "oracle_form": "all-pairs: every pixel tested for every primary (no cell "
+                                              "grid), FP64",
                                "sample": f"primaries [0, {k}) of the same map against all pixels (brute force "
                                          f"over all secondaries), FP64, {r.npairs} pairs in {el:.1f}s"}
     print(json.dumps(out), flush=True)
@@ -878,10 +932,14 @@ def main():
     ms64, sweep64, st64, z64, t64 = time_path(tpcf, torch, dev, "fp64", f64_steps, 1, tune, fixed)
     value64 = st64["n_pairs"] / (ms64 / 1000.0)
     log(f"[bench] fp64: {ms64:.1f} ms/step, sweep {sweep64:.1f} ms, {value64:.3e} pairs/s")
-    err = []
-    for l in range(LMAX + 1):
-        s = np.abs(z64[l]).max()
-        err.append(float(np.abs(zmix[l] - z64[l]).max() / s) if s > 0 else 0.0)
+    err, worst_vs_fp64 = rel_errors(zmix, z64)
+    check = oracle_check(cat, w, {"mixed": (zmix, st), "fp64": (z64, st64)})
+    if check is None:
+        log("[bench] no stored oracle zeta for this catalogue: oracle comparison skipped")
+    elif not check.get("within_tolerance", False):
+        log(f"[bench] WARNING: outside the oracle bars: {check}")
+    else:
+        log(f"[bench] vs oracle: mixed worst {check['worst']['mixed']}, fp64 worst {check['worst']['fp64']}")
 
     flops = pairs * F_PAIR + st["n_primaries"] * F_PRIM
     achieved = flops / (sweep_ms / 1000.0) / 1e12
@@ -912,7 +970,11 @@ def main():
         "fp64": {"value": value64, "unit": "pairs/s", "ms_per_step": ms64, "sweep_ms": sweep64,
                  "tuning": t64},
         "mixed_over_fp64_speedup": value / value64,
-        "max_rel_err_mixed_vs_fp64_per_l": max(err),
+        "max_rel_err_vs_oracle_per_l": check["per_l"].get("mixed") if check else None,
+        "worst_vs_oracle": check["worst"].get("mixed") if check else None,
+        "oracle_check": check,
+        "max_rel_err_mixed_vs_fp64_per_l": err,
+        "worst_mixed_vs_fp64": worst_vs_fp64,
         "grid_ms": st["ms_grid"],
         "roofline": {
             "bound": "alu",
@@ -936,8 +998,10 @@ def main():
             "unit": "pairs/s",
             "cores": threads,
             "kind": "oracle",
+            "oracle_form": "all-pairs: every secondary tested for every primary (no cell grid), "
+                           "trigonometric Y_lm, FP64",
             "sample": f"{nprim} random primaries (seed 12345) of the same 1e6-point catalogue against "
-                      f"all secondaries, FP64, {cp} pairs in {el:.1f}s",
+                      f"all 1e6 secondaries (all-pairs oracle), FP64, {cp} pairs in {el:.1f}s",
         }
         log(f"[bench] cpu oracle: {cp / el:.3e} pairs/s on {threads} threads")
         c1, el1 = cpu_baseline_one_thread(cat, w)
