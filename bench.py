@@ -319,7 +319,8 @@ def run_sphere_batch(args):
 def run_batch(args):
     """Batch form: independent log-normal mocks (seeds 0..M-1, sizes log-uniform in [2e5, 2e6]
     from seed 1000), L = 1000 periodic, unit weights, 20 bins [10, 200), l_max = 10, mixed, one
-    persistent launch per call, captured as a HIP graph on a non-default stream and replayed."""
+    persistent launch per call, captured as a HIP graph on a non-default stream and replayed. The
+    autotuner runs on one mock, the pair-weighted median one."""
     import multiprocessing as mp
 
     import catalogs
@@ -346,8 +347,11 @@ def run_batch(args):
         ctx.set_precision("mixed")
         tuning = None
         if not args.no_autotune:
-            # tuned on the median-size mock
-            k = int(np.argsort(sizes)[len(sizes) // 2])
+            # tuned on the pair-weighted median mock (pairs grow as n^2, so the larger mocks carry
+            # most of the sweep)
+            order = np.argsort(sizes)
+            cum = np.cumsum(sizes[order].astype(np.float64) ** 2)
+            k = int(order[int(np.searchsorted(cum, 0.5 * cum[-1]))])
             ctx.set_catalog(*[t[off[k]:off[k + 1]] for t in dev], None, box=BOX, periodic=True)
             tuning = ctx.autotune()
             log(f"[bench] batch autotune on mock {k} ({sizes[k]} points): {tuning}")

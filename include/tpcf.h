@@ -81,7 +81,7 @@ typedef struct tpcf_stats {
 typedef struct tpcf_tuning {
     double points_per_cell; /* grid density */
     int waves_per_cu;       /* persistent waves per compute unit */
-    int scratch_blocks;     /* scratch blocks of 64 secondaries per wave in use (not tuned) */
+    int scratch_blocks;     /* scratch blocks of 64 secondaries per wave (pair-list length) */
     int candidates;         /* configurations timed */
     double ms_best;         /* sweep time of the sample with the chosen configuration */
     double ms_default;      /* sweep time of the sample with the configuration in force before */
@@ -187,8 +187,9 @@ int tpcf_set_deterministic(tpcf_ctx* ctx, int enable);
  * spaced runs of consecutive cell-sorted points, so the sample follows the catalogue's density and
  * keeps the full sweep's neighbour sharing; each configuration timed twice after a warm-up, the
  * faster run kept)
- * for grid densities of 3-24 points per cell and 6 or 8 waves per compute
- * unit (8 or 12 with a catalogue on the sphere), then keeps the fastest as if set by
+ * for grid densities of 3-48 points per cell (9 values) and two wave counts per compute unit (12
+ * and 8 on the FP32 paths, 8 and 6 on FP64), then, at the fastest of those, for half and twice the
+ * scratch blocks per wave in use, and keeps the fastest of the 20 configurations as if set by
  * tpcf_set_tuning. sample_fraction in (0, 1]; 0 means
  * 0.05. Results of later compute calls do not depend on the tuning. The call synchronises the
  * context's stream. Stats of the last compute call are kept; its debug output is dropped

@@ -1331,6 +1331,8 @@ int tpcf_autotune(tpcf_ctx* c, double sample_fraction, tpcf_tuning* out) {
   const double ppc0 = c->ppc;
   const int wpc_set = c->waves_per_cu;
   const int wpc0 = waves_per_cu_for(c);
+  const int sb_set = c->scratch_blocks;
+  const int sb0 = scratch_blocks_for(c);
   c->debug = false;
 
   // Up to 16 evenly spaced runs of consecutive cell-sorted points, sample_fraction of all: the
@@ -1353,9 +1355,10 @@ int tpcf_autotune(tpcf_ctx* c, double sample_fraction, tpcf_tuning* out) {
 
   // Times one configuration: grid for it, one untimed sweep of the sample, then the faster
   // of two timed sweeps.
-  auto time_config = [&](double ppc, int wpc, double& ms) -> int {
+  auto time_config = [&](double ppc, int wpc, int sb, double& ms) -> int {
     c->ppc = ppc;
     c->waves_per_cu = wpc;
+    c->scratch_blocks = sb;
     int r;
     if (!grid_current(c)) {
       if ((r = prepare_grid(c)) || (r = record_grid(c))) return r;
@@ -1378,38 +1381,46 @@ int tpcf_autotune(tpcf_ctx* c, double sample_fraction, tpcf_tuning* out) {
     return TPCF_OK;
   };
   double ms_default = 0.0;
-  rc = time_config(ppc0, wpc0, ms_default);
+  rc = time_config(ppc0, wpc0, sb0, ms_default);
   double best_ms = ms_default, best_ppc = ppc0;
-  int best_wpc = wpc0, tried = 1;
-  const double ppcs[] = {3.0, 4.0, 6.0, 8.0, 12.0, 16.0, 24.0};
-  // The FP32 kernels are built for three waves per SIMD (12 per CU), FP64 for two (8 per CU).
+  int best_wpc = wpc0, best_sb = sb0, tried = 1;
+  auto consider = [&](double ppc, int wpc, int sb) {
+    double ms = 0.0;
+    rc = time_config(ppc, wpc, sb, ms);
+    ++tried;
+    if (rc == TPCF_OK && ms < best_ms) {
+      best_ms = ms;
+      best_ppc = ppc;
+      best_wpc = wpc;
+      best_sb = sb;
+    }
+  };
+  // Grid densities and wave counts first (the FP32 kernels are built for three waves per SIMD, 12
+  // per CU, FP64 for two, 8 per CU), then the pair-list length at the best of them.
+  const double ppcs[] = {3.0, 4.0, 6.0, 8.0, 12.0, 16.0, 24.0, 32.0, 48.0};
   const int wpcs[] = {wpc0, c->precision == TPCF_PREC_FP64 ? 6 : 8};
   for (int wi = 0; wi < 2 && rc == TPCF_OK; ++wi)
-    for (int pi = 0; pi < 7 && rc == TPCF_OK; ++pi) {
-      if (ppcs[pi] == ppc0 && wpcs[wi] == wpc0) continue;
-      double ms = 0.0;
-      rc = time_config(ppcs[pi], wpcs[wi], ms);
-      ++tried;
-      if (rc == TPCF_OK && ms < best_ms) {
-        best_ms = ms;
-        best_ppc = ppcs[pi];
-        best_wpc = wpcs[wi];
-      }
-    }
+    for (int pi = 0; pi < 9 && rc == TPCF_OK; ++pi)
+      if (!(ppcs[pi] == ppc0 && wpcs[wi] == wpc0)) consider(ppcs[pi], wpcs[wi], sb0);
+  const int sbs[] = {(sb0 / 2) & ~63, (sb0 * 2) & ~63};  // set_tuning takes multiples of 64
+  for (int si = 0; si < 2 && rc == TPCF_OK; ++si)
+    if (sbs[si] >= kMinRegionBlocks * c->nbins && sbs[si] != sb0) consider(best_ppc, best_wpc, sbs[si]);
   c->debug = saved_debug;
   c->stats = saved_stats;
   c->dbg_valid = false;  // debug output is kept by sorted position, and the grid was rebuilt
   if (rc) {
     c->ppc = ppc0;
     c->waves_per_cu = wpc_set;
+    c->scratch_blocks = sb_set;
     return rc;
   }
   c->ppc = best_ppc;
   c->waves_per_cu = best_wpc;
+  c->scratch_blocks = best_sb;
   if (out) {
     out->points_per_cell = best_ppc;
     out->waves_per_cu = best_wpc;
-    out->scratch_blocks = scratch_blocks_for(c);
+    out->scratch_blocks = best_sb;
     out->candidates = tried;
     out->ms_best = best_ms;
     out->ms_default = ms_default;
