@@ -123,8 +123,8 @@ int tpcf_set_precision(tpcf_ctx* ctx, int precision);
 /*
  * Optional tuning: target mean points per grid cell (default 8; the grid side in y and z follows
  * from it and the catalogue density, and each such cell is split into up to 4 thinner cells along
- * x), persistent waves per compute unit (default 12 for the mixed and
- * sphere sweeps, 8 for FP64; capped by what the compute unit's LDS holds), and scratch blocks
+ * x), persistent waves per compute unit (default 12, or 8 for the FP64 sweep of a 3D catalogue;
+ * capped by what the compute unit's LDS holds), and scratch blocks
  * of 64 secondaries per wave (default 1024 in 3D and 512 on the sphere). A value of 0 keeps the
  * current setting.
  * Errors: TPCF_E_INVALID_ARG for negative values or scratch_blocks not a multiple of 64; a
@@ -187,8 +187,8 @@ int tpcf_set_deterministic(tpcf_ctx* ctx, int enable);
  * spaced runs of consecutive cell-sorted points, so the sample follows the catalogue's density and
  * keeps the full sweep's neighbour sharing; each configuration timed twice after a warm-up, the
  * faster run kept)
- * for grid densities of 3-48 points per cell (9 values) and two wave counts per compute unit (12
- * and 8 on the FP32 paths, 8 and 6 on FP64), then, at the fastest of those, for half and twice the
+ * for grid densities of 3-48 points per cell (9 values) and 12 and 8 waves per compute unit (the
+ * default and the other one), then, at the fastest of those, for half and twice the
  * scratch blocks per wave in use, and keeps the fastest of the 20 configurations as if set by
  * tpcf_set_tuning. sample_fraction in (0, 1]; 0 means
  * 0.05. Results of later compute calls do not depend on the tuning. The call synchronises the

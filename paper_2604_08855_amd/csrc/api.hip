@@ -2,6 +2,8 @@
 // up, stencil rows, spherical-harmonic normalisation, launches, HIP-graph replay of batches and
 // the extern "C" entry points declared in include/tpcf.h.
 #include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -160,8 +162,36 @@ struct tpcf_ctx {
 
 namespace {
 
+// Log messages: TPCF_LOG_LEVEL = 0 (default) silent, 1 errors, 2 also one line per catalogue and
+// compute call (stage times, pairs, device memory held), 3 also every device allocation and every
+// autotuner configuration. They go to stderr, or appended to the file TPCF_LOG_FILE names.
+int log_level() {
+  const char* s = getenv("TPCF_LOG_LEVEL");
+  return (s && *s) ? atoi(s) : 0;
+}
+
+std::mutex g_log_mu;
+
+__attribute__((format(printf, 2, 3))) void logf(int level, const char* fmt, ...) {
+  if (log_level() < level) return;
+  static const char* const names[] = {"", "error", "info", "debug"};
+  std::lock_guard<std::mutex> lock(g_log_mu);
+  const char* path = getenv("TPCF_LOG_FILE");
+  FILE* f = (path && *path) ? fopen(path, "a") : nullptr;
+  FILE* out = f ? f : stderr;
+  fprintf(out, "tpcf[%s] ", names[level < 0 ? 0 : level > 3 ? 3 : level]);
+  va_list ap;
+  va_start(ap, fmt);
+  vfprintf(out, fmt, ap);
+  va_end(ap);
+  fputc('\n', out);
+  if (f) fclose(f);
+  else fflush(out);
+}
+
 int fail(tpcf_ctx* c, int code, const std::string& msg) {
   if (c) c->err = msg;
+  logf(1, "status %d: %s", code, msg.c_str());
   return code;
 }
 
@@ -237,6 +267,7 @@ int ensure(tpcf_ctx* c, DevBuf& b, size_t bytes, const char* what) {
     b.user = nullptr;
     b.fixed = true;
     c->arena.used = at + bytes;
+    logf(3, "static scratch: %s %zu bytes at offset %zu", what, bytes, at);
     return TPCF_OK;
   }
   const size_t cap = device_cap();
@@ -257,6 +288,7 @@ int ensure(tpcf_ctx* c, DevBuf& b, size_t bytes, const char* what) {
     }
   }
   b.bytes = bytes;
+  logf(3, "device buffer: %s %zu bytes (%zu held)", what, bytes, total_bytes(c));
   return TPCF_OK;
 }
 
@@ -653,6 +685,8 @@ int stage(tpcf_ctx* c, const std::vector<HostCat>& cats, int64_t ntot, const voi
   } else {
     HIP_TRY(c, hipStreamSynchronize(c->stream));
   }
+  logf(2, "catalogue: %lld points in %zu catalogue(s)%s, inputs in %s memory", (long long)ntot, cats.size(),
+       (!cats.empty() && cats[0].sphere) ? " on the sphere" : "", memspace == TPCF_MEM_HOST ? "host" : "device");
   c->cats = cats;
   c->ntot = ntot;
   c->have_w = w != nullptr;
@@ -745,10 +779,11 @@ int scratch_blocks_for(const tpcf_ctx* c) {
 }
 
 // Persistent waves per compute unit, unless set by tpcf_set_tuning: 12 (three per SIMD, as the
-// register allocation of the FP32 sweeps allows) for the mixed and sphere kernels, 8 for FP64.
+// register allocation of the FP32 sweeps and of the FP64 sphere sweep allows), 8 for the FP64 3D
+// sweep (two per SIMD).
 int waves_per_cu_for(const tpcf_ctx* c) {
   if (c->waves_per_cu > 0) return c->waves_per_cu;
-  return c->precision == TPCF_PREC_FP64 ? 8 : 12;
+  return (c->precision == TPCF_PREC_FP64 && !is_sphere(c)) ? 8 : 12;
 }
 
 // Device bytes that prepare_sweep and setup_det request after the per-wave scratch and tiles
@@ -958,6 +993,11 @@ int finish_stats(tpcf_ctx* c, bool grid_built, uint32_t ntask) {
   c->dbg_f64 = c->precision == TPCF_PREC_FP64;
   c->dbg_nb = c->nbins;
   c->dbg_nc = ncomp(c->lmax, is_sphere(c));
+  logf(2, "compute: %zu catalogue(s), %u primaries, %lld pairs, %lld candidates, %s%s, grid %.3f ms, sweep %.3f ms, "
+       "%d waves, device memory %zu bytes%s",
+       c->cd.size(), ntask, (long long)st[0], (long long)st[1], c->precision == TPCF_PREC_FP64 ? "fp64" : "mixed",
+       c->deterministic ? " deterministic" : "", c->stats.ms_grid, c->stats.ms_sweep, c->stats.waves,
+       c->arena.on ? c->arena.used : total_bytes(c), c->arena.on ? " of the static scratch" : " held");
   return TPCF_OK;
 }
 
@@ -1382,12 +1422,16 @@ int tpcf_autotune(tpcf_ctx* c, double sample_fraction, tpcf_tuning* out) {
   };
   double ms_default = 0.0;
   rc = time_config(ppc0, wpc0, sb0, ms_default);
+  if (rc == TPCF_OK)
+    logf(3, "autotune: %g points per cell, %d waves per CU, %d scratch blocks: %.3f ms (in force)", ppc0, wpc0, sb0,
+         ms_default);
   double best_ms = ms_default, best_ppc = ppc0;
   int best_wpc = wpc0, best_sb = sb0, tried = 1;
   auto consider = [&](double ppc, int wpc, int sb) {
     double ms = 0.0;
     rc = time_config(ppc, wpc, sb, ms);
     ++tried;
+    if (rc == TPCF_OK) logf(3, "autotune: %g points per cell, %d waves per CU, %d scratch blocks: %.3f ms", ppc, wpc, sb, ms);
     if (rc == TPCF_OK && ms < best_ms) {
       best_ms = ms;
       best_ppc = ppc;
@@ -1395,10 +1439,12 @@ int tpcf_autotune(tpcf_ctx* c, double sample_fraction, tpcf_tuning* out) {
       best_sb = sb;
     }
   };
-  // Grid densities and wave counts first (the FP32 kernels are built for three waves per SIMD, 12
-  // per CU, FP64 for two, 8 per CU), then the pair-list length at the best of them.
+  // Grid densities and wave counts first (12 and 8 per CU), then the pair-list length at the best
+  // of them.
   const double ppcs[] = {3.0, 4.0, 6.0, 8.0, 12.0, 16.0, 24.0, 32.0, 48.0};
-  const int wpcs[] = {wpc0, c->precision == TPCF_PREC_FP64 ? 6 : 8};
+  // More waves than fit at once still help the FP64 3D sweep a little: the later ones start as
+  // the first finish and keep the tail of the queue short.
+  const int wpcs[] = {wpc0, wpc0 == 12 ? 8 : 12};
   for (int wi = 0; wi < 2 && rc == TPCF_OK; ++wi)
     for (int pi = 0; pi < 9 && rc == TPCF_OK; ++pi)
       if (!(ppcs[pi] == ppc0 && wpcs[wi] == wpc0)) consider(ppcs[pi], wpcs[wi], sb0);
@@ -1417,6 +1463,8 @@ int tpcf_autotune(tpcf_ctx* c, double sample_fraction, tpcf_tuning* out) {
   c->ppc = best_ppc;
   c->waves_per_cu = best_wpc;
   c->scratch_blocks = best_sb;
+  logf(2, "autotune: %g points per cell, %d waves per CU, %d scratch blocks: %.3f ms on the sample (%.3f ms before), "
+       "%d configurations", best_ppc, best_wpc, best_sb, best_ms, ms_default, tried);
   if (out) {
     out->points_per_cell = best_ppc;
     out->waves_per_cu = best_wpc;

@@ -159,69 +159,95 @@ __global__ void k_scatter(const uint32_t* __restrict__ cell, const uint32_t* __r
   slot_idx[cell_start[c] + k] = i;
 }
 
-// Cells strided over the grid (which may be far smaller than the cell count of a sparsely filled
-// grid). Small cells: one wavefront per cell, each lane ranks its entry by input index.
+// Cells are visited in chunks strided over the grid: a sparsely filled grid (a map on the sphere
+// occupies a thin shell of its cube) has far more cells than points, so each chunk first reads the
+// sizes of many cells at once and only the cells that need work are then processed one by one.
+// Small cells: one wavefront per chunk of 64 cells; each cell of 2 to 64 points is sorted by the
+// whole wave, each lane ranking its entry by input index (a one-point cell is copied).
 constexpr uint32_t kCellSortGrid = 65536;
 constexpr uint32_t kCellSortSmall = 64;
 
 __global__ __launch_bounds__(64) void k_cellsort(const uint32_t* __restrict__ cell_start,
                                                  const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
                                                  uint32_t ncell) {
-  for (uint32_t c = blockIdx.x; c < ncell; c += gridDim.x) {
-    const uint32_t beg = cell_start[c], end = cell_start[c + 1];
-    const uint32_t n = end - beg;
-    if (n > kCellSortSmall) continue;  // k_cellsort_large
-    if (threadIdx.x < n) {
-      const uint32_t v = in[beg + threadIdx.x];
-      uint32_t rank = 0;
-      for (uint32_t m = 0; m < n; ++m) rank += in[beg + m] < v ? 1u : 0u;
-      out[beg + rank] = v;
+  const uint32_t lane = threadIdx.x;
+  for (uint32_t c0 = blockIdx.x * 64u; c0 < ncell; c0 += gridDim.x * 64u) {
+    const uint32_t c = c0 + lane;
+    uint32_t beg = 0, n = 0;
+    if (c < ncell) {
+      beg = cell_start[c];
+      n = cell_start[c + 1] - beg;
+    }
+    uint64_t todo = __ballot(n > 0 && n <= kCellSortSmall);
+    while (todo) {
+      const int k = __ffsll((unsigned long long)todo) - 1;
+      todo &= todo - 1;
+      const uint32_t b = __builtin_amdgcn_readlane(beg, k);
+      const uint32_t m = __builtin_amdgcn_readlane(n, k);
+      if (lane < m) {
+        const uint32_t v = in[b + lane];
+        uint32_t rank = 0;
+        for (uint32_t q = 0; q < m; ++q) rank += in[b + q] < v ? 1u : 0u;
+        out[b + rank] = v;
+      }
     }
   }
 }
 
-// Larger cells, one workgroup of 256 per cell: a bitonic sort of the cell's input indices in LDS
-// (padded with 0xFFFFFFFF to a power of two) up to kCellSortMax entries, beyond that a rank count
-// over the cell.
+// Larger cells, one workgroup of 256 per chunk of 256 cells: the chunk's cells above 64 points are
+// listed in LDS, then each is sorted in turn by the whole workgroup: a bitonic sort of the cell's
+// input indices in LDS (padded with 0xFFFFFFFF to a power of two) up to kCellSortMax entries,
+// beyond that a rank count over the cell.
 __global__ __launch_bounds__(256) void k_cellsort_large(const uint32_t* __restrict__ cell_start,
                                                         const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
                                                         uint32_t ncell) {
   __shared__ uint32_t buf[kCellSortMax];
+  __shared__ uint32_t list[256];
+  __shared__ uint32_t nlist;
   const uint32_t tid = threadIdx.x;
-  for (uint32_t c = blockIdx.x; c < ncell; c += gridDim.x) {
-    const uint32_t beg = cell_start[c], end = cell_start[c + 1];
-    const uint32_t n = end - beg;
-    if (n <= kCellSortSmall) continue;
-    if (n > (uint32_t)kCellSortMax) {
-      for (uint32_t k = tid; k < n; k += 256) {
-        const uint32_t v = in[beg + k];
-        uint32_t rank = 0;
-        for (uint32_t m = 0; m < n; ++m) rank += in[beg + m] < v ? 1u : 0u;
-        out[beg + rank] = v;
-      }
-      continue;
-    }
-    uint32_t P = 1;
-    while (P < n) P <<= 1;
-    for (uint32_t k = tid; k < P; k += 256) buf[k] = k < n ? in[beg + k] : 0xFFFFFFFFu;
+  for (uint32_t c0 = blockIdx.x * 256u; c0 < ncell; c0 += gridDim.x * 256u) {
+    if (tid == 0) nlist = 0;
     __syncthreads();
-    for (uint32_t size = 2; size <= P; size <<= 1) {
-      for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-        for (uint32_t t = tid; t < (P >> 1); t += 256) {
-          const uint32_t i = 2 * t - (t & (stride - 1));  // lower index of the pair
-          const uint32_t j = i + stride;
-          const uint32_t a = buf[i], b = buf[j];
-          const bool up = (i & size) == 0;
-          if ((a > b) == up) {
-            buf[i] = b;
-            buf[j] = a;
-          }
+    const uint32_t cc = c0 + tid;
+    if (cc < ncell && cell_start[cc + 1] - cell_start[cc] > kCellSortSmall) list[atomicAdd(&nlist, 1u)] = cc;
+    __syncthreads();
+    const uint32_t cnt = nlist;
+    for (uint32_t q = 0; q < cnt; ++q) {
+      const uint32_t c = list[q];
+      const uint32_t beg = cell_start[c], end = cell_start[c + 1];
+      const uint32_t n = end - beg;
+      if (n > (uint32_t)kCellSortMax) {
+        for (uint32_t k = tid; k < n; k += 256) {
+          const uint32_t v = in[beg + k];
+          uint32_t rank = 0;
+          for (uint32_t m = 0; m < n; ++m) rank += in[beg + m] < v ? 1u : 0u;
+          out[beg + rank] = v;
         }
-        __syncthreads();
+        continue;
       }
+      uint32_t P = 1;
+      while (P < n) P <<= 1;
+      for (uint32_t k = tid; k < P; k += 256) buf[k] = k < n ? in[beg + k] : 0xFFFFFFFFu;
+      __syncthreads();
+      for (uint32_t size = 2; size <= P; size <<= 1) {
+        for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+          for (uint32_t t = tid; t < (P >> 1); t += 256) {
+            const uint32_t i = 2 * t - (t & (stride - 1));  // lower index of the pair
+            const uint32_t j = i + stride;
+            const uint32_t a = buf[i], b = buf[j];
+            const bool up = (i & size) == 0;
+            if ((a > b) == up) {
+              buf[i] = b;
+              buf[j] = a;
+            }
+          }
+          __syncthreads();
+        }
+      }
+      for (uint32_t k = tid; k < n; k += 256) out[beg + k] = buf[k];
+      __syncthreads();
     }
-    for (uint32_t k = tid; k < n; k += 256) out[beg + k] = buf[k];
-    __syncthreads();
+    __syncthreads();  // every thread has read nlist and list before the next chunk resets them
   }
 }
 
@@ -355,9 +381,10 @@ hipError_t build_grid(const double* x, const double* y, const double* z, const d
                      ncell, n);
   if (n) {
     hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, s, cell, cell_start, hist, idx_a, n);
-    const uint32_t grid = ncell < kCellSortGrid ? ncell : kCellSortGrid;
-    hipLaunchKernelGGL(k_cellsort, dim3(grid), dim3(64), 0, s, cell_start, idx_a, idx_b, ncell);
-    hipLaunchKernelGGL(k_cellsort_large, dim3(grid), dim3(256), 0, s, cell_start, idx_a, idx_b, ncell);
+    const uint32_t g_small = std::min<uint32_t>(kCellSortGrid, (ncell + 63) / 64);
+    const uint32_t g_large = std::min<uint32_t>(kCellSortGrid, (ncell + 255) / 256);
+    hipLaunchKernelGGL(k_cellsort, dim3(g_small), dim3(64), 0, s, cell_start, idx_a, idx_b, ncell);
+    hipLaunchKernelGGL(k_cellsort_large, dim3(g_large), dim3(256), 0, s, cell_start, idx_a, idx_b, ncell);
   }
   hipLaunchKernelGGL(k_gather, dim3(blocks_for(n + 1, 256)), dim3(256), 0, s, idx_b, qtmp, w, rec, w64, perm, n);
   return hipGetLastError();

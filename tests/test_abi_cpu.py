@@ -210,3 +210,40 @@ def test_one_call_forms_marshal_catalogues():
         tpcf._columns(rng.random((4, 2)))
     with pytest.raises(ValueError):
         tpcf._concat([(b[0],)])
+
+
+_LOG_CHILD = """
+import paper_2604_08855_amd as tpcf
+c = tpcf.Context(0)
+try:
+    c.set_bins(0, 1.0, 2.0, 2)
+except tpcf.TpcfError:
+    pass
+"""
+
+
+def test_log_levels(tmp_path):
+    """TPCF_LOG_LEVEL: 0 (default) prints nothing, 1 reports each failing call with its status and
+    message on stderr; TPCF_LOG_FILE sends the lines to a file instead."""
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+    def run(**env):
+        e = dict(os.environ)
+        e.pop("TPCF_LOG_LEVEL", None)
+        e.pop("TPCF_LOG_FILE", None)
+        e.update(env)
+        return subprocess.run([sys.executable, "-c", _LOG_CHILD], cwd=root, env=e, capture_output=True, text=True,
+                              timeout=120)
+
+    quiet = run()
+    assert quiet.returncode == 0 and "tpcf[" not in quiet.stderr
+    loud = run(TPCF_LOG_LEVEL="1")
+    assert loud.returncode == 0
+    assert "tpcf[error] status 1: nbins" in loud.stderr, loud.stderr
+    path = tmp_path / "tpcf.log"
+    filed = run(TPCF_LOG_LEVEL="3", TPCF_LOG_FILE=str(path))
+    assert "tpcf[" not in filed.stderr
+    assert "tpcf[error] status 1: nbins" in path.read_text()

@@ -285,7 +285,7 @@ def test_autotune_keeps_results(tpcf, prec):
     t = ctx.autotune(0.25)
     say("autotune", t)
     assert t["points_per_cell"] in (3.0, 4.0, 6.0, 8.0, 12.0, 16.0, 24.0, 32.0, 48.0)
-    assert t["waves_per_cu"] in ((8, 6) if prec == "fp64" else (12, 8))
+    assert t["waves_per_cu"] in (12, 8)
     assert t["candidates"] == 20
     assert t["scratch_blocks"] in (512, 1024, 2048)
     assert 0.0 < t["ms_best"] <= t["ms_default"]
