@@ -48,12 +48,15 @@ def log(*a):
 
 
 PHASE_ALIGNED = -1  # --phase-aligned: -1 by neighbourhood size, 0 off, 1 on
+DETERMINISTIC = False  # --deterministic: fixed tiles and a fixed-order reduction
 
 
 def make_ctx(tpcf, stream):
-    """A library context on device 0 and `stream`, with the run's phase-alignment setting."""
+    """A library context on device 0 and `stream`, with the run's phase-alignment and
+    deterministic settings."""
     ctx = tpcf.Context(0, stream)
     ctx.set_phase_aligned(PHASE_ALIGNED)
+    ctx.set_deterministic(DETERMINISTIC)
     return ctx
 
 
@@ -888,6 +891,8 @@ def main():
                                                          "in mean pixel separations")
     ap.add_argument("--phase-aligned", type=int, default=-1, choices=(-1, 0, 1),
                     help="phase-aligned stencil sweeps (-1 by neighbourhood size, 0 off, 1 on)")
+    ap.add_argument("--deterministic", action="store_true",
+                    help="bit-reproducible results (tpcf_set_deterministic): fixed tiles, fixed-order reduction")
     ap.add_argument("--exact-chunks", type=int, default=0, help="sphere form above nside 1024: time the exact "
                                                                 "sum on this many of the --chunks ranges (0: all)")
     args = ap.parse_args()
@@ -895,8 +900,9 @@ def main():
         print("bench.py measures one GPU only: the library has no multi-GPU path "
               f"(asked for --gpus {args.gpus}).", file=sys.stderr)
         sys.exit(2)
-    global PHASE_ALIGNED
+    global PHASE_ALIGNED, DETERMINISTIC
     PHASE_ALIGNED = args.phase_aligned
+    DETERMINISTIC = args.deterministic
     if args.workload == "batch":
         run_batch(args)
         return
@@ -970,6 +976,7 @@ def main():
             "points_per_cell": N / st["cells_per_axis"] ** 3,
             "waves": st["waves"],
             "tuning": tmix,
+            "deterministic": DETERMINISTIC,
         },
         "fp64": {"value": value64, "unit": "pairs/s", "ms_per_step": ms64, "sweep_ms": sweep64,
                  "tuning": t64},
