@@ -540,7 +540,7 @@ def run_pivots(args):
         ctx = make_ctx(tpcf, torch.cuda.current_stream())
         ctx.set_bins(NB, RMIN, RMAX, LMAX)
         ctx.set_precision(prec)
-        ctx.set_tuning(16.0, 8)
+        ctx.set_tuning(16.0, 12 if prec == "mixed" else 8)  # the library's default waves per CU
         ctx.set_pivot_cell(side)
         ctx.set_catalog(*dev[:3], dev[3], box=BOX, periodic=True)
         z = ctx.compute_zeta(device_output=True)  # warmup
