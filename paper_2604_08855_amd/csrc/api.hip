@@ -172,7 +172,7 @@ int log_level() {
 
 std::mutex g_log_mu;
 
-__attribute__((format(printf, 2, 3))) void logf(int level, const char* fmt, ...) {
+__attribute__((format(printf, 2, 3))) void log_msg(int level, const char* fmt, ...) {
   if (log_level() < level) return;
   static const char* const names[] = {"", "error", "info", "debug"};
   std::lock_guard<std::mutex> lock(g_log_mu);
@@ -191,7 +191,7 @@ __attribute__((format(printf, 2, 3))) void logf(int level, const char* fmt, ...)
 
 int fail(tpcf_ctx* c, int code, const std::string& msg) {
   if (c) c->err = msg;
-  logf(1, "status %d: %s", code, msg.c_str());
+  log_msg(1, "status %d: %s", code, msg.c_str());
   return code;
 }
 
@@ -267,7 +267,7 @@ int ensure(tpcf_ctx* c, DevBuf& b, size_t bytes, const char* what) {
     b.user = nullptr;
     b.fixed = true;
     c->arena.used = at + bytes;
-    logf(3, "static scratch: %s %zu bytes at offset %zu", what, bytes, at);
+    log_msg(3, "static scratch: %s %zu bytes at offset %zu", what, bytes, at);
     return TPCF_OK;
   }
   const size_t cap = device_cap();
@@ -288,7 +288,7 @@ int ensure(tpcf_ctx* c, DevBuf& b, size_t bytes, const char* what) {
     }
   }
   b.bytes = bytes;
-  logf(3, "device buffer: %s %zu bytes (%zu held)", what, bytes, total_bytes(c));
+  log_msg(3, "device buffer: %s %zu bytes (%zu held)", what, bytes, total_bytes(c));
   return TPCF_OK;
 }
 
@@ -685,7 +685,7 @@ int stage(tpcf_ctx* c, const std::vector<HostCat>& cats, int64_t ntot, const voi
   } else {
     HIP_TRY(c, hipStreamSynchronize(c->stream));
   }
-  logf(2, "catalogue: %lld points in %zu catalogue(s)%s, inputs in %s memory", (long long)ntot, cats.size(),
+  log_msg(2, "catalogue: %lld points in %zu catalogue(s)%s, inputs in %s memory", (long long)ntot, cats.size(),
        (!cats.empty() && cats[0].sphere) ? " on the sphere" : "", memspace == TPCF_MEM_HOST ? "host" : "device");
   c->cats = cats;
   c->ntot = ntot;
@@ -993,7 +993,7 @@ int finish_stats(tpcf_ctx* c, bool grid_built, uint32_t ntask) {
   c->dbg_f64 = c->precision == TPCF_PREC_FP64;
   c->dbg_nb = c->nbins;
   c->dbg_nc = ncomp(c->lmax, is_sphere(c));
-  logf(2, "compute: %zu catalogue(s), %u primaries, %lld pairs, %lld candidates, %s%s, grid %.3f ms, sweep %.3f ms, "
+  log_msg(2, "compute: %zu catalogue(s), %u primaries, %lld pairs, %lld candidates, %s%s, grid %.3f ms, sweep %.3f ms, "
        "%d waves, device memory %zu bytes%s",
        c->cd.size(), ntask, (long long)st[0], (long long)st[1], c->precision == TPCF_PREC_FP64 ? "fp64" : "mixed",
        c->deterministic ? " deterministic" : "", c->stats.ms_grid, c->stats.ms_sweep, c->stats.waves,
@@ -1423,7 +1423,7 @@ int tpcf_autotune(tpcf_ctx* c, double sample_fraction, tpcf_tuning* out) {
   double ms_default = 0.0;
   rc = time_config(ppc0, wpc0, sb0, ms_default);
   if (rc == TPCF_OK)
-    logf(3, "autotune: %g points per cell, %d waves per CU, %d scratch blocks: %.3f ms (in force)", ppc0, wpc0, sb0,
+    log_msg(3, "autotune: %g points per cell, %d waves per CU, %d scratch blocks: %.3f ms (in force)", ppc0, wpc0, sb0,
          ms_default);
   double best_ms = ms_default, best_ppc = ppc0;
   int best_wpc = wpc0, best_sb = sb0, tried = 1;
@@ -1431,7 +1431,7 @@ int tpcf_autotune(tpcf_ctx* c, double sample_fraction, tpcf_tuning* out) {
     double ms = 0.0;
     rc = time_config(ppc, wpc, sb, ms);
     ++tried;
-    if (rc == TPCF_OK) logf(3, "autotune: %g points per cell, %d waves per CU, %d scratch blocks: %.3f ms", ppc, wpc, sb, ms);
+    if (rc == TPCF_OK) log_msg(3, "autotune: %g points per cell, %d waves per CU, %d scratch blocks: %.3f ms", ppc, wpc, sb, ms);
     if (rc == TPCF_OK && ms < best_ms) {
       best_ms = ms;
       best_ppc = ppc;
@@ -1463,7 +1463,7 @@ int tpcf_autotune(tpcf_ctx* c, double sample_fraction, tpcf_tuning* out) {
   c->ppc = best_ppc;
   c->waves_per_cu = best_wpc;
   c->scratch_blocks = best_sb;
-  logf(2, "autotune: %g points per cell, %d waves per CU, %d scratch blocks: %.3f ms on the sample (%.3f ms before), "
+  log_msg(2, "autotune: %g points per cell, %d waves per CU, %d scratch blocks: %.3f ms on the sample (%.3f ms before), "
        "%d configurations", best_ppc, best_wpc, best_sb, best_ms, ms_default, tried);
   if (out) {
     out->points_per_cell = best_ppc;
@@ -1774,6 +1774,7 @@ int tpcf_compute_batch_noalloc(tpcf_ctx* c, int ncat, const int64_t* offsets, co
   c->arena.used = 0;
   rc = stage(c, cats, offsets[ncat], x, y, z, w, memspace);
   if (!rc) rc = compute(c, 0, c->ntot, zeta, memspace, false);  // returns after the stream has drained
+  if (rc) (void)hipStreamSynchronize(c->stream);  // nothing queued may still use the array after a failure
   const tpcf_stats stats = c->stats;
   const std::string err = rc ? c->err : std::string();
   *c = saved;
