@@ -11,28 +11,33 @@
 // (T_k = 2 z T_{k-1} - T_{k-2}) and is shared by all m, so a pair costs about one FMA per real
 // moment plus the powers of (x - i y).
 //
-// One wavefront owns one primary at a time (tasks come from a global atomic queue):
+// One wavefront owns one primary at a time; persistent waves take tasks from an atomic queue cut
+// into one segment per XCD (a wave starts on its own XCD's segment and moves on when it is empty):
 //   stencil : the primary's own stencil: every (y, z) row of cells whose slab comes within
-//             r_max of the primary, clipped in x to the chord of the r_max sphere (cell
-//             granularity). Rows are built 64 at a time, one per lane; the rows' cell ranges are
-//             contiguous runs of the cell-sorted records. For large neighbourhoods the rows are
-//             taken in a rotated order, phase-aligned across the waves in flight (L2 sharing).
-//   pass    : rounds of 64 consecutive candidates, packed across runs. Each candidate's bin is
-//             decided in FP32 when its fractional bin position is farther than a proven error
-//             bound from a bin edge, and otherwise exactly (FP64 squared lattice separation
-//             against integer thresholds). Accepted candidates go to a per-bin LDS bucket; a
-//             full bucket becomes one scratch block of 64 sorted positions, tagged with its bin.
-//   shells  : bin by bin, the wave replays that bin's blocks: each lane adds its pair's moments
-//             into register accumulators; every <= 64 rounds the 64 lanes are combined with a
-//             transpose-reduction (permlane32/16 swaps, then DPP) into a compensated (Kahan)
-//             shell sum (mixed precision) or a plain FP64 sum. At the end of the bin the moments
-//             are turned into normalised a_lm through LDS.
+//             r_max of the primary, clipped in x to the chord of the r_max sphere (cells are up
+//             to four times thinner in x, so the clip is tighter). Rows are built 64 at a time,
+//             one per lane; each row's cells are one contiguous run of the cell-sorted records.
+//             For large neighbourhoods the rows are taken in a rotated order, phase-aligned
+//             across the waves in flight (L2 sharing).
+//   pass    : batches of four rounds of 64 consecutive candidates, packed across runs. Each
+//             candidate's bin is decided in FP32 when its fractional bin position is farther than
+//             a proven error bound from a bin edge, and otherwise exactly (FP64 squared lattice
+//             separation against integer thresholds). An accepted candidate takes the next entry
+//             of its bin's region in the wave's scratch (one LDS cursor increment) and stores its
+//             sorted position there.
+//   shells  : when a region is nearly full or the stencil is done, the wave replays bin by bin:
+//             each lane adds its pair's moments into register accumulators; every <= 64 rounds
+//             the 64 lanes are combined with a transpose-reduction (permlane32/16 swaps, then DPP)
+//             into a compensated (Kahan) shell sum (mixed precision) or a plain FP64 sum. At the
+//             end of the bin the moments are turned into normalised a_lm through LDS.
 //   contract: every 32 (mixed) or 16 (FP64) primaries, the wave multiplies its tile of shells on
 //             MFMA: per l, zeta_l += X_l diag(f w) X_l^T with X_l the [bins x (primaries*(2l+1))]
 //             matrix of real components. Mixed: three-piece BF16 split, six products, FP32
 //             accumulation within the tile. FP64: v_mfma_f64_16x16x4. Tile results are added into
 //             a per-wave FP64 partial; partials are added into zeta (FP64 atomics) when the wave
-//             changes catalogue and when it finishes.
+//             changes catalogue and when it finishes. In the deterministic form each tile of
+//             consecutive primaries writes a slot of its own instead, and a second kernel adds the
+//             slots in tile order.
 //
 // Projected fields on the unit sphere (the paper's own geometry, Statement of need, Features and
 // Performance sections) run through the same skeleton with 2D multipoles of the position angle:
