@@ -120,3 +120,35 @@ def test_large_cells_sorted(tpcf, ppc):
     ref = oracle.zeta(cat.x, cat.y, cat.z, w, cat.box, True, 6, 2.0, 20.0, 3, want_counts=True)
     np.testing.assert_array_equal(ctx.pair_counts(), ref.counts)
     assert rel_err_per_l(zs[0], ref.zeta).max() <= TOL["fp64"]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_sphere_bit_identical(tpcf, prec):
+    """A HEALPix nside-32 map (12,288 pixels, log-normal values), 8 angular bins in [0.02, 0.3)
+    rad, m_max = 6: deterministic runs with 12 and 3 waves per CU give the same bits, and match
+    the sphere oracle."""
+    m = catalogs.sphere_map(32, 5, grid=32)
+    zs = []
+    for waves in (12, 3):
+        ctx = det_ctx(tpcf, prec, 8, 0.02, 0.3, 6, waves)
+        ctx.set_sphere_catalog(m.x, m.y, m.z, m.w)
+        zs.append(ctx.compute_zeta())
+    assert np.array_equal(zs[0], zs[1])
+    ref = oracle.zeta_sphere(m.x, m.y, m.z, m.w, 8, 0.02, 0.3, 6).zeta
+    assert rel_err_per_l(zs[0], ref).max() <= TOL[prec]
+
+
+def test_shared_pivots_bit_identical(tpcf):
+    """Shared pivots (cells of 3, 6,000 log-normal points, signed weights): the deterministic
+    pivot sweep gives the same bits with 12 and 4 waves per CU and matches the pivot oracle."""
+    cat = catalogs.lognormal(6000, 150.0, 4, grid=64)
+    w = catalogs.gaussian_weights(cat.n, 9, 0.4, 1.0)
+    zs = []
+    for waves in (12, 4):
+        ctx = det_ctx(tpcf, "mixed", 10, 3.0, 30.0, 6, waves)
+        ctx.set_pivot_cell(3.0)
+        ctx.set_catalog(cat.x, cat.y, cat.z, w, box=cat.box, periodic=True)
+        zs.append(ctx.compute_zeta())
+    assert np.array_equal(zs[0], zs[1])
+    ref = oracle.zeta_pivots(cat.x, cat.y, cat.z, w, cat.box, True, 10, 3.0, 30.0, 6, 3.0).zeta
+    assert rel_err_per_l(zs[0], ref).max() <= TOL["mixed"]
