@@ -1064,6 +1064,51 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSweepWaves<
 
     // ---- shells: replay every bin's blocks (one copy of this code)
     auto process_blocks = [&]() {
+      // Look-ahead across bins (the FP32 sphere replay, whose bins hold few short rounds): the
+      // first four entries of the next non-empty bin are requested when a bin's replay starts,
+      // and its first two records when that replay ends, so that a bin's first rounds do not wait
+      // on two dependent loads. (The FP64 sphere kernel would need more VGPRs than three waves
+      // per SIMD allow.)
+      constexpr bool kAhead = SPH && !F64;
+      using RecA = std::conditional_t<F64, uint3, uint4>;
+      auto rec_at = [&](uint32_t j) -> RecA {
+        if constexpr (F64) {
+          const uint4* r = a.rec + j;
+          return make_uint3(r->x, r->y, r->z);
+        } else {
+          return a.rec[j];
+        }
+      };
+      auto next_bin = [&](int from) {
+        int q = from;
+        while (q < nb && uniform((int)bblk[q]) == 0) ++q;
+        return q;
+      };
+      int b_ahead = nb, nblk_ahead = 0;
+      uint32_t aJ[4] = {a.sentinel, a.sentinel, a.sentinel, a.sentinel};
+      RecA aR[2] = {};
+      real aW[2] = {real(0), real(0)};
+      auto request_idx = [&](int bb) {
+        nblk_ahead = uniform((int)bblk[bb]);
+        const uint32_t* sa = scratch + (size_t)uniform((int)reg[bb]) * kBlock + lane;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) aJ[k] = sa[k * kBlock];  // raw: range-checked at use
+      };
+      auto request_rec = [&]() {
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const uint32_t j = k < nblk_ahead ? aJ[k] : a.sentinel;
+          aR[k] = rec_at(j);
+          if constexpr (F64) aW[k] = a.w64[j];
+        }
+      };
+      if constexpr (kAhead) {
+        b_ahead = next_bin(0);
+        if (b_ahead < nb) {
+          request_idx(b_ahead);
+          request_rec();
+        }
+      }
       for (int b = 0; b < nb; ++b) {
         const int nblk_b = uniform((int)bblk[b]);
         if (nblk_b == 0) continue;
@@ -1117,9 +1162,27 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSweepWaves<
               if constexpr (F64) return a.w64[j];
               else return real(0);  // mixed: the weight travels in the record
             };
-            RecT R0 = pos_at(idx_at(0)), R1 = pos_at(idx_at(1));
-            real W0 = wt_at(idx_at(0)), W1 = wt_at(idx_at(1));
-            uint32_t J0 = idx_at(2), J1 = idx_at(3);
+            RecT R0, R1;
+            real W0, W1;
+            uint32_t J0, J1;
+            if constexpr (kAhead) {
+              // this bin's first entries were requested during the previous bin
+              R0 = aR[0];
+              R1 = aR[1];
+              W0 = aW[0];
+              W1 = aW[1];
+              J0 = aJ[2];
+              J1 = aJ[3];
+              b_ahead = next_bin(b + 1);
+              if (b_ahead < nb) request_idx(b_ahead);
+            } else {
+              R0 = pos_at(idx_at(0));
+              R1 = pos_at(idx_at(1));
+              W0 = wt_at(idx_at(0));
+              W1 = wt_at(idx_at(1));
+              J0 = idx_at(2);
+              J1 = idx_at(3);
+            }
             int i = 0;
             auto step = [&](RecT& R, real& W, uint32_t& J, auto WRITE) {
               // rounds stay in order, so each waits only for its own loads
@@ -1153,6 +1216,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSweepWaves<
               }
               if (!(n & 1)) step(R1, W1, J1, std::false_type{});
               flush_acc();
+            }
+            if constexpr (kAhead) {
+              if (b_ahead < nb) {
+                // the record addresses depend on this bin's sums, so the loads stay here
+                asm volatile("" : "+v"(aJ[0]), "+v"(aJ[1]) : "v"(hi[0]));
+                request_rec();
+              }
             }
           } else {
             // Mixed 3D: one round of software pipeline (the record of the next round and the
