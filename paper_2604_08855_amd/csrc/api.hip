@@ -36,7 +36,7 @@ hipError_t launch_sweep(int lmax, bool f64, bool sphere, const SweepArgs& args, 
 hipError_t launch_det_reduce(const double* det_out, uint32_t stride, const uint2* chunks, uint32_t nchunk,
                              const uint32_t* cat_chunk, int ncat, uint32_t Z, int nb, double* part1, double* zeta,
                              double* dd, hipStream_t s);
-size_t sweep_lds_bytes(int nb, bool f64);
+size_t sweep_lds_bytes(int nb, int lmax, bool f64, bool sphere);
 size_t sweep_tile_bytes_per_wave(int lmax, int nb, bool f64, bool sphere);
 std::vector<double> threej_squared_table(int lmax);
 hipError_t launch_edge_correct(int ncat, int lmax, int nb, const double* N, const double* R, const double* t3,
@@ -817,7 +817,7 @@ int prepare_sweep(tpcf_ctx* c, const uint32_t* tasks_d, uint32_t ntask, SweepArg
   // From the static scratch, shorter pair lists by default (more waves fit in it).
   if (c->arena.on && c->scratch_blocks <= 0) S = std::min(S, std::max(kMinRegionBlocks * nb, kStaticScratchBlocks));
   int rc;
-  const size_t lds = sweep_lds_bytes(nb, f64);
+  const size_t lds = sweep_lds_bytes(nb, L, f64, sph);
   if (lds > 160 * 1024) return fail(c, TPCF_E_UNSUPPORTED, "LDS layout too large");
   // no more waves per CU than its 160 KiB of LDS holds (allocated in 512-byte granules)
   const int lds_waves = (int)((160 * 1024) / ((lds + 511) & ~(size_t)511));

@@ -619,7 +619,14 @@ struct Lds {
   static constexpr int CUR = RUNS + 1024;        // uint64[kMaxBins]: bin cursors
   static constexpr int PARK = CUR + 8 * kMaxBins;  // uint4[kBatch][64] records, uint32[kBatch][64] ids
   static constexpr int END = PARK + kBatch * 64 * 20;
-  static __host__ __device__ int bytes(int) { return END; }
+  // 3D only: the moment -> a_lm conversion, real coef[NC][kConvTerms] then int16 idx[NC][kConvTerms]
+  static constexpr int CONV = END;
+  static __host__ __device__ constexpr int conv_bytes(int lmax, bool f64, bool sph) {
+    return sph ? 0 : (((lmax + 1) * (lmax + 1) * kConvTerms * ((f64 ? 8 : 4) + 2) + 15) & ~15);
+  }
+  static __host__ __device__ constexpr int bytes(int lmax, bool f64, bool sph) {
+    return END + conv_bytes(lmax, f64, sph);
+  }
 };
 
 // One row of the per-primary stencil: up to two runs [b, e) of sorted positions.
@@ -749,8 +756,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSweepWaves<
   real* mom = reinterpret_cast<real*>(smem + Lds::MOM);
   uint2* runs = reinterpret_cast<uint2*>(smem + Lds::RUNS);
   unsigned long long* cur = reinterpret_cast<unsigned long long*>(smem + Lds::CUR);
+  real* scoef = reinterpret_cast<real*>(smem + Lds::CONV);
+  int16_t* sidx = reinterpret_cast<int16_t*>(smem + Lds::CONV + NC * kConvTerms * sizeof(real));
 
   const int lane = threadIdx.x;
+  // The conversion table stays in LDS for the whole sweep (the epilogue of every bin reads it);
+  // unused terms point at moment 0 with a zero coefficient, so the sums need no test.
+  if constexpr (!SPH) {
+    for (int i = lane; i < NC * kConvTerms; i += 64) {
+      const int mi = a.conv_idx[i];
+      sidx[i] = (int16_t)(mi >= 0 ? mi : 0);
+      scoef[i] = mi >= 0 ? (F64 ? (real)a.conv_coef64[i] : (real)a.conv_coef32[i]) : real(0);
+    }
+  }
   const int nb = a.nb;
   const int S = a.scratch_blocks;
   const uint32_t wave = blockIdx.x;
@@ -1262,24 +1280,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSweepWaves<
         __syncthreads();
         if (lane == b) sdd += (double)mom[0];  // M_00 = sum of w_j over the bin
         // moments -> normalised a_lm of bin b (on the sphere the moments are the a_m)
-        for (int c = lane; c < NC; c += 64) {
-          real v = real(0);
-          if constexpr (SPH) {
-            v = mom[c];
-          } else {
+        // both passes over the components unrolled, so their LDS reads are in flight together
 #pragma unroll
-            for (int q = 0; q < kConvTerms; ++q) {
-              const int mi = a.conv_idx[c * kConvTerms + q];
-              if (mi >= 0) {
-                const real cf =
-                    F64 ? (real)a.conv_coef64[c * kConvTerms + q] : (real)a.conv_coef32[c * kConvTerms + q];
-                v += cf * mom[mi];
-              }
+        for (int it = 0; it < (NC + 63) / 64; ++it) {
+          const int c = lane + 64 * it;
+          if (c < NC) {
+            real v = real(0);
+            if constexpr (SPH) {
+              v = mom[c];
+            } else {
+#pragma unroll
+              for (int q = 0; q < kConvTerms; ++q) v += scoef[c * kConvTerms + q] * mom[sidx[c * kConvTerms + q]];
             }
+            real* dst = slot + b * NC + c;
+            if (written & (1u << b)) v += *dst;
+            *dst = v;
           }
-          real* dst = slot + b * NC + c;
-          if (written & (1u << b)) v += *dst;
-          *dst = v;
         }
         __syncthreads();
         written |= 1u << b;
@@ -1516,9 +1532,9 @@ hipError_t launch_det_reduce(const double* det_out, uint32_t stride, const uint2
   return hipGetLastError();
 }
 
-size_t sweep_lds_bytes(int nb, bool f64) {
-  (void)f64;
-  return (size_t)Lds::bytes(nb);
+size_t sweep_lds_bytes(int nb, int lmax, bool f64, bool sphere) {
+  (void)nb;
+  return (size_t)Lds::bytes(lmax, f64, sphere);
 }
 
 // Bytes of per-wave tile area, including the FP64 zeta partial.
@@ -1536,7 +1552,7 @@ static hipError_t launch_l(bool f64, bool sphere, const SweepArgs& args, int wav
 }
 
 hipError_t launch_sweep(int lmax, bool f64, bool sphere, const SweepArgs& args, int waves, hipStream_t stream) {
-  const size_t lds = sweep_lds_bytes(args.nb, f64);
+  const size_t lds = sweep_lds_bytes(args.nb, lmax, f64, sphere);
   hipError_t err = hipErrorInvalidValue;
   switch (lmax) {
     case 0: err = launch_l<0>(f64, sphere, args, waves, lds, stream); break;
