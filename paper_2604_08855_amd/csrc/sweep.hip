@@ -344,6 +344,14 @@ struct Tangent {
   real e1x, e1y, e1z, e2x, e2y, e2z;
 };
 
+// Orders LDS accesses between the lanes of the wavefront: a workgroup is one wavefront, whose LDS
+// operations complete in issue order, so only the compiler must not move accesses across this
+// point (no wait on outstanding global memory operations, unlike a workgroup barrier).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 __device__ __forceinline__ float uniform_f(float v) {
   return __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(v)));
 }
@@ -1277,7 +1285,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSweepWaves<
             if (ms >= 0 && ms < NC) mom[ms] = F64 ? hi[k] : (hi[k] - lo[k]);
           }
         });
-        __syncthreads();
+        wave_sync();  // the moments in LDS, for every lane
         if (lane == b) sdd += (double)mom[0];  // M_00 = sum of w_j over the bin
         // moments -> normalised a_lm of bin b (on the sphere the moments are the a_m)
         // both passes over the components unrolled, so their LDS reads are in flight together
@@ -1297,7 +1305,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSweepWaves<
             *dst = v;
           }
         }
-        __syncthreads();
+        wave_sync();  // mom is rewritten by the next bin (the tile is read after a barrier)
         written |= 1u << b;
       }
     };
@@ -1462,6 +1470,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSweepWaves<
     for (int off = 32; off > 0; off >>= 1) pairs_p += __shfl_xor(pairs_p, off);
     my_pairs += pairs_p;
     if (a.alm_debug) {
+      __syncthreads();  // the tile's stores by every lane
       real* dbg = reinterpret_cast<real*>(a.alm_debug) + (size_t)p * nb * NC;
       for (int i = lane; i < nb * NC; i += 64) dbg[i] = slot[i];
     }
