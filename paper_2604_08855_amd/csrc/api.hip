@@ -142,6 +142,7 @@ struct tpcf_ctx {
   bool sums_valid = false;
   int sums_ncat = 0, sums_nb = 0;
   int conv_lmax = -1;
+  int conv_q = 0;  // terms per lane of the conversion table in use
   int regions_key = -1;
 
   // results of the last compute
@@ -382,6 +383,42 @@ void conversion(int lmax, std::vector<int16_t>& idx, std::vector<double>& coef) 
         }
       }
     }
+  }
+}
+
+// The conversion's non-zero terms spread over the 64 lanes of a wave, so that each lane runs a few
+// terms instead of every term slot of its components (at l_max = 10, 286 terms in 726 slots):
+// components are taken longest first, each to the lane with the fewest terms so far, and a lane
+// runs its components' terms in sequence. Entry (q, lane) is coef[q * 64 + lane] and
+// meta[q * 64 + lane] = moment | component << 7 | (last term of the component) << 14; padding
+// entries are zero. Q is the longest lane (at most kConvTerms).
+void conversion_lanes(int lmax, const std::vector<int16_t>& idx, const std::vector<double>& coef, int& Q,
+                      std::vector<int16_t>& meta, std::vector<double>& lcoef) {
+  const int nc = (lmax + 1) * (lmax + 1);
+  std::vector<int> count(nc, 0), order(nc);
+  for (int c = 0; c < nc; ++c) {
+    order[c] = c;
+    while (count[c] < kConvTerms && idx[(size_t)c * kConvTerms + count[c]] >= 0) ++count[c];
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return count[x] > count[y]; });
+  std::vector<std::vector<int>> lanes(64);
+  std::vector<int> load(64, 0);
+  for (int c : order) {
+    const int ln = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    lanes[ln].push_back(c);
+    load[ln] += count[c];
+  }
+  Q = *std::max_element(load.begin(), load.end());
+  meta.assign((size_t)kConvTerms * 64, 0);
+  lcoef.assign((size_t)kConvTerms * 64, 0.0);
+  for (int ln = 0; ln < 64; ++ln) {
+    int q = 0;
+    for (int c : lanes[ln])
+      for (int t = 0; t < count[c]; ++t, ++q) {
+        const int mi = idx[(size_t)c * kConvTerms + t];
+        meta[(size_t)q * 64 + ln] = (int16_t)(mi | (c << 7) | (t + 1 == count[c] ? 1 << 14 : 0));
+        lcoef[(size_t)q * 64 + ln] = coef[(size_t)c * kConvTerms + t];
+      }
   }
 }
 
@@ -795,7 +832,7 @@ size_t later_sweep_bytes(const tpcf_ctx* c, uint32_t ntask) {
   const size_t ncat = c->cd.size(), n = (size_t)c->ntot;
   auto up = [](size_t b) { return (std::max<size_t>(b, 16) + kArenaAlign - 1) & ~(kArenaAlign - 1); };
   size_t t = up(ncat * (L + 1) * nb * nb * 8) + up(kQueueSegments * 4) + up(16) + 2 * up(ncat * nb * 8);
-  const size_t nconv = (L + 1) * (L + 1) * kConvTerms;
+  const size_t nconv = (size_t)kConvTerms * 64;  // the conversion spread over the lanes
   t += up(nconv * 2) + up(nconv * 8) + up(nconv * 4) + up((nb + 1) * 4);
   if (c->debug) t += up(n * nb * 4) + up(n * nb * NC * (f64 ? 8 : 4));
   if (c->deterministic) {
@@ -846,9 +883,11 @@ int prepare_sweep(tpcf_ctx* c, const uint32_t* tasks_d, uint32_t ntask, SweepArg
       (rc = ensure(c, c->bin_dd, (size_t)ncat * nb * 8, "pair sums")))
     return rc;
   if (c->conv_lmax != L) {
-    std::vector<int16_t> idx;
-    std::vector<double> coef;
-    conversion(L, idx, coef);
+    std::vector<int16_t> idx0, idx;
+    std::vector<double> coef0, coef;
+    conversion(L, idx0, coef0);
+    conversion_lanes(L, idx0, coef0, c->conv_q, idx, coef);
+    if (c->conv_q > kConvTerms) return fail(c, TPCF_E_UNSUPPORTED, "conversion table does not fit the lanes");
     std::vector<float> coef32(coef.begin(), coef.end());
     if ((rc = ensure(c, c->conv_idx, idx.size() * 2, "constants")) ||
         (rc = ensure(c, c->conv64, coef.size() * 8, "constants")) ||
@@ -893,6 +932,7 @@ int prepare_sweep(tpcf_ctx* c, const uint32_t* tasks_d, uint32_t ntask, SweepArg
   a.bin_pairs = (unsigned long long*)c->bin_pairs.p;
   a.bin_dd = (double*)c->bin_dd.p;
   a.conv_idx = (const int16_t*)c->conv_idx.p;
+  a.conv_q = c->conv_q;
   a.conv_coef32 = (const float*)c->conv32.p;
   a.conv_coef64 = (const double*)c->conv64.p;
   a.phase_rows = phase_aligned(c);

@@ -627,10 +627,11 @@ struct Lds {
   static constexpr int CUR = RUNS + 1024;        // uint64[kMaxBins]: bin cursors
   static constexpr int PARK = CUR + 8 * kMaxBins;  // uint4[kBatch][64] records, uint32[kBatch][64] ids
   static constexpr int END = PARK + kBatch * 64 * 20;
-  // 3D only: the moment -> a_lm conversion, real coef[NC][kConvTerms] then int16 idx[NC][kConvTerms]
+  // 3D only: the moment -> a_lm conversion spread over the lanes, real coef[kConvTerms][64] then
+  // int16 meta[kConvTerms][64]
   static constexpr int CONV = END;
   static __host__ __device__ constexpr int conv_bytes(int lmax, bool f64, bool sph) {
-    return sph ? 0 : (((lmax + 1) * (lmax + 1) * kConvTerms * ((f64 ? 8 : 4) + 2) + 15) & ~15);
+    return sph ? 0 : ((kConvTerms * 64 * ((f64 ? 8 : 4) + 2) + 15) & ~15) + 0 * lmax;
   }
   static __host__ __device__ constexpr int bytes(int lmax, bool f64, bool sph) {
     return END + conv_bytes(lmax, f64, sph);
@@ -765,16 +766,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSweepWaves<
   uint2* runs = reinterpret_cast<uint2*>(smem + Lds::RUNS);
   unsigned long long* cur = reinterpret_cast<unsigned long long*>(smem + Lds::CUR);
   real* scoef = reinterpret_cast<real*>(smem + Lds::CONV);
-  int16_t* sidx = reinterpret_cast<int16_t*>(smem + Lds::CONV + NC * kConvTerms * sizeof(real));
+  int16_t* smeta = reinterpret_cast<int16_t*>(smem + Lds::CONV + kConvTerms * 64 * sizeof(real));
 
   const int lane = threadIdx.x;
-  // The conversion table stays in LDS for the whole sweep (the epilogue of every bin reads it);
-  // unused terms point at moment 0 with a zero coefficient, so the sums need no test.
+  // The conversion table stays in LDS for the whole sweep (the epilogue of every bin reads it).
   if constexpr (!SPH) {
-    for (int i = lane; i < NC * kConvTerms; i += 64) {
-      const int mi = a.conv_idx[i];
-      sidx[i] = (int16_t)(mi >= 0 ? mi : 0);
-      scoef[i] = mi >= 0 ? (F64 ? (real)a.conv_coef64[i] : (real)a.conv_coef32[i]) : real(0);
+    for (int i = lane; i < a.conv_q * 64; i += 64) {
+      smeta[i] = a.conv_idx[i];
+      scoef[i] = F64 ? (real)a.conv_coef64[i] : (real)a.conv_coef32[i];
     }
   }
   const int nb = a.nb;
@@ -1288,21 +1287,25 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSweepWaves<
         wave_sync();  // the moments in LDS, for every lane
         if (lane == b) sdd += (double)mom[0];  // M_00 = sum of w_j over the bin
         // moments -> normalised a_lm of bin b (on the sphere the moments are the a_m)
-        // both passes over the components unrolled, so their LDS reads are in flight together
-#pragma unroll
-        for (int it = 0; it < (NC + 63) / 64; ++it) {
-          const int c = lane + 64 * it;
-          if (c < NC) {
-            real v = real(0);
-            if constexpr (SPH) {
-              v = mom[c];
-            } else {
-#pragma unroll
-              for (int q = 0; q < kConvTerms; ++q) v += scoef[c * kConvTerms + q] * mom[sidx[c * kConvTerms + q]];
-            }
+        if constexpr (SPH) {
+          for (int c = lane; c < NC; c += 64) {
+            real v = mom[c];
             real* dst = slot + b * NC + c;
             if (written & (1u << b)) v += *dst;
             *dst = v;
+          }
+        } else {
+          // this lane's terms in sequence; a component is stored after its last term
+          real v = real(0);
+          for (int q = 0; q < a.conv_q; ++q) {
+            const int meta = smeta[q * 64 + lane];
+            v += scoef[q * 64 + lane] * mom[meta & 0x7F];
+            if (meta & 0x4000) {
+              real* dst = slot + b * NC + ((meta >> 7) & 0x7F);
+              if (written & (1u << b)) v += *dst;
+              *dst = v;
+              v = real(0);
+            }
           }
         }
         wave_sync();  // mom is rewritten by the next bin (the tile is read after a barrier)

@@ -81,10 +81,13 @@ struct SweepArgs {
   unsigned long long* stats;    // [0] pairs, [1] candidates
   unsigned long long* bin_pairs;  // [ncat][nb] ordered pairs per bin
   double* bin_dd;               // [ncat][nb] sum over pairs of w_p w_j per bin
-  // moments -> a_lm: component c = sum_t conv_coef[c][t] * moment[conv_idx[c][t]] (t < kConvTerms)
+  // moments -> a_lm, spread over the lanes: entry (q, lane), q < conv_q, adds
+  // conv_coef[q * 64 + lane] * moment[m] to component c, with conv_idx[q * 64 + lane] =
+  // m | c << 7 | last << 14 (last: the component is complete)
   const int16_t* conv_idx;
   const float* conv_coef32;
   const double* conv_coef64;
+  int32_t conv_q;
   // deterministic form (NULL det_tiles: off): tile k covers tasks [det_tiles[k].x, det_tiles[k].y)
   // of one catalogue; its zeta contraction and weight sums go to det_out + k * det_stride
   const uint2* det_tiles;
