@@ -780,6 +780,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSweepWaves<
   const int S = a.scratch_blocks;
   const uint32_t wave = blockIdx.x;
   uint32_t* scratch = a.scratch + (size_t)wave * (S + kScratchTail) * kBlock;
+  // Scratch accesses as a wave-uniform address plus a 32-bit byte offset per lane (a wave's
+  // scratch is far below 4 GiB), which the loads and stores take in their scalar-base form:
+  // no 64-bit address arithmetic on the VALU.
+  uint32_t lane4 = (uint32_t)lane * 4u;
+  auto entry = [&](const uint32_t* blk) -> uint32_t {  // this lane's entry of a block
+    asm volatile("" : "+v"(lane4));  // keeps the per-lane part apart from the uniform address
+    return *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(blk) + lane4);
+  };
+  auto put = [&](uint32_t k, uint32_t v) {  // entry k of the wave's scratch
+    *reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(scratch) + (k << 2)) = v;
+  };
   real* tile = reinterpret_cast<real*>(a.tile) + (size_t)wave * (TP * nb * NC + (LMAX + 1) * nb * nb * (F64 ? 1 : 2));
   double* part = reinterpret_cast<double*>(tile + TP * nb * NC);
   // DET: slot of the current tile, [(LMAX+1) nb nb] zeta then [nb] weight sums
@@ -1115,9 +1126,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSweepWaves<
       real aW[2] = {real(0), real(0)};
       auto request_idx = [&](int bb) {
         nblk_ahead = uniform((int)bblk[bb]);
-        const uint32_t* sa = scratch + (size_t)uniform((int)reg[bb]) * kBlock + lane;
+        const uint32_t* sa = scratch + (size_t)uniform((int)reg[bb]) * kBlock;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) aJ[k] = sa[k * kBlock];  // raw: range-checked at use
+        for (int k = 0; k < 4; ++k) aJ[k] = entry(sa + k * kBlock);  // raw: range-checked at use
       };
       auto request_rec = [&]() {
 #pragma unroll
@@ -1138,8 +1149,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSweepWaves<
         const int nblk_b = uniform((int)bblk[b]);
         if (nblk_b == 0) continue;
         const int k0 = uniform((int)reg[b]);
-        // this lane's entry of block i of the bin is sb[i * kBlock]
-        const uint32_t* sb = scratch + (size_t)k0 * kBlock + lane;
+        // this lane's entry of block i of the bin is entry(sb + i * kBlock)
+        const uint32_t* sb = scratch + (size_t)k0 * kBlock;
         static_for<0, P::NG>([&](auto G) {
           constexpr int SG = P::slots(G);
           constexpr int per = SG >= 64 ? SG / 64 : 1;
@@ -1174,7 +1185,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSweepWaves<
             // Reads past a bin's last block stay inside the wave's scratch (kScratchTail spare
             // blocks follow the regions); such entries are replaced by the sentinel before use.
             using RecT = std::conditional_t<F64, uint3, uint4>;
-            auto idx_at = [&](int k) -> uint32_t { return k < nblk_b ? sb[k * kBlock] : a.sentinel; };
+            auto idx_at = [&](int k) -> uint32_t { return k < nblk_b ? entry(sb + k * kBlock) : a.sentinel; };
             auto pos_at = [&](uint32_t j) -> RecT {
               if constexpr (F64) {
                 const uint4* r = a.rec + j;
@@ -1221,12 +1232,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSweepWaves<
               // record address depend on this round's unit vector and weight, so the loads cannot
               // be hoisted above their last use.
               // J holds the raw entry of round i + 2 (read two rounds ago, possibly past the
-              // bin's end): it is range-checked here, at its use.
-              uint32_t jr = i + 2 < nblk_b ? J : a.sentinel;
+              // bin's end). Clamped to the sentinel index (the last record) it addresses a
+              // record in any case; past the bin's end that record is never evaluated.
+              uint32_t jr = min(J, a.sentinel);
               asm volatile("" : "+v"(jr), "+v"(w) : "v"(vx));
               R = pos_at(jr);
               if constexpr (F64) W = a.w64[jr];
-              J = sb[(i + 4) * kBlock];
+              J = entry(sb + (i + 4) * kBlock);
               accumulate<LMAX, F64, SPH, G, decltype(WRITE)::value>(acc, vx, vy, vz, w);
               ++i;
             };
@@ -1252,16 +1264,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSweepWaves<
           } else {
             // Mixed 3D: one round of software pipeline (the record of the next round and the
             // index of the round after it are in flight while the current round is evaluated);
-            // its rounds are long enough to cover the latency.
-            uint32_t jn = nblk_b > 1 ? sb[kBlock] : a.sentinel;
-            uint4 r = a.rec[sb[0]];
+            // its rounds are long enough to cover the latency. (Two alternating register sets
+            // instead of the copies at the end of each round measured slower.)
+            uint32_t jn = nblk_b > 1 ? entry(sb + kBlock) : a.sentinel;
+            uint4 r = a.rec[entry(sb)];
             int i = 0;
             auto step = [&](auto WRITE) {
               uint4 rn = r;
               uint32_t jnn = a.sentinel;
               if (i + 1 < nblk_b) {
                 rn = a.rec[jn];
-                if (i + 2 < nblk_b) jnn = sb[(i + 2) * kBlock];
+                if (i + 2 < nblk_b) jnn = entry(sb + (i + 2) * kBlock);
               }
               real vx, vy, vz;
               direction<SPH>(P0, tb, r, vx, vy, vz);
@@ -1344,33 +1357,47 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSweepWaves<
     // passed its soft limit.
     // FP32 bin position of a candidate: 3D linear in the separation, sphere linear in
     // theta = 2 asin(chord / 2). fast: far enough from a bin edge for the FP32 decision.
-    auto bin_pos = [&](const uint4& r, int& bb, bool& fast) {
+    // The bin constants are copied into VGPRs once per batch: the kernel's wave-uniform values
+    // outnumber the scalar registers, and a spilled one read back per candidate costs a VALU
+    // issue slot (v_readlane) each time.
+    struct BinK {
+      float inv_dl, u0, eps, one_me, hinv;
+    };
+    auto bin_consts = [&]() {
+      BinK k = {cu.inv_dl, cu.u0, cu.eps, cu.one_me, cu.hinv};
+      // (3D only: the sphere kernel measured faster with its constants left to the compiler)
+      if constexpr (!SPH) asm volatile("" : "+v"(k.inv_dl), "+v"(k.u0), "+v"(k.eps), "+v"(k.one_me));
+      return k;
+    };
+    auto bin_pos = [&](const uint4& r, const BinK& k, int& bb, bool& fast) {
       const float fx = (float)sdiff(r.x, P0.qx), fy = (float)sdiff(r.y, P0.qy), fz = (float)sdiff(r.z, P0.qz);
       const float r2 = fx * fx + fy * fy + fz * fz;
       float uu;
       if constexpr (SPH) {
-        const float x = __builtin_amdgcn_sqrtf(r2) * cu.hinv;
-        uu = (cu.asin_small ? asin_small(x) : asin01(x)) * cu.inv_dl + cu.u0;
+        const float x = __builtin_amdgcn_sqrtf(r2) * k.hinv;
+        uu = (cu.asin_small ? asin_small(x) : asin01(x)) * k.inv_dl + k.u0;
       } else {
-        uu = __builtin_amdgcn_sqrtf(r2) * cu.inv_dl + cu.u0;
+        uu = __builtin_amdgcn_sqrtf(r2) * k.inv_dl + k.u0;
       }
-      const float fl = floorf(uu);
-      const float fr = uu - fl;
-      bb = (int)fl;
-      fast = fr >= cu.eps && fr <= cu.one_me;
+      // uu - floor(uu): exact for uu >= 0 (Sterbenz); a negative uu is outside the bins anyway.
+      // v_cvt_flr_i32_f32 is floor and conversion in one instruction.
+      const float fr = __builtin_amdgcn_fractf(uu);
+      asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(bb) : "v"(uu));
+      fast = fr >= k.eps && fr <= k.one_me;
     };
     auto process_batch = [&](const uint32_t(&id)[kBatch], const uint4(&rc)[kBatch]) -> bool {
       bool soft = false;
       bool accv[kBatch];
       unsigned long long cwv[kBatch];  // set (and read) on accepted lanes only
       bool slow = false;  // this lane has a candidate near a bin edge
+      const BinK bk = bin_consts();
       // all cursor increments of the batch are issued before the first result is used, so their
       // LDS round trips overlap
 #pragma unroll
       for (int u = 0; u < kBatch; ++u) {
         int bb;
         bool fast;
-        bin_pos(rc[u], bb, fast);
+        bin_pos(rc[u], bk, bb, fast);
         const bool ok = id[u] != a.sentinel;
         const bool acc = ok && fast && (uint32_t)bb < (uint32_t)nb;
         slow |= ok && !fast;
@@ -1382,7 +1409,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSweepWaves<
         if (accv[u]) {
           const unsigned long long cw = cwv[u];
           soft |= (uint32_t)cw >= (uint32_t)(cw >> 32);
-          scratch[(uint32_t)cw] = id[u];
+          put((uint32_t)cw, id[u]);
         }
       }
       if (__builtin_amdgcn_ballot_w64(slow)) {  // rare: the FP32 position is recomputed rather than kept
@@ -1390,7 +1417,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSweepWaves<
         for (int u = 0; u < kBatch; ++u) {
           int bb;
           bool fast;
-          bin_pos(rc[u], bb, fast);
+          bin_pos(rc[u], bk, bb, fast);
           if (id[u] != a.sentinel && !fast) {
             const double ddx = sdiff(rc[u].x, P0.qx) >> cu.sh, ddy = sdiff(rc[u].y, P0.qy) >> cu.sh,
                          ddz = sdiff(rc[u].z, P0.qz) >> cu.sh;
@@ -1401,7 +1428,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSweepWaves<
               while (bb + 1 < nb && R2 >= sT[bb + 1]) ++bb;
               const unsigned long long cw = atomicAdd(&cur[bb], 1ull);
               soft |= (uint32_t)cw >= (uint32_t)(cw >> 32);
-              scratch[(uint32_t)cw] = id[u];
+              put((uint32_t)cw, id[u]);
             }
           }
         }
