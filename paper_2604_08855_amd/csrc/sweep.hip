@@ -1047,6 +1047,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSweepWaves<
       pre_v = lane < cnt ? pre : kInvalid;
       dl_v = rr.x - pre;
       sub_T = uniform(__builtin_amdgcn_readlane(incl, 63));
+      my_cand += sub_T;  // the batches of the sub-chunk cover its candidates once
       run_next += cnt;
       o = 0;
       lds_order();
@@ -1087,7 +1088,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSweepWaves<
           if (g[u] >= ps) delta[u] = ds;
         delta_c = ds;
       }
-      my_cand += (unsigned long long)min(sub_T - o, span);
 #pragma unroll
       for (int u = 0; u < kBatch; ++u) id[u] = g[u] < sub_T ? g[u] + delta[u] : a.sentinel;
       o += span;
