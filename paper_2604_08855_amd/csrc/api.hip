@@ -836,7 +836,7 @@ size_t later_sweep_bytes(const tpcf_ctx* c, uint32_t ntask) {
   t += up(nconv * 2) + up(nconv * 8) + up(nconv * 4) + up((nb + 1) * 4);
   if (c->debug) t += up(n * nb * 4) + up(n * nb * NC * (f64 ? 8 : 4));
   if (c->deterministic) {
-    const size_t TP = f64 ? kTileF64 : kTileF32;
+    const size_t TP = tile_primaries(f64, sph);
     const size_t tiles = ntask / TP + ncat + 1, chunks = tiles / kDetChunk + ncat + 1;
     const size_t stride = (L + 1) * nb * nb + nb;
     t += up(tiles * 8) + up(tiles * stride * 8) + up(chunks * 8) + up((ncat + 1) * 4) + up(chunks * stride * 8);
@@ -944,7 +944,7 @@ int prepare_sweep(tpcf_ctx* c, const uint32_t* tasks_d, uint32_t ntask, SweepArg
 // fixed-order reduction (chunks of kDetChunk consecutive tiles, then the chunks of a catalogue).
 int setup_det(tpcf_ctx* c, const std::vector<uint32_t>& starts, SweepArgs& a) {
   const int ncat = (int)starts.size() - 1;
-  const uint32_t TP = c->precision == TPCF_PREC_FP64 ? kTileF64 : kTileF32;
+  const uint32_t TP = tile_primaries(c->precision == TPCF_PREC_FP64, is_sphere(c));
   std::vector<uint2> tiles, chunks;
   std::vector<uint32_t> cat_chunk(ncat + 1, 0);
   for (int k = 0; k < ncat; ++k) {

@@ -618,7 +618,7 @@ __device__ __forceinline__ T uniform(T v) {
 // LDS layout (bytes), one wavefront per workgroup.
 struct Lds {
   static constexpr int T = 0;                    // double[kMaxBins + 1] thresholds
-  static constexpr int WT = 272;                 // real[32] tile weights
+  static constexpr int WT = 272;                 // real[<= 64] tile weights (256 bytes)
   static constexpr int BTOT = WT + 256;          // uint32[32] pairs per bin (this primary)
   static constexpr int BBLK = BTOT + 128;        // uint32[32] filled scratch blocks per bin
   static constexpr int REG = BBLK + 128;         // uint32[33] scratch region start per bin (blocks)
@@ -754,7 +754,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSweepWaves<
   using real = std::conditional_t<F64, double, float>;
   using P = std::conditional_t<SPH, PlanSph<LMAX>, Plan<LMAX, F64>>;
   constexpr int NC = P::NC;
-  constexpr int TP = F64 ? kTileF64 : kTileF32;
+  constexpr int TP = tile_primaries(F64, SPH);
 
   extern __shared__ __align__(16) unsigned char smem[];
   double* sT = reinterpret_cast<double*>(smem + Lds::T);
@@ -1579,7 +1579,7 @@ size_t sweep_lds_bytes(int nb, int lmax, bool f64, bool sphere) {
 // Bytes of per-wave tile area, including the FP64 zeta partial.
 size_t sweep_tile_bytes_per_wave(int lmax, int nb, bool f64, bool sphere) {
   const int NC = ncomp(lmax, sphere);
-  const size_t tp = f64 ? kTileF64 : kTileF32;
+  const size_t tp = tile_primaries(f64, sphere);
   const size_t elem = f64 ? 8 : 4;
   return tp * nb * NC * elem + (size_t)(lmax + 1) * nb * nb * 8;
 }

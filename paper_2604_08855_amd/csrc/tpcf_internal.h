@@ -18,8 +18,12 @@ constexpr int kMinRegionBlocks = kBatch + 1;
 // a region's last block.
 constexpr int kScratchTail = 4;
 constexpr int kQueueSegments = 8;  // task-queue segments, one per XCD
-constexpr int kTileF32 = 32;     // primaries per contraction tile, mixed precision
-constexpr int kTileF64 = 16;     // primaries per contraction tile, FP64
+constexpr int kTileF32 = 32;        // primaries per contraction tile, mixed precision
+constexpr int kTileF32Sphere = 64;  // the same on the sphere (few components, many primaries)
+constexpr int kTileF64 = 16;        // primaries per contraction tile, FP64
+__host__ __device__ constexpr int tile_primaries(bool f64, bool sphere) {
+  return f64 ? kTileF64 : (sphere ? kTileF32Sphere : kTileF32);
+}
 
 // One catalogue as the kernels see it. Points of catalogue c occupy sorted positions
 // [point_base, point_base + npoints) of the concatenated arrays; its cells occupy
