@@ -127,8 +127,9 @@ int tpcf_set_precision(tpcf_ctx* ctx, int precision);
  * capped by what the compute unit's LDS holds), and scratch blocks
  * of 64 secondaries per wave (default 1024 in 3D and 512 on the sphere). A value of 0 keeps the
  * current setting.
- * Errors: TPCF_E_INVALID_ARG for negative values or scratch_blocks not a multiple of 64; a
- * compute call with scratch_blocks below 5 x nbins fails with TPCF_E_INVALID_ARG.
+ * Errors: TPCF_E_INVALID_ARG for negative or non-finite values, waves_per_cu above 64, or
+ * scratch_blocks not a multiple of 64 or above 8192; a compute call with scratch_blocks below
+ * 5 x nbins fails with TPCF_E_INVALID_ARG.
  */
 int tpcf_set_tuning(tpcf_ctx* ctx, double points_per_cell, int waves_per_cu, int scratch_blocks);
 
