@@ -1237,8 +1237,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSweepWaves<
               // J holds the raw entry of round i + 2 (read two rounds ago, possibly past the
               // bin's end): it is range-checked here, at its use. (Clamping it to the sentinel
               // index instead would also be safe, but past the bin's end it then fetches stale
-              // records that miss the caches and hold up the next waits: the FP64 sphere sweep
-              // took 875 ms against 805 ms.)
+              // records that may miss the caches and hold up the next waits: measured 0.6%
+              // slower on the FP64 sphere sweep.)
               uint32_t jr = i + 2 < nblk_b ? J : a.sentinel;
               asm volatile("" : "+v"(jr), "+v"(w) : "v"(vx));
               R = pos_at(jr);
