@@ -1357,10 +1357,16 @@ int tpcf_set_precision(tpcf_ctx* c, int precision) {
   return TPCF_OK;
 }
 
+// Upper bound of scratch blocks per wave. The sweep addresses a wave's scratch with 32-bit byte
+// offsets from the wave's base.
+constexpr int kMaxScratchBlocks = 8192;
+static_assert((uint64_t)(kMaxScratchBlocks + kScratchTail) * kBlock * 4 < (1ull << 32),
+              "a wave's scratch must stay below 4 GiB");
+
 int tpcf_set_tuning(tpcf_ctx* c, double points_per_cell, int waves_per_cu, int scratch_blocks) {
   if (!c) return TPCF_E_INVALID_ARG;
   if (!(points_per_cell >= 0.0) || !is_finite(points_per_cell) || waves_per_cu < 0 || scratch_blocks < 0 ||
-      scratch_blocks % 64 != 0 || scratch_blocks > 8192 || waves_per_cu > 64)
+      scratch_blocks % 64 != 0 || scratch_blocks > kMaxScratchBlocks || waves_per_cu > 64)
     return fail(c, TPCF_E_INVALID_ARG, "invalid tuning value");
   if (points_per_cell > 0.0) c->ppc = points_per_cell;
   if (waves_per_cu > 0) c->waves_per_cu = waves_per_cu;
@@ -1490,7 +1496,8 @@ int tpcf_autotune(tpcf_ctx* c, double sample_fraction, tpcf_tuning* out) {
       if (!(ppcs[pi] == ppc0 && wpcs[wi] == wpc0)) consider(ppcs[pi], wpcs[wi], sb0);
   const int sbs[] = {(sb0 / 2) & ~63, (sb0 * 2) & ~63};  // set_tuning takes multiples of 64
   for (int si = 0; si < 2 && rc == TPCF_OK; ++si)
-    if (sbs[si] >= kMinRegionBlocks * c->nbins && sbs[si] != sb0) consider(best_ppc, best_wpc, sbs[si]);
+    if (sbs[si] >= kMinRegionBlocks * c->nbins && sbs[si] <= kMaxScratchBlocks && sbs[si] != sb0)
+      consider(best_ppc, best_wpc, sbs[si]);
   c->debug = saved_debug;
   c->stats = saved_stats;
   c->dbg_valid = false;  // debug output is kept by sorted position, and the grid was rebuilt
